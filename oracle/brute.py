@@ -1,0 +1,65 @@
+"""High-precision brute force for tiny systems (oracle, mpmath).
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+These routines take no shortcut of the method: the propagators are matrix
+exponentials evaluated in multiprecision, the Green's function is the plain
+inverse of I + B ... B, and weights are plain determinants.  They pin the
+FP64 oracle (QR-stabilized chains, rank-one ratios) on the smallest lattices.
+"""
+from __future__ import annotations
+
+import mpmath as mp
+import numpy as np
+
+from . import dqmc
+
+
+def _mp_matrix(a: np.ndarray):
+    return mp.matrix([[mp.mpf(float(x)) for x in row] for row in a])
+
+
+def mp_propagator(model: dqmc.Model, dps: int = 50):
+    """exp(-dtau (K - mu)) in multiprecision."""
+    with mp.workdps(dps):
+        km = _mp_matrix(model.K) - mp.mpf(model.mu) * mp.eye(model.N)
+        return mp.expm(-mp.mpf(model.dtau) * km)
+
+
+def mp_green(model: dqmc.Model, fields: np.ndarray, l: int, dps: int = 50, e=None) -> np.ndarray:
+    """G(l) = [I + B_l ... B_1 B_{L_tau} ... B_{l+1}]^{-1} in multiprecision,
+    returned as float64."""
+    with mp.workdps(dps):
+        if e is None:
+            e = mp_propagator(model, dps)
+        n = model.N
+        a = mp.mpf(model.alpha)
+        p = mp.eye(n)
+        for j in dqmc.chain_order(l, fields.shape[0]):
+            ev = [mp.exp(a * int(x)) for x in fields[j - 1]]
+            b = e.copy()
+            for c in range(n):
+                for r in range(n):
+                    b[r, c] *= ev[c]
+            p = b * p
+        g = (mp.eye(n) + p) ** -1
+        return np.array([[float(g[r, c]) for c in range(n)] for r in range(n)])
+
+
+def mp_log_weight(model: dqmc.Model, fields: np.ndarray, dps: int = 50, e=None):
+    """log of prod exp(-alpha s) det(I + B_{L_tau} ... B_1)^2 in multiprecision."""
+    with mp.workdps(dps):
+        if e is None:
+            e = mp_propagator(model, dps)
+        n = model.N
+        a = mp.mpf(model.alpha)
+        p = mp.eye(n)
+        for j in range(1, fields.shape[0] + 1):
+            ev = [mp.exp(a * int(x)) for x in fields[j - 1]]
+            b = e.copy()
+            for c in range(n):
+                for r in range(n):
+                    b[r, c] *= ev[c]
+            p = b * p
+        det = mp.det(mp.eye(n) + p)
+        return 2 * mp.log(abs(det)) - a * int(fields.sum())

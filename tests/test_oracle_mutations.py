@@ -1,0 +1,106 @@
+"""Planted mistakes in the oracle (CPU only): each plausible slip must make at
+least one pin fail, so the pins are not tautologies of the oracle's code."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from oracle import dqmc, lattice
+import test_oracle_dqmc as tdq
+import test_oracle_lattice as tla
+
+
+def _c1():
+    w = si.C1
+    m = dqmc.Model.from_workload(w)
+    return w, m, si.ising_fields(w.L, m.L_tau, w.seed)
+
+
+def test_transposed_shift_is_caught(monkeypatch):
+    orig = lattice.shift_matrix
+    monkeypatch.setattr(lattice, "shift_matrix", lambda L: orig(L).T.copy())
+    with pytest.raises(AssertionError):
+        tla.test_K_neighbour_lists(4)
+
+
+def test_wrong_intracell_entry_is_caught(monkeypatch):
+    orig = lattice.intracell_deltas
+
+    def bad():
+        da, db, dc = orig()
+        return da, db, dc.T.copy()
+    monkeypatch.setattr(lattice, "intracell_deltas", bad)
+    with pytest.raises(AssertionError):
+        tla.test_K_neighbour_lists(5)
+
+
+def test_missing_kron_term_is_caught(monkeypatch):
+    def bad(L, t=1.0):
+        eye = np.eye(L)
+        ks = lattice.shift_matrix(L)
+        da, db, dc = lattice.intracell_deltas()
+        m = (np.kron(np.kron(eye, eye + ks), da) + np.kron(np.kron(eye + ks, eye), db)
+             + np.kron(np.kron(eye, eye), dc))
+        return -t * (m + m.T)
+    monkeypatch.setattr(lattice, "kagome_K", bad)
+    with pytest.raises(AssertionError):
+        tla.test_K_spectrum_closed_form(6)
+
+
+def test_wrong_alpha_is_caught(monkeypatch):
+    monkeypatch.setattr(dqmc, "hs_alpha", lambda U, dtau: float(np.arccosh(np.exp(dtau * abs(U)))))
+    with pytest.raises(AssertionError):
+        tdq.test_hs_decoupling_identity(-4.0)
+
+
+def test_wrong_delta_sign_is_caught(monkeypatch):
+    monkeypatch.setattr(dqmc, "flip_delta", lambda a, s: float(np.exp(2.0 * a * s) - 1.0))
+    with pytest.raises(AssertionError):
+        tdq.test_flip_ratio_vs_determinants(_c1())
+
+
+def test_missing_sign_factor_in_ratio_is_caught(monkeypatch):
+    def bad(alpha, s, g_ii):
+        delta = dqmc.flip_delta(alpha, s)
+        r = 1.0 + delta * (1.0 - g_ii)
+        return r * r, r, delta
+    monkeypatch.setattr(dqmc, "flip_ratio", bad)
+    with pytest.raises(AssertionError):
+        tdq.test_flip_ratio_vs_determinants(_c1())
+
+
+def test_wrap_sides_swapped_is_caught(monkeypatch):
+    def bad(model, g, s_l):
+        ev = np.exp(model.alpha * s_l.astype(float))
+        gt = ev[:, None] * g / ev[None, :]
+        return model.EKinv @ gt @ model.EK
+    monkeypatch.setattr(dqmc, "wrap", bad)
+    with pytest.raises(AssertionError):
+        tdq.test_wrap_relation(_c1())
+
+
+def test_dropped_small_scales_is_caught(monkeypatch):
+    def bad(u, d, t):
+        db = np.maximum(d, 1.0)
+        rhs = u.T / db[:, None]
+        return np.linalg.solve(rhs + t, rhs)
+    monkeypatch.setattr(dqmc, "green_from_udt", bad)
+    with pytest.raises(AssertionError):
+        tdq.test_green_scratch_vs_multiprecision(_c1())
+
+
+def test_wrong_chain_order_is_caught(monkeypatch):
+    monkeypatch.setattr(dqmc, "chain_order", lambda l, Lt: list(range(1, Lt + 1)))
+    with pytest.raises(AssertionError):
+        tdq.test_wrap_relation(_c1())
+
+
+def test_wrong_update_row_is_caught(monkeypatch):
+    orig = dqmc.update_slice
+
+    def bad(gt, s, alpha, u=None, forced=None, k=1):
+        gt = gt.T.copy()   # rows and columns exchanged in the rank-one factor
+        g, a, r = orig(gt, s, alpha, u, forced, k)
+        return g.T.copy(), a, r
+    monkeypatch.setattr(dqmc, "update_slice", bad)
+    with pytest.raises(AssertionError):
+        tdq.test_rank_one_update_then_wrap_equals_scratch(_c1())
