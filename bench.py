@@ -1,0 +1,184 @@
+"""Benchmark: HS-field sweeps per second of the kagome DQMC hot path on one GPU.
+
+One step = one full sweep (L_tau slices of window decisions, delayed rank-k
+flushes and FFT wraps, plus a QR-stabilization every n_stab slices and the
+left-stack rebuild at the end), on seeded synthetic fields and uniforms that
+are resident in device memory before the timed region starts.
+
+Prints ONE JSON line.  `roofline` is for the dominant kernel (largest share
+of the timed region's kernel time, from HIP events recorded by the library
+around every launch); `cpu_baseline` times the CPU oracle on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+import numpy as np  # noqa: E402
+
+import seeded_inputs as si  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFS = 78.6           # MI355X FP64 (vector and matrix)
+F16_PEAK_TFS = 2500.0          # MI355X dense FP16/BF16 MFMA
+
+CONFIGS = {"c1": si.C1, "c2": si.C2, "c3": si.C3, "c5": si.C5}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, n_slices):
+    """Oracle (NumPy/SciPy FP64) on the first n_slices slices of a sweep of the
+    same workload, including its stabilizations; scaled to sweeps/s."""
+    from oracle import dqmc
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        threads = os.cpu_count()
+    m = dqmc.Model.from_workload(w, mu=-1.0)
+    f = si.ising_fields(w.L, m.L_tau, w.seed)
+    u = si.metropolis_uniforms(w.L, m.L_tau, w.seed)[0]
+    g0 = dqmc.green_scratch(m, f, 0)
+    t0 = time.perf_counter()
+    dqmc.sweep(m, f, g0, uniforms=u, k=w.delay_k, n_stab=w.n_stab, record=False, l_stop=n_slices)
+    dt = time.perf_counter() - t0
+    per_sweep = dt * m.L_tau / n_slices
+    return {"value": 1.0 / per_sweep, "unit": "sweeps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n_slices} of {m.L_tau} slices (incl. {n_slices // w.n_stab} stabilizations) "
+                      f"of one sweep, {dt:.1f} s, scaled by L_tau/{n_slices}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--prec", default=None, help="fp64 | mixed_f16 | mixed_bf16 (default: workload's)")
+    ap.add_argument("--delay-k", type=int, default=None)
+    ap.add_argument("--window", type=int, default=0)
+    ap.add_argument("--fft-tile", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-slices", type=int, default=40)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(independent chains shard across GPUs without collectives; "
+                                   "see the design notes)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2608_03894_amd import kdqmc
+
+    w = CONFIGS[args.config]
+    prec = args.prec or ("fp64" if w.prec == "fp64" else w.prec)
+    k = args.delay_k or w.delay_k
+    dev = torch.device("cuda:0")
+    p = kdqmc.make_params(w.L, w.U, w.beta, w.dtau, mu=-1.0, n_stab=w.n_stab, delay_k=k,
+                          window=args.window, fft_tile=args.fft_tile, prec=prec)
+    ch = kdqmc.Chain(p, device=dev)
+    N, Lt = ch.N, ch.L_tau
+    total = args.warmup + args.steps
+    fields = torch.from_numpy(si.ising_fields(w.L, Lt, w.seed)).to(dev)
+    uni = torch.from_numpy(si.metropolis_uniforms(w.L, Lt, w.seed, n_sweeps=total)).to(dev)
+    acc = torch.zeros((Lt, N), dtype=torch.uint8, device=dev)
+    errs = torch.zeros(Lt // w.n_stab, dtype=torch.float64, device=dev)
+    log(f"workload {w.name} prec={prec} k={k} N={N} L_tau={Lt}")
+    ch.set_fields(fields)
+    for s in range(args.warmup):
+        ch.sweep(uni[s], None, acc, None, errs)
+        log(f"warmup sweep {s + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+
+    ch.profile_enable(True)
+    accepts = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ch.sweep(uni[args.warmup + s], None, acc, None, errs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ch.profile_read()
+    ch.profile_enable(False)
+    accepts = int(acc.sum().item())  # last sweep's accepts
+    wrap_err = float(errs.max().item())
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+    log(f"timed {args.steps} sweeps in {elapsed:.3f} s -> {value:.3f} sweeps/s")
+    for name, (ms, n) in prof.items():
+        if n:
+            log(f"  {name:10s} {ms:10.3f} ms  {n:7d} launches  {1000 * ms / n:9.2f} us/launch")
+
+    # dominant kernel (stabilize is a composite of bmul/qr_panel/gemm and others)
+    kern = {n: v for n, v in prof.items() if n != "stabilize" and v[1] > 0}
+    dom = max(kern, key=lambda n: kern[n][0])
+    es = 8 if prec == "fp64" else 4
+    roof = None
+    dms, dn = kern[dom]
+    avg_s = dms / dn / 1000.0
+    if dom in ("wrap_cols", "wrap_rows", "bmul"):
+        e = 8 if dom == "bmul" else es
+        byt = 2.0 * N * N * e
+        ach = byt / avg_s / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "algorithmic": f"{byt:.0f} B per launch (N^2 read + N^2 write, {e} B elements)"}
+    elif dom == "flush":
+        kavg = accepts / max(1, prof["flush"][1] / args.steps)
+        fl = 2.0 * N * N * kavg
+        ach = fl / avg_s / 1e12
+        pk = FP64_PEAK_TFS if prec == "fp64" else F16_PEAK_TFS
+        roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": pk, "unit": "TFLOP/s",
+                "frac": ach / pk, "traffic": None,
+                "algorithmic": f"2 N^2 k flops per launch, k = {kavg:.1f} accepted flips per flush"}
+    else:
+        # latency-bound single-workgroup kernels: report against one CU's FP64 rate
+        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFS / 256,
+                "unit": "TFLOP/s", "frac": None, "traffic": None,
+                "algorithmic": "sequential per-site decisions / panel factorization on one workgroup"}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on {args.cpu_slices} slices ...")
+        cpu = cpu_baseline(w, min(args.cpu_slices, Lt))
+        log(f"cpu baseline {cpu['value']:.4f} sweeps/s")
+
+    out = {
+        "metric": "HS-field sweeps/sec",
+        "value": value,
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else f"f32+{prec.split('_')[1]}",
+        "data": "synthetic",
+        "config": {"workload": w.name, "L": w.L, "N": N, "U": w.U, "beta": w.beta, "L_tau": Lt,
+                   "delay_k": k, "window": ch.p.window, "prec": prec,
+                   "field_updates_per_s": value * N * Lt},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "phases_ms_per_sweep": {n: round(v[0] / args.steps, 4) for n, v in prof.items() if v[1]},
+        "launches_per_sweep": {n: v[1] // args.steps for n, v in prof.items() if v[1]},
+        "acceptance": accepts / (N * Lt),
+        "max_wrap_err": wrap_err,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

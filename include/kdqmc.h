@@ -1,0 +1,197 @@
+/*
+ * kdqmc.h -- C ABI of the MI355X (gfx950) DQMC hot path for the attractive
+ * Hubbard model on the L x L kagome lattice (N = 3 L^2 sites, 3-site cell).
+ *
+ * Method (Zhang, Li, Wang, "Accelerated quantum Monte Carlo simulations of
+ * the attractive Hubbard model on the kagome lattice"):
+ *   - the kinetic propagator exp(-dtau K) is applied to dense N x N matrices
+ *     through the momentum-space block form of Eqs. (2)-(4): per vector, one
+ *     2D FFT per sublattice, a 3x3 Bloch-block multiply per momentum, and
+ *     the inverse FFT (Eq. (6), the product of Eq. (5));
+ *   - the Ising auxiliary field is updated with the delay-update algorithm
+ *     cited in Sec. II: accepted rank-one Green's-function updates are
+ *     accumulated and added to G as one rank-k product.
+ *
+ * Conventions (all entry points):
+ *   - Site order i = (x1*L + x2)*3 + s, s = 0,1,2 for sublattices A,B,C (the
+ *     Kronecker order of Eq. (3)).  Matrices are row-major N x N.
+ *   - Every pointer argument named *_dev is DEVICE memory owned by the
+ *     caller; the library never allocates device memory.  All device work
+ *     is enqueued on the stream given to kdqmc_init_lattice and is
+ *     asynchronous: the caller synchronizes (kdqmc_sync) before reading
+ *     results on the host.
+ *   - Slices are 1-based: G(l) = [I + B_l ... B_1 B_{L_tau} ... B_{l+1}]^-1,
+ *     B_l = exp(-dtau (K - mu)) exp(V_l), V_l = diag(alpha s_l),
+ *     cosh(alpha) = exp(dtau |U| / 2) (discrete charge-channel decoupling).
+ *   - Return value: KDQMC_OK (0) or a negative error code; the message of
+ *     the last error on the calling thread is kdqmc_last_error().  A failed
+ *     call leaves the context usable unless it returns KDQMC_EHIP.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef KDQMC_H
+#define KDQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  KDQMC_OK = 0,
+  KDQMC_EINVAL = -1,       /* bad argument (NULL, out of range, fields not +-1, ...) */
+  KDQMC_EUNSUPPORTED = -2, /* lattice size or precision not compiled in */
+  KDQMC_ESTATE = -3,       /* call out of order (slice index, stabilize point) */
+  KDQMC_EHIP = -4,         /* a HIP runtime call failed */
+  KDQMC_ENUMERIC = -5,     /* non-finite value detected */
+  KDQMC_ENOSPACE = -6      /* workspace smaller than kdqmc_workspace_bytes() */
+};
+
+typedef enum {
+  KDQMC_FP64 = 0,       /* G, wrap, flush and stabilization in FP64 */
+  KDQMC_MIXED_F16 = 1,  /* FP32 G and wrap; flush as split FP16 MFMA products
+                           with FP32 accumulation; ratios and stabilization FP64 */
+  KDQMC_MIXED_BF16 = 2  /* as MIXED_F16 with split BF16 products */
+} kdqmc_prec;
+
+typedef struct {
+  int L;          /* cells per side; supported: 3, 6, 9, 12, 15, 18, 24 */
+  double t;       /* hopping, K_ij = -t on nearest neighbours (Eq. (1)) */
+  double U;       /* Hubbard interaction, U <= 0 (attractive) */
+  double mu;      /* chemical potential (kdqmc_dirac_mu gives the Dirac energy) */
+  double beta;    /* inverse temperature, beta = L_tau * dtau */
+  double dtau;    /* imaginary-time step */
+  int n_stab;     /* slices between stabilizations; must divide L_tau */
+  int delay_k;    /* largest rank of one delayed flush, 1..512 */
+  int window;     /* sites per decision window, 0 = min(delay_k, 64) */
+  int fft_tile;   /* complex vectors per wrap workgroup, 0 = automatic */
+  int prec;       /* kdqmc_prec */
+} kdqmc_params;
+
+typedef struct kdqmc_ctx kdqmc_ctx;
+
+/* Bytes of device workspace the context needs for these parameters
+ * (G, Bloch tables, fields, delay buffers, the two stabilization stacks of
+ * L_tau/n_stab + 1 UDT entries each, and linear-algebra scratch).
+ * Returns 0 for invalid parameters (kdqmc_last_error says why). */
+size_t kdqmc_workspace_bytes(const kdqmc_params* p);
+
+/* Chemical potential at the Dirac energy of the kagome bands: the energy at
+ * which the two dispersive bands of the 3x3 Bloch block (Eq. (4)) touch,
+ * -t (exact; the Dirac filling rho = 2/3 of Sec. IV). */
+double kdqmc_dirac_mu(int L, double t);
+
+/* Builds the Bloch tables (Eq. (4): H(k) per momentum; exp(-+dtau H(k)) and
+ * exp(-dtau (H(k) - mu)) with the 1/L^2 of the FFT pair folded in), carves
+ * the caller's workspace and binds the HIP stream (NULL = default stream).
+ * The workspace must stay allocated until kdqmc_destroy.  No fields are set:
+ * call kdqmc_set_fields (or kdqmc_set_G) next. */
+int kdqmc_init_lattice(kdqmc_ctx** out, const kdqmc_params* p, void* workspace_dev,
+                       size_t workspace_bytes, void* hip_stream);
+
+/* Copies the Ising fields s_dev[L_tau][N] (int8, each +1 or -1), builds the
+ * left stabilization stack from the top slice down, computes G(0) in FP64
+ * from it, and sets the current slice to 0.  Invalid values -> KDQMC_EINVAL
+ * (checked on the device; the call synchronizes for that check). */
+int kdqmc_set_fields(kdqmc_ctx* c, const int8_t* s_dev);
+
+/* Copies the current fields to s_dev[L_tau][N] (a checkpoint). */
+int kdqmc_get_fields(kdqmc_ctx* c, int8_t* s_dev);
+
+/* Loads an externally computed G(l) (FP64, N x N row-major) and sets the
+ * current slice to l (0 <= l <= L_tau).  The stabilization stacks are not
+ * touched (they must come from kdqmc_set_fields for kdqmc_stabilize). */
+int kdqmc_set_G(kdqmc_ctx* c, const double* G_dev, int l);
+
+/* G(l) = B_l G(l-1) B_l^{-1} with unchanged fields: the column pass applies
+ * exp(V_l) then exp(-dtau K) to every column (batched 2D FFTs, 3x3 block
+ * multiply, inverse FFTs), the row pass applies exp(+dtau K) to every row
+ * (exp(dtau K) is symmetric).  Requires l == current slice + 1. */
+int kdqmc_wrap_slice(kdqmc_ctx* c, int l);
+
+/* One slice of the Monte Carlo sweep (requires l == current slice + 1):
+ * G~ = exp(V_l) G(l-1) exp(-V_l); sites i = 0..N-1 in order, in windows of
+ * `window` sites; a flip of s_{l,i} is accepted iff u_dev[i] < ratio
+ * (Metropolis) or, when forced_dev is not NULL, iff forced_dev[i] != 0;
+ * ratio = exp(2 alpha s) R^2, R = 1 + Delta (1 - G~_ii),
+ * Delta = exp(-2 alpha s) - 1, always in FP64.  Accepted rank-one updates
+ * are accumulated and added to G~ as rank-<=delay_k products; then
+ * G(l) = exp(-dtau K) G~ exp(dtau K).
+ * u_dev[N] (float64) is required unless forced_dev[N] (uint8) is given;
+ * accepted_dev[N] (uint8) and ratio_dev[N] (float64) are optional outputs. */
+int kdqmc_sweep_slice(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* forced_dev,
+                      uint8_t* accepted_dev, double* ratio_dev);
+
+/* Recomputes G(l) in FP64 for the current slice l (l must be a multiple of
+ * n_stab, l > 0) from the QR-stabilized stacks (UDT form, pre-pivoted
+ * Householder QR, Loh-Gubernatis scale separation), writes
+ * max |G_current - G_fresh| to wrap_err_dev[0] (float64, optional) and
+ * replaces G.  At l == L_tau it also rebuilds the left stack from the new
+ * fields and sets the current slice to 0 (G(0) = G(L_tau)). */
+int kdqmc_stabilize(kdqmc_ctx* c, double* wrap_err_dev);
+
+/* A full sweep: kdqmc_sweep_slice for l = 1..L_tau with the uniforms
+ * u_dev[L_tau][N] (float64) or forced_dev[L_tau][N], and kdqmc_stabilize
+ * after every n_stab slices.  Optional outputs accepted_dev[L_tau][N],
+ * ratio_dev[L_tau][N] and wrap_err_dev[L_tau / n_stab].  Requires the
+ * current slice to be 0. */
+int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev,
+                uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev);
+
+/* Copies G(current slice) to G_dev (FP64, N x N row-major, site order above). */
+int kdqmc_measure_G(kdqmc_ctx* c, double* G_dev);
+
+/* Current slice index (0..L_tau), or a negative error code. */
+int kdqmc_current_slice(const kdqmc_ctx* c);
+
+/* Blocks until all work enqueued by this context has finished. */
+int kdqmc_sync(kdqmc_ctx* c);
+
+/* Frees the host-side context (not the caller's workspace). */
+void kdqmc_destroy(kdqmc_ctx* c);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* kdqmc_last_error(void);
+
+/* ---- profiling: HIP events around every kernel launch of the context ---- */
+
+#define KDQMC_NPHASE 10
+/* Phases: 0 wrap_cols, 1 wrap_rows (the two FFT passes of the wrap),
+ * 2 decide, 3 extend, 4 prep (window decisions and delayed factors),
+ * 5 flush (rank-k MFMA update), 6 bmul (B-chain products of the stacks),
+ * 7 qr_panel, 8 gemm (stabilization linear algebra), 9 stabilize (whole
+ * kdqmc_stabilize calls, which contain phases 6-8). */
+
+/* on != 0 starts recording (clearing earlier records); 0 stops. */
+int kdqmc_profile_enable(kdqmc_ctx* c, int on);
+
+/* Synchronizes, then writes the summed milliseconds ms[KDQMC_NPHASE] and the
+ * launch counts launches[KDQMC_NPHASE] (host arrays) recorded since the last
+ * enable/read, and clears the records. */
+int kdqmc_profile_read(kdqmc_ctx* c, double* ms, int* launches);
+
+/* Name of a phase index ("" if out of range). */
+const char* kdqmc_phase_name(int phase);
+
+/* ---- kernel-level entry points (the building blocks, for tests/tuning) ---- */
+
+/* C(M x N) = alpha * op(A) op(B) + beta * C, FP64, row-major, on the
+ * context's stream; op(X) = X or X^T (trans_* != 0).  lda/ldb/ldc are row
+ * strides in elements.  FP64 MFMA kernel. */
+int kdqmc_gemm_f64(kdqmc_ctx* c, int trans_a, int trans_b, int M, int N, int K, double alpha,
+                   const double* A_dev, int lda, const double* B_dev, int ldb, double beta,
+                   double* C_dev, int ldc);
+
+/* Householder QR of the n x n row-major A_dev (FP64) in place: on return
+ * Q_dev holds Q (n x n), A_dev holds R in its upper triangle (zeros below).
+ * No pivoting.  A_dev and Q_dev are N x N buffers (row stride N, N the
+ * context's site count); the leading n x n block is factored (1 <= n <= N).
+ * Uses the context's linear-algebra scratch. */
+int kdqmc_qr_f64(kdqmc_ctx* c, int n, double* A_dev, double* Q_dev);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDQMC_H */

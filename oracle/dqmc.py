@@ -234,12 +234,14 @@ def update_slice(gt: np.ndarray, s: np.ndarray, alpha: float, u=None, forced=Non
 
 
 def sweep(model: Model, fields: np.ndarray, g0: np.ndarray, uniforms=None, forced=None,
-          k: int = 1, n_stab: int = 10, record: bool = True):
+          k: int = 1, n_stab: int = 10, record: bool = True, l_stop=None):
     """One upward pass l = 1..L_tau over the slices.
 
     Per slice: G~ = exp(V_l) G exp(-V_l); sequential updates (delay k);
     G = exp(-dtau K) G~ exp(dtau K); every n_stab slices G is replaced by the
     QR-stabilized G(l) and max|G - G_fresh| is logged as the wrap error.
+
+    ``l_stop`` ends the pass after that slice (a partial sweep).
 
     Returns a dict with the final fields, G after every slice (``G_slices``,
     index l-1, taken after the stabilization of that slice when there is one),
@@ -253,7 +255,7 @@ def sweep(model: Model, fields: np.ndarray, g0: np.ndarray, uniforms=None, force
     wrap_err = {}
     g_slices, g_pre = [], {}
     g = g0.copy()
-    for l in range(1, L_tau + 1):
+    for l in range(1, (L_tau if l_stop is None else l_stop) + 1):
         s = fields[l - 1]
         ev = np.exp(model.alpha * s.astype(float))
         gt = ev[:, None] * g / ev[None, :]

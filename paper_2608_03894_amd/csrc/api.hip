@@ -1,0 +1,453 @@
+// C ABI of the library: parameter checks, workspace carving, slice order,
+// and the composition of the kernels into the calls declared in kdqmc.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace kdqmc {
+
+namespace {
+thread_local std::string g_last_error;
+
+struct Derived {
+  int N = 0, Ltau = 0, nc = 0, w = 0, nw = 0, F = 0, kmax = 0, P = 0, P64 = 0;
+  bool fp64 = true;
+};
+
+int auto_tile(int L, size_t elem, int requested) {
+  if (requested > 0) return requested;
+  const int N = 3 * L * L;
+  int P = 1;
+  for (int q = 1; q <= 8; ++q) {
+    if (2 * (size_t)N * q * elem <= 64 * 1024 && 3 * L * q <= 512) P = q;
+  }
+  return P;
+}
+
+int derive(const kdqmc_params* p, Derived* d) {
+  if (!p) return set_error(KDQMC_EINVAL, "params is NULL");
+  if (!lattice_supported(p->L))
+    return set_error(KDQMC_EUNSUPPORTED, "L must be one of 3, 6, 9, 12, 15, 18, 24");
+  if (!(std::isfinite(p->t) && std::isfinite(p->U) && std::isfinite(p->mu)))
+    return set_error(KDQMC_EINVAL, "t, U, mu must be finite");
+  if (p->U > 0.0)
+    return set_error(KDQMC_EUNSUPPORTED, "only the attractive (U <= 0) charge-channel decoupling is built");
+  if (!(p->dtau > 0.0) || !(p->beta > 0.0)) return set_error(KDQMC_EINVAL, "beta and dtau must be > 0");
+  const double lt = p->beta / p->dtau;
+  const int Ltau = (int)std::lround(lt);
+  if (Ltau < 1 || std::fabs(Ltau - lt) > 1e-9 * lt)
+    return set_error(KDQMC_EINVAL, "beta must be an integer multiple of dtau");
+  if (p->n_stab < 1 || Ltau % p->n_stab != 0)
+    return set_error(KDQMC_EINVAL, "n_stab must divide L_tau");
+  if (Ltau / p->n_stab > 1024) return set_error(KDQMC_EINVAL, "too many stabilization checkpoints");
+  if (p->n_stab > 1024) return set_error(KDQMC_EINVAL, "n_stab above 1024");
+  if (p->delay_k < 1 || p->delay_k > 512) return set_error(KDQMC_EINVAL, "delay_k must be in 1..512");
+  if (p->prec != KDQMC_FP64 && p->prec != KDQMC_MIXED_F16 && p->prec != KDQMC_MIXED_BF16)
+    return set_error(KDQMC_EINVAL, "unknown precision");
+  int w = p->window > 0 ? p->window : std::min(p->delay_k, 64);
+  if (w > 64) return set_error(KDQMC_EINVAL, "window above 64");
+  if (w > p->delay_k) return set_error(KDQMC_EINVAL, "window larger than delay_k");
+  d->N = 3 * p->L * p->L;
+  d->Ltau = Ltau;
+  d->nc = Ltau / p->n_stab;
+  d->w = std::min(w, d->N);
+  d->nw = (d->N + d->w - 1) / d->w;
+  d->F = std::max(1, p->delay_k / d->w);
+  d->kmax = d->F * d->w;
+  d->fp64 = (p->prec == KDQMC_FP64);
+  const size_t es = d->fp64 ? 8 : 4;
+  d->P = auto_tile(p->L, es, p->fft_tile);
+  d->P64 = d->fp64 ? d->P : auto_tile(p->L, 8, 0);
+  if (2 * (size_t)d->N * d->P * es > 160 * 1024 || 3 * p->L * d->P > 512)
+    return set_error(KDQMC_EINVAL, "fft_tile exceeds LDS or thread limits");
+  return KDQMC_OK;
+}
+
+// Carves the workspace; with c == nullptr only measures.  Returns bytes.
+size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) & ~size_t(255);
+    char* ptr = base ? base + off : nullptr;
+    off += bytes;
+    return ptr;
+  };
+  const size_t N = d.N, nn = N * N, L2 = (size_t)p->L * p->L;
+  const size_t es = d.fp64 ? 8 : 4;
+  const size_t nb = 16;
+  char* G = take(nn * es);
+  char* G64 = take(nn * 8);
+  char* fields = take((size_t)d.Ltau * N);
+  char* ev = take(N * 8);
+  char* evinv = take(N * 8);
+  char* tab_m = take(L2 * 18 * es);
+  char* tab_p = take(L2 * 18 * es);
+  char* tab_mu64 = take(L2 * 18 * 8);
+  char* Up = take((size_t)d.kmax * N * es);
+  char* Wp = take((size_t)d.kmax * N * es);
+  char* win_a = take((size_t)d.nw * 4);
+  char* win_p = take((size_t)d.nw * d.w * 4);
+  char* Zg = take((size_t)d.w * d.w * 8);
+  char* Zpg = take((size_t)d.w * d.w * 8);
+  char* Gs = take((size_t)d.w * d.w * 8);
+  char* flag = take(64);
+  char* err = take(1024 * 8);
+  char* RU = take((d.nc + 1) * nn * 8);
+  char* RT = take((d.nc + 1) * nn * 8);
+  char* RD = take((d.nc + 1) * N * 8);
+  char* LU = take((d.nc + 1) * nn * 8);
+  char* LT = take((d.nc + 1) * nn * 8);
+  char* LD = take((d.nc + 1) * N * 8);
+  char* S[8];
+  for (int i = 0; i < 8; ++i) S[i] = take(nn * 8);
+  char* Vq = take(nn * 8);
+  char* Tq = take((N / nb + 2) * nb * nb * 8);
+  char* Wq = take(2 * nb * N * 8);
+  char* tau = take(N * 8);
+  char* nrm = take(2 * N * 8);
+  char* perm = take(N * 4);
+  if (c) {
+    c->G = G;
+    c->G64 = (double*)G64;
+    c->fields = (int8_t*)fields;
+    c->ev = (double*)ev;
+    c->evinv = (double*)evinv;
+    c->tab_m = tab_m;
+    c->tab_p = tab_p;
+    c->tab_mu64 = (double*)tab_mu64;
+    c->Upend = Up;
+    c->Wpend = Wp;
+    c->win_a = (int*)win_a;
+    c->win_p = (int*)win_p;
+    c->Xw = (double*)Zg;
+    c->Yw = (double*)Zpg;
+    c->Gs = (double*)Gs;
+    c->flag = (int*)flag;
+    c->err = (double*)err;
+    c->RU = (double*)RU; c->RT = (double*)RT; c->RD = (double*)RD;
+    c->LU = (double*)LU; c->LT = (double*)LT; c->LD = (double*)LD;
+    for (int i = 0; i < 8; ++i) c->S[i] = (double*)S[i];
+    c->Vq = (double*)Vq;
+    c->Tq = (double*)Tq;
+    c->Wq = (double*)Wq;
+    c->tau = (double*)tau;
+    c->nrm = (double*)nrm;
+    c->perm = (int*)perm;
+  }
+  return ((off + 255) & ~size_t(255)) + 256;  // slack for base alignment
+}
+
+__global__ void k_check_fields(const int8_t* __restrict__ s, size_t n, int* __restrict__ bad) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && s[i] != 1 && s[i] != -1) atomicOr(bad, 1);
+}
+
+__global__ void k_zero_int(int* __restrict__ x, int n) {
+  const int i = threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+
+int check_ctx(const kdqmc_ctx* c) {
+  if (!c) return set_error(KDQMC_EINVAL, "context is NULL");
+  return KDQMC_OK;
+}
+
+}  // namespace
+
+int prof_mark(kdqmc_ctx* c) {
+  if (!c->prof_on) return -1;
+  if (c->prof_next == (int)c->prof_events.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    c->prof_events.push_back(e);
+  }
+  const int i = c->prof_next++;
+  if (hipEventRecord(c->prof_events[i], c->stream) != hipSuccess) return -1;
+  return i;
+}
+
+void prof_pair(kdqmc_ctx* c, int phase, int e0, int e1) {
+  if (!c->prof_on || e0 < 0 || e1 < 0) return;
+  c->prof_triples.push_back(phase);
+  c->prof_triples.push_back(e0);
+  c->prof_triples.push_back(e1);
+}
+
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+void clear_error() { g_last_error.clear(); }
+
+}  // namespace kdqmc
+
+using namespace kdqmc;
+
+extern "C" {
+
+size_t kdqmc_workspace_bytes(const kdqmc_params* p) {
+  Derived d;
+  if (derive(p, &d) != KDQMC_OK) return 0;
+  return carve(p, d, nullptr, nullptr);
+}
+
+double kdqmc_dirac_mu(int L, double t) { return kdqmc::dirac_mu(L, t); }
+
+int kdqmc_init_lattice(kdqmc_ctx** out, const kdqmc_params* p, void* workspace_dev,
+                       size_t workspace_bytes, void* hip_stream) {
+  if (!out) return set_error(KDQMC_EINVAL, "out is NULL");
+  *out = nullptr;
+  Derived d;
+  KDQMC_TRY(derive(p, &d));
+  if (!workspace_dev) return set_error(KDQMC_EINVAL, "workspace is NULL");
+  const size_t need = carve(p, d, nullptr, nullptr);
+  if (workspace_bytes < need)
+    return set_error(KDQMC_ENOSPACE, "workspace smaller than kdqmc_workspace_bytes()");
+  kdqmc_ctx* c = new kdqmc_ctx();
+  c->p = *p;
+  c->N = d.N;
+  c->L = p->L;
+  c->Ltau = d.Ltau;
+  c->nc = d.nc;
+  c->w = d.w;
+  c->nw = d.nw;
+  c->F = d.F;
+  c->kmax = d.kmax;
+  c->P = d.P;
+  c->P64 = d.P64;
+  c->nb = 16;
+  c->fp64 = d.fp64;
+  c->alpha = std::acosh(std::exp(p->dtau * std::fabs(p->U) / 2.0));
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  char* base = static_cast<char*>(workspace_dev);
+  base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(base) + 255) & ~uintptr_t(255));
+  carve(p, d, c, base);
+  // Bloch tables: exp(-dtau H(k)) and exp(+dtau H(k)) for the wrap (mu cancels),
+  // exp(-dtau (H(k) - mu)) for the B-chains; 1/L^2 folded in.
+  const size_t L2 = (size_t)p->L * p->L;
+  std::vector<double> tm(L2 * 18), tp(L2 * 18), tmu(L2 * 18);
+  bloch_table(p->L, p->t, -p->dtau, 0.0, tm.data());
+  bloch_table(p->L, p->t, +p->dtau, 0.0, tp.data());
+  bloch_table(p->L, p->t, -p->dtau, p->mu, tmu.data());
+  int rc = KDQMC_OK;
+  auto upload = [&](void* dst, const std::vector<double>& src, bool as_float) -> int {
+    if (as_float) {
+      std::vector<float> f(src.begin(), src.end());
+      KDQMC_HIP(hipMemcpyAsync(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice, c->stream));
+      KDQMC_HIP(hipStreamSynchronize(c->stream));
+    } else {
+      KDQMC_HIP(hipMemcpyAsync(dst, src.data(), src.size() * 8, hipMemcpyHostToDevice, c->stream));
+      KDQMC_HIP(hipStreamSynchronize(c->stream));
+    }
+    return KDQMC_OK;
+  };
+  if ((rc = upload(c->tab_m, tm, !c->fp64)) != KDQMC_OK ||
+      (rc = upload(c->tab_p, tp, !c->fp64)) != KDQMC_OK ||
+      (rc = upload(c->tab_mu64, tmu, false)) != KDQMC_OK) {
+    delete c;
+    return rc;
+  }
+  c->l_cur = -1;
+  c->stacks_valid = false;
+  *out = c;
+  clear_error();
+  return KDQMC_OK;
+}
+
+int kdqmc_set_fields(kdqmc_ctx* c, const int8_t* s_dev) {
+  KDQMC_TRY(check_ctx(c));
+  if (!s_dev) return set_error(KDQMC_EINVAL, "fields pointer is NULL");
+  const size_t n = (size_t)c->Ltau * c->N;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, c->stream, c->flag, 16);
+  hipLaunchKernelGGL(k_check_fields, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, s_dev, n, c->flag);
+  int bad = 0;
+  KDQMC_HIP(hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  KDQMC_HIP(hipStreamSynchronize(c->stream));
+  if (bad) return set_error(KDQMC_EINVAL, "fields must be +1 or -1");
+  KDQMC_HIP(hipMemcpyAsync(c->fields, s_dev, n, hipMemcpyDeviceToDevice, c->stream));
+  KDQMC_TRY(stab_build_left(c));
+  KDQMC_TRY(stab_identity(c, false, 0));
+  KDQMC_TRY(stab_green(c, 0, c->G64));
+  KDQMC_TRY(copy_64_to_G(c, c->G64));
+  c->l_cur = 0;
+  c->stacks_valid = true;
+  return KDQMC_OK;
+}
+
+int kdqmc_get_fields(kdqmc_ctx* c, int8_t* s_dev) {
+  KDQMC_TRY(check_ctx(c));
+  if (!s_dev) return set_error(KDQMC_EINVAL, "fields pointer is NULL");
+  KDQMC_HIP(hipMemcpyAsync(s_dev, c->fields, (size_t)c->Ltau * c->N, hipMemcpyDeviceToDevice, c->stream));
+  return KDQMC_OK;
+}
+
+int kdqmc_set_G(kdqmc_ctx* c, const double* G_dev, int l) {
+  KDQMC_TRY(check_ctx(c));
+  if (!G_dev) return set_error(KDQMC_EINVAL, "G pointer is NULL");
+  if (l < 0 || l > c->Ltau) return set_error(KDQMC_EINVAL, "slice index out of range");
+  KDQMC_TRY(copy_64_to_G(c, G_dev));
+  c->l_cur = l;
+  return KDQMC_OK;
+}
+
+static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev);
+
+static int wrap_pass(kdqmc_ctx* c) {
+  if (c->fp64) {
+    KDQMC_TRY(launch_kinetic_f64(c, (double*)c->G, c->N, true, (const double*)c->tab_m, c->ev, c->evinv, nullptr));
+    KDQMC_TRY(launch_kinetic_f64(c, (double*)c->G, c->N, false, (const double*)c->tab_p, nullptr, nullptr, nullptr));
+  } else {
+    KDQMC_TRY(launch_kinetic_f32(c, (float*)c->G, c->N, true, (const float*)c->tab_m, c->ev, c->evinv, nullptr));
+    KDQMC_TRY(launch_kinetic_f32(c, (float*)c->G, c->N, false, (const float*)c->tab_p, nullptr, nullptr, nullptr));
+  }
+  return KDQMC_OK;
+}
+
+int kdqmc_wrap_slice(kdqmc_ctx* c, int l) {
+  KDQMC_TRY(check_ctx(c));
+  if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded (set_fields or set_G first)");
+  if (l != c->l_cur + 1 || l > c->Ltau) return set_error(KDQMC_ESTATE, "wrap_slice needs l == current slice + 1");
+  KDQMC_TRY(launch_frame_scale(c, l));
+  KDQMC_TRY(wrap_pass(c));
+  c->l_cur = l;
+  return KDQMC_OK;
+}
+
+int kdqmc_sweep_slice(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* forced_dev,
+                      uint8_t* accepted_dev, double* ratio_dev) {
+  KDQMC_TRY(check_ctx(c));
+  if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded (set_fields or set_G first)");
+  if (l != c->l_cur + 1 || l > c->Ltau) return set_error(KDQMC_ESTATE, "sweep_slice needs l == current slice + 1");
+  if (!u_dev && !forced_dev) return set_error(KDQMC_EINVAL, "need uniforms or forced decisions");
+  KDQMC_TRY(launch_frame_scale(c, l));
+  KDQMC_TRY(run_slice_updates(c, l, u_dev, forced_dev, accepted_dev, ratio_dev));
+  KDQMC_TRY(wrap_pass(c));
+  c->l_cur = l;
+  return KDQMC_OK;
+}
+
+int kdqmc_stabilize(kdqmc_ctx* c, double* wrap_err_dev) {
+  KDQMC_TRY(check_ctx(c));
+  const int e0 = prof_mark(c);
+  const int rc = stabilize_impl(c, wrap_err_dev);
+  prof_pair(c, PH_STABILIZE, e0, prof_mark(c));
+  return rc;
+}
+
+static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev) {
+  if (!c->stacks_valid) return set_error(KDQMC_ESTATE, "stacks not built (call set_fields)");
+  const int l = c->l_cur;
+  if (l <= 0 || l % c->p.n_stab != 0) return set_error(KDQMC_ESTATE, "stabilize needs the current slice to be a positive multiple of n_stab");
+  const int j = l / c->p.n_stab;
+  KDQMC_TRY(stab_right_step(c, j));
+  KDQMC_TRY(stab_green(c, j, c->G64));
+  if (wrap_err_dev) KDQMC_TRY(max_abs_diff(c, c->G64, c->N, wrap_err_dev));
+  KDQMC_TRY(copy_64_to_G(c, c->G64));
+  if (j == c->nc) {
+    KDQMC_TRY(stab_build_left(c));
+    c->l_cur = 0;
+  }
+  return KDQMC_OK;
+}
+
+int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, uint8_t* accepted_dev,
+                double* ratio_dev, double* wrap_err_dev) {
+  KDQMC_TRY(check_ctx(c));
+  if (c->l_cur != 0) return set_error(KDQMC_ESTATE, "sweep needs the current slice to be 0");
+  if (!c->stacks_valid) return set_error(KDQMC_ESTATE, "stacks not built (call set_fields)");
+  const size_t N = c->N;
+  for (int l = 1; l <= c->Ltau; ++l) {
+    const size_t o = (size_t)(l - 1) * N;
+    KDQMC_TRY(kdqmc_sweep_slice(c, l, u_dev ? u_dev + o : nullptr, forced_dev ? forced_dev + o : nullptr,
+                                accepted_dev ? accepted_dev + o : nullptr, ratio_dev ? ratio_dev + o : nullptr));
+    if (l % c->p.n_stab == 0)
+      KDQMC_TRY(kdqmc_stabilize(c, wrap_err_dev ? wrap_err_dev + (l / c->p.n_stab - 1) : nullptr));
+  }
+  return KDQMC_OK;
+}
+
+int kdqmc_measure_G(kdqmc_ctx* c, double* G_dev) {
+  KDQMC_TRY(check_ctx(c));
+  if (!G_dev) return set_error(KDQMC_EINVAL, "G pointer is NULL");
+  if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded");
+  return copy_G_to64(c, G_dev);
+}
+
+int kdqmc_current_slice(const kdqmc_ctx* c) {
+  if (!c) return set_error(KDQMC_EINVAL, "context is NULL");
+  return c->l_cur;
+}
+
+int kdqmc_sync(kdqmc_ctx* c) {
+  KDQMC_TRY(check_ctx(c));
+  KDQMC_HIP(hipStreamSynchronize(c->stream));
+  return KDQMC_OK;
+}
+
+void kdqmc_destroy(kdqmc_ctx* c) {
+  if (!c) return;
+  for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int kdqmc_profile_enable(kdqmc_ctx* c, int on) {
+  KDQMC_TRY(check_ctx(c));
+  c->prof_on = (on != 0);
+  c->prof_next = 0;
+  c->prof_triples.clear();
+  return KDQMC_OK;
+}
+
+int kdqmc_profile_read(kdqmc_ctx* c, double* ms, int* launches) {
+  KDQMC_TRY(check_ctx(c));
+  if (!ms || !launches) return set_error(KDQMC_EINVAL, "NULL output");
+  for (int i = 0; i < KDQMC_NPHASE; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  KDQMC_HIP(hipStreamSynchronize(c->stream));
+  for (size_t q = 0; q + 2 < c->prof_triples.size(); q += 3) {
+    float t = 0.0f;
+    KDQMC_HIP(hipEventElapsedTime(&t, c->prof_events[c->prof_triples[q + 1]],
+                                  c->prof_events[c->prof_triples[q + 2]]));
+    ms[c->prof_triples[q]] += t;
+    launches[c->prof_triples[q]] += 1;
+  }
+  c->prof_next = 0;
+  c->prof_triples.clear();
+  return KDQMC_OK;
+}
+
+const char* kdqmc_phase_name(int phase) {
+  static const char* names[KDQMC_NPHASE] = {"wrap_cols", "wrap_rows", "decide", "extend", "prep",
+                                            "flush", "bmul", "qr_panel", "gemm", "stabilize"};
+  return (phase >= 0 && phase < KDQMC_NPHASE) ? names[phase] : "";
+}
+
+const char* kdqmc_last_error(void) { return g_last_error.c_str(); }
+
+int kdqmc_gemm_f64(kdqmc_ctx* c, int trans_a, int trans_b, int M, int N, int K, double alpha,
+                   const double* A_dev, int lda, const double* B_dev, int ldb, double beta,
+                   double* C_dev, int ldc) {
+  KDQMC_TRY(check_ctx(c));
+  if (!A_dev || !B_dev || !C_dev) return set_error(KDQMC_EINVAL, "NULL matrix");
+  if (M < 0 || N < 0 || K < 0) return set_error(KDQMC_EINVAL, "negative size");
+  const int acols = trans_a ? M : K, bcols = trans_b ? K : N;
+  if (lda < std::max(1, acols) || ldb < std::max(1, bcols) || ldc < std::max(1, N))
+    return set_error(KDQMC_EINVAL, "leading dimension too small");
+  return gemm_f64(c, trans_a != 0, trans_b != 0, M, N, K, alpha, A_dev, lda, B_dev, ldb, beta, C_dev, ldc);
+}
+
+int kdqmc_qr_f64(kdqmc_ctx* c, int n, double* A_dev, double* Q_dev) {
+  KDQMC_TRY(check_ctx(c));
+  if (!A_dev || !Q_dev) return set_error(KDQMC_EINVAL, "NULL matrix");
+  if (n < 1 || n > c->N) return set_error(KDQMC_EINVAL, "QR order must be in 1..N");
+  // the routine works with row stride N; callers pass N x N buffers
+  return qr_f64(c, n, A_dev, Q_dev);
+}
+
+}  // extern "C"

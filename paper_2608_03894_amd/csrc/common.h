@@ -1,0 +1,217 @@
+// Shared declarations of the kdqmc HIP library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/kdqmc.h"
+
+namespace kdqmc {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+int set_error(int code, const std::string& msg);
+void clear_error();
+
+#define KDQMC_HIP(call)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return ::kdqmc::set_error(KDQMC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define KDQMC_TRY(call)        \
+  do {                         \
+    int r_ = (call);           \
+    if (r_ != KDQMC_OK) return r_; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Compile-time trigonometry for FFT twiddles: cos/sin(2 pi e / n) by exact
+// quadrant reduction of the rational angle and a Taylor series on
+// |phi| <= pi/4 (error below 1 ulp of double after rounding).
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+constexpr double taylor_sin(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int k = 1; k < 16; ++k) {
+    term *= -x2 / double((2 * k) * (2 * k + 1));
+    sum += term;
+  }
+  return sum;
+}
+
+constexpr double taylor_cos(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int k = 1; k < 16; ++k) {
+    term *= -x2 / double((2 * k - 1) * (2 * k));
+    sum += term;
+  }
+  return sum;
+}
+
+// returns {cos, sin} of 2 pi e / n as a pair via two functions
+constexpr long mod_pos(long a, long n) { return ((a % n) + n) % n; }
+
+constexpr double cos2pi(long e, long n) {
+  const long ee = mod_pos(e, n);
+  const long q = (4 * ee + n / 2) / n;  // nearest quarter turn
+  const long r = 4 * ee - q * n;        // |r| <= n/2
+  const double phi = (kPi / 2) * double(r) / double(n);
+  const double c = taylor_cos(phi), s = taylor_sin(phi);
+  switch (q & 3) {
+    case 0: return c;
+    case 1: return -s;
+    case 2: return -c;
+    default: return s;
+  }
+}
+
+constexpr double sin2pi(long e, long n) {
+  const long ee = mod_pos(e, n);
+  const long q = (4 * ee + n / 2) / n;
+  const long r = 4 * ee - q * n;
+  const double phi = (kPi / 2) * double(r) / double(n);
+  const double c = taylor_cos(phi), s = taylor_sin(phi);
+  switch (q & 3) {
+    case 0: return s;
+    case 1: return c;
+    case 2: return -s;
+    default: return -c;
+  }
+}
+
+template <int N>
+struct TwiddleTable {
+  double c[N];
+  double s[N];
+  constexpr TwiddleTable() : c(), s() {
+    for (int e = 0; e < N; ++e) {
+      c[e] = cos2pi(e, N);
+      s[e] = sin2pi(e, N);
+    }
+  }
+};
+
+template <int N>
+inline constexpr TwiddleTable<N> kTw{};
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+struct Layout;  // workspace carving, see api.hip
+
+}  // namespace kdqmc
+
+namespace kdqmc {
+// Phases timed by the optional HIP-event profiler (kdqmc_profile_*).
+enum Phase {
+  PH_WRAP_COLS = 0, PH_WRAP_ROWS, PH_DECIDE, PH_EXTEND, PH_PREP, PH_FLUSH, PH_BMUL, PH_QR_PANEL,
+  PH_GEMM, PH_STABILIZE, PH_COUNT
+};
+}  // namespace kdqmc
+
+struct kdqmc_ctx {
+  kdqmc_params p;
+  // profiler: event pool and recorded (phase, begin, end) triples
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_events;
+  int prof_next = 0;
+  std::vector<int> prof_triples;
+  int N = 0, L = 0, Ltau = 0, nc = 0;     // sites, cells/side, slices, stack checkpoints
+  int w = 0, nw = 0, F = 0;               // window size, windows per slice, windows per flush
+  int P = 0;                              // complex vectors per wrap workgroup (storage type)
+  int P64 = 0;                            // same for the FP64 stack products
+  int kmax = 0;                           // columns of the pending factors (F * w)
+  int nb = 32;                            // QR panel width
+  double alpha = 0.0;
+  hipStream_t stream = nullptr;
+  int l_cur = -1;
+  bool stacks_valid = false;
+  bool fp64 = true;
+
+  // device buffers (carved from the caller's workspace)
+  void* G = nullptr;           // N*N, double (FP64) or float (mixed)
+  double* G64 = nullptr;       // N*N FP64: fresh G from stabilization / measure staging
+  int8_t* fields = nullptr;    // Ltau*N
+  double* ev = nullptr;        // N: exp(alpha s) frame scale of the current slice
+  double* evinv = nullptr;     // N: exp(-alpha s)
+  void* tab_m = nullptr;       // L*L*9 complex (T): exp(-dtau H(k)) / L^2
+  void* tab_p = nullptr;       // L*L*9 complex (T): exp(+dtau H(k)) / L^2
+  double* tab_mu64 = nullptr;  // L*L*9 complex FP64: exp(-dtau (H(k) - mu)) / L^2
+  double* tab_mu64t = nullptr; // unused placeholder for symmetry
+  double* tab_m64 = nullptr;   // FP64 copies (wrap tables) for FP64 helpers
+  double* tab_p64 = nullptr;
+  void* Upend = nullptr;       // kmax*N (T), store frame, column j contiguous over rows
+  void* Wpend = nullptr;       // kmax*N (T)
+  int* win_a = nullptr;        // nw: accepted count per window
+  int* win_p = nullptr;        // nw*w: window-local positions of the accepts
+  double* win_c = nullptr;     // nw*w: Delta/R of the accepts
+  double* Xw = nullptr;        // w*w: -Gs[p_n][q] at the time of accept n
+  double* Yw = nullptr;        // w*w: -c_n Gs[q][p_n] at the time of accept n
+  double* Gs = nullptr;        // w*w: G~cur[S,S] of the next window
+  int* flag = nullptr;         // small device status words
+  double* err = nullptr;       // reduction scratch
+  // stabilization stacks: entry j holds the UDT form of the chain up to checkpoint j
+  double* RU = nullptr; double* RT = nullptr; double* RD = nullptr;
+  double* LU = nullptr; double* LT = nullptr; double* LD = nullptr;
+  // linear-algebra scratch (N*N each unless noted)
+  double* S[8] = {nullptr};
+  double* Vq = nullptr;        // N*N explicit Householder vectors
+  double* Tq = nullptr;        // (N/nb+1)*nb*nb block-reflector factors
+  double* Wq = nullptr;        // nb*N
+  double* tau = nullptr;       // N
+  double* nrm = nullptr;       // N
+  int* perm = nullptr;         // N
+};
+
+namespace kdqmc {
+
+// ---------------------------------------------------------------------------
+// Host helpers implemented in lattice.hip
+// ---------------------------------------------------------------------------
+bool lattice_supported(int L);
+// Fills tab[L*L*9] complex (interleaved re, im) with exp(scale * (H(k) - shift)) / L^2.
+void bloch_table(int L, double t, double scale, double shift, double* tab);
+double dirac_mu(int L, double t);
+
+// ---------------------------------------------------------------------------
+// Launchers (all enqueue on c->stream)
+// ---------------------------------------------------------------------------
+// Vector-batched kinetic operator: for every column (cols=true) or row of the
+// N x N matrix A (row stride lda): x <- post_e .* Op( pre_e .* x .* pre_v[v] ),
+// with Op the table operator.  Pointers pre_e/pre_v/post_e may be null.
+int launch_kinetic_f64(kdqmc_ctx* c, double* A, int lda, bool cols, const double* tab,
+                       const double* pre_e, const double* pre_v, const double* post_e);
+int launch_kinetic_f32(kdqmc_ctx* c, float* A, int lda, bool cols, const float* tab,
+                       const double* pre_e, const double* pre_v, const double* post_e);
+
+int launch_frame_scale(kdqmc_ctx* c, int l);
+int run_slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, uint8_t* acc,
+                      double* ratio);
+
+int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
+             int lda, const double* B, int ldb, double beta, double* C, int ldc);
+int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q);
+int trsm_upper_f64(kdqmc_ctx* c, int n, const double* R, double* X);
+
+int stab_identity(kdqmc_ctx* c, bool left, int j);
+int stab_build_left(kdqmc_ctx* c);
+int stab_green(kdqmc_ctx* c, int j, double* out);   // G at checkpoint j into out (FP64)
+int stab_right_step(kdqmc_ctx* c, int j);           // right stack entry j from j-1
+int copy_G_to64(kdqmc_ctx* c, double* out);
+int copy_64_to_G(kdqmc_ctx* c, const double* in);
+int max_abs_diff(kdqmc_ctx* c, const double* a, int n, double* out);  // max |G - a|
+
+// Profiler: prof_mark records an event on the stream (returns its index, or
+// -1 when profiling is off); prof_pair attributes the interval to a phase.
+int prof_mark(kdqmc_ctx* c);
+void prof_pair(kdqmc_ctx* c, int phase, int e0, int e1);
+
+}  // namespace kdqmc

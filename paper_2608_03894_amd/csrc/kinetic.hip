@@ -1,0 +1,333 @@
+// Kinetic propagator applied to every column (or row) of a dense N x N
+// matrix through the momentum-space block form (Eq. (6)): per vector, a 2D
+// L x L FFT of each sublattice component, a 3x3 complex block multiply per
+// momentum, and the inverse 2D FFT.  Two real vectors travel as one complex
+// vector (the operator is real, so the real and imaginary parts do not mix).
+//
+// One workgroup owns P complex vectors (2P real columns or rows), staged in
+// LDS as separate real/imaginary planes [element][vector]; the FFT lines are
+// processed in registers, one line per thread.
+#include "common.h"
+
+namespace kdqmc {
+
+// ---------------------------------------------------------------------------
+// In-register mixed-radix FFT (decimation in time), twiddles from the
+// compile-time table kTw<N>.  SIGN = -1: forward exp(-2 pi i nk/N); +1: inverse
+// (both unnormalized).
+// ---------------------------------------------------------------------------
+template <typename T, int R, int SIGN>
+struct SmallDFT;
+
+template <typename T, int SIGN>
+struct SmallDFT<T, 2, SIGN> {
+  __device__ __forceinline__ static void run(T* re, T* im) {
+    const T r0 = re[0] + re[1], i0 = im[0] + im[1];
+    re[1] = re[0] - re[1];
+    im[1] = im[0] - im[1];
+    re[0] = r0;
+    im[0] = i0;
+  }
+};
+
+template <typename T, int SIGN>
+struct SmallDFT<T, 3, SIGN> {
+  __device__ __forceinline__ static void run(T* re, T* im) {
+    const T h = T(SIGN * 0.86602540378443864676372317075293618);  // SIGN sin(2 pi/3)
+    const T tr = re[1] + re[2], ti = im[1] + im[2];
+    const T dr = re[1] - re[2], di = im[1] - im[2];
+    const T mr = re[0] - T(0.5) * tr, mi = im[0] - T(0.5) * ti;
+    re[0] += tr;
+    im[0] += ti;
+    re[1] = mr - h * di;
+    im[1] = mi + h * dr;
+    re[2] = mr + h * di;
+    im[2] = mi - h * dr;
+  }
+};
+
+template <typename T, int SIGN>
+struct SmallDFT<T, 4, SIGN> {
+  __device__ __forceinline__ static void run(T* re, T* im) {
+    const T t0r = re[0] + re[2], t0i = im[0] + im[2];
+    const T t1r = re[0] - re[2], t1i = im[0] - im[2];
+    const T t2r = re[1] + re[3], t2i = im[1] + im[3];
+    const T t3r = re[1] - re[3], t3i = im[1] - im[3];
+    re[0] = t0r + t2r;
+    im[0] = t0i + t2i;
+    re[2] = t0r - t2r;
+    im[2] = t0i - t2i;
+    // X1 = t1 + SIGN i t3, X3 = t1 - SIGN i t3
+    re[1] = t1r - T(SIGN) * t3i;
+    im[1] = t1i + T(SIGN) * t3r;
+    re[3] = t1r + T(SIGN) * t3i;
+    im[3] = t1i - T(SIGN) * t3r;
+  }
+};
+
+template <typename T, int SIGN>
+struct SmallDFT<T, 5, SIGN> {
+  __device__ __forceinline__ static void run(T* re, T* im) {
+    const T c1 = T(kTw<5>.c[1]), c2 = T(kTw<5>.c[2]);
+    const T s1 = T(SIGN * kTw<5>.s[1]), s2 = T(SIGN * kTw<5>.s[2]);
+    const T t1r = re[1] + re[4], t1i = im[1] + im[4];
+    const T t2r = re[2] + re[3], t2i = im[2] + im[3];
+    const T t3r = re[1] - re[4], t3i = im[1] - im[4];
+    const T t4r = re[2] - re[3], t4i = im[2] - im[3];
+    const T ar = re[0] + c1 * t1r + c2 * t2r, ai = im[0] + c1 * t1i + c2 * t2i;
+    const T br = re[0] + c2 * t1r + c1 * t2r, bi = im[0] + c2 * t1i + c1 * t2i;
+    // i * (s1 t3 + s2 t4) and i * (s2 t3 - s1 t4)
+    const T pr = s1 * t3r + s2 * t4r, pi = s1 * t3i + s2 * t4i;
+    const T qr = s2 * t3r - s1 * t4r, qi = s2 * t3i - s1 * t4i;
+    re[0] = re[0] + t1r + t2r;
+    im[0] = im[0] + t1i + t2i;
+    re[1] = ar - pi;
+    im[1] = ai + pr;
+    re[4] = ar + pi;
+    im[4] = ai - pr;
+    re[2] = br - qi;
+    im[2] = bi + qr;
+    re[3] = br + qi;
+    im[3] = bi - qr;
+  }
+};
+
+constexpr int pick_radix(int n) {
+  return (n % 4 == 0) ? 4 : (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : (n % 5 == 0) ? 5 : 0;
+}
+
+template <typename T, int N, int SIGN>
+struct FFT {
+  static constexpr int R = pick_radix(N);
+  static_assert(R != 0, "FFT length must factor into 2, 3 and 5");
+  static constexpr int M = N / R;
+  __device__ __forceinline__ static void run(T* re, T* im) {
+    if constexpr (M == 1) {
+      SmallDFT<T, R, SIGN>::run(re, im);
+    } else {
+      T yr[R][M], yi[R][M];
+#pragma unroll
+      for (int n1 = 0; n1 < R; ++n1)
+#pragma unroll
+        for (int n2 = 0; n2 < M; ++n2) {
+          yr[n1][n2] = re[R * n2 + n1];
+          yi[n1][n2] = im[R * n2 + n1];
+        }
+#pragma unroll
+      for (int n1 = 0; n1 < R; ++n1) FFT<T, M, SIGN>::run(yr[n1], yi[n1]);
+#pragma unroll
+      for (int k2 = 0; k2 < M; ++k2) {
+        T tr[R], ti[R];
+#pragma unroll
+        for (int n1 = 0; n1 < R; ++n1) {
+          const int e = (n1 * k2) % N;
+          if (e == 0) {
+            tr[n1] = yr[n1][k2];
+            ti[n1] = yi[n1][k2];
+          } else {
+            const T cw = T(kTw<N>.c[e]);
+            const T sw = T(SIGN * kTw<N>.s[e]);
+            tr[n1] = yr[n1][k2] * cw - yi[n1][k2] * sw;
+            ti[n1] = yr[n1][k2] * sw + yi[n1][k2] * cw;
+          }
+        }
+        SmallDFT<T, R, SIGN>::run(tr, ti);
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1) {
+          re[k2 + M * k1] = tr[k1];
+          im[k2 + M * k1] = ti[k1];
+        }
+      }
+    }
+  }
+};
+
+// One FFT stage over all lines of the tile: line (a, s, c) for a in [0, L),
+// s in [0, 3), c in [0, P): elements e = base(a, s) + m * stride, m in [0, L).
+// AXIS == 2: lines along x2 (a = x1, stride 3); AXIS == 1: along x1 (a = x2, stride 3L).
+template <typename T, int L, int AXIS, int SIGN>
+__device__ __forceinline__ void fft_stage(T* sre, T* sim, int P) {
+  const int nlines = 3 * L * P;
+  for (int idx = threadIdx.x; idx < nlines; idx += blockDim.x) {
+    const int c = idx % P;
+    const int q = idx / P;  // q = a*3 + s
+    const int s = q % 3;
+    const int a = q / 3;
+    const int base = (AXIS == 2) ? (a * L * 3 + s) : (a * 3 + s);
+    constexpr int stride = (AXIS == 2) ? 3 : 3 * L;
+    T re[L], im[L];
+#pragma unroll
+    for (int m = 0; m < L; ++m) {
+      re[m] = sre[(base + m * stride) * P + c];
+      im[m] = sim[(base + m * stride) * P + c];
+    }
+    FFT<T, L, SIGN>::run(re, im);
+#pragma unroll
+    for (int m = 0; m < L; ++m) {
+      sre[(base + m * stride) * P + c] = re[m];
+      sim[(base + m * stride) * P + c] = im[m];
+    }
+  }
+}
+
+// Per momentum k and vector c: (x_A, x_B, x_C) <- T(k) (x_A, x_B, x_C).
+template <typename T, int L>
+__device__ __forceinline__ void mix_stage(T* sre, T* sim, int P, const T* __restrict__ tab) {
+  const int nitems = L * L * P;
+  for (int idx = threadIdx.x; idx < nitems; idx += blockDim.x) {
+    const int c = idx % P;
+    const int k = idx / P;
+    const T* tk = tab + 18 * k;
+    T xr[3], xi[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      xr[s] = sre[(3 * k + s) * P + c];
+      xi[s] = sim[(3 * k + s) * P + c];
+    }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      T yr = T(0), yi = T(0);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const T ar = tk[2 * (3 * s + t)], ai = tk[2 * (3 * s + t) + 1];
+        yr += ar * xr[t] - ai * xi[t];
+        yi += ar * xi[t] + ai * xr[t];
+      }
+      sre[(3 * k + s) * P + c] = yr;
+      sim[(3 * k + s) * P + c] = yi;
+    }
+  }
+}
+
+template <typename T, int L, bool COLS>
+__global__ void __launch_bounds__(512)
+k_kinetic(T* __restrict__ A, int lda, int P, const T* __restrict__ tab,
+          const double* __restrict__ pre_e, const double* __restrict__ pre_v,
+          const double* __restrict__ post_e) {
+  constexpr int NS = 3 * L * L;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sre = reinterpret_cast<T*>(smem_raw);
+  T* sim = sre + NS * P;
+  const int vbase = 2 * blockIdx.x * P;      // first real vector of this workgroup
+  const int nreal = min(2 * P, NS - vbase);  // real vectors present (ragged tail)
+
+  // ---- load (with optional scaling) ----
+  if constexpr (COLS) {
+    for (int idx = threadIdx.x; idx < NS * P; idx += blockDim.x) {
+      const int c = idx % P, e = idx / P;
+      const int r0 = 2 * c, r1 = 2 * c + 1;
+      const double se = pre_e ? pre_e[e] : 1.0;
+      T x0 = T(0), x1 = T(0);
+      if (r0 < nreal) x0 = T(double(A[(size_t)e * lda + vbase + r0]) * se * (pre_v ? pre_v[vbase + r0] : 1.0));
+      if (r1 < nreal) x1 = T(double(A[(size_t)e * lda + vbase + r1]) * se * (pre_v ? pre_v[vbase + r1] : 1.0));
+      sre[e * P + c] = x0;
+      sim[e * P + c] = x1;
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < NS * 2 * P; idx += blockDim.x) {
+      const int e = idx % NS, r = idx / NS;
+      T x = T(0);
+      if (r < nreal) {
+        x = A[(size_t)(vbase + r) * lda + e];
+        if (pre_e || pre_v)
+          x = T(double(x) * (pre_e ? pre_e[e] : 1.0) * (pre_v ? pre_v[vbase + r] : 1.0));
+      }
+      if (r & 1)
+        sim[e * P + (r >> 1)] = x;
+      else
+        sre[e * P + (r >> 1)] = x;
+    }
+  }
+  __syncthreads();
+  fft_stage<T, L, 2, -1>(sre, sim, P);
+  __syncthreads();
+  fft_stage<T, L, 1, -1>(sre, sim, P);
+  __syncthreads();
+  mix_stage<T, L>(sre, sim, P, tab);
+  __syncthreads();
+  fft_stage<T, L, 1, +1>(sre, sim, P);
+  __syncthreads();
+  fft_stage<T, L, 2, +1>(sre, sim, P);
+  __syncthreads();
+  // ---- store ----
+  if constexpr (COLS) {
+    for (int idx = threadIdx.x; idx < NS * P; idx += blockDim.x) {
+      const int c = idx % P, e = idx / P;
+      const int r0 = 2 * c, r1 = 2 * c + 1;
+      const double se = post_e ? post_e[e] : 1.0;
+      if (r0 < nreal) A[(size_t)e * lda + vbase + r0] = T(double(sre[e * P + c]) * se);
+      if (r1 < nreal) A[(size_t)e * lda + vbase + r1] = T(double(sim[e * P + c]) * se);
+    }
+  } else {
+    for (int idx = threadIdx.x; idx < NS * 2 * P; idx += blockDim.x) {
+      const int e = idx % NS, r = idx / NS;
+      if (r < nreal) {
+        T x = (r & 1) ? sim[e * P + (r >> 1)] : sre[e * P + (r >> 1)];
+        if (post_e) x = T(double(x) * post_e[e]);
+        A[(size_t)(vbase + r) * lda + e] = x;
+      }
+    }
+  }
+}
+
+namespace {
+
+template <typename T, int L>
+int launch_L(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double* pre_e,
+             const double* pre_v, const double* post_e) {
+  constexpr int NS = 3 * L * L;
+  int P = (sizeof(T) == 8) ? c->P64 : c->P;
+  if (P <= 0) P = 1;
+  const size_t lds = size_t(2) * NS * P * sizeof(T);
+  if (lds > 160 * 1024)
+    return set_error(KDQMC_EINVAL, "fft_tile too large for LDS");
+  const int ncomplex = (NS + 1) / 2;
+  const int grid = (ncomplex + P - 1) / P;
+  int threads = 3 * L * P;
+  threads = ((threads + 63) / 64) * 64;
+  if (threads > 512) threads = 512;
+  if (threads < 64) threads = 64;
+  static bool attr_set[2] = {false, false};
+  if (!attr_set[cols]) {
+    KDQMC_HIP(hipFuncSetAttribute((const void*)k_kinetic<T, L, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    KDQMC_HIP(hipFuncSetAttribute((const void*)k_kinetic<T, L, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr_set[0] = attr_set[1] = true;
+  }
+  const int e0 = prof_mark(c);
+  if (cols)
+    hipLaunchKernelGGL((k_kinetic<T, L, true>), dim3(grid), dim3(threads), lds, c->stream, A, lda, P, tab, pre_e, pre_v, post_e);
+  else
+    hipLaunchKernelGGL((k_kinetic<T, L, false>), dim3(grid), dim3(threads), lds, c->stream, A, lda, P, tab, pre_e, pre_v, post_e);
+  prof_pair(c, (sizeof(T) == 8 && tab == (const T*)c->tab_mu64) ? PH_BMUL : (cols ? PH_WRAP_COLS : PH_WRAP_ROWS), e0, prof_mark(c));
+  KDQMC_HIP(hipGetLastError());
+  return KDQMC_OK;
+}
+
+template <typename T>
+int launch_any(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double* pre_e,
+               const double* pre_v, const double* post_e) {
+  switch (c->L) {
+    case 3: return launch_L<T, 3>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+    case 6: return launch_L<T, 6>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+    case 9: return launch_L<T, 9>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+    case 12: return launch_L<T, 12>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+    case 15: return launch_L<T, 15>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+    case 18: return launch_L<T, 18>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+    case 24: return launch_L<T, 24>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+    default: return set_error(KDQMC_EUNSUPPORTED, "lattice size not compiled in");
+  }
+}
+
+}  // namespace
+
+int launch_kinetic_f64(kdqmc_ctx* c, double* A, int lda, bool cols, const double* tab,
+                       const double* pre_e, const double* pre_v, const double* post_e) {
+  return launch_any<double>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+}
+
+int launch_kinetic_f32(kdqmc_ctx* c, float* A, int lda, bool cols, const float* tab,
+                       const double* pre_e, const double* pre_v, const double* post_e) {
+  return launch_any<float>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+}
+
+}  // namespace kdqmc

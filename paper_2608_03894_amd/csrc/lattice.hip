@@ -1,0 +1,168 @@
+// Host-side lattice algebra: the 3x3 Bloch blocks of the kagome kinetic
+// matrix (Eqs. (3)-(4)) and their exponentials, tabulated per momentum.
+#include <cmath>
+#include <complex>
+
+#include "common.h"
+
+namespace kdqmc {
+
+namespace {
+
+using cd = std::complex<double>;
+
+// One directed hopping term of Eq. (3): row sublattice `to`, column
+// sublattice `from`, cell displacement (row cell - column cell) = (d1, d2).
+struct Hop {
+  int to, from, d1, d2;
+};
+
+// Eq. (3) term by term (s = 0, 1, 2 for A, B, C; K_s maps cell x to x+1):
+//   I (x) (I + K_s) (x) delta_a : B <- A, displacements (0,0), (0,+1)
+//   (I + K_s) (x) I (x) delta_b : C <- A, displacements (0,0), (+1,0)
+//   (I (x) I + K_s (x) K_s^T) (x) delta_c : C <- B, displacements (0,0), (+1,-1)
+// plus the Hermitian conjugate of each (from <-> to, d -> -d).
+constexpr Hop kHops[6] = {
+    {1, 0, 0, 0}, {1, 0, 0, 1}, {2, 0, 0, 0}, {2, 0, 1, 0}, {2, 1, 0, 0}, {2, 1, 1, -1},
+};
+
+// H(k)_{s s'} = sum over hops (s <- s', d) of -t exp(-i k.d), for the forward
+// transform v^(k) = sum_x exp(-i k.x) v(x) (so (K v)^ = H(k) v^).
+void bloch_H(double t, double k1, double k2, cd h[3][3]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) h[a][b] = 0.0;
+  for (const Hop& hp : kHops) {
+    const double ph = -(k1 * hp.d1 + k2 * hp.d2);
+    const cd v = -t * std::polar(1.0, ph);
+    h[hp.to][hp.from] += v;
+    h[hp.from][hp.to] += std::conj(v);
+  }
+}
+
+void matmul3(const cd a[3][3], const cd b[3][3], cd out[3][3]) {
+  cd r[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      cd s = 0.0;
+      for (int k = 0; k < 3; ++k) s += a[i][k] * b[k][j];
+      r[i][j] = s;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) out[i][j] = r[i][j];
+}
+
+// exp(A) for a 3x3 complex matrix: scaling and squaring with a Taylor
+// series of 30 terms on ||A / 2^s|| <= 1/2.
+void expm3(const cd a[3][3], cd out[3][3]) {
+  double nrm = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    double row = 0.0;
+    for (int j = 0; j < 3; ++j) row += std::abs(a[i][j]);
+    nrm = std::max(nrm, row);
+  }
+  int s = 0;
+  while (nrm > 0.5) {
+    nrm *= 0.5;
+    ++s;
+  }
+  const double sc = std::ldexp(1.0, -s);
+  cd x[3][3], term[3][3], sum[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      x[i][j] = a[i][j] * sc;
+      term[i][j] = (i == j) ? 1.0 : 0.0;
+      sum[i][j] = term[i][j];
+    }
+  for (int n = 1; n <= 30; ++n) {
+    matmul3(term, x, term);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        term[i][j] /= double(n);
+        sum[i][j] += term[i][j];
+      }
+  }
+  for (int q = 0; q < s; ++q) matmul3(sum, sum, sum);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) out[i][j] = sum[i][j];
+}
+
+// Real eigenvalues of a 3x3 Hermitian matrix (trigonometric solution of the
+// characteristic cubic), ascending.
+void eig3_hermitian(const cd h[3][3], double ev[3]) {
+  const double a = h[0][0].real(), b = h[1][1].real(), c = h[2][2].real();
+  const double tr = a + b + c;
+  const double m = tr / 3.0;
+  // shifted matrix B = H - m I
+  cd s[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) s[i][j] = h[i][j] - ((i == j) ? m : 0.0);
+  double p2 = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) p2 += std::norm(s[i][j]);
+  const double p = std::sqrt(p2 / 6.0);
+  if (p == 0.0) {
+    ev[0] = ev[1] = ev[2] = m;
+    return;
+  }
+  cd bm[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) bm[i][j] = s[i][j] / p;
+  const cd det = bm[0][0] * (bm[1][1] * bm[2][2] - bm[1][2] * bm[2][1]) -
+                 bm[0][1] * (bm[1][0] * bm[2][2] - bm[1][2] * bm[2][0]) +
+                 bm[0][2] * (bm[1][0] * bm[2][1] - bm[1][1] * bm[2][0]);
+  double r = det.real() / 2.0;
+  r = std::max(-1.0, std::min(1.0, r));
+  const double phi = std::acos(r) / 3.0;
+  const double e0 = m + 2.0 * p * std::cos(phi);
+  const double e2 = m + 2.0 * p * std::cos(phi + 2.0 * kPi / 3.0);
+  const double e1 = tr - e0 - e2;
+  ev[0] = e2;
+  ev[1] = e1;
+  ev[2] = e0;
+}
+
+}  // namespace
+
+bool lattice_supported(int L) {
+  switch (L) {
+    case 3: case 6: case 9: case 12: case 15: case 18: case 24:
+      return true;
+    default:
+      return false;
+  }
+}
+
+void bloch_table(int L, double t, double scale, double shift, double* tab) {
+  const double norm = 1.0 / double(L * L);
+  for (int m1 = 0; m1 < L; ++m1)
+    for (int m2 = 0; m2 < L; ++m2) {
+      const double k1 = 2.0 * kPi * m1 / L, k2 = 2.0 * kPi * m2 / L;
+      cd h[3][3], e[3][3];
+      bloch_H(t, k1, k2, h);
+      for (int i = 0; i < 3; ++i) {
+        h[i][i] -= shift;
+        for (int j = 0; j < 3; ++j) h[i][j] *= scale;
+      }
+      expm3(h, e);
+      double* out = tab + 18 * (m1 * L + m2);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          out[2 * (3 * i + j)] = e[i][j].real() * norm;
+          out[2 * (3 * i + j) + 1] = e[i][j].imag() * norm;
+        }
+    }
+}
+
+double dirac_mu(int /*L*/, double t) {
+  // The Dirac point of the kagome bands sits at k = (2 pi/3, -2 pi/3) in the
+  // reciprocal basis of the cell coordinates; there the two dispersive
+  // bands are degenerate.  Return that doubly degenerate eigenvalue.
+  cd h[3][3];
+  bloch_H(t, 2.0 * kPi / 3.0, -2.0 * kPi / 3.0, h);
+  double ev[3];
+  eig3_hermitian(h, ev);
+  return (std::abs(ev[0] - ev[1]) < std::abs(ev[1] - ev[2])) ? 0.5 * (ev[0] + ev[1])
+                                                              : 0.5 * (ev[1] + ev[2]);
+}
+
+}  // namespace kdqmc

@@ -1,0 +1,451 @@
+// Delayed Ising-field updates of one time slice (the delay-update algorithm
+// cited in Sec. II of the paper), organised for one GPU:
+//
+//   * sites are visited in order in windows S of w consecutive sites;
+//   * k_decide (one workgroup) holds G~cur[S,S] in LDS and runs the
+//     sequential Metropolis tests of the window; each accepted flip updates
+//     the window submatrix by a rank-one Sherman-Morrison step, and two small
+//     triangular factors Z, Z' are grown so that the window's accepted flips
+//     together add  G~cur[:,A] Z Z' (I - G~cur)[A,:]  to G~ (A = accepted
+//     sites of the window);
+//   * k_extend turns that into a := |A| new columns of the pending factors
+//     U (N x k) and W (k x N), G~cur = G~ + U W;
+//   * k_flush adds U W to G as one rank-(<= delay_k) MFMA product once the
+//     pending rank could exceed delay_k, and at the end of the slice.
+//
+// Frames: G holds D^{-1} G~ D with D = diag(exp(alpha s_l)) taken from the
+// fields at the start of the slice (ev, evinv); the pending factors are
+// stored in the same frame (U_store = D^{-1} U, W_store = W D), so the flush
+// is a plain G += U_store W_store and the column pass of the wrap applies D.
+#include "common.h"
+
+namespace kdqmc {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// ev = exp(alpha s), evinv = exp(-alpha s) for the fields of one slice.
+__global__ void k_frame_scale(const int8_t* __restrict__ s, int n, double ea, double eainv,
+                              double* __restrict__ ev, double* __restrict__ evinv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const bool up = s[i] > 0;
+    ev[i] = up ? ea : eainv;
+    evinv[i] = up ? eainv : ea;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sequential decisions of one window (single workgroup).
+// LDS: Gs[w][w+1] (window submatrix, tilde frame), Z[w][w], Zp[w][w].
+// Invariant after the accept at window position p: entries (x, y) with
+// x, y > p are current; row p and column p keep the values they had when p
+// was decided, which are exactly the coefficients the recursions for Z and
+// Z' need later (rows/columns of earlier accepts are never written again).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
+         const double* __restrict__ evinv, int8_t* __restrict__ s_l,
+         const double* __restrict__ u, const uint8_t* __restrict__ forced,
+         uint8_t* __restrict__ acc_out, double* __restrict__ ratio_out, int w0, int wn, int W,
+         const double* __restrict__ Gs_in, double em2a, double ep2a, int win,
+         int* __restrict__ win_a, int* __restrict__ win_p, double* __restrict__ Zg,
+         double* __restrict__ Zpg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ldg = wn + 1;
+  double* Gs = reinterpret_cast<double*>(smem_raw);  // wn * ldg
+  double* Z = Gs + wn * ldg;                          // wn * wn, Z[n'][n] at n'*wn + n
+  double* Zp = Z + wn * wn;                           // Zp[n][n'] at n*wn + n'
+  double* cl = Zp + wn * wn;                          // wn: c of accept n
+  int* pl = reinterpret_cast<int*>(cl + wn);          // wn: window position of accept n
+  int8_t* sl = reinterpret_cast<int8_t*>(pl + wn);    // wn: fields of the window
+  const int tid = threadIdx.x, nth = blockDim.x;
+
+  for (int idx = tid; idx < wn * wn; idx += nth) {
+    const int x = idx / wn, y = idx % wn;
+    double g;
+    if (Gs_in) {
+      g = Gs_in[x * W + y];
+    } else {
+      const int gx = w0 + x, gy = w0 + y;
+      g = double(G[(size_t)gx * N + gy]) * ev[gx] * evinv[gy];
+    }
+    Gs[x * ldg + y] = g;
+    Z[idx] = 0.0;
+    Zp[idx] = 0.0;
+  }
+  for (int p = tid; p < wn; p += nth) sl[p] = s_l[w0 + p];
+  __syncthreads();
+
+  int na = 0;
+  for (int p = 0; p < wn; ++p) {
+    const int s = sl[p];
+    const double gpp = Gs[p * ldg + p];
+    const double delta = (s > 0 ? em2a : ep2a) - 1.0;
+    const double e2as = s > 0 ? ep2a : em2a;
+    const double R = 1.0 + delta * (1.0 - gpp);
+    const double ratio = e2as * R * R;
+    const bool a = forced ? (forced[w0 + p] != 0) : (u[w0 + p] < ratio);
+    if (tid == 0) {
+      if (ratio_out) ratio_out[w0 + p] = ratio;
+      if (acc_out) acc_out[w0 + p] = a ? 1 : 0;
+    }
+    if (!a) continue;
+    const double c = delta / R;
+    const int n = na;
+    if (tid == 0) {
+      s_l[w0 + p] = int8_t(-s);
+      cl[n] = c;
+      pl[n] = p;
+    }
+    // Z[:, n] and Z'[n, :] from the frozen rows/columns of earlier accepts:
+    //   Z[q][n]  = -c (delta_qn + sum_{q<=m<n} Z[q][m] X[m][n]),  X[m][n] = -Gs[p_m][p]
+    //   Z'[n][q] = delta_nq - sum_{q<=m<n} Y[m][n] Z'[m][q],       Y[m][n] = -c_m Gs[p][p_m]
+    for (int q = tid; q <= n; q += nth) {
+      double zs = (q == n) ? 1.0 : 0.0;
+      double zp = (q == n) ? 1.0 : 0.0;
+      for (int m = q; m < n; ++m) {
+        const int pm = pl[m];
+        zs += Z[q * wn + m] * (-Gs[pm * ldg + p]);
+        zp -= (-cl[m] * Gs[p * ldg + pm]) * Zp[m * wn + q];
+      }
+      Z[q * wn + n] = -c * zs;
+      Zp[n * wn + q] = zp;
+    }
+    // rank-one update of the live part: Gs[x][y] += c Gs[x][p] Gs[p][y], x, y > p
+    const int rem = wn - p - 1;
+    for (int idx = tid; idx < rem * rem; idx += nth) {
+      const int x = p + 1 + idx / rem, y = p + 1 + idx % rem;
+      Gs[x * ldg + y] += c * Gs[x * ldg + p] * Gs[p * ldg + y];
+    }
+    ++na;
+    __syncthreads();
+  }
+  // publish the window's result
+  if (tid == 0) win_a[win] = na;
+  for (int idx = tid; idx < na * na; idx += nth) {
+    const int q = idx / na, n = idx % na;
+    Zg[q * W + n] = Z[q * wn + n];
+    Zpg[q * W + n] = Zp[q * wn + n];
+  }
+  for (int n = tid; n < na; n += nth) win_p[win * W + n] = pl[n];
+}
+
+// ---------------------------------------------------------------------------
+// New pending columns of the window: with g[r][n] = G~cur[r, i_n] and
+// h[n][r] = delta(r, i_n) - G~cur[i_n, r] (G~cur includes the m pending
+// columns of this flush group),
+//   U[:, m+n] = sum_{q<=n} g[:, q] Z[q][n],   W[m+n, :] = sum_{q<=n} Z'[n][q] h[q, :].
+// One workgroup per block of RB rows r; Z, Z' staged in LDS.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_extend(const T* __restrict__ G, int N, const double* __restrict__ ev,
+         const double* __restrict__ evinv, T* __restrict__ Up, T* __restrict__ Wp,
+         const int* __restrict__ win_a, int win, int grp0, const int* __restrict__ win_p,
+         const double* __restrict__ Zg, const double* __restrict__ Zpg, int W, int w0, int RB) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int a = win_a[win];
+  if (a == 0) return;
+  int m = 0;
+  for (int j = grp0; j < win; ++j) m += win_a[j];
+  double* Z = reinterpret_cast<double*>(smem_raw);  // a*a
+  double* Zp = Z + a * a;                            // a*a
+  double* gl = Zp + a * a;                           // RB*a : gl[rr*a + n]
+  double* hl = gl + RB * a;                          // a*RB : hl[n*RB + rr]
+  int* il = reinterpret_cast<int*>(hl + a * RB);     // a
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int r0 = blockIdx.x * RB;
+  for (int idx = tid; idx < a * a; idx += nth) {
+    const int q = idx / a, n = idx % a;
+    Z[idx] = Zg[q * W + n];
+    Zp[idx] = Zpg[q * W + n];
+  }
+  for (int n = tid; n < a; n += nth) il[n] = w0 + win_p[win * W + n];
+  __syncthreads();
+  // phase 1: g and h for the RB rows of this block
+  for (int idx = tid; idx < RB * a; idx += nth) {
+    const int n = idx % a, rr = idx / a;
+    const int r = r0 + rr;
+    if (r >= N) continue;
+    const int i = il[n];
+    double gv = double(G[(size_t)r * N + i]);
+    double hv = double(G[(size_t)i * N + r]);
+    for (int j = 0; j < m; ++j) {
+      gv += double(Up[(size_t)j * N + r]) * double(Wp[(size_t)j * N + i]);
+      hv += double(Up[(size_t)j * N + i]) * double(Wp[(size_t)j * N + r]);
+    }
+    gl[rr * a + n] = gv * ev[r] * evinv[i];
+    hl[n * RB + rr] = ((r == i) ? 1.0 : 0.0) - hv * ev[i] * evinv[r];
+  }
+  __syncthreads();
+  // phase 2: triangular combinations, stored in the store frame
+  for (int idx = tid; idx < RB * a; idx += nth) {
+    const int rr = idx % RB, n = idx / RB;
+    const int r = r0 + rr;
+    if (r >= N) continue;
+    double uv = 0.0, wv = 0.0;
+    for (int q = 0; q <= n; ++q) {
+      uv += gl[rr * a + q] * Z[q * a + n];
+      wv += Zp[n * a + q] * hl[q * RB + rr];
+    }
+    Up[(size_t)(m + n) * N + r] = T(uv * evinv[r]);
+    Wp[(size_t)(m + n) * N + r] = T(wv * ev[r]);
+  }
+}
+
+// Window submatrix of the next window from G and the pending factors:
+// Gs[x][y] = ev_x evinv_y (G[x,y] + sum_{j<m} U[j][x] W[j][y]).
+template <typename T>
+__global__ void k_prep(const T* __restrict__ G, int N, const double* __restrict__ ev,
+                       const double* __restrict__ evinv, const T* __restrict__ Up,
+                       const T* __restrict__ Wp, const int* __restrict__ win_a, int grp0,
+                       int upto, int w0, int wn, int W, double* __restrict__ Gs) {
+  int m = 0;
+  for (int j = grp0; j <= upto; ++j) m += win_a[j];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= wn * wn) return;
+  const int x = w0 + idx / wn, y = w0 + idx % wn;
+  double g = double(G[(size_t)x * N + y]);
+  for (int j = 0; j < m; ++j) g += double(Up[(size_t)j * N + x]) * double(Wp[(size_t)j * N + y]);
+  Gs[(idx / wn) * W + (idx % wn)] = g * ev[x] * evinv[y];
+}
+
+// ---------------------------------------------------------------------------
+// Rank-K flush G += U^T W (U, W stored K x N), K = accepted flips of the
+// flush group (read on the device).  FP64: v_mfma_f64_16x16x4.
+// Tile 64 x 64 per workgroup (4 waves, each 32 x 32 = 2 x 2 MFMA blocks).
+// MFMA 16x16x4 f64 operand layout (lane l): A[l%16][l/16], B[l/16][l%16];
+// result element j of lane l is D[4*(l/16)+j][l%16].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_flush_f64(double* __restrict__ G, int N, const double* __restrict__ Up,
+            const double* __restrict__ Wp, const int* __restrict__ win_a, int grp0, int grp1) {
+  int K = 0;
+  for (int j = grp0; j < grp1; ++j) K += win_a[j];
+  if (K == 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int col0 = blockIdx.x * 64 + (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4d acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + 16 * bi + 4 * lk + j, cc = col0 + 16 * bj + lr;
+        acc[bi][bj][j] = (r < N && cc < N) ? G[(size_t)r * N + cc] : 0.0;
+      }
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + lk;
+    double a[2], b[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const int r = row0 + 16 * bi + lr;
+      a[bi] = (k < K && r < N) ? Up[(size_t)k * N + r] : 0.0;
+      const int cc = col0 + 16 * bi + lr;
+      b[bi] = (k < K && cc < N) ? Wp[(size_t)k * N + cc] : 0.0;
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + 16 * bi + 4 * lk + j, cc = col0 + 16 * bj + lr;
+        if (r < N && cc < N) G[(size_t)r * N + cc] = acc[bi][bj][j];
+      }
+}
+
+// Split-precision flush for FP32 G: x = hi + lo * 2^-S with hi, lo in H
+// (FP16 or BF16); U W ~= hi_u hi_w + 2^-S (hi_u lo_w + lo_u hi_w), the two
+// parts accumulated in FP32 by v_mfma_f32_16x16x32_{f16,bf16}.
+// MFMA 16x16x32 operand layout (lane l): A row l%16, k = 8*(l/16) .. +7;
+// B column l%16, same k; result as in the f64 kernel.
+template <typename H>
+struct SplitTraits;
+template <>
+struct SplitTraits<_Float16> {
+  typedef v8h vec;
+  static constexpr float kScale = 4096.0f;  // 2^12 keeps the low part normal in FP16
+  __device__ static v4f mfma(vec a, vec b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct SplitTraits<__bf16> {
+  typedef v8bf vec;
+  static constexpr float kScale = 256.0f;
+  __device__ static v4f mfma(vec a, vec b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename H>
+__global__ void __launch_bounds__(256)
+k_flush_split(float* __restrict__ G, int N, const float* __restrict__ Up,
+              const float* __restrict__ Wp, const int* __restrict__ win_a, int grp0, int grp1) {
+  typedef SplitTraits<H> Tr;
+  typedef typename Tr::vec vec;
+  int K = 0;
+  for (int j = grp0; j < grp1; ++j) K += win_a[j];
+  if (K == 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int col0 = blockIdx.x * 64 + (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4f hh[2][2], cr[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + 16 * bi + 4 * lk + j, cc = col0 + 16 * bj + lr;
+        hh[bi][bj][j] = (r < N && cc < N) ? G[(size_t)r * N + cc] : 0.0f;
+        cr[bi][bj][j] = 0.0f;
+      }
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    vec ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const int r = row0 + 16 * bi + lr;
+      const int cc = col0 + 16 * bi + lr;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = k0 + 8 * lk + t;
+        const float xa = (k < K && r < N) ? Up[(size_t)k * N + r] : 0.0f;
+        const float xb = (k < K && cc < N) ? Wp[(size_t)k * N + cc] : 0.0f;
+        const H ha = H(xa), hb = H(xb);
+        ah[bi][t] = ha;
+        bh[bi][t] = hb;
+        al[bi][t] = H((xa - float(ha)) * Tr::kScale);
+        bl[bi][t] = H((xb - float(hb)) * Tr::kScale);
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        hh[bi][bj] = Tr::mfma(ah[bi], bh[bj], hh[bi][bj]);
+        cr[bi][bj] = Tr::mfma(ah[bi], bl[bj], cr[bi][bj]);
+        cr[bi][bj] = Tr::mfma(al[bi], bh[bj], cr[bi][bj]);
+      }
+  }
+  const float inv = 1.0f / Tr::kScale;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + 16 * bi + 4 * lk + j, cc = col0 + 16 * bj + lr;
+        if (r < N && cc < N) G[(size_t)r * N + cc] = hh[bi][bj][j] + cr[bi][bj][j] * inv;
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Host orchestration of one slice's updates.
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T>
+int set_lds_limits() {
+  static bool done = false;
+  if (!done) {
+    KDQMC_HIP(hipFuncSetAttribute((const void*)k_decide<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    KDQMC_HIP(hipFuncSetAttribute((const void*)k_extend<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    done = true;
+  }
+  return KDQMC_OK;
+}
+
+template <typename T>
+int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, uint8_t* acc,
+                  double* ratio) {
+  KDQMC_TRY(set_lds_limits<T>());
+  const int N = c->N, W = c->w;
+  T* G = static_cast<T*>(c->G);
+  T* Up = static_cast<T*>(c->Upend);
+  T* Wp = static_cast<T*>(c->Wpend);
+  int8_t* s_l = c->fields + (size_t)(l - 1) * N;
+  const double em2a = std::exp(-2.0 * c->alpha), ep2a = std::exp(2.0 * c->alpha);
+  const int RB = 32;
+  for (int win = 0; win < c->nw; ++win) {
+    const int w0 = win * W;
+    const int wn = std::min(W, N - w0);
+    const int grp0 = (win / c->F) * c->F;
+    const bool first_in_group = (win == grp0);
+    // decide
+    const size_t lds_d = size_t(wn) * (wn + 1) * 8 + 2 * size_t(wn) * wn * 8 + size_t(wn) * 8 +
+                         size_t(wn) * 4 + size_t(wn) + 16;
+    const int e_d = prof_mark(c);
+    hipLaunchKernelGGL(k_decide<T>, dim3(1), dim3(256), lds_d, c->stream, G, N, c->ev, c->evinv,
+                       s_l, u ? u + 0 : nullptr, forced, acc, ratio, w0, wn, W,
+                       first_in_group ? nullptr : c->Gs, em2a, ep2a, win, c->win_a, c->win_p,
+                       c->Xw, c->Yw);
+    const int e_e = prof_mark(c);
+    prof_pair(c, PH_DECIDE, e_d, e_e);
+    // extend
+    const size_t lds_e = 2 * size_t(W) * W * 8 + 2 * size_t(RB) * W * 8 + size_t(W) * 4 + 16;
+    hipLaunchKernelGGL(k_extend<T>, dim3((N + RB - 1) / RB), dim3(256), lds_e, c->stream, G, N,
+                       c->ev, c->evinv, Up, Wp, c->win_a, win, grp0, c->win_p, c->Xw, c->Yw, W,
+                       w0, RB);
+    const int e_x = prof_mark(c);
+    prof_pair(c, PH_EXTEND, e_e, e_x);
+    const bool last_in_group = (win - grp0 == c->F - 1) || (win == c->nw - 1);
+    if (last_in_group) {
+      dim3 grid((N + 63) / 64, (N + 63) / 64);
+      if constexpr (sizeof(T) == 8) {
+        hipLaunchKernelGGL(k_flush_f64, grid, dim3(256), 0, c->stream, (double*)G, N,
+                           (const double*)Up, (const double*)Wp, c->win_a, grp0, win + 1);
+      } else {
+        if (c->p.prec == KDQMC_MIXED_BF16)
+          hipLaunchKernelGGL(k_flush_split<__bf16>, grid, dim3(256), 0, c->stream, (float*)G, N,
+                             (const float*)Up, (const float*)Wp, c->win_a, grp0, win + 1);
+        else
+          hipLaunchKernelGGL(k_flush_split<_Float16>, grid, dim3(256), 0, c->stream, (float*)G, N,
+                             (const float*)Up, (const float*)Wp, c->win_a, grp0, win + 1);
+      }
+      prof_pair(c, PH_FLUSH, e_x, prof_mark(c));
+    } else {
+      const int nx = win + 1;
+      const int nw0 = nx * W;
+      const int nwn = std::min(W, N - nw0);
+      hipLaunchKernelGGL(k_prep<T>, dim3((nwn * nwn + 255) / 256), dim3(256), 0, c->stream, G, N,
+                         c->ev, c->evinv, Up, Wp, c->win_a, grp0, win, nw0, nwn, W, c->Gs);
+      prof_pair(c, PH_PREP, e_x, prof_mark(c));
+    }
+  }
+  KDQMC_HIP(hipGetLastError());
+  return KDQMC_OK;
+}
+
+}  // namespace
+
+int launch_frame_scale(kdqmc_ctx* c, int l) {
+  const double ea = std::exp(c->alpha), eainv = std::exp(-c->alpha);
+  hipLaunchKernelGGL(k_frame_scale, dim3((c->N + 255) / 256), dim3(256), 0, c->stream,
+                     c->fields + (size_t)(l - 1) * c->N, c->N, ea, eainv, c->ev, c->evinv);
+  KDQMC_HIP(hipGetLastError());
+  return KDQMC_OK;
+}
+
+int run_slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, uint8_t* acc,
+                      double* ratio) {
+  if (c->fp64) return slice_updates<double>(c, l, u, forced, acc, ratio);
+  return slice_updates<float>(c, l, u, forced, acc, ratio);
+}
+
+}  // namespace kdqmc

@@ -1,0 +1,223 @@
+"""ctypes binding of libkdqmc.so (include/kdqmc.h): argument marshalling only.
+
+Every computation happens in the HIP library.  PyTorch supplies device
+memory (the caller-owned workspace and the input/output tensors) and the HIP
+stream; no array here is ever computed on the host.  If the shared library is
+missing, ``load()`` raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkdqmc.so")
+
+FP64, MIXED_F16, MIXED_BF16 = 0, 1, 2
+PREC = {"fp64": FP64, "mixed_f16": MIXED_F16, "mixed_bf16": MIXED_BF16, "fp32": MIXED_F16}
+
+OK, EINVAL, EUNSUPPORTED, ESTATE, EHIP, ENUMERIC, ENOSPACE = 0, -1, -2, -3, -4, -5, -6
+
+
+class KdqmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"kdqmc error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int),
+        ("t", ctypes.c_double),
+        ("U", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("dtau", ctypes.c_double),
+        ("n_stab", ctypes.c_int),
+        ("delay_k", ctypes.c_int),
+        ("window", ctypes.c_int),
+        ("fft_tile", ctypes.c_int),
+        ("prec", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_SIGS = {
+    "kdqmc_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Params)]),
+    "kdqmc_dirac_mu": (ctypes.c_double, [ctypes.c_int, ctypes.c_double]),
+    "kdqmc_init_lattice": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(Params), _vp,
+                                          ctypes.c_size_t, _vp]),
+    "kdqmc_set_fields": (ctypes.c_int, [_vp, _vp]),
+    "kdqmc_get_fields": (ctypes.c_int, [_vp, _vp]),
+    "kdqmc_set_G": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "kdqmc_wrap_slice": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "kdqmc_sweep_slice": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "kdqmc_stabilize": (ctypes.c_int, [_vp, _vp]),
+    "kdqmc_sweep": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "kdqmc_measure_G": (ctypes.c_int, [_vp, _vp]),
+    "kdqmc_current_slice": (ctypes.c_int, [_vp]),
+    "kdqmc_sync": (ctypes.c_int, [_vp]),
+    "kdqmc_destroy": (None, [_vp]),
+    "kdqmc_last_error": (ctypes.c_char_p, []),
+    "kdqmc_gemm_f64": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_double, _vp, ctypes.c_int, _vp,
+                                      ctypes.c_int, ctypes.c_double, _vp, ctypes.c_int]),
+    "kdqmc_qr_f64": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
+    "kdqmc_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "kdqmc_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int)]),
+    "kdqmc_phase_name": (ctypes.c_char_p, [ctypes.c_int]),
+}
+
+NPHASE = 10
+
+
+def load():
+    """Loads the in-tree libkdqmc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not built: run __graft_entry__.build() or "
+                           "python paper_2608_03894_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def gpu_available() -> bool:
+    import torch
+    return torch.cuda.is_available()
+
+
+def last_error() -> str:
+    return load().kdqmc_last_error().decode()
+
+
+def _check(rc):
+    if rc != OK:
+        raise KdqmcError(rc, last_error())
+
+
+def make_params(L, U, beta, dtau=0.1, t=1.0, mu=None, n_stab=10, delay_k=32, window=0,
+                fft_tile=0, prec="fp64") -> Params:
+    if mu is None:
+        mu = dirac_mu(L, t)
+    if isinstance(prec, str):
+        prec = PREC[prec]
+    return Params(L=L, t=t, U=U, mu=mu, beta=beta, dtau=dtau, n_stab=n_stab, delay_k=delay_k,
+                  window=window, fft_tile=fft_tile, prec=prec)
+
+
+def workspace_bytes(p: Params) -> int:
+    return int(load().kdqmc_workspace_bytes(ctypes.byref(p)))
+
+
+def dirac_mu(L: int, t: float = 1.0) -> float:
+    return float(load().kdqmc_dirac_mu(L, t))
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    return ctypes.c_void_p(x.data_ptr())
+
+
+class Chain:
+    """One Markov chain: a context, its workspace tensor and its stream."""
+
+    def __init__(self, params: Params, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.p = params
+        self.lib = load()
+        self.device = torch.device(device)
+        self.N = 3 * params.L * params.L
+        self.L_tau = int(round(params.beta / params.dtau))
+        nbytes = workspace_bytes(params)
+        if nbytes == 0:
+            raise KdqmcError(EINVAL, last_error())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        _check(self.lib.kdqmc_init_lattice(ctypes.byref(ctx), ctypes.byref(params),
+                                           _ptr(self.ws), nbytes,
+                                           ctypes.c_void_p(self.stream.cuda_stream)))
+        self.ctx = ctx
+
+    # -- the calls of the C ABI, same names ---------------------------------
+    def set_fields(self, s):
+        _check(self.lib.kdqmc_set_fields(self.ctx, _ptr(s)))
+
+    def get_fields(self, out):
+        _check(self.lib.kdqmc_get_fields(self.ctx, _ptr(out)))
+
+    def set_G(self, G, l):
+        _check(self.lib.kdqmc_set_G(self.ctx, _ptr(G), l))
+
+    def wrap_slice(self, l):
+        _check(self.lib.kdqmc_wrap_slice(self.ctx, l))
+
+    def sweep_slice(self, l, u=None, forced=None, accepted=None, ratio=None):
+        _check(self.lib.kdqmc_sweep_slice(self.ctx, l, _ptr(u), _ptr(forced), _ptr(accepted),
+                                          _ptr(ratio)))
+
+    def stabilize(self, wrap_err=None):
+        _check(self.lib.kdqmc_stabilize(self.ctx, _ptr(wrap_err)))
+
+    def sweep(self, u=None, forced=None, accepted=None, ratio=None, wrap_err=None):
+        _check(self.lib.kdqmc_sweep(self.ctx, _ptr(u), _ptr(forced), _ptr(accepted), _ptr(ratio),
+                                    _ptr(wrap_err)))
+
+    def measure_G(self, out):
+        _check(self.lib.kdqmc_measure_G(self.ctx, _ptr(out)))
+
+    def current_slice(self) -> int:
+        r = self.lib.kdqmc_current_slice(self.ctx)
+        if r < 0:
+            _check(r)
+        return r
+
+    def sync(self):
+        _check(self.lib.kdqmc_sync(self.ctx))
+
+    def gemm_f64(self, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc):
+        _check(self.lib.kdqmc_gemm_f64(self.ctx, int(ta), int(tb), M, N, K, alpha, _ptr(A), lda,
+                                       _ptr(B), ldb, beta, _ptr(C), ldc))
+
+    def qr_f64(self, n, A, Q):
+        _check(self.lib.kdqmc_qr_f64(self.ctx, n, _ptr(A), _ptr(Q)))
+
+    def profile_enable(self, on=True):
+        _check(self.lib.kdqmc_profile_enable(self.ctx, 1 if on else 0))
+
+    def profile_read(self):
+        """{phase: (milliseconds, launches)} recorded since the last enable/read."""
+        ms = (ctypes.c_double * NPHASE)()
+        n = (ctypes.c_int * NPHASE)()
+        _check(self.lib.kdqmc_profile_read(self.ctx, ms, n))
+        return {self.lib.kdqmc_phase_name(i).decode(): (ms[i], n[i]) for i in range(NPHASE)}
+
+    # -- conveniences ---------------------------------------------------------
+    def G(self):
+        out = self.torch.empty((self.N, self.N), dtype=self.torch.float64, device=self.device)
+        self.measure_G(out)
+        self.sync()
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.kdqmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,174 @@
+"""GPU parity of the full hot path through the C ABI against the oracle on
+identical seeded fields, with the oracle's accept/reject decisions replayed:
+G(0) from the stabilized stacks, every slice of a sweep, the ratios, every
+stabilization, Metropolis decisions, mixed precision, and state errors."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from gpu_helpers import chain, dev, model, oracle_run, say, torch
+from oracle import dqmc
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def run_forced_sweep(ch, f, r, record=True):
+    """Replays the oracle's decisions slice by slice; returns per-slice G and ratios."""
+    t = torch()
+    L_tau, N = f.shape
+    ch.set_fields(dev(f))
+    forced = dev(r["accepted"].astype(np.uint8))
+    ratio = t.zeros((L_tau, N), dtype=t.float64, device="cuda:0")
+    acc = t.zeros((L_tau, N), dtype=t.uint8, device="cuda:0")
+    errs = t.zeros(L_tau // 10, dtype=t.float64, device="cuda:0")
+    gs = []
+    for l in range(1, L_tau + 1):
+        ch.sweep_slice(l, None, forced[l - 1], acc[l - 1], ratio[l - 1])
+        if l % 10 == 0:
+            ch.stabilize(errs[l // 10 - 1])
+        if record:
+            gs.append(ch.G().cpu().numpy())
+    ch.sync()
+    return gs, ratio.cpu().numpy(), acc.cpu().numpy(), errs.cpu().numpy()
+
+
+@pytest.mark.parametrize("L,beta,seed", [(3, 2.0, 3), (6, 2.0, 6), (12, 1.0, 12)])
+def test_green_zero_from_stacks(gpu_lib, L, beta, seed):
+    say("G0", L, beta, seed)
+    m = model(L, -4.0, beta)
+    f = si.ising_fields(L, m.L_tau, seed)
+    ch = chain(L, -4.0, beta)
+    ch.set_fields(dev(f))
+    got = ch.G().cpu().numpy()
+    want = dqmc.green_scratch(m, f, 0)
+    say("G0 err", np.abs(got - want).max())
+    assert np.abs(got - want).max() < TOL64
+
+
+@pytest.mark.parametrize("k,window", [(1, 1), (5, 5), (8, 4), (32, 0)])
+def test_c1_sweep_forced(gpu_lib, k, window):
+    """Smallest workload (L=3, U=-4, beta=2): every slice within 1e-10."""
+    say("c1 sweep", k, window)
+    m, f, g0, r, u = oracle_run(3, -4.0, 2.0, 3)
+    ch = chain(3, -4.0, 2.0, delay_k=k, window=window)
+    gs, ratio, acc, errs = run_forced_sweep(ch, f, r)
+    for l, (a, b) in enumerate(zip(gs, r["G_slices"]), start=1):
+        assert np.abs(a - b).max() < TOL64, (l, np.abs(a - b).max())
+    assert np.array_equal(acc.astype(bool), r["accepted"])
+    assert np.abs(ratio - r["ratios"]).max() < 1e-9 * max(1.0, np.abs(r["ratios"]).max())
+    fields = torch().zeros(f.shape, dtype=torch().int8, device="cuda:0")
+    ch.get_fields(fields)
+    assert np.array_equal(fields.cpu().numpy(), r["fields"])
+    assert ch.current_slice() == 0
+    for j, e in enumerate(errs):
+        assert abs(e - r["wrap_err"][10 * (j + 1)]) < 1e-10
+
+
+def test_l6_sweep_forced(gpu_lib):
+    say("L6 sweep")
+    m, f, g0, r, u = oracle_run(6, -4.0, 2.0, 6)
+    ch = chain(6, -4.0, 2.0, delay_k=16)
+    gs, ratio, acc, errs = run_forced_sweep(ch, f, r)
+    worst = max(np.abs(a - b).max() for a, b in zip(gs, r["G_slices"]))
+    say("L6 worst", worst)
+    assert worst < TOL64
+
+
+def test_c2_ten_slices_forced(gpu_lib):
+    """The benchmark lattice (L=12, N=432, U=-4, beta=8, k=32): first ten
+    slices and the first stabilization, decisions replayed."""
+    say("C2 ten slices")
+    w = si.C2
+    m, f, g0, r, u = oracle_run(12, -4.0, 8.0, w.seed, l_stop=10)
+    t = torch()
+    ch = chain(12, -4.0, 8.0, delay_k=32)
+    ch.set_fields(dev(f))
+    g = ch.G().cpu().numpy()
+    assert np.abs(g - g0).max() < TOL64
+    forced = dev(r["accepted"].astype(np.uint8))
+    ratio = t.zeros((10, m.N), dtype=t.float64, device="cuda:0")
+    for l in range(1, 11):
+        ch.sweep_slice(l, None, forced[l - 1], None, ratio[l - 1])
+        if l < 10:
+            got = ch.G().cpu().numpy()
+            err = np.abs(got - r["G_slices"][l - 1]).max()
+            say("C2 slice", l, err)
+            assert err < TOL64
+    got = ch.G().cpu().numpy()
+    assert np.abs(got - r["G_prestab"][10]).max() < TOL64
+    e = t.zeros(1, dtype=t.float64, device="cuda:0")
+    ch.stabilize(e)
+    got = ch.G().cpu().numpy()
+    err = np.abs(got - r["G_slices"][9]).max()
+    say("C2 stabilized", err, float(e.cpu()[0]), r["wrap_err"][10])
+    assert err < TOL64
+    rr = ratio.cpu().numpy()
+    assert np.abs(rr - r["ratios"][:10]).max() < 1e-9 * np.abs(r["ratios"][:10]).max()
+
+
+def test_c1_metropolis_decisions(gpu_lib):
+    """Without replay the GPU takes the same decisions from the same uniforms
+    (barring ties within rounding of the ratio)."""
+    say("c1 metropolis")
+    m, f, g0, r, u = oracle_run(3, -4.0, 2.0, 3)
+    t = torch()
+    ch = chain(3, -4.0, 2.0, delay_k=8, window=8)
+    ch.set_fields(dev(f))
+    acc = t.zeros(f.shape, dtype=t.uint8, device="cuda:0")
+    ratio = t.zeros(f.shape, dtype=t.float64, device="cuda:0")
+    ch.sweep(dev(u), None, acc, ratio, None)
+    ch.sync()
+    near = np.abs(u - r["ratios"]) < 1e-9 * np.maximum(1.0, r["ratios"])
+    assert not near.any()
+    assert np.array_equal(acc.cpu().numpy().astype(bool), r["accepted"])
+    assert np.abs(ch.G().cpu().numpy() - r["G"]).max() < TOL64
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed_f16", 1e-5), ("mixed_bf16", 1e-3)])
+def test_mixed_precision_error(gpu_lib, prec, tol):
+    """FP32 G and wrap with split FP16 / BF16 flushes vs the FP64 oracle."""
+    say("mixed", prec)
+    m, f, g0, r, u = oracle_run(6, -4.0, 2.0, 6)
+    ch = chain(6, -4.0, 2.0, delay_k=16, prec=prec)
+    gs, ratio, acc, errs = run_forced_sweep(ch, f, r)
+    worst = max(np.abs(a - b).max() for a, b in zip(gs, r["G_slices"]))
+    rerr = np.abs(ratio - r["ratios"]).max() / np.abs(r["ratios"]).max()
+    say(prec, "max|dG|", worst, "ratio rel err", rerr)
+    assert worst < tol
+    assert rerr < tol
+
+
+def test_fp64_deterministic(gpu_lib):
+    say("determinism")
+    m, f, g0, r, u = oracle_run(6, -4.0, 2.0, 6)
+    outs = []
+    for _ in range(2):
+        ch = chain(6, -4.0, 2.0, delay_k=16)
+        ch.set_fields(dev(f))
+        ch.sweep(dev(u), None, None, None, None)
+        outs.append(ch.G().cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_state_errors(gpu_lib):
+    from paper_2608_03894_amd import kdqmc
+    say("state errors")
+    ch = chain(3, -4.0, 2.0)
+    with pytest.raises(kdqmc.KdqmcError) as e:
+        ch.wrap_slice(1)
+    assert e.value.code == kdqmc.ESTATE
+    bad = np.ones((20, 27), dtype=np.int8)
+    bad[3, 4] = 0
+    with pytest.raises(kdqmc.KdqmcError) as e:
+        ch.set_fields(dev(bad))
+    assert e.value.code == kdqmc.EINVAL
+    ch.set_fields(dev(np.ones((20, 27), dtype=np.int8)))
+    with pytest.raises(kdqmc.KdqmcError) as e:
+        ch.wrap_slice(2)
+    assert e.value.code == kdqmc.ESTATE
+    ch.wrap_slice(1)
+    with pytest.raises(kdqmc.KdqmcError) as e:
+        ch.stabilize()
+    assert e.value.code == kdqmc.ESTATE
