@@ -69,7 +69,7 @@ k_gemm_f64(int M, int N, int K, double alpha, const double* __restrict__ A, int 
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = m0 + wr + 16 * bi + 4 * lk + j, cc = n0 + wc + 16 * bj + lr;
+        const int r = m0 + wr + 16 * bi + lk + 4 * j, cc = n0 + wc + 16 * bj + lr;
         if (r < M && cc < N) {
           double v = alpha * acc[bi][bj][j];
           if (beta != 0.0) v += beta * C[(size_t)r * ldc + cc];

@@ -219,7 +219,7 @@ __global__ void k_prep(const T* __restrict__ G, int N, const double* __restrict_
 // flush group (read on the device).  FP64: v_mfma_f64_16x16x4.
 // Tile 64 x 64 per workgroup (4 waves, each 32 x 32 = 2 x 2 MFMA blocks).
 // MFMA 16x16x4 f64 operand layout (lane l): A[l%16][l/16], B[l/16][l%16];
-// result element j of lane l is D[4*(l/16)+j][l%16].
+// result element j of lane l is D[l/16 + 4j][l%16] (checked on gfx950).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_flush_f64(double* __restrict__ G, int N, const double* __restrict__ Up,
@@ -238,7 +238,7 @@ k_flush_f64(double* __restrict__ G, int N, const double* __restrict__ Up,
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = row0 + 16 * bi + 4 * lk + j, cc = col0 + 16 * bj + lr;
+        const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
         acc[bi][bj][j] = (r < N && cc < N) ? G[(size_t)r * N + cc] : 0.0;
       }
   for (int k0 = 0; k0 < K; k0 += 4) {
@@ -263,7 +263,7 @@ k_flush_f64(double* __restrict__ G, int N, const double* __restrict__ Up,
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = row0 + 16 * bi + 4 * lk + j, cc = col0 + 16 * bj + lr;
+        const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
         if (r < N && cc < N) G[(size_t)r * N + cc] = acc[bi][bj][j];
       }
 }
@@ -272,7 +272,8 @@ k_flush_f64(double* __restrict__ G, int N, const double* __restrict__ Up,
 // (FP16 or BF16); U W ~= hi_u hi_w + 2^-S (hi_u lo_w + lo_u hi_w), the two
 // parts accumulated in FP32 by v_mfma_f32_16x16x32_{f16,bf16}.
 // MFMA 16x16x32 operand layout (lane l): A row l%16, k = 8*(l/16) .. +7;
-// B column l%16, same k; result as in the f64 kernel.
+// B column l%16, same k; result element j of lane l is D[4*(l/16)+j][l%16]
+// (checked on gfx950; note the different row order from the f64 MFMA).
 template <typename H>
 struct SplitTraits;
 template <>

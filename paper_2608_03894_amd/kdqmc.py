@@ -82,6 +82,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} not built: run __graft_entry__.build() or "
                            "python paper_2608_03894_amd/build.py")
+    # torch's HIP runtime must be in the process first: the library's
+    # dependency libamdhip64.so.7 then binds to that same runtime by soname,
+    # so device memory and streams from torch are valid in the library.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         f = getattr(lib, name)
