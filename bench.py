@@ -69,7 +69,7 @@ def main():
     ap.add_argument("--window", type=int, default=0)
     ap.add_argument("--fft-tile", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slices", type=int, default=40)
+    ap.add_argument("--cpu-slices", type=int, default=20)
     args = ap.parse_args()
 
     if args.gpus != 1:
