@@ -139,6 +139,13 @@ int kdqmc_stabilize(kdqmc_ctx* c, double* wrap_err_dev);
 int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev,
                 uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev);
 
+/* Graph mode (default on): kdqmc_sweep captures its whole launch sequence
+ * once per distinct set of pointer arguments into a HIP graph (on a
+ * non-blocking stream the context creates) and replays it on the context's
+ * stream; results are identical to the eager launches.  on = 0 launches
+ * every kernel directly. */
+int kdqmc_use_graphs(kdqmc_ctx* c, int on);
+
 /* Copies G(current slice) to G_dev (FP64, N x N row-major, site order above). */
 int kdqmc_measure_G(kdqmc_ctx* c, double* G_dev);
 

@@ -160,21 +160,35 @@ int check_ctx(const kdqmc_ctx* c) {
 
 int prof_mark(kdqmc_ctx* c) {
   if (!c->prof_on) return -1;
-  if (c->prof_next == (int)c->prof_events.size()) {
+  std::vector<hipEvent_t>& pool = c->capturing ? c->graph_events : c->prof_events;
+  int& next = c->capturing ? c->graph_next : c->prof_next;
+  if (next == (int)pool.size()) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return -1;
-    c->prof_events.push_back(e);
+    pool.push_back(e);
   }
-  const int i = c->prof_next++;
-  if (hipEventRecord(c->prof_events[i], c->stream) != hipSuccess) return -1;
+  const int i = next++;
+  if (hipEventRecord(pool[i], c->stream) != hipSuccess) return -1;
   return i;
 }
 
 void prof_pair(kdqmc_ctx* c, int phase, int e0, int e1) {
   if (!c->prof_on || e0 < 0 || e1 < 0) return;
-  c->prof_triples.push_back(phase);
-  c->prof_triples.push_back(e0);
-  c->prof_triples.push_back(e1);
+  std::vector<int>& t = c->capturing ? c->graph_triples : c->prof_triples;
+  t.push_back(phase);
+  t.push_back(e0);
+  t.push_back(e1);
+}
+
+// Adds the elapsed times of recorded (phase, e0, e1) triples to the accumulators.
+static int prof_accumulate(kdqmc_ctx* c, const std::vector<hipEvent_t>& pool, const std::vector<int>& t) {
+  for (size_t q = 0; q + 2 < t.size(); q += 3) {
+    float ms = 0.0f;
+    KDQMC_HIP(hipEventElapsedTime(&ms, pool[t[q + 1]], pool[t[q + 2]]));
+    c->prof_acc_ms[t[q]] += ms;
+    c->prof_acc_n[t[q]] += 1;
+  }
+  return KDQMC_OK;
 }
 
 int set_error(int code, const std::string& msg) {
@@ -207,6 +221,8 @@ int kdqmc_init_lattice(kdqmc_ctx** out, const kdqmc_params* p, void* workspace_d
   const size_t need = carve(p, d, nullptr, nullptr);
   if (workspace_bytes < need)
     return set_error(KDQMC_ENOSPACE, "workspace smaller than kdqmc_workspace_bytes()");
+  KDQMC_TRY(prepare_kinetic(p->L));
+  KDQMC_TRY(prepare_updates());
   kdqmc_ctx* c = new kdqmc_ctx();
   c->p = *p;
   c->N = d.N;
@@ -354,11 +370,8 @@ static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev) {
   return KDQMC_OK;
 }
 
-int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, uint8_t* accepted_dev,
-                double* ratio_dev, double* wrap_err_dev) {
-  KDQMC_TRY(check_ctx(c));
-  if (c->l_cur != 0) return set_error(KDQMC_ESTATE, "sweep needs the current slice to be 0");
-  if (!c->stacks_valid) return set_error(KDQMC_ESTATE, "stacks not built (call set_fields)");
+static int sweep_eager(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev,
+                       uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev) {
   const size_t N = c->N;
   for (int l = 1; l <= c->Ltau; ++l) {
     const size_t o = (size_t)(l - 1) * N;
@@ -366,6 +379,67 @@ int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, ui
                                 accepted_dev ? accepted_dev + o : nullptr, ratio_dev ? ratio_dev + o : nullptr));
     if (l % c->p.n_stab == 0)
       KDQMC_TRY(kdqmc_stabilize(c, wrap_err_dev ? wrap_err_dev + (l / c->p.n_stab - 1) : nullptr));
+  }
+  return KDQMC_OK;
+}
+
+int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, uint8_t* accepted_dev,
+                double* ratio_dev, double* wrap_err_dev) {
+  KDQMC_TRY(check_ctx(c));
+  if (c->l_cur != 0) return set_error(KDQMC_ESTATE, "sweep needs the current slice to be 0");
+  if (!c->stacks_valid) return set_error(KDQMC_ESTATE, "stacks not built (call set_fields)");
+  if (!u_dev && !forced_dev) return set_error(KDQMC_EINVAL, "need uniforms or forced decisions");
+  if (!c->use_graphs) return sweep_eager(c, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
+  const void* key[6] = {u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev,
+                        c->prof_on ? (const void*)c : nullptr};
+  bool same = c->sweep_exec != nullptr;
+  for (int i = 0; i < 6 && same; ++i) same = (key[i] == c->sweep_key[i]);
+  if (!same) {
+    if (c->sweep_exec) {
+      (void)hipGraphExecDestroy(c->sweep_exec);
+      c->sweep_exec = nullptr;
+    }
+    if (!c->cap_stream) KDQMC_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    c->graph_next = 0;
+    c->graph_triples.clear();
+    hipStream_t user = c->stream;
+    KDQMC_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    c->stream = c->cap_stream;
+    c->capturing = true;
+    const int rc = sweep_eager(c, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
+    c->capturing = false;
+    c->stream = user;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+    if (rc != KDQMC_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      c->l_cur = 0;
+      return rc;
+    }
+    if (ec != hipSuccess) return set_error(KDQMC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&c->sweep_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      c->sweep_exec = nullptr;
+      return set_error(KDQMC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    for (int i = 0; i < 6; ++i) c->sweep_key[i] = key[i];
+  }
+  KDQMC_HIP(hipGraphLaunch(c->sweep_exec, c->stream));
+  c->l_cur = 0;  // a whole sweep ends at slice 0 (stabilized G(L_tau) = G(0))
+  if (c->prof_on) {
+    KDQMC_HIP(hipStreamSynchronize(c->stream));
+    KDQMC_TRY(prof_accumulate(c, c->graph_events, c->graph_triples));
+  }
+  return KDQMC_OK;
+}
+
+int kdqmc_use_graphs(kdqmc_ctx* c, int on) {
+  KDQMC_TRY(check_ctx(c));
+  c->use_graphs = (on != 0);
+  if (!c->use_graphs && c->sweep_exec) {
+    (void)hipGraphExecDestroy(c->sweep_exec);
+    c->sweep_exec = nullptr;
   }
   return KDQMC_OK;
 }
@@ -390,7 +464,10 @@ int kdqmc_sync(kdqmc_ctx* c) {
 
 void kdqmc_destroy(kdqmc_ctx* c) {
   if (!c) return;
+  if (c->sweep_exec) (void)hipGraphExecDestroy(c->sweep_exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->graph_events) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -399,6 +476,10 @@ int kdqmc_profile_enable(kdqmc_ctx* c, int on) {
   c->prof_on = (on != 0);
   c->prof_next = 0;
   c->prof_triples.clear();
+  for (int i = 0; i < 16; ++i) {
+    c->prof_acc_ms[i] = 0.0;
+    c->prof_acc_n[i] = 0;
+  }
   return KDQMC_OK;
 }
 
@@ -410,12 +491,12 @@ int kdqmc_profile_read(kdqmc_ctx* c, double* ms, int* launches) {
     launches[i] = 0;
   }
   KDQMC_HIP(hipStreamSynchronize(c->stream));
-  for (size_t q = 0; q + 2 < c->prof_triples.size(); q += 3) {
-    float t = 0.0f;
-    KDQMC_HIP(hipEventElapsedTime(&t, c->prof_events[c->prof_triples[q + 1]],
-                                  c->prof_events[c->prof_triples[q + 2]]));
-    ms[c->prof_triples[q]] += t;
-    launches[c->prof_triples[q]] += 1;
+  KDQMC_TRY(prof_accumulate(c, c->prof_events, c->prof_triples));
+  for (int i = 0; i < KDQMC_NPHASE; ++i) {
+    ms[i] = c->prof_acc_ms[i];
+    launches[i] = c->prof_acc_n[i];
+    c->prof_acc_ms[i] = 0.0;
+    c->prof_acc_n[i] = 0;
   }
   c->prof_next = 0;
   c->prof_triples.clear();

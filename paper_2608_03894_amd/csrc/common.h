@@ -124,6 +124,17 @@ struct kdqmc_ctx {
   std::vector<hipEvent_t> prof_events;
   int prof_next = 0;
   std::vector<int> prof_triples;
+  // hipGraph of a whole sweep: captured on cap_stream, replayed on stream
+  bool use_graphs = true;
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t sweep_exec = nullptr;
+  const void* sweep_key[6] = {nullptr};
+  std::vector<hipEvent_t> graph_events;   // events that are nodes of the captured graph
+  int graph_next = 0;
+  std::vector<int> graph_triples;
+  double prof_acc_ms[16] = {0};
+  int prof_acc_n[16] = {0};
   int N = 0, L = 0, Ltau = 0, nc = 0;     // sites, cells/side, slices, stack checkpoints
   int w = 0, nw = 0, F = 0;               // window size, windows per slice, windows per flush
   int P = 0;                              // complex vectors per wrap workgroup (storage type)
@@ -192,6 +203,8 @@ int launch_kinetic_f64(kdqmc_ctx* c, double* A, int lda, bool cols, const double
 int launch_kinetic_f32(kdqmc_ctx* c, float* A, int lda, bool cols, const float* tab,
                        const double* pre_e, const double* pre_v, const double* post_e);
 
+int prepare_kinetic(int L);
+int prepare_updates();
 int launch_frame_scale(kdqmc_ctx* c, int l);
 int run_slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, uint8_t* acc,
                       double* ratio);
@@ -208,6 +221,9 @@ int stab_right_step(kdqmc_ctx* c, int j);           // right stack entry j from 
 int copy_G_to64(kdqmc_ctx* c, double* out);
 int copy_64_to_G(kdqmc_ctx* c, const double* in);
 int max_abs_diff(kdqmc_ctx* c, const double* a, int n, double* out);  // max |G - a|
+
+// Device-to-device copy of n doubles as a kernel (graph-capture friendly).
+int copy_f64(kdqmc_ctx* c, double* dst, const double* src, size_t n);
 
 // Profiler: prof_mark records an event on the stream (returns its index, or
 // -1 when profiling is off); prof_pair attributes the interval to a phase.

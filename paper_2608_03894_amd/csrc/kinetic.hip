@@ -287,12 +287,6 @@ int launch_L(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double*
   threads = ((threads + 63) / 64) * 64;
   if (threads > 512) threads = 512;
   if (threads < 64) threads = 64;
-  static bool attr_set[2] = {false, false};
-  if (!attr_set[cols]) {
-    KDQMC_HIP(hipFuncSetAttribute((const void*)k_kinetic<T, L, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    KDQMC_HIP(hipFuncSetAttribute((const void*)k_kinetic<T, L, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    attr_set[0] = attr_set[1] = true;
-  }
   const int e0 = prof_mark(c);
   if (cols)
     hipLaunchKernelGGL((k_kinetic<T, L, true>), dim3(grid), dim3(threads), lds, c->stream, A, lda, P, tab, pre_e, pre_v, post_e);
@@ -301,6 +295,27 @@ int launch_L(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double*
   prof_pair(c, (sizeof(T) == 8 && tab == (const T*)c->tab_mu64) ? PH_BMUL : (cols ? PH_WRAP_COLS : PH_WRAP_ROWS), e0, prof_mark(c));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
+}
+
+template <typename T, int L>
+int prepare_L() {
+  KDQMC_HIP(hipFuncSetAttribute((const void*)k_kinetic<T, L, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  KDQMC_HIP(hipFuncSetAttribute((const void*)k_kinetic<T, L, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  return KDQMC_OK;
+}
+
+template <typename T>
+int prepare_any(int L) {
+  switch (L) {
+    case 3: return prepare_L<T, 3>();
+    case 6: return prepare_L<T, 6>();
+    case 9: return prepare_L<T, 9>();
+    case 12: return prepare_L<T, 12>();
+    case 15: return prepare_L<T, 15>();
+    case 18: return prepare_L<T, 18>();
+    case 24: return prepare_L<T, 24>();
+    default: return set_error(KDQMC_EUNSUPPORTED, "lattice size not compiled in");
+  }
 }
 
 template <typename T>
@@ -319,6 +334,13 @@ int launch_any(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const doubl
 }
 
 }  // namespace
+
+// Raises the dynamic-LDS limit of the kinetic kernels of this lattice size
+// (done once at context creation, outside any graph capture).
+int prepare_kinetic(int L) {
+  KDQMC_TRY(prepare_any<double>(L));
+  return prepare_any<float>(L);
+}
 
 int launch_kinetic_f64(kdqmc_ctx* c, double* A, int lda, bool cols, const double* tab,
                        const double* pre_e, const double* pre_v, const double* post_e) {

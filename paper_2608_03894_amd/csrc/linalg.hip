@@ -385,7 +385,7 @@ int trsm_upper_f64(kdqmc_ctx* c, int n, const double* R, double* X) {
     KDQMC_TRY(gemm_f64(c, false, false, nbp, n, nbp, 1.0, Rinv + (size_t)b * nb * nb, nb,
                        X + (size_t)b0 * ld, ld, 0.0, Y + (size_t)b0 * ld, ld));
   }
-  KDQMC_HIP(hipMemcpyAsync(X, Y, sizeof(double) * (size_t)n * ld, hipMemcpyDeviceToDevice, c->stream));
+  KDQMC_TRY(copy_f64(c, X, Y, (size_t)n * ld));
   return KDQMC_OK;
 }
 

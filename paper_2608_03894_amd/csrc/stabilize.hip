@@ -160,6 +160,17 @@ __global__ void k_convert(TO* __restrict__ dst, const TI* __restrict__ src, size
   if (idx < count) dst[idx] = TO(src[idx]);
 }
 
+__global__ void k_copy_f64(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+int copy_f64(kdqmc_ctx* c, double* dst, const double* src, size_t n) {
+  hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, dst, src, n);
+  KDQMC_HIP(hipGetLastError());
+  return KDQMC_OK;
+}
+
 namespace {
 
 inline dim3 grid_for(size_t count) { return dim3((unsigned)((count + 255) / 256)); }
@@ -178,7 +189,7 @@ int udt_step(kdqmc_ctx* c, const double* Uin, const double* Din, const double* T
   double* Cp = c->S[1];
   double* Tp = c->S[3];
   double* evs = c->nrm + n;  // second half of the norm buffer holds the slice scale
-  KDQMC_HIP(hipMemcpyAsync(C, Uin, nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  KDQMC_TRY(copy_f64(c, C, Uin, nn));
   const double ea = std::exp(c->alpha), eainv = std::exp(-c->alpha);
   for (int q = 0; q < nsl; ++q) {
     const int l = slices[q];
@@ -265,7 +276,7 @@ int stab_green(kdqmc_ctx* c, int j, double* out) {
 int copy_G_to64(kdqmc_ctx* c, double* out) {
   const size_t nn = (size_t)c->N * c->N;
   if (c->fp64) {
-    KDQMC_HIP(hipMemcpyAsync(out, c->G, nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    KDQMC_TRY(copy_f64(c, out, (const double*)c->G, nn));
   } else {
     hipLaunchKernelGGL((k_convert<double, float>), grid_for(nn), dim3(256), 0, c->stream, out,
                        (const float*)c->G, nn);
@@ -278,7 +289,7 @@ int copy_64_to_G(kdqmc_ctx* c, const double* in) {
   const size_t nn = (size_t)c->N * c->N;
   if (c->fp64) {
     if (in != c->G)
-      KDQMC_HIP(hipMemcpyAsync(c->G, in, nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      KDQMC_TRY(copy_f64(c, (double*)c->G, in, nn));
   } else {
     hipLaunchKernelGGL((k_convert<float, double>), grid_for(nn), dim3(256), 0, c->stream,
                        (float*)c->G, in, nn);

@@ -363,19 +363,14 @@ namespace {
 
 template <typename T>
 int set_lds_limits() {
-  static bool done = false;
-  if (!done) {
-    KDQMC_HIP(hipFuncSetAttribute((const void*)k_decide<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    KDQMC_HIP(hipFuncSetAttribute((const void*)k_extend<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    done = true;
-  }
+  KDQMC_HIP(hipFuncSetAttribute((const void*)k_decide<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  KDQMC_HIP(hipFuncSetAttribute((const void*)k_extend<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   return KDQMC_OK;
 }
 
 template <typename T>
 int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, uint8_t* acc,
                   double* ratio) {
-  KDQMC_TRY(set_lds_limits<T>());
   const int N = c->N, W = c->w;
   T* G = static_cast<T*>(c->G);
   T* Up = static_cast<T*>(c->Upend);
@@ -434,6 +429,11 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
 }
 
 }  // namespace
+
+int prepare_updates() {
+  KDQMC_TRY(set_lds_limits<double>());
+  return set_lds_limits<float>();
+}
 
 int launch_frame_scale(kdqmc_ctx* c, int l) {
   const double ea = std::exp(c->alpha), eainv = std::exp(-c->alpha);

@@ -69,6 +69,7 @@ _SIGS = {
     "kdqmc_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int)]),
     "kdqmc_phase_name": (ctypes.c_char_p, [ctypes.c_int]),
+    "kdqmc_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
 }
 
 NPHASE = 10
@@ -197,6 +198,9 @@ class Chain:
 
     def qr_f64(self, n, A, Q):
         _check(self.lib.kdqmc_qr_f64(self.ctx, n, _ptr(A), _ptr(Q)))
+
+    def use_graphs(self, on=True):
+        _check(self.lib.kdqmc_use_graphs(self.ctx, 1 if on else 0))
 
     def profile_enable(self, on=True):
         _check(self.lib.kdqmc_profile_enable(self.ctx, 1 if on else 0))
