@@ -60,8 +60,10 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
   double* Z = Gs + wn * ldg;                          // wn * wn, Z[n'][n] at n'*wn + n
   double* Zp = Z + wn * wn;                           // Zp[n][n'] at n*wn + n'
   double* cl = Zp + wn * wn;                          // wn: c of accept n
-  int* pl = reinterpret_cast<int*>(cl + wn);          // wn: window position of accept n
+  double* ul = cl + wn;                               // wn: uniforms of the window
+  int* pl = reinterpret_cast<int*>(ul + wn);          // wn: window position of accept n
   int8_t* sl = reinterpret_cast<int8_t*>(pl + wn);    // wn: fields of the window
+  uint8_t* fl = reinterpret_cast<uint8_t*>(sl + wn);  // wn: forced decisions
   const int tid = threadIdx.x, nth = blockDim.x;
 
   for (int idx = tid; idx < wn * wn; idx += nth) {
@@ -77,7 +79,11 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     Z[idx] = 0.0;
     Zp[idx] = 0.0;
   }
-  for (int p = tid; p < wn; p += nth) sl[p] = s_l[w0 + p];
+  for (int p = tid; p < wn; p += nth) {
+    sl[p] = s_l[w0 + p];
+    ul[p] = u ? u[w0 + p] : 0.0;
+    fl[p] = forced ? forced[w0 + p] : 0;
+  }
   __syncthreads();
 
   int na = 0;
@@ -88,7 +94,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     const double e2as = s > 0 ? ep2a : em2a;
     const double R = 1.0 + delta * (1.0 - gpp);
     const double ratio = e2as * R * R;
-    const bool a = forced ? (forced[w0 + p] != 0) : (u[w0 + p] < ratio);
+    const bool a = forced ? (fl[p] != 0) : (ul[p] < ratio);
     if (tid == 0) {
       if (ratio_out) ratio_out[w0 + p] = ratio;
       if (acc_out) acc_out[w0 + p] = a ? 1 : 0;
@@ -384,8 +390,8 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
     const int grp0 = (win / c->F) * c->F;
     const bool first_in_group = (win == grp0);
     // decide
-    const size_t lds_d = size_t(wn) * (wn + 1) * 8 + 2 * size_t(wn) * wn * 8 + size_t(wn) * 8 +
-                         size_t(wn) * 4 + size_t(wn) + 16;
+    const size_t lds_d = size_t(wn) * (wn + 1) * 8 + 2 * size_t(wn) * wn * 8 + 2 * size_t(wn) * 8 +
+                         size_t(wn) * 4 + 2 * size_t(wn) + 16;
     const int e_d = prof_mark(c);
     hipLaunchKernelGGL(k_decide<T>, dim3(1), dim3(256), lds_d, c->stream, G, N, c->ev, c->evinv,
                        s_l, u ? u + 0 : nullptr, forced, acc, ratio, w0, wn, W,
