@@ -1,0 +1,91 @@
+"""Autotuner for the delay rank k (with its decision window) and the FFT tile.
+
+For one workload (L, U, beta, precision) it times whole sweeps through the C
+ABI for every candidate (delay_k, window) and FFT tile, and keeps the fastest.
+Candidates whose parameters the library rejects are skipped.  Results are
+cached in a JSON file keyed by the workload, so later runs reuse the choice.
+The tuned knobs change only the schedule (flush grouping, window size, tile
+width), never the result beyond rounding order.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import kdqmc
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+
+# (delay_k, window) pairs: k is the largest flush rank, window the sites per
+# decision window (flush every k // window windows).
+DELAY_CANDIDATES = [(8, 8), (16, 16), (32, 32), (32, 16), (64, 32), (64, 64), (128, 32), (128, 64)]
+TILE_CANDIDATES = [0, 1, 2, 3, 4, 6, 8]
+
+
+def _key(L, U, beta, dtau, prec, n_stab):
+    return f"L{L}_U{U:g}_b{beta:g}_d{dtau:g}_{prec}_s{n_stab}"
+
+
+def _time_sweeps(params, fields, uni, sweeps, device):
+    import torch
+    ch = kdqmc.Chain(params, device=device)
+    try:
+        ch.set_fields(fields)
+        ch.sweep(uni[0])           # capture + first replay (not timed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(sweeps):
+            ch.sweep(uni[1 + s])
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / sweeps
+    finally:
+        ch.close()
+
+
+def autotune(L, U, beta, dtau=0.1, prec="fp64", n_stab=10, seed=0, sweeps=2, device="cuda:0",
+             cache=DEFAULT_CACHE, refresh=False, log=None):
+    """Returns {"delay_k", "window", "fft_tile", "sec_per_sweep"} for the workload."""
+    import torch
+
+    import seeded_inputs as si
+
+    key = _key(L, U, beta, dtau, prec, n_stab)
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as fh:
+            table = json.load(fh)
+    if key in table and not refresh:
+        return table[key]
+    L_tau = si.l_tau(beta, dtau)
+    fields = torch.from_numpy(si.ising_fields(L, L_tau, seed)).to(device)
+    uni = torch.from_numpy(si.metropolis_uniforms(L, L_tau, seed, n_sweeps=1 + sweeps)).to(device)
+    best = None
+    # stage 1: delay rank and window at the automatic tile
+    for k, w in DELAY_CANDIDATES:
+        p = kdqmc.make_params(L, U, beta, dtau, n_stab=n_stab, delay_k=k, window=w, prec=prec)
+        if kdqmc.workspace_bytes(p) == 0:
+            continue
+        t = _time_sweeps(p, fields, uni, sweeps, device)
+        if log:
+            log(f"autotune {key}: k={k} window={w} -> {1e3 * t:.2f} ms/sweep")
+        if best is None or t < best["sec_per_sweep"]:
+            best = {"delay_k": k, "window": w, "fft_tile": 0, "sec_per_sweep": t}
+    # stage 2: FFT tile at the chosen delay
+    for tile in TILE_CANDIDATES[1:]:
+        p = kdqmc.make_params(L, U, beta, dtau, n_stab=n_stab, delay_k=best["delay_k"],
+                              window=best["window"], fft_tile=tile, prec=prec)
+        if kdqmc.workspace_bytes(p) == 0:
+            continue
+        t = _time_sweeps(p, fields, uni, sweeps, device)
+        if log:
+            log(f"autotune {key}: fft_tile={tile} -> {1e3 * t:.2f} ms/sweep")
+        if t < best["sec_per_sweep"]:
+            best = dict(best, fft_tile=tile, sec_per_sweep=t)
+    if cache:
+        table[key] = best
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return best

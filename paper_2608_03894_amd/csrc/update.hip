@@ -39,11 +39,17 @@ __global__ void k_frame_scale(const int8_t* __restrict__ s, int n, double ea, do
 
 // ---------------------------------------------------------------------------
 // Sequential decisions of one window (single workgroup).
-// LDS: Gs[w][w+1] (window submatrix, tilde frame), Z[w][w], Zp[w][w].
-// Invariant after the accept at window position p: entries (x, y) with
-// x, y > p are current; row p and column p keep the values they had when p
-// was decided, which are exactly the coefficients the recursions for Z and
-// Z' need later (rows/columns of earlier accepts are never written again).
+// LDS: Gs[w][w+1] (window submatrix, tilde frame) and two coefficient blocks
+// Cf[w][w+1], Cr[w][w+1].  After the accepts so far,
+//   G~cur[:, y] = G0[:, y] + sum_q G0[:, i_q] Cf[q][y]   (columns y of the window)
+//   G~cur[x, :] = G0[x, :] + sum_q Cr[x][q] h_q           (rows x of the window)
+// with G0 the window-start matrix and h_q = e_{i_q} - G0[i_q, :].  The accept
+// number n at window position p (c = Delta/R) therefore has the factors
+//   u_n = sum_q G0[:, i_q] Z[q][n],  Z[q][n] = -c (delta_qn + Cf[q][p]),
+//   w_n = sum_q Z'[n][q] h_q,        Z'[n][q] = delta_nq - Cr[p][q],
+// and Cf, Cr, Gs receive rank-one updates on their live part (indices > p).
+// Row p and column p of all three blocks are never written again, so every
+// update reads only frozen values and one barrier per accept suffices.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -55,12 +61,11 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
          int* __restrict__ win_a, int* __restrict__ win_p, double* __restrict__ Zg,
          double* __restrict__ Zpg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int ldg = wn + 1;
-  double* Gs = reinterpret_cast<double*>(smem_raw);  // wn * ldg
-  double* Z = Gs + wn * ldg;                          // wn * wn, Z[n'][n] at n'*wn + n
-  double* Zp = Z + wn * wn;                           // Zp[n][n'] at n*wn + n'
-  double* cl = Zp + wn * wn;                          // wn: c of accept n
-  double* ul = cl + wn;                               // wn: uniforms of the window
+  const int ld = wn + 1;
+  double* Gs = reinterpret_cast<double*>(smem_raw);  // wn * ld
+  double* Cf = Gs + wn * ld;                          // wn * ld, Cf[q][y] at q*ld + y
+  double* Cr = Cf + wn * ld;                          // wn * ld, Cr[x][q] at x*ld + q
+  double* ul = Cr + wn * ld;                          // wn: uniforms of the window
   int* pl = reinterpret_cast<int*>(ul + wn);          // wn: window position of accept n
   int8_t* sl = reinterpret_cast<int8_t*>(pl + wn);    // wn: fields of the window
   uint8_t* fl = reinterpret_cast<uint8_t*>(sl + wn);  // wn: forced decisions
@@ -75,9 +80,9 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
       const int gx = w0 + x, gy = w0 + y;
       g = double(G[(size_t)gx * N + gy]) * ev[gx] * evinv[gy];
     }
-    Gs[x * ldg + y] = g;
-    Z[idx] = 0.0;
-    Zp[idx] = 0.0;
+    Gs[x * ld + y] = g;
+    Cf[x * ld + y] = 0.0;
+    Cr[x * ld + y] = 0.0;
   }
   for (int p = tid; p < wn; p += nth) {
     sl[p] = s_l[w0 + p];
@@ -89,7 +94,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
   int na = 0;
   for (int p = 0; p < wn; ++p) {
     const int s = sl[p];
-    const double gpp = Gs[p * ldg + p];
+    const double gpp = Gs[p * ld + p];
     const double delta = (s > 0 ? em2a : ep2a) - 1.0;
     const double e2as = s > 0 ? ep2a : em2a;
     const double R = 1.0 + delta * (1.0 - gpp);
@@ -104,39 +109,37 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     const int n = na;
     if (tid == 0) {
       s_l[w0 + p] = int8_t(-s);
-      cl[n] = c;
       pl[n] = p;
     }
-    // Z[:, n] and Z'[n, :] from the frozen rows/columns of earlier accepts:
-    //   Z[q][n]  = -c (delta_qn + sum_{q<=m<n} Z[q][m] X[m][n]),  X[m][n] = -Gs[p_m][p]
-    //   Z'[n][q] = delta_nq - sum_{q<=m<n} Y[m][n] Z'[m][q],       Y[m][n] = -c_m Gs[p][p_m]
+    // the accept's triangular factor entries (published for k_extend)
     for (int q = tid; q <= n; q += nth) {
-      double zs = (q == n) ? 1.0 : 0.0;
-      double zp = (q == n) ? 1.0 : 0.0;
-      for (int m = q; m < n; ++m) {
-        const int pm = pl[m];
-        zs += Z[q * wn + m] * (-Gs[pm * ldg + p]);
-        zp -= (-cl[m] * Gs[p * ldg + pm]) * Zp[m * wn + q];
-      }
-      Z[q * wn + n] = -c * zs;
-      Zp[n * wn + q] = zp;
+      Zg[q * W + n] = -c * ((q == n ? 1.0 : 0.0) + Cf[q * ld + p]);
+      Zpg[n * W + q] = (q == n ? 1.0 : 0.0) - Cr[p * ld + q];
     }
-    // rank-one update of the live part: Gs[x][y] += c Gs[x][p] Gs[p][y], x, y > p
+    // live part: y > p (columns of Cf and Gs), x > p (rows of Cr and Gs)
     const int rem = wn - p - 1;
+    const int na1 = n + 1;
+    // Cf[q][y] += Z[q][n] * w_n[y],  w_n[y] = -Gs[p][y]
+    for (int idx = tid; idx < na1 * rem; idx += nth) {
+      const int q = idx / rem, y = p + 1 + idx % rem;
+      const double z = -c * ((q == n ? 1.0 : 0.0) + Cf[q * ld + p]);
+      Cf[q * ld + y] -= z * Gs[p * ld + y];
+    }
+    // Cr[x][q] += u_n[x] * Z'[n][q],  u_n[x] = -c Gs[x][p]
+    for (int idx = tid; idx < rem * na1; idx += nth) {
+      const int x = p + 1 + idx / na1, q = idx % na1;
+      const double zp = (q == n ? 1.0 : 0.0) - Cr[p * ld + q];
+      Cr[x * ld + q] -= c * Gs[x * ld + p] * zp;
+    }
+    // Gs[x][y] += u_n[x] w_n[y] = c Gs[x][p] Gs[p][y]
     for (int idx = tid; idx < rem * rem; idx += nth) {
       const int x = p + 1 + idx / rem, y = p + 1 + idx % rem;
-      Gs[x * ldg + y] += c * Gs[x * ldg + p] * Gs[p * ldg + y];
+      Gs[x * ld + y] += c * Gs[x * ld + p] * Gs[p * ld + y];
     }
     ++na;
     __syncthreads();
   }
-  // publish the window's result
   if (tid == 0) win_a[win] = na;
-  for (int idx = tid; idx < na * na; idx += nth) {
-    const int q = idx / na, n = idx % na;
-    Zg[q * W + n] = Z[q * wn + n];
-    Zpg[q * W + n] = Zp[q * wn + n];
-  }
   for (int n = tid; n < na; n += nth) win_p[win * W + n] = pl[n];
 }
 
@@ -390,8 +393,8 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
     const int grp0 = (win / c->F) * c->F;
     const bool first_in_group = (win == grp0);
     // decide
-    const size_t lds_d = size_t(wn) * (wn + 1) * 8 + 2 * size_t(wn) * wn * 8 + 2 * size_t(wn) * 8 +
-                         size_t(wn) * 4 + 2 * size_t(wn) + 16;
+    const size_t lds_d = 3 * size_t(wn) * (wn + 1) * 8 + size_t(wn) * 8 + size_t(wn) * 4 +
+                         2 * size_t(wn) + 16;
     const int e_d = prof_mark(c);
     hipLaunchKernelGGL(k_decide<T>, dim3(1), dim3(256), lds_d, c->stream, G, N, c->ev, c->evinv,
                        s_l, u ? u + 0 : nullptr, forced, acc, ratio, w0, wn, W,
