@@ -101,21 +101,34 @@ def main():
         log(f"warmup sweep {s + 1}/{args.warmup} done")
     torch.cuda.synchronize()
 
-    ch.profile_enable(True)
-    accepts = 0
+    # timed region: K sweeps replayed from the captured HIP graph
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         ch.sweep(uni[args.warmup + s], None, acc, None, errs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = ch.profile_read()
-    ch.profile_enable(False)
     accepts = int(acc.sum().item())  # last sweep's accepts
     wrap_err = float(errs.max().item())
     elapsed = t1 - t0
     value = args.steps / elapsed
     log(f"timed {args.steps} sweeps in {elapsed:.3f} s -> {value:.3f} sweeps/s")
+
+    # the same K sweeps again with a HIP event around every kernel launch
+    # (direct launches: events inside a graph are not timed)
+    ch.set_fields(fields)
+    for s in range(args.warmup):
+        ch.sweep(uni[s], None, acc, None, errs)
+    ch.profile_enable(True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for s in range(args.steps):
+        ch.sweep(uni[args.warmup + s], None, acc, None, errs)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    prof = ch.profile_read()
+    ch.profile_enable(False)
+    log(f"profiled (direct launches) {args.steps} sweeps in {t3 - t2:.3f} s")
     for name, (ms, n) in prof.items():
         if n:
             log(f"  {name:10s} {ms:10.3f} ms  {n:7d} launches  {1000 * ms / n:9.2f} us/launch")
@@ -172,6 +185,7 @@ def main():
                    "field_updates_per_s": value * N * Lt},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "profiled_ms_per_step": 1000.0 * (t3 - t2) / args.steps,
         "phases_ms_per_sweep": {n: round(v[0] / args.steps, 4) for n, v in prof.items() if v[1]},
         "launches_per_sweep": {n: v[1] // args.steps for n, v in prof.items() if v[1]},
         "acceptance": accepts / (N * Lt),

@@ -143,7 +143,8 @@ int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev,
  * once per distinct set of pointer arguments into a HIP graph (on a
  * non-blocking stream the context creates) and replays it on the context's
  * stream; results are identical to the eager launches.  on = 0 launches
- * every kernel directly. */
+ * every kernel directly; while profiling is enabled sweeps also launch
+ * directly (events inside a graph are not timed). */
 int kdqmc_use_graphs(kdqmc_ctx* c, int on);
 
 /* Copies G(current slice) to G_dev (FP64, N x N row-major, site order above). */

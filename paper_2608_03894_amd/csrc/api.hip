@@ -389,9 +389,10 @@ int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, ui
   if (c->l_cur != 0) return set_error(KDQMC_ESTATE, "sweep needs the current slice to be 0");
   if (!c->stacks_valid) return set_error(KDQMC_ESTATE, "stacks not built (call set_fields)");
   if (!u_dev && !forced_dev) return set_error(KDQMC_EINVAL, "need uniforms or forced decisions");
-  if (!c->use_graphs) return sweep_eager(c, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
-  const void* key[6] = {u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev,
-                        c->prof_on ? (const void*)c : nullptr};
+  // events recorded inside a captured graph cannot be timed: profiling runs eager
+  if (!c->use_graphs || c->prof_on)
+    return sweep_eager(c, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
+  const void* key[6] = {u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev, nullptr};
   bool same = c->sweep_exec != nullptr;
   for (int i = 0; i < 6 && same; ++i) same = (key[i] == c->sweep_key[i]);
   if (!same) {
@@ -427,10 +428,6 @@ int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, ui
   }
   KDQMC_HIP(hipGraphLaunch(c->sweep_exec, c->stream));
   c->l_cur = 0;  // a whole sweep ends at slice 0 (stabilized G(L_tau) = G(0))
-  if (c->prof_on) {
-    KDQMC_HIP(hipStreamSynchronize(c->stream));
-    KDQMC_TRY(prof_accumulate(c, c->graph_events, c->graph_triples));
-  }
   return KDQMC_OK;
 }
 
