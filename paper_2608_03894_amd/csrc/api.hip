@@ -105,7 +105,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   char* S[8];
   for (int i = 0; i < 8; ++i) S[i] = take(nn * 8);
   char* Vq = take(nn * 8);
-  char* Tq = take((N / nb + 2) * nb * nb * 8);
+  char* Tq = take((N / nb + 2) * 32 * 32 * 8);
   char* Wq = take(2 * nb * N * 8);
   char* tau = take(N * 8);
   char* nrm = take(2 * N * 8);

@@ -175,7 +175,10 @@ struct kdqmc_ctx {
   // linear-algebra scratch (N*N each unless noted)
   double* S[8] = {nullptr};
   double* Vq = nullptr;        // N*N explicit Householder vectors
-  double* Tq = nullptr;        // (N/nb+1)*nb*nb block-reflector factors
+  double* Tq = nullptr;        // per-panel 32 x 32 block-reflector factors
+  int qr_npan = 0;             // panels of the last QR (start column, width)
+  int qr_panel_start[160] = {0};
+  int qr_panel_width[160] = {0};
   double* Wq = nullptr;        // nb*N
   double* tau = nullptr;       // N
   double* nrm = nullptr;       // N
@@ -212,6 +215,7 @@ int run_slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* force
 int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
              int lda, const double* B, int ldb, double beta, double* C, int ldc);
 int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q);
+int apply_qt_f64(kdqmc_ctx* c, int n, double* X);
 int trsm_upper_f64(kdqmc_ctx* c, int n, const double* R, double* X);
 
 int stab_identity(kdqmc_ctx* c, bool left, int j);

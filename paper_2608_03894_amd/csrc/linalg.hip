@@ -97,29 +97,33 @@ int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, 
 }
 
 // ---------------------------------------------------------------------------
-// Householder panel: one workgroup of 1024 threads factors the m x nbp panel (nbp <= 16)
-// A[j:n, j:j+nbp] held in registers (thread t owns rows j+t and j+t+1024).
-// H_c = I - tau_c v_c v_c^T with v_c[jc] = 1 (LAPACK convention); the block
-// reflector H_0 ... H_{nbp-1} = I - V T V^T.  Outputs: R in A (zeros below
-// the diagonal of the panel), explicit V in Vq (unit diagonal, zeros above),
-// T in Tq (nbp x nbp, row stride 16), tau.
+// Householder QR, blocked (compact WY form).
+//
+// Panels of width nbp (32 while the panel has at most 1024 rows, else 16) are
+// factored by one workgroup of 512 threads holding the panel in registers
+// (thread t owns rows j+t, j+t+512, ...).  H_c = I - tau_c v_c v_c^T with
+// v_c[jc] = 1 (LAPACK convention); H_0 ... H_{nbp-1} = I - V T V^T.
+// Outputs: R in A (zeros below the diagonal), explicit V in Vq (unit diagonal,
+// zeros above), T in Tq (row stride 32), tau.
+// The block reflector is applied to the trailing columns (and later to the
+// identity to form Q, or to a right-hand side) by k_apply_wy, one launch per
+// panel, with both products on the FP64 MFMA.
 // ---------------------------------------------------------------------------
-constexpr int kNB = 16;
-constexpr int kPanelThreads = 1024;
+constexpr int kNBmax = 32;
+constexpr int kPanelThreads = 512;
 
-// Sum of vals[0..kNB) over the workgroup (vals is consumed); result in out[]
-// (LDS) for every thread.
-__device__ __forceinline__ void block_reduce_nb(double (&cur)[kNB], double* red, double* out) {
+template <int NB>
+__device__ __forceinline__ void block_reduce_nb(double (&cur)[NB], double* red, double* out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // transposed butterfly: after log2(kNB) stages lane holds the partial sum
-  // of value (lane % kNB) over the lanes that share bits >= log2(kNB)
-  int cnt = kNB;
+  // transposed butterfly: after log2(NB) stages, lane holds the partial sum of
+  // value (lane % NB) over the lanes that share its bits >= log2(NB)
+  int cnt = NB;
 #pragma unroll
-  for (int b = 0; (1 << b) < kNB; ++b) {
+  for (int b = 0; (1 << b) < NB; ++b) {
     const int bit = (lane >> b) & 1;
     cnt >>= 1;
 #pragma unroll
-    for (int i = 0; i < kNB / 2; ++i) {
+    for (int i = 0; i < NB / 2; ++i) {
       if (i < cnt) {
         const double keep = bit ? cur[2 * i + 1] : cur[2 * i];
         const double send = bit ? cur[2 * i] : cur[2 * i + 1];
@@ -129,12 +133,12 @@ __device__ __forceinline__ void block_reduce_nb(double (&cur)[kNB], double* red,
   }
   double v = cur[0];
 #pragma unroll
-  for (int o = kNB; o < 64; o <<= 1) v += __shfl_xor(v, o);
-  if (lane < kNB) red[wave * kNB + lane] = v;
+  for (int o = NB; o < 64; o <<= 1) v += __shfl_xor(v, o);
+  if (lane < NB) red[wave * NB + lane] = v;
   __syncthreads();
-  if (threadIdx.x < kNB) {
+  if (threadIdx.x < NB) {
     double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w * kNB + threadIdx.x];
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w * NB + threadIdx.x];
     out[threadIdx.x] = s;
   }
   __syncthreads();
@@ -152,44 +156,43 @@ __device__ __forceinline__ double block_reduce1(double v, double* red) {
   return s;
 }
 
-template <int RPT>
+template <int RPT, int NB>
 __global__ void __launch_bounds__(kPanelThreads)
 k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __restrict__ Vq,
            double* __restrict__ Tq, double* __restrict__ tau_out) {
-  __shared__ double red[16 * kNB];
-  __shared__ double dots[kNB];
-  __shared__ double Ts[kNB][kNB + 1];
-  __shared__ double betas[kNB];
-  __shared__ double taus[kNB];
+  __shared__ double red[8 * NB];
+  __shared__ double dots[NB];
+  __shared__ double Ts[NB][NB + 1];
+  __shared__ double betas[NB];
+  __shared__ double taus[NB];
   __shared__ double bcast[2];
   const int tid = threadIdx.x;
-  double a[RPT][kNB];
+  double a[RPT][NB];
   int row[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     row[q] = j + tid + q * kPanelThreads;
 #pragma unroll
-    for (int cc = 0; cc < kNB; ++cc)
+    for (int cc = 0; cc < NB; ++cc)
       a[q][cc] = (row[q] < n && cc < nbp) ? A[(size_t)row[q] * lda + j + cc] : 0.0;
   }
-  for (int idx = tid; idx < kNB * (kNB + 1); idx += kPanelThreads) (&Ts[0][0])[idx] = 0.0;
+  for (int idx = tid; idx < NB * (NB + 1); idx += kPanelThreads) (&Ts[0][0])[idx] = 0.0;
   __syncthreads();
 
 #pragma unroll 1
   for (int cc = 0; cc < nbp; ++cc) {
     const int jc = j + cc;
-    // norm^2 of column cc over rows >= jc, and the diagonal value
     double ss = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       double x = 0.0;
 #pragma unroll
-      for (int t = 0; t < kNB; ++t)
+      for (int t = 0; t < NB; ++t)
         if (t == cc) x = a[q][t];
       if (row[q] >= jc && row[q] < n) ss += x * x;
       if (row[q] == jc) bcast[0] = x;
     }
-    ss = block_reduce1(ss, red);  // contains a barrier after bcast write
+    ss = block_reduce1(ss, red);  // its barriers also publish bcast[0]
     const double alpha = bcast[0];
     const double sub = ss - alpha * alpha;
     double tau_c, beta, scale;
@@ -203,13 +206,12 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
       tau_c = (beta - alpha) / beta;
       scale = 1.0 / (alpha - beta);
     }
-    // column cc becomes v (unit at jc, zero above within the panel rows)
     double vq[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       double x = 0.0;
 #pragma unroll
-      for (int t = 0; t < kNB; ++t)
+      for (int t = 0; t < NB; ++t)
         if (t == cc) x = a[q][t];
       double v;
       if (row[q] < jc || row[q] >= n) v = 0.0;
@@ -218,49 +220,47 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
       vq[q] = v;
       if (row[q] >= jc) {
 #pragma unroll
-        for (int t = 0; t < kNB; ++t)
+        for (int t = 0; t < NB; ++t)
           if (t == cc) a[q][t] = v;
       }
     }
-    // dots[t] = v^T col_t for all panel columns (previous v's and the trailing columns)
-    double part[kNB];
+    // dots[t] = v^T (column t): earlier v's (t < cc) and trailing columns (t > cc)
+    double part[NB];
 #pragma unroll
-    for (int t = 0; t < kNB; ++t) {
+    for (int t = 0; t < NB; ++t) {
       double s = 0.0;
 #pragma unroll
       for (int q = 0; q < RPT; ++q) s += vq[q] * a[q][t];
       part[t] = s;
     }
-    block_reduce_nb(part, red, dots);
+    block_reduce_nb<NB>(part, red, dots);
     if (tid == 0) {
       betas[cc] = beta;
       taus[cc] = tau_c;
     }
-    // T column: T[0:cc, cc] = -tau_c T[0:cc, 0:cc] (V^T v_cc)[0:cc],  T[cc][cc] = tau_c
+    // T[0:cc, cc] = -tau_c T[0:cc, 0:cc] (V^T v_cc)[0:cc],  T[cc][cc] = tau_c
     if (tid < cc) {
       double s = 0.0;
       for (int t = tid; t < cc; ++t) s += Ts[tid][t] * dots[t];
       Ts[tid][cc] = -tau_c * s;
     }
     if (tid == cc) Ts[cc][cc] = tau_c;
-    // trailing columns: a[:, t] -= tau v dots[t], t > cc
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       if (row[q] >= jc && row[q] < n) {
 #pragma unroll
-        for (int t = 0; t < kNB; ++t)
+        for (int t = 0; t < NB; ++t)
           if (t > cc) a[q][t] -= tau_c * vq[q] * dots[t];
       }
     }
     __syncthreads();
   }
-  // write back: R in A (upper part within the panel rows, zeros below), V explicit
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = row[q];
     if (r >= n) continue;
 #pragma unroll
-    for (int cc = 0; cc < kNB; ++cc) {
+    for (int cc = 0; cc < NB; ++cc) {
       if (cc >= nbp) continue;
       const int jc = j + cc;
       double rv, vv;
@@ -271,11 +271,96 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
       Vq[(size_t)r * lda + jc] = vv;
     }
   }
-  for (int idx = tid; idx < kNB * kNB; idx += kPanelThreads) {
-    const int r = idx / kNB, cc = idx % kNB;
+  for (int idx = tid; idx < kNBmax * kNBmax; idx += kPanelThreads) {
+    const int r = idx / kNBmax, cc = idx % kNBmax;
     Tq[idx] = (r < nbp && cc < nbp) ? Ts[r][cc] : 0.0;
   }
   if (tid < nbp) tau_out[j + tid] = taus[tid];
+}
+
+// C[j:n, s0:s0+32] -= V op(T) (V^T C[j:n, s0:s0+32]) for the panel at column
+// j (width nbp <= 32): op(T) = T^T applies H^T = H_{nbp-1} ... H_0 (the
+// factorization / Q^T direction), op(T) = T applies H = H_0 ... H_{nbp-1}.
+// One workgroup (4 waves) per 32-column stripe.  W = V^T C: the waves split
+// the rows and their partial 32 x 32 products are summed in LDS; then
+// C -= V W2 with the waves splitting the rows.
+__global__ void __launch_bounds__(256)
+k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
+           const double* __restrict__ V, int ldv, const double* __restrict__ T, int trans) {
+  __shared__ double Wp[4][32][33];
+  __shared__ double W2[32][33];
+  __shared__ double Tl[32][33];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int s0 = blockIdx.x * 32;
+  const int m = n - j;
+  for (int idx = tid; idx < 32 * 32; idx += 256) {
+    const int r = idx >> 5, cc = idx & 31;
+    Tl[r][cc] = (r < nbp && cc < nbp) ? T[r * kNBmax + cc] : 0.0;
+  }
+  // W = V^T C (32 x 32), rows split over waves in chunks of 4
+  v4d acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int kb = wave * 4; kb < m; kb += 16) {
+    const int r = j + kb + lk;
+    double av[2], bv[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const int vc = bi * 16 + lr;
+      av[bi] = (r < n && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
+      const int cc = s0 + bi * 16 + lr;
+      bv[bi] = (r < n && cc < ncols) ? C[(size_t)r * ldc + cc] : 0.0;
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Wp[wave][bi * 16 + lk + 4 * e][bj * 16 + lr] = acc[bi][bj][e];
+  __syncthreads();
+  for (int idx = tid; idx < 32 * 32; idx += 256) {
+    const int r = idx >> 5, cc = idx & 31;
+    Wp[0][r][cc] = Wp[0][r][cc] + Wp[1][r][cc] + Wp[2][r][cc] + Wp[3][r][cc];
+  }
+  __syncthreads();
+  // W2 = op(T) W
+  for (int idx = tid; idx < 32 * 32; idx += 256) {
+    const int r = idx >> 5, cc = idx & 31;
+    double sacc = 0.0;
+    for (int t = 0; t < 32; ++t) sacc += (trans ? Tl[t][r] : Tl[r][t]) * Wp[0][t][cc];
+    W2[r][cc] = sacc;
+  }
+  __syncthreads();
+  // C -= V W2, 16-row blocks split over waves
+  for (int rb = wave * 16; rb < m; rb += 64) {
+    v4d d[2];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) d[bj] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4) {
+      const int r = j + rb + lr, vc = kk + lk;
+      const double av = (r < n && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        d[bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W2[kk + lk][bj * 16 + lr], d[bj], 0, 0, 0);
+    }
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = j + rb + lk + 4 * e, cc = s0 + bj * 16 + lr;
+        if (r < n && cc < ncols) C[(size_t)r * ldc + cc] -= d[bj][e];
+      }
+  }
 }
 
 __global__ void k_set_identity(double* __restrict__ Q, int n, int ld) {
@@ -291,101 +376,164 @@ __global__ void k_zero(double* __restrict__ X, size_t count) {
   if (idx < count) X[idx] = 0.0;
 }
 
-// A (n x n, leading dimension ld) = Q R; Q explicit in Q (ld).  Scratch from
-// the context: Vq (explicit reflectors), Tq (per-panel T), Wq (2 nb x n).
+namespace {
+
+inline int panel_width(int rows) { return rows > 1024 ? 16 : 32; }
+
+int launch_panel(kdqmc_ctx* c, double* A, int ld, int n, int j, int nbp, double* Tp) {
+  const int m = n - j;
+  const int e0 = prof_mark(c);
+  if (nbp > 16) {
+    if (m <= kPanelThreads)
+      hipLaunchKernelGGL((k_qr_panel<1, 32>), dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+    else
+      hipLaunchKernelGGL((k_qr_panel<2, 32>), dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+  } else {
+    hipLaunchKernelGGL((k_qr_panel<4, 16>), dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+  }
+  prof_pair(c, PH_QR_PANEL, e0, prof_mark(c));
+  return KDQMC_OK;
+}
+
+int launch_apply(kdqmc_ctx* c, double* C, int ld, int n, int j, int nbp, int col0, int ncols,
+                 const double* Tp, bool trans) {
+  if (ncols <= col0) return KDQMC_OK;
+  const int e0 = prof_mark(c);
+  const int stripes = (ncols - col0 + 31) / 32;
+  // the kernel indexes columns from C's base: shift the base to col0
+  hipLaunchKernelGGL(k_apply_wy, dim3(stripes), dim3(256), 0, c->stream, C + col0, ld, n, j, nbp,
+                     ncols - col0, c->Vq, ld, Tp, trans ? 1 : 0);
+  prof_pair(c, PH_GEMM, e0, prof_mark(c));
+  return KDQMC_OK;
+}
+
+}  // namespace
+
+// A (n x n, leading dimension N) = Q R.  With Q != nullptr, Q is formed
+// explicitly; the panels' V and T stay in Vq / Tq for apply_qt_f64.
 int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q) {
   const int ld = c->N;
-  const int nb = kNB;
-  if (n > 2 * kPanelThreads) return set_error(KDQMC_EUNSUPPORTED, "QR order above 2048");
+  if (n > 2048) return set_error(KDQMC_EUNSUPPORTED, "QR order above 2048");
   const size_t nn = (size_t)n * ld;
   hipLaunchKernelGGL(k_zero, dim3((nn + 255) / 256), dim3(256), 0, c->stream, c->Vq, nn);
-  const int npan = (n + nb - 1) / nb;
-  double* W1 = c->Wq;
-  double* W2 = c->Wq + (size_t)nb * ld;
-  for (int p = 0; p < npan; ++p) {
-    const int j = p * nb;
-    const int nbp = std::min(nb, n - j);
-    double* Tp = c->Tq + (size_t)p * nb * nb;
-    const int e0 = prof_mark(c);
-    if (n - j > kPanelThreads)
-      hipLaunchKernelGGL(k_qr_panel<2>, dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
-    else
-      hipLaunchKernelGGL(k_qr_panel<1>, dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
-    prof_pair(c, PH_QR_PANEL, e0, prof_mark(c));
-    const int nt = n - j - nbp;
-    if (nt > 0) {
-      // A[j:, j+nbp:] -= V T^T (V^T A[j:, j+nbp:])
-      const double* V = c->Vq + (size_t)j * ld + j;
-      double* At = A + (size_t)j * ld + j + nbp;
-      KDQMC_TRY(gemm_f64(c, true, false, nbp, nt, n - j, 1.0, V, ld, At, ld, 0.0, W1, ld));
-      KDQMC_TRY(gemm_f64(c, true, false, nbp, nt, nbp, 1.0, Tp, nb, W1, ld, 0.0, W2, ld));
-      KDQMC_TRY(gemm_f64(c, false, false, n - j, nt, nbp, -1.0, V, ld, W2, ld, 1.0, At, ld));
+  int npan = 0;
+  for (int j = 0; j < n; ++npan) {
+    const int nbp = std::min(panel_width(n - j), n - j);
+    double* Tp = c->Tq + (size_t)npan * kNBmax * kNBmax;
+    KDQMC_TRY(launch_panel(c, A, ld, n, j, nbp, Tp));
+    KDQMC_TRY(launch_apply(c, A, ld, n, j, nbp, j + nbp, n, Tp, true));
+    c->qr_panel_start[npan] = j;
+    c->qr_panel_width[npan] = nbp;
+    j += nbp;
+  }
+  c->qr_npan = npan;
+  if (Q) {
+    hipLaunchKernelGGL(k_set_identity, dim3((n * n + 255) / 256), dim3(256), 0, c->stream, Q, n, ld);
+    for (int p = npan - 1; p >= 0; --p) {
+      const int j = c->qr_panel_start[p];
+      KDQMC_TRY(launch_apply(c, Q, ld, n, j, c->qr_panel_width[p], j, n,
+                             c->Tq + (size_t)p * kNBmax * kNBmax, false));
     }
   }
-  // Q = H_0 H_1 ... : backward accumulation, Q[j:, j:] = (I - V T V^T) Q[j:, j:]
-  hipLaunchKernelGGL(k_set_identity, dim3((n * n + 255) / 256), dim3(256), 0, c->stream, Q, n, ld);
-  for (int p = npan - 1; p >= 0; --p) {
-    const int j = p * nb;
-    const int nbp = std::min(nb, n - j);
-    const double* Tp = c->Tq + (size_t)p * nb * nb;
-    const double* V = c->Vq + (size_t)j * ld + j;
-    double* Qs = Q + (size_t)j * ld + j;
-    const int mm = n - j;
-    KDQMC_TRY(gemm_f64(c, true, false, nbp, mm, mm, 1.0, V, ld, Qs, ld, 0.0, W1, ld));
-    KDQMC_TRY(gemm_f64(c, false, false, nbp, mm, nbp, 1.0, Tp, nb, W1, ld, 0.0, W2, ld));
-    KDQMC_TRY(gemm_f64(c, false, false, mm, mm, nbp, -1.0, V, ld, W2, ld, 1.0, Qs, ld));
+  KDQMC_HIP(hipGetLastError());
+  return KDQMC_OK;
+}
+
+// X <- Q^T X for the Q of the last qr_f64 call (n x n, ld = N).
+int apply_qt_f64(kdqmc_ctx* c, int n, double* X) {
+  const int ld = c->N;
+  for (int p = 0; p < c->qr_npan; ++p) {
+    const int j = c->qr_panel_start[p];
+    KDQMC_TRY(launch_apply(c, X, ld, n, j, c->qr_panel_width[p], 0, n,
+                           c->Tq + (size_t)p * kNBmax * kNBmax, true));
   }
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
 
 // ---------------------------------------------------------------------------
-// Upper-triangular solve R Y = X in place on X (n x n, ld = N): inverse of
-// each 32 x 32 diagonal block by back substitution in LDS, then blocked
-// backward substitution with GEMMs.
+// Upper-triangular solve R Y = X in place on X (n x n, ld = N).  Columns of
+// X are independent: one workgroup owns 16 columns and walks the 32-row
+// block rows from the bottom, X_b = R_bb^{-1} (X_b - R[b, b1:] X[b1:]), with
+// the 32 x 32 diagonal-block inverses precomputed by k_trinv_blocks.
 // ---------------------------------------------------------------------------
+constexpr int kTB = 32;
+
 __global__ void k_trinv_blocks(const double* __restrict__ R, int n, int ld, double* __restrict__ Rinv) {
-  __shared__ double Rb[kNB][kNB + 1];
+  __shared__ double Rb[kTB][kTB + 1];
   const int b = blockIdx.x;
-  const int b0 = b * kNB;
-  const int nbp = min(kNB, n - b0);
-  for (int idx = threadIdx.x; idx < kNB * kNB; idx += blockDim.x) {
-    const int r = idx / kNB, cc = idx % kNB;
+  const int b0 = b * kTB;
+  const int nbp = min(kTB, n - b0);
+  for (int idx = threadIdx.x; idx < kTB * kTB; idx += blockDim.x) {
+    const int r = idx / kTB, cc = idx % kTB;
     Rb[r][cc] = (r < nbp && cc < nbp) ? R[(size_t)(b0 + r) * ld + b0 + cc] : 0.0;
   }
   __syncthreads();
-  const int col = threadIdx.x;  // column of the inverse
-  if (col < kNB) {
-    double x[kNB];
+  const int col = threadIdx.x;
+  if (col < kTB) {
+    double x[kTB];
 #pragma unroll
-    for (int r = kNB - 1; r >= 0; --r) {
+    for (int r = kTB - 1; r >= 0; --r) {
       double s = (r == col) ? 1.0 : 0.0;
 #pragma unroll
-      for (int t = r + 1; t < kNB; ++t) s -= Rb[r][t] * x[t];
+      for (int t = r + 1; t < kTB; ++t) s -= Rb[r][t] * x[t];
       x[r] = (r < nbp) ? s / Rb[r][r] : 0.0;
     }
 #pragma unroll
-    for (int r = 0; r < kNB; ++r) Rinv[(size_t)b * kNB * kNB + r * kNB + col] = x[r];
+    for (int r = 0; r < kTB; ++r) Rinv[(size_t)b * kTB * kTB + r * kTB + col] = x[r];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_trsm_upper(const double* __restrict__ R, const double* __restrict__ Rinv, double* __restrict__ X,
+             int n, int ld) {
+  __shared__ double tmp[kTB][17];
+  const int tid = threadIdx.x;
+  const int r = tid >> 3;          // 0..31: row within the block row
+  const int cg = tid & 7;          // two columns each
+  const int c0 = blockIdx.x * 16 + 2 * cg;
+  const int nblk = (n + kTB - 1) / kTB;
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int b0 = b * kTB;
+    const int b1 = min(n, b0 + kTB);
+    const int gr = b0 + r;
+    double a0 = 0.0, a1 = 0.0;
+    if (gr < n) {
+      if (c0 < n) a0 = X[(size_t)gr * ld + c0];
+      if (c0 + 1 < n) a1 = X[(size_t)gr * ld + c0 + 1];
+      for (int k = b1; k < n; ++k) {
+        const double rv = R[(size_t)gr * ld + k];
+        if (c0 < n) a0 -= rv * X[(size_t)k * ld + c0];
+        if (c0 + 1 < n) a1 -= rv * X[(size_t)k * ld + c0 + 1];
+      }
+    }
+    tmp[r][2 * cg] = a0;
+    tmp[r][2 * cg + 1] = a1;
+    __syncthreads();
+    double y0 = 0.0, y1 = 0.0;
+    const double* Ri = Rinv + (size_t)b * kTB * kTB + r * kTB;
+#pragma unroll 8
+    for (int s = 0; s < kTB; ++s) {
+      y0 += Ri[s] * tmp[s][2 * cg];
+      y1 += Ri[s] * tmp[s][2 * cg + 1];
+    }
+    if (gr < n) {
+      if (c0 < n) X[(size_t)gr * ld + c0] = y0;
+      if (c0 + 1 < n) X[(size_t)gr * ld + c0 + 1] = y1;
+    }
+    __syncthreads();
   }
 }
 
 int trsm_upper_f64(kdqmc_ctx* c, int n, const double* R, double* X) {
-  const int ld = c->N, nb = kNB;
-  const int nblk = (n + nb - 1) / nb;
-  double* Rinv = c->Tq;  // nblk * nb * nb
+  const int ld = c->N;
+  const int nblk = (n + kTB - 1) / kTB;
+  double* Rinv = c->Tq;  // nblk * 32 * 32 (the QR's T factors are no longer needed)
+  const int e0 = prof_mark(c);
   hipLaunchKernelGGL(k_trinv_blocks, dim3(nblk), dim3(64), 0, c->stream, R, n, ld, Rinv);
-  double* Y = c->S[7];
-  for (int b = nblk - 1; b >= 0; --b) {
-    const int b0 = b * nb;
-    const int nbp = std::min(nb, n - b0);
-    const int b1 = b0 + nbp;
-    if (b1 < n)
-      KDQMC_TRY(gemm_f64(c, false, false, nbp, n, n - b1, -1.0, R + (size_t)b0 * ld + b1, ld,
-                         Y + (size_t)b1 * ld, ld, 1.0, X + (size_t)b0 * ld, ld));
-    KDQMC_TRY(gemm_f64(c, false, false, nbp, n, nbp, 1.0, Rinv + (size_t)b * nb * nb, nb,
-                       X + (size_t)b0 * ld, ld, 0.0, Y + (size_t)b0 * ld, ld));
-  }
-  KDQMC_TRY(copy_f64(c, X, Y, (size_t)n * ld));
+  hipLaunchKernelGGL(k_trsm_upper, dim3((n + 15) / 16), dim3(256), 0, c->stream, R, Rinv, X, n, ld);
+  prof_pair(c, PH_GEMM, e0, prof_mark(c));
+  KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
 

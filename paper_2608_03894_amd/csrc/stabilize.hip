@@ -257,15 +257,13 @@ int stab_green(kdqmc_ctx* c, int j, double* out) {
   const double* TL = stackT(c, true, j);
   double* X1 = c->S[0];
   double* X2 = c->S[1];
-  double* Q = c->S[2];
-  double* Z = c->S[3];
   double* Y = c->S[4];
   KDQMC_TRY(gemm_f64(c, true, false, n, n, n, 1.0, UR, n, UL, n, 0.0, X1, n));
   KDQMC_TRY(gemm_f64(c, false, true, n, n, n, 1.0, TR, n, TL, n, 0.0, X2, n));
   hipLaunchKernelGGL(k_combine_M, grid_for(nn), dim3(256), 0, c->stream, X1, X2, n, DR, DL);
-  KDQMC_TRY(qr_f64(c, n, X1, Q));
-  hipLaunchKernelGGL(k_transpose_scale, grid_for(nn), dim3(256), 0, c->stream, Z, UR, n, DR);
-  KDQMC_TRY(gemm_f64(c, true, false, n, n, n, 1.0, Q, n, Z, n, 0.0, Y, n));
+  KDQMC_TRY(qr_f64(c, n, X1, nullptr));
+  hipLaunchKernelGGL(k_transpose_scale, grid_for(nn), dim3(256), 0, c->stream, Y, UR, n, DR);
+  KDQMC_TRY(apply_qt_f64(c, n, Y));
   KDQMC_TRY(trsm_upper_f64(c, n, X1, Y));
   hipLaunchKernelGGL(k_scale_rows_big, grid_for(nn), dim3(256), 0, c->stream, Y, n, DL);
   KDQMC_TRY(gemm_f64(c, false, false, n, n, n, 1.0, UL, n, Y, n, 0.0, out, n));

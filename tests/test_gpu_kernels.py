@@ -56,6 +56,27 @@ def test_qr_f64(ch6, n):
     assert np.allclose(np.abs(np.diag(R)), np.abs(np.diag(r_ref)), rtol=1e-10, atol=0)
 
 
+@pytest.mark.parametrize("L,n", [(12, 432), (12, 300), (24, 1728), (24, 1100)])
+def test_qr_f64_large(gpu_lib, L, n):
+    """Panels of 32 (<= 1024 rows) and 16 (more rows) columns, ragged tails."""
+    say("qr-large", L, n)
+    ch = chain(L, 0.0, 1.0)
+    N = ch.N
+    rng = np.random.default_rng(n)
+    A = np.zeros((N, N))
+    A[:n, :n] = rng.standard_normal((n, n)) * np.logspace(0, -6, n)[None, :]
+    a = dev(A)
+    q = dev(np.zeros((N, N)))
+    ch.qr_f64(n, a, q)
+    ch.sync()
+    R = a.cpu().numpy()[:n, :n]
+    Q = q.cpu().numpy()[:n, :n]
+    assert np.abs(np.tril(R, -1)).max() == 0.0
+    assert np.abs(Q.T @ Q - np.eye(n)).max() < 1e-12
+    err = np.abs(Q @ R - A[:n, :n]).max(axis=0) / np.abs(A[:n, :n]).max(axis=0)
+    assert err.max() < 1e-11
+
+
 @pytest.mark.parametrize("L", [3, 6, 9, 12, 15, 18, 24])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed_f16", 2e-6)])
 def test_wrap_free(gpu_lib, L, prec, tol):
