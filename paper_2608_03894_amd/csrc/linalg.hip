@@ -112,61 +112,19 @@ int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, 
 constexpr int kNBmax = 32;
 constexpr int kPanelThreads = 512;
 
-template <int NB>
-__device__ __forceinline__ void block_reduce_nb(double (&cur)[NB], double* red, double* out) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // transposed butterfly: after log2(NB) stages, lane holds the partial sum of
-  // value (lane % NB) over the lanes that share its bits >= log2(NB)
-  int cnt = NB;
-#pragma unroll
-  for (int b = 0; (1 << b) < NB; ++b) {
-    const int bit = (lane >> b) & 1;
-    cnt >>= 1;
-#pragma unroll
-    for (int i = 0; i < NB / 2; ++i) {
-      if (i < cnt) {
-        const double keep = bit ? cur[2 * i + 1] : cur[2 * i];
-        const double send = bit ? cur[2 * i] : cur[2 * i + 1];
-        cur[i] = keep + __shfl_xor(send, 1 << b);
-      }
-    }
-  }
-  double v = cur[0];
-#pragma unroll
-  for (int o = NB; o < 64; o <<= 1) v += __shfl_xor(v, o);
-  if (lane < NB) red[wave * NB + lane] = v;
-  __syncthreads();
-  if (threadIdx.x < NB) {
-    double s = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w * NB + threadIdx.x];
-    out[threadIdx.x] = s;
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ double block_reduce1(double v, double* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-  __syncthreads();
-  return s;
-}
-
 template <int RPT, int NB>
 __global__ void __launch_bounds__(kPanelThreads)
 k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __restrict__ Vq,
            double* __restrict__ Tq, double* __restrict__ tau_out) {
-  __shared__ double red[8 * NB];
+  constexpr int NW = kPanelThreads / 64;
+  __shared__ double red2[2][NW][2];   // (norm^2, diagonal) partials, double-buffered
+  __shared__ double redn[NW * NB];    // dot-product partials
   __shared__ double dots[NB];
+  __shared__ double Sv[NB][NB + 1];   // V^T V (column cc of rows < cc)
   __shared__ double Ts[NB][NB + 1];
   __shared__ double betas[NB];
   __shared__ double taus[NB];
-  __shared__ double bcast[2];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double a[RPT][NB];
   int row[RPT];
 #pragma unroll
@@ -176,13 +134,12 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
     for (int cc = 0; cc < NB; ++cc)
       a[q][cc] = (row[q] < n && cc < nbp) ? A[(size_t)row[q] * lda + j + cc] : 0.0;
   }
-  for (int idx = tid; idx < NB * (NB + 1); idx += kPanelThreads) (&Ts[0][0])[idx] = 0.0;
-  __syncthreads();
 
 #pragma unroll 1
   for (int cc = 0; cc < nbp; ++cc) {
     const int jc = j + cc;
-    double ss = 0.0;
+    // one reduction gives ||a[jc:, cc]||^2 and the diagonal value a[jc, cc]
+    double ss = 0.0, dg = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       double x = 0.0;
@@ -190,10 +147,26 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
       for (int t = 0; t < NB; ++t)
         if (t == cc) x = a[q][t];
       if (row[q] >= jc && row[q] < n) ss += x * x;
-      if (row[q] == jc) bcast[0] = x;
+      if (row[q] == jc) dg = x;
     }
-    ss = block_reduce1(ss, red);  // its barriers also publish bcast[0]
-    const double alpha = bcast[0];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      ss += __shfl_xor(ss, o);
+      dg += __shfl_xor(dg, o);
+    }
+    const int buf = cc & 1;
+    if (lane == 0) {
+      red2[buf][wave][0] = ss;
+      red2[buf][wave][1] = dg;
+    }
+    __syncthreads();
+    ss = 0.0;
+    double alpha = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      ss += red2[buf][w][0];
+      alpha += red2[buf][w][1];
+    }
     const double sub = ss - alpha * alpha;
     double tau_c, beta, scale;
     if (!(sub > 0.0)) {  // nothing below the diagonal: H = I
@@ -233,18 +206,39 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
       for (int q = 0; q < RPT; ++q) s += vq[q] * a[q][t];
       part[t] = s;
     }
-    block_reduce_nb<NB>(part, red, dots);
+    {
+      int cnt = NB;
+#pragma unroll
+      for (int b = 0; (1 << b) < NB; ++b) {
+        const int bit = (lane >> b) & 1;
+        cnt >>= 1;
+#pragma unroll
+        for (int i = 0; i < NB / 2; ++i) {
+          if (i < cnt) {
+            const double keep = bit ? part[2 * i + 1] : part[2 * i];
+            const double send = bit ? part[2 * i] : part[2 * i + 1];
+            part[i] = keep + __shfl_xor(send, 1 << b);
+          }
+        }
+      }
+      double v = part[0];
+#pragma unroll
+      for (int o = NB; o < 64; o <<= 1) v += __shfl_xor(v, o);
+      if (lane < NB) redn[wave * NB + lane] = v;
+    }
+    __syncthreads();
+    if (tid < NB) {
+      double sacc = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sacc += redn[w * NB + tid];
+      dots[tid] = sacc;
+      if (tid < cc) Sv[tid][cc] = sacc;  // (V^T V)[tid][cc]
+    }
     if (tid == 0) {
       betas[cc] = beta;
       taus[cc] = tau_c;
     }
-    // T[0:cc, cc] = -tau_c T[0:cc, 0:cc] (V^T v_cc)[0:cc],  T[cc][cc] = tau_c
-    if (tid < cc) {
-      double s = 0.0;
-      for (int t = tid; t < cc; ++t) s += Ts[tid][t] * dots[t];
-      Ts[tid][cc] = -tau_c * s;
-    }
-    if (tid == cc) Ts[cc][cc] = tau_c;
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       if (row[q] >= jc && row[q] < n) {
@@ -253,8 +247,24 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
           if (t > cc) a[q][t] -= tau_c * vq[q] * dots[t];
       }
     }
-    __syncthreads();
   }
+  // T of the block reflector from V^T V: T[cc][cc] = tau_cc,
+  // T[0:cc, cc] = -tau_cc T[0:cc, 0:cc] (V^T V)[0:cc, cc]  (one wave, no barriers)
+  if (wave == 0) {
+    for (int cc = 0; cc < nbp; ++cc) {
+      double tv = 0.0;
+      if (lane < cc) {
+        for (int t = lane; t < cc; ++t) tv += Ts[lane][t] * Sv[t][cc];
+        tv *= -taus[cc];
+      }
+      if (lane < cc) Ts[lane][cc] = tv;
+      if (lane == cc) Ts[cc][cc] = taus[cc];
+      if (lane > cc && lane < NB) Ts[lane][cc] = 0.0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = row[q];
@@ -304,6 +314,7 @@ k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
   for (int kb = wave * 4; kb < m; kb += 16) {
     const int r = j + kb + lk;
     double av[2], bv[2];
@@ -341,6 +352,7 @@ k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
   }
   __syncthreads();
   // C -= V W2, 16-row blocks split over waves
+#pragma unroll 2
   for (int rb = wave * 16; rb < m; rb += 64) {
     v4d d[2];
 #pragma unroll
