@@ -38,20 +38,24 @@ __global__ void k_frame_scale(const int8_t* __restrict__ s, int n, double ea, do
 }
 
 // ---------------------------------------------------------------------------
-// Sequential decisions of one window (single workgroup).
-// LDS: Gs[w][w+1] (window submatrix, tilde frame) and two coefficient blocks
-// Cf[w][w+1], Cr[w][w+1].  After the accepts so far,
+// Sequential decisions of one window (single workgroup of 256 threads).
+// Three wn x wn blocks are kept: the window submatrix Gs (tilde frame) and two
+// coefficient blocks Cf, Cr.  After the accepts so far,
 //   G~cur[:, y] = G0[:, y] + sum_q G0[:, i_q] Cf[q][y]   (columns y of the window)
 //   G~cur[x, :] = G0[x, :] + sum_q Cr[x][q] h_q           (rows x of the window)
 // with G0 the window-start matrix and h_q = e_{i_q} - G0[i_q, :].  The accept
 // number n at window position p (c = Delta/R) therefore has the factors
 //   u_n = sum_q G0[:, i_q] Z[q][n],  Z[q][n] = -c (delta_qn + Cf[q][p]),
 //   w_n = sum_q Z'[n][q] h_q,        Z'[n][q] = delta_nq - Cr[p][q],
-// and Cf, Cr, Gs receive rank-one updates on their live part (indices > p).
-// Row p and column p of all three blocks are never written again, so every
-// update reads only frozen values and one barrier per accept suffices.
+// and Gs, Cf, Cr receive rank-one updates on their live part (indices > p);
+// row p and column p of all three are never written again.
+// Register layout: thread t owns the WS x WS entries (x, y) with
+// x = t/16 + 16 i, y = t%16 + 16 k of each block.  Per accept the owners
+// publish row p / column p through LDS (barrier), everyone updates its
+// registers and the diagonal owners publish the new diagonal (barrier).  A
+// rejected flip reads one LDS word and needs no barrier.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int WS>
 __global__ void __launch_bounds__(256)
 k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
          const double* __restrict__ evinv, int8_t* __restrict__ s_l,
@@ -60,31 +64,34 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
          const double* __restrict__ Gs_in, double em2a, double ep2a, int win,
          int* __restrict__ win_a, int* __restrict__ win_p, double* __restrict__ Zg,
          double* __restrict__ Zpg) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int ld = wn + 1;
-  double* Gs = reinterpret_cast<double*>(smem_raw);  // wn * ld
-  double* Cf = Gs + wn * ld;                          // wn * ld, Cf[q][y] at q*ld + y
-  double* Cr = Cf + wn * ld;                          // wn * ld, Cr[x][q] at x*ld + q
-  double* ul = Cr + wn * ld;                          // wn: uniforms of the window
-  int* pl = reinterpret_cast<int*>(ul + wn);          // wn: window position of accept n
-  int8_t* sl = reinterpret_cast<int8_t*>(pl + wn);    // wn: fields of the window
-  uint8_t* fl = reinterpret_cast<uint8_t*>(sl + wn);  // wn: forced decisions
-  const int tid = threadIdx.x, nth = blockDim.x;
-
-  for (int idx = tid; idx < wn * wn; idx += nth) {
-    const int x = idx / wn, y = idx % wn;
-    double g;
-    if (Gs_in) {
-      g = Gs_in[x * W + y];
-    } else {
-      const int gx = w0 + x, gy = w0 + y;
-      g = double(G[(size_t)gx * N + gy]) * ev[gx] * evinv[gy];
+  constexpr int WM = 16 * WS;  // largest window this instance handles
+  __shared__ double rowp[WM], colp[WM], cfp[WM], crp[WM], diagL[WM], ul[WM];
+  __shared__ int pl[WM];
+  __shared__ int8_t sl[WM];
+  __shared__ uint8_t fl[WM];
+  const int tid = threadIdx.x;
+  const int rx = tid >> 4, cy = tid & 15;
+  double gs[WS][WS], cf[WS][WS], cr[WS][WS];
+#pragma unroll
+  for (int i = 0; i < WS; ++i)
+#pragma unroll
+    for (int k = 0; k < WS; ++k) {
+      const int x = rx + 16 * i, y = cy + 16 * k;
+      double g = 0.0;
+      if (x < wn && y < wn) {
+        if (Gs_in) {
+          g = Gs_in[x * W + y];
+        } else {
+          const int gx = w0 + x, gy = w0 + y;
+          g = double(G[(size_t)gx * N + gy]) * ev[gx] * evinv[gy];
+        }
+      }
+      gs[i][k] = g;
+      cf[i][k] = 0.0;
+      cr[i][k] = 0.0;
+      if (x == y && x < wn) diagL[x] = g;
     }
-    Gs[x * ld + y] = g;
-    Cf[x * ld + y] = 0.0;
-    Cr[x * ld + y] = 0.0;
-  }
-  for (int p = tid; p < wn; p += nth) {
+  for (int p = tid; p < wn; p += 256) {
     sl[p] = s_l[w0 + p];
     ul[p] = u ? u[w0 + p] : 0.0;
     fl[p] = forced ? forced[w0 + p] : 0;
@@ -94,7 +101,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
   int na = 0;
   for (int p = 0; p < wn; ++p) {
     const int s = sl[p];
-    const double gpp = Gs[p * ld + p];
+    const double gpp = diagL[p];
     const double delta = (s > 0 ? em2a : ep2a) - 1.0;
     const double e2as = s > 0 ? ep2a : em2a;
     const double R = 1.0 + delta * (1.0 - gpp);
@@ -107,40 +114,80 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     if (!a) continue;
     const double c = delta / R;
     const int n = na;
+    const int ip = p >> 4, pr = p & 15;
+    // phase A: publish row p of Gs and Cr, column p of Gs and Cf
+    if (rx == pr) {
+#pragma unroll
+      for (int k = 0; k < WS; ++k) {
+        double g = 0.0, r = 0.0;
+#pragma unroll
+        for (int i = 0; i < WS; ++i)
+          if (i == ip) {
+            g = gs[i][k];
+            r = cr[i][k];
+          }
+        rowp[cy + 16 * k] = g;
+        crp[cy + 16 * k] = r;
+      }
+    }
+    if (cy == pr) {
+#pragma unroll
+      for (int i = 0; i < WS; ++i) {
+        double g = 0.0, f = 0.0;
+#pragma unroll
+        for (int k = 0; k < WS; ++k)
+          if (k == ip) {
+            g = gs[i][k];
+            f = cf[i][k];
+          }
+        colp[rx + 16 * i] = g;
+        cfp[rx + 16 * i] = f;
+      }
+    }
     if (tid == 0) {
       s_l[w0 + p] = int8_t(-s);
       pl[n] = p;
     }
-    // the accept's triangular factor entries (published for k_extend)
-    for (int q = tid; q <= n; q += nth) {
-      Zg[q * W + n] = -c * ((q == n ? 1.0 : 0.0) + Cf[q * ld + p]);
-      Zpg[n * W + q] = (q == n ? 1.0 : 0.0) - Cr[p * ld + q];
+    __syncthreads();
+    // phase B: rank-one updates of the live parts; publish the accept's factors
+    double cx[WS], qx[WS], ry[WS], zpy[WS];
+#pragma unroll
+    for (int i = 0; i < WS; ++i) {
+      const int x = rx + 16 * i;
+      cx[i] = colp[x];
+      qx[i] = -c * ((x == n ? 1.0 : 0.0) + cfp[x]);   // Z[x][n] (rows q = x of Cf)
     }
-    // live part: y > p (columns of Cf and Gs), x > p (rows of Cr and Gs)
-    const int rem = wn - p - 1;
-    const int na1 = n + 1;
-    // Cf[q][y] += Z[q][n] * w_n[y],  w_n[y] = -Gs[p][y]
-    for (int idx = tid; idx < na1 * rem; idx += nth) {
-      const int q = idx / rem, y = p + 1 + idx % rem;
-      const double z = -c * ((q == n ? 1.0 : 0.0) + Cf[q * ld + p]);
-      Cf[q * ld + y] -= z * Gs[p * ld + y];
+#pragma unroll
+    for (int k = 0; k < WS; ++k) {
+      const int y = cy + 16 * k;
+      ry[k] = rowp[y];
+      zpy[k] = (y == n ? 1.0 : 0.0) - crp[y];        // Z'[n][y] (columns q = y of Cr)
     }
-    // Cr[x][q] += u_n[x] * Z'[n][q],  u_n[x] = -c Gs[x][p]
-    for (int idx = tid; idx < rem * na1; idx += nth) {
-      const int x = p + 1 + idx / na1, q = idx % na1;
-      const double zp = (q == n ? 1.0 : 0.0) - Cr[p * ld + q];
-      Cr[x * ld + q] -= c * Gs[x * ld + p] * zp;
+#pragma unroll
+    for (int i = 0; i < WS; ++i)
+#pragma unroll
+      for (int k = 0; k < WS; ++k) {
+        const int x = rx + 16 * i, y = cy + 16 * k;
+        if (x > p && y > p) gs[i][k] += c * cx[i] * ry[k];
+        if (x <= n && y > p) cf[i][k] -= qx[i] * ry[k];
+        if (x > p && y <= n) cr[i][k] -= c * cx[i] * zpy[k];
+      }
+    if (tid <= n) {
+      Zg[tid * W + n] = -c * ((tid == n ? 1.0 : 0.0) + cfp[tid]);
+      Zpg[n * W + tid] = (tid == n ? 1.0 : 0.0) - crp[tid];
     }
-    // Gs[x][y] += u_n[x] w_n[y] = c Gs[x][p] Gs[p][y]
-    for (int idx = tid; idx < rem * rem; idx += nth) {
-      const int x = p + 1 + idx / rem, y = p + 1 + idx % rem;
-      Gs[x * ld + y] += c * Gs[x * ld + p] * Gs[p * ld + y];
+    if (rx == cy) {
+#pragma unroll
+      for (int i = 0; i < WS; ++i) {
+        const int x = rx + 16 * i;
+        if (x > p && x < wn) diagL[x] = gs[i][i];
+      }
     }
     ++na;
     __syncthreads();
   }
   if (tid == 0) win_a[win] = na;
-  for (int n = tid; n < na; n += nth) win_p[win * W + n] = pl[n];
+  for (int n = tid; n < na; n += 256) win_p[win * W + n] = pl[n];
 }
 
 // ---------------------------------------------------------------------------
@@ -372,7 +419,6 @@ namespace {
 
 template <typename T>
 int set_lds_limits() {
-  KDQMC_HIP(hipFuncSetAttribute((const void*)k_decide<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   KDQMC_HIP(hipFuncSetAttribute((const void*)k_extend<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   return KDQMC_OK;
 }
@@ -393,13 +439,19 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
     const int grp0 = (win / c->F) * c->F;
     const bool first_in_group = (win == grp0);
     // decide
-    const size_t lds_d = 3 * size_t(wn) * (wn + 1) * 8 + size_t(wn) * 8 + size_t(wn) * 4 +
-                         2 * size_t(wn) + 16;
     const int e_d = prof_mark(c);
-    hipLaunchKernelGGL(k_decide<T>, dim3(1), dim3(256), lds_d, c->stream, G, N, c->ev, c->evinv,
-                       s_l, u ? u + 0 : nullptr, forced, acc, ratio, w0, wn, W,
-                       first_in_group ? nullptr : c->Gs, em2a, ep2a, win, c->win_a, c->win_p,
-                       c->Xw, c->Yw);
+    if (wn <= 16)
+      hipLaunchKernelGGL((k_decide<T, 1>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
+                         s_l, u, forced, acc, ratio, w0, wn, W, first_in_group ? nullptr : c->Gs,
+                         em2a, ep2a, win, c->win_a, c->win_p, c->Xw, c->Yw);
+    else if (wn <= 32)
+      hipLaunchKernelGGL((k_decide<T, 2>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
+                         s_l, u, forced, acc, ratio, w0, wn, W, first_in_group ? nullptr : c->Gs,
+                         em2a, ep2a, win, c->win_a, c->win_p, c->Xw, c->Yw);
+    else
+      hipLaunchKernelGGL((k_decide<T, 4>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
+                         s_l, u, forced, acc, ratio, w0, wn, W, first_in_group ? nullptr : c->Gs,
+                         em2a, ep2a, win, c->win_a, c->win_p, c->Xw, c->Yw);
     const int e_e = prof_mark(c);
     prof_pair(c, PH_DECIDE, e_d, e_e);
     // extend
