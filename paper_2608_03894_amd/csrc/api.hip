@@ -18,13 +18,14 @@ struct Derived {
   bool fp64 = true;
 };
 
+// Complex vectors per wrap workgroup: at least one workgroup per compute
+// unit (256) where the matrix allows, within 64 KB of LDS and 512 threads.
 int auto_tile(int L, size_t elem, int requested) {
   if (requested > 0) return requested;
   const int N = 3 * L * L;
-  int P = 1;
-  for (int q = 1; q <= 8; ++q) {
-    if (2 * (size_t)N * q * elem <= 64 * 1024 && 3 * L * q <= 512) P = q;
-  }
+  const int ncomplex = (N + 1) / 2;
+  int P = std::max(1, ncomplex / 256);
+  while (P > 1 && (2 * (size_t)N * P * elem > 64 * 1024 || 3 * L * P > 512)) --P;
   return P;
 }
 

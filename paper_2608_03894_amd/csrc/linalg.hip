@@ -100,8 +100,8 @@ int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, 
 // Householder QR, blocked (compact WY form).
 //
 // Panels of width nbp (32 while the panel has at most 1024 rows, else 16) are
-// factored by one workgroup of 512 threads holding the panel in registers
-// (thread t owns rows j+t, j+t+512, ...).  H_c = I - tau_c v_c v_c^T with
+// factored by one workgroup of 256 threads holding the panel in registers
+// (thread t owns rows j+t, j+t+256, ...).  H_c = I - tau_c v_c v_c^T with
 // v_c[jc] = 1 (LAPACK convention); H_0 ... H_{nbp-1} = I - V T V^T.
 // Outputs: R in A (zeros below the diagonal), explicit V in Vq (unit diagonal,
 // zeros above), T in Tq (row stride 32), tau.
@@ -110,7 +110,23 @@ int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, 
 // panel, with both products on the FP64 MFMA.
 // ---------------------------------------------------------------------------
 constexpr int kNBmax = 32;
-constexpr int kPanelThreads = 512;
+constexpr int kPanelThreads = 256;
+
+// Lane exchange within a wave for a double: DPP quad permutations for xor 1
+// and xor 2 (no LDS traffic), ds_bpermute otherwise.
+__device__ __forceinline__ double xchg_xor(double v, int mask) {
+  if (mask == 1) {  // quad_perm [1,0,3,2]
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0xB1, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+  }
+  if (mask == 2) {  // quad_perm [2,3,0,1]
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x4E, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x4E, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+  }
+  return __shfl_xor(v, mask);
+}
 
 template <int RPT, int NB>
 __global__ void __launch_bounds__(kPanelThreads)
@@ -151,8 +167,8 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
-      ss += __shfl_xor(ss, o);
-      dg += __shfl_xor(dg, o);
+      ss += xchg_xor(ss, o);
+      dg += xchg_xor(dg, o);
     }
     const int buf = cc & 1;
     if (lane == 0) {
@@ -217,13 +233,13 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
           if (i < cnt) {
             const double keep = bit ? part[2 * i + 1] : part[2 * i];
             const double send = bit ? part[2 * i] : part[2 * i + 1];
-            part[i] = keep + __shfl_xor(send, 1 << b);
+            part[i] = keep + xchg_xor(send, 1 << b);
           }
         }
       }
       double v = part[0];
 #pragma unroll
-      for (int o = NB; o < 64; o <<= 1) v += __shfl_xor(v, o);
+      for (int o = NB; o < 64; o <<= 1) v += xchg_xor(v, o);
       if (lane < NB) redn[wave * NB + lane] = v;
     }
     __syncthreads();
@@ -396,12 +412,12 @@ int launch_panel(kdqmc_ctx* c, double* A, int ld, int n, int j, int nbp, double*
   const int m = n - j;
   const int e0 = prof_mark(c);
   if (nbp > 16) {
-    if (m <= kPanelThreads)
-      hipLaunchKernelGGL((k_qr_panel<1, 32>), dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
-    else
+    if (m <= 2 * kPanelThreads)
       hipLaunchKernelGGL((k_qr_panel<2, 32>), dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+    else
+      hipLaunchKernelGGL((k_qr_panel<4, 32>), dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
   } else {
-    hipLaunchKernelGGL((k_qr_panel<4, 16>), dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+    hipLaunchKernelGGL((k_qr_panel<8, 16>), dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
   }
   prof_pair(c, PH_QR_PANEL, e0, prof_mark(c));
   return KDQMC_OK;
@@ -496,42 +512,68 @@ __global__ void k_trinv_blocks(const double* __restrict__ R, int n, int ld, doub
   }
 }
 
+// One workgroup per 32-column stripe of X; for each 32-row block row from the
+// bottom: acc = R[b, b1:] X[b1:, stripe] on the FP64 MFMA (4 waves split K,
+// partials summed in LDS), then X_b = Rinv_bb (X_b - acc).
 __global__ void __launch_bounds__(256)
 k_trsm_upper(const double* __restrict__ R, const double* __restrict__ Rinv, double* __restrict__ X,
              int n, int ld) {
-  __shared__ double tmp[kTB][17];
-  const int tid = threadIdx.x;
-  const int r = tid >> 3;          // 0..31: row within the block row
-  const int cg = tid & 7;          // two columns each
-  const int c0 = blockIdx.x * 16 + 2 * cg;
+  __shared__ double Wp[4][32][33];
+  __shared__ double Rb[32][33];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int s0 = blockIdx.x * 32;
   const int nblk = (n + kTB - 1) / kTB;
   for (int b = nblk - 1; b >= 0; --b) {
     const int b0 = b * kTB;
     const int b1 = min(n, b0 + kTB);
-    const int gr = b0 + r;
-    double a0 = 0.0, a1 = 0.0;
-    if (gr < n) {
-      if (c0 < n) a0 = X[(size_t)gr * ld + c0];
-      if (c0 + 1 < n) a1 = X[(size_t)gr * ld + c0 + 1];
-      for (int k = b1; k < n; ++k) {
-        const double rv = R[(size_t)gr * ld + k];
-        if (c0 < n) a0 -= rv * X[(size_t)k * ld + c0];
-        if (c0 + 1 < n) a1 -= rv * X[(size_t)k * ld + c0 + 1];
+    v4d acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = b1 + wave * 4; k0 < n; k0 += 16) {
+      const int k = k0 + lk;
+      double av[2], bv[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int r = b0 + bi * 16 + lr;
+        av[bi] = (r < n && k < n) ? R[(size_t)r * ld + k] : 0.0;
+        const int cc = s0 + bi * 16 + lr;
+        bv[bi] = (k < n && cc < n) ? X[(size_t)k * ld + cc] : 0.0;
       }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
     }
-    tmp[r][2 * cg] = a0;
-    tmp[r][2 * cg + 1] = a1;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Wp[wave][bi * 16 + lk + 4 * e][bj * 16 + lr] = acc[bi][bj][e];
+    for (int idx = tid; idx < 32 * 32; idx += 256) {
+      const int r = idx >> 5, cc = idx & 31;
+      Rb[r][cc] = Rinv[(size_t)b * kTB * kTB + r * kTB + cc];
+    }
     __syncthreads();
-    double y0 = 0.0, y1 = 0.0;
-    const double* Ri = Rinv + (size_t)b * kTB * kTB + r * kTB;
-#pragma unroll 8
-    for (int s = 0; s < kTB; ++s) {
-      y0 += Ri[s] * tmp[s][2 * cg];
-      y1 += Ri[s] * tmp[s][2 * cg + 1];
+    for (int idx = tid; idx < 32 * 32; idx += 256) {
+      const int r = idx >> 5, cc = idx & 31;
+      const int gr = b0 + r, gc = s0 + cc;
+      const double xv = (gr < n && gc < n) ? X[(size_t)gr * ld + gc] : 0.0;
+      Wp[0][r][cc] = xv - (Wp[0][r][cc] + Wp[1][r][cc] + Wp[2][r][cc] + Wp[3][r][cc]);
     }
-    if (gr < n) {
-      if (c0 < n) X[(size_t)gr * ld + c0] = y0;
-      if (c0 + 1 < n) X[(size_t)gr * ld + c0 + 1] = y1;
+    __syncthreads();
+    for (int idx = tid; idx < 32 * 32; idx += 256) {
+      const int r = idx >> 5, cc = idx & 31;
+      double y = 0.0;
+#pragma unroll 8
+      for (int t = 0; t < 32; ++t) y += Rb[r][t] * Wp[0][t][cc];
+      const int gr = b0 + r, gc = s0 + cc;
+      if (gr < n && gc < n) X[(size_t)gr * ld + gc] = y;
     }
     __syncthreads();
   }
@@ -543,7 +585,7 @@ int trsm_upper_f64(kdqmc_ctx* c, int n, const double* R, double* X) {
   double* Rinv = c->Tq;  // nblk * 32 * 32 (the QR's T factors are no longer needed)
   const int e0 = prof_mark(c);
   hipLaunchKernelGGL(k_trinv_blocks, dim3(nblk), dim3(64), 0, c->stream, R, n, ld, Rinv);
-  hipLaunchKernelGGL(k_trsm_upper, dim3((n + 15) / 16), dim3(256), 0, c->stream, R, Rinv, X, n, ld);
+  hipLaunchKernelGGL(k_trsm_upper, dim3((n + 31) / 32), dim3(256), 0, c->stream, R, Rinv, X, n, ld);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;

@@ -40,16 +40,23 @@ __global__ void k_scale_cols(double* __restrict__ C, int n, const double* __rest
   if (idx < (size_t)n * n) C[idx] *= d[idx % n];
 }
 
-// squared column norms (one thread per column, rows looped: coalesced across threads)
-__global__ void k_colnorm2(const double* __restrict__ C, int n, double* __restrict__ nrm) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+// squared column norms: a workgroup owns 64 columns, its 4 waves split the
+// rows (lanes over columns: coalesced), partial sums combined in LDS
+__global__ void __launch_bounds__(256) k_colnorm2(const double* __restrict__ C, int n, double* __restrict__ nrm) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int r = 0; r < n; ++r) {
-    const double x = C[(size_t)r * n + c];
-    s += x * x;
+  if (c < n) {
+#pragma unroll 4
+    for (int r = wave; r < n; r += 4) {
+      const double x = C[(size_t)r * n + c];
+      s += x * x;
+    }
   }
-  nrm[c] = s;
+  part[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && c < n) nrm[c] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
 }
 
 // perm[rank] = column, descending norm, ties by column index (stable); n <= 2048
@@ -201,7 +208,7 @@ int udt_step(kdqmc_ctx* c, const double* Uin, const double* Din, const double* T
       KDQMC_TRY(launch_kinetic_f64(c, C, n, true, c->tab_mu64, evs, nullptr, nullptr));
   }
   hipLaunchKernelGGL(k_scale_cols, grid_for(nn), dim3(256), 0, c->stream, C, n, Din);
-  hipLaunchKernelGGL(k_colnorm2, dim3((n + 255) / 256), dim3(256), 0, c->stream, C, n, c->nrm);
+  hipLaunchKernelGGL(k_colnorm2, dim3((n + 63) / 64), dim3(256), 0, c->stream, C, n, c->nrm);
   hipLaunchKernelGGL(k_rank_perm, dim3(1), dim3(1024), 0, c->stream, c->nrm, n, c->perm);
   hipLaunchKernelGGL(k_gather_cols, grid_for(nn), dim3(256), 0, c->stream, Cp, C, n, c->perm);
   KDQMC_TRY(qr_f64(c, n, Cp, Uout));

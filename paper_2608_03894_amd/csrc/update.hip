@@ -65,10 +65,13 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
          int* __restrict__ win_a, int* __restrict__ win_p, double* __restrict__ Zg,
          double* __restrict__ Zpg) {
   constexpr int WM = 16 * WS;  // largest window this instance handles
-  __shared__ double rowp[WM], colp[WM], cfp[WM], crp[WM], diagL[WM], ul[WM];
+  // Everything the loop produces stays in LDS until the end: a barrier also
+  // waits for outstanding global stores, so none are issued inside the loop.
+  __shared__ double rowp[WM], colp[WM], cfp[WM], crp[WM], diagL[WM], ul[WM], rl[WM];
+  __shared__ double Zs[WM][WM + 1], Zps[WM][WM + 1];
   __shared__ int pl[WM];
   __shared__ int8_t sl[WM];
-  __shared__ uint8_t fl[WM];
+  __shared__ uint8_t fl[WM], al[WM];
   const int tid = threadIdx.x;
   const int rx = tid >> 4, cy = tid & 15;
   double gs[WS][WS], cf[WS][WS], cr[WS][WS];
@@ -108,8 +111,8 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     const double ratio = e2as * R * R;
     const bool a = forced ? (fl[p] != 0) : (ul[p] < ratio);
     if (tid == 0) {
-      if (ratio_out) ratio_out[w0 + p] = ratio;
-      if (acc_out) acc_out[w0 + p] = a ? 1 : 0;
+      rl[p] = ratio;
+      al[p] = a ? 1 : 0;
     }
     if (!a) continue;
     const double c = delta / R;
@@ -145,7 +148,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
       }
     }
     if (tid == 0) {
-      s_l[w0 + p] = int8_t(-s);
+      sl[p] = int8_t(-s);
       pl[n] = p;
     }
     __syncthreads();
@@ -173,8 +176,8 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
         if (x > p && y <= n) cr[i][k] -= c * cx[i] * zpy[k];
       }
     if (tid <= n) {
-      Zg[tid * W + n] = -c * ((tid == n ? 1.0 : 0.0) + cfp[tid]);
-      Zpg[n * W + tid] = (tid == n ? 1.0 : 0.0) - crp[tid];
+      Zs[tid][n] = -c * ((tid == n ? 1.0 : 0.0) + cfp[tid]);
+      Zps[n][tid] = (tid == n ? 1.0 : 0.0) - crp[tid];
     }
     if (rx == cy) {
 #pragma unroll
@@ -186,8 +189,19 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     ++na;
     __syncthreads();
   }
+  __syncthreads();
   if (tid == 0) win_a[win] = na;
   for (int n = tid; n < na; n += 256) win_p[win * W + n] = pl[n];
+  for (int p = tid; p < wn; p += 256) {
+    s_l[w0 + p] = sl[p];
+    if (ratio_out) ratio_out[w0 + p] = rl[p];
+    if (acc_out) acc_out[w0 + p] = al[p];
+  }
+  for (int idx = tid; idx < na * na; idx += 256) {
+    const int q = idx / na, n = idx % na;
+    if (q <= n) Zg[q * W + n] = Zs[q][n];
+    if (n <= q) Zpg[q * W + n] = Zps[q][n];
+  }
 }
 
 // ---------------------------------------------------------------------------
