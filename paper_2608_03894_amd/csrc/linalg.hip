@@ -151,17 +151,17 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
       a[q][cc] = (row[q] < n && cc < nbp) ? A[(size_t)row[q] * lda + j + cc] : 0.0;
   }
 
-#pragma unroll 1
-  for (int cc = 0; cc < nbp; ++cc) {
+  // fully unrolled over the panel's columns: every register index is static
+  // (columns at or beyond nbp are skipped by a uniform branch)
+#pragma clang loop unroll(full)
+  for (int cc = 0; cc < NB; ++cc) {
+    if (cc < nbp) {
     const int jc = j + cc;
     // one reduction gives ||a[jc:, cc]||^2 and the diagonal value a[jc, cc]
     double ss = 0.0, dg = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      double x = 0.0;
-#pragma unroll
-      for (int t = 0; t < NB; ++t)
-        if (t == cc) x = a[q][t];
+      const double x = a[q][cc];
       if (row[q] >= jc && row[q] < n) ss += x * x;
       if (row[q] == jc) dg = x;
     }
@@ -198,20 +198,13 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
     double vq[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      double x = 0.0;
-#pragma unroll
-      for (int t = 0; t < NB; ++t)
-        if (t == cc) x = a[q][t];
+      const double x = a[q][cc];
       double v;
       if (row[q] < jc || row[q] >= n) v = 0.0;
       else if (row[q] == jc) v = 1.0;
       else v = x * scale;
       vq[q] = v;
-      if (row[q] >= jc) {
-#pragma unroll
-        for (int t = 0; t < NB; ++t)
-          if (t == cc) a[q][t] = v;
-      }
+      if (row[q] >= jc) a[q][cc] = v;
     }
     // dots[t] = v^T (column t): earlier v's (t < cc) and trailing columns (t > cc)
     double part[NB];
@@ -256,12 +249,12 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      if (row[q] >= jc && row[q] < n) {
+    for (int t = cc + 1; t < NB; ++t) {
+      const double dt = tau_c * dots[t];
 #pragma unroll
-        for (int t = 0; t < NB; ++t)
-          if (t > cc) a[q][t] -= tau_c * vq[q] * dots[t];
-      }
+      for (int q = 0; q < RPT; ++q)
+        if (row[q] >= jc && row[q] < n) a[q][t] -= vq[q] * dt;
+    }
     }
   }
   // T of the block reflector from V^T V: T[cc][cc] = tau_cc,
