@@ -100,8 +100,8 @@ int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, 
 // Householder QR, blocked (compact WY form).
 //
 // Panels of width nbp (32 while the panel has at most 1024 rows, else 16) are
-// factored by one workgroup of 256 threads holding the panel in registers
-// (thread t owns rows j+t, j+t+256, ...).  H_c = I - tau_c v_c v_c^T with
+// factored by one workgroup of NT threads (128 for at most 512 rows, else 256)
+// holding the panel in registers (thread t owns rows j+t, j+t+NT, ...).  H_c = I - tau_c v_c v_c^T with
 // v_c[jc] = 1 (LAPACK convention); H_0 ... H_{nbp-1} = I - V T V^T.
 // Outputs: R in A (zeros below the diagonal), explicit V in Vq (unit diagonal,
 // zeros above), T in Tq (row stride 32), tau.
@@ -128,11 +128,11 @@ __device__ __forceinline__ double xchg_xor(double v, int mask) {
   return __shfl_xor(v, mask);
 }
 
-template <int RPT, int NB>
-__global__ void __launch_bounds__(kPanelThreads)
+template <int RPT, int NB, int NT>
+__global__ void __launch_bounds__(NT)
 k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __restrict__ Vq,
            double* __restrict__ Tq, double* __restrict__ tau_out) {
-  constexpr int NW = kPanelThreads / 64;
+  constexpr int NW = NT / 64;
   __shared__ double red2[2][NW][2];   // (norm^2, diagonal) partials, double-buffered
   __shared__ double redn[NW * NB];    // dot-product partials
   __shared__ double dots[NB];
@@ -145,7 +145,7 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
   int row[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
-    row[q] = j + tid + q * kPanelThreads;
+    row[q] = j + tid + q * NT;
 #pragma unroll
     for (int cc = 0; cc < NB; ++cc)
       a[q][cc] = (row[q] < n && cc < nbp) ? A[(size_t)row[q] * lda + j + cc] : 0.0;
@@ -290,7 +290,7 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
       Vq[(size_t)r * lda + jc] = vv;
     }
   }
-  for (int idx = tid; idx < kNBmax * kNBmax; idx += kPanelThreads) {
+  for (int idx = tid; idx < kNBmax * kNBmax; idx += NT) {
     const int r = idx / kNBmax, cc = idx % kNBmax;
     Tq[idx] = (r < nbp && cc < nbp) ? Ts[r][cc] : 0.0;
   }
@@ -300,20 +300,21 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
 // C[j:n, s0:s0+32] -= V op(T) (V^T C[j:n, s0:s0+32]) for the panel at column
 // j (width nbp <= 32): op(T) = T^T applies H^T = H_{nbp-1} ... H_0 (the
 // factorization / Q^T direction), op(T) = T applies H = H_0 ... H_{nbp-1}.
-// One workgroup (4 waves) per 32-column stripe.  W = V^T C: the waves split
+// One workgroup (8 waves) per 32-column stripe.  W = V^T C: the waves split
 // the rows and their partial 32 x 32 products are summed in LDS; then
 // C -= V W2 with the waves splitting the rows.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
            const double* __restrict__ V, int ldv, const double* __restrict__ T, int trans) {
-  __shared__ double Wp[4][32][33];
+  constexpr int NW = 8;
+  __shared__ double Wp[NW][32][33];
   __shared__ double W2[32][33];
   __shared__ double Tl[32][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int s0 = blockIdx.x * 32;
   const int m = n - j;
-  for (int idx = tid; idx < 32 * 32; idx += 256) {
+  for (int idx = tid; idx < 32 * 32; idx += 512) {
     const int r = idx >> 5, cc = idx & 31;
     Tl[r][cc] = (r < nbp && cc < nbp) ? T[r * kNBmax + cc] : 0.0;
   }
@@ -324,7 +325,7 @@ k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-  for (int kb = wave * 4; kb < m; kb += 16) {
+  for (int kb = wave * 4; kb < m; kb += 4 * NW) {
     const int r = j + kb + lk;
     double av[2], bv[2];
 #pragma unroll
@@ -347,13 +348,16 @@ k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
 #pragma unroll
       for (int e = 0; e < 4; ++e) Wp[wave][bi * 16 + lk + 4 * e][bj * 16 + lr] = acc[bi][bj][e];
   __syncthreads();
-  for (int idx = tid; idx < 32 * 32; idx += 256) {
+  for (int idx = tid; idx < 32 * 32; idx += 512) {
     const int r = idx >> 5, cc = idx & 31;
-    Wp[0][r][cc] = Wp[0][r][cc] + Wp[1][r][cc] + Wp[2][r][cc] + Wp[3][r][cc];
+    double sacc = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sacc += Wp[w][r][cc];
+    Wp[0][r][cc] = sacc;
   }
   __syncthreads();
   // W2 = op(T) W
-  for (int idx = tid; idx < 32 * 32; idx += 256) {
+  for (int idx = tid; idx < 32 * 32; idx += 512) {
     const int r = idx >> 5, cc = idx & 31;
     double sacc = 0.0;
     for (int t = 0; t < 32; ++t) sacc += (trans ? Tl[t][r] : Tl[r][t]) * Wp[0][t][cc];
@@ -362,7 +366,7 @@ k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
   __syncthreads();
   // C -= V W2, 16-row blocks split over waves
 #pragma unroll 2
-  for (int rb = wave * 16; rb < m; rb += 64) {
+  for (int rb = wave * 16; rb < m; rb += 16 * NW) {
     v4d d[2];
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) d[bj] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -405,12 +409,12 @@ int launch_panel(kdqmc_ctx* c, double* A, int ld, int n, int j, int nbp, double*
   const int m = n - j;
   const int e0 = prof_mark(c);
   if (nbp > 16) {
-    if (m <= 2 * kPanelThreads)
-      hipLaunchKernelGGL((k_qr_panel<2, 32>), dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+    if (m <= 512)
+      hipLaunchKernelGGL((k_qr_panel<4, 32, 128>), dim3(1), dim3(128), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
     else
-      hipLaunchKernelGGL((k_qr_panel<4, 32>), dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+      hipLaunchKernelGGL((k_qr_panel<4, 32, 256>), dim3(1), dim3(256), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
   } else {
-    hipLaunchKernelGGL((k_qr_panel<8, 16>), dim3(1), dim3(kPanelThreads), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+    hipLaunchKernelGGL((k_qr_panel<8, 16, 256>), dim3(1), dim3(256), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
   }
   prof_pair(c, PH_QR_PANEL, e0, prof_mark(c));
   return KDQMC_OK;
@@ -422,7 +426,7 @@ int launch_apply(kdqmc_ctx* c, double* C, int ld, int n, int j, int nbp, int col
   const int e0 = prof_mark(c);
   const int stripes = (ncols - col0 + 31) / 32;
   // the kernel indexes columns from C's base: shift the base to col0
-  hipLaunchKernelGGL(k_apply_wy, dim3(stripes), dim3(256), 0, c->stream, C + col0, ld, n, j, nbp,
+  hipLaunchKernelGGL(k_apply_wy, dim3(stripes), dim3(512), 0, c->stream, C + col0, ld, n, j, nbp,
                      ncols - col0, c->Vq, ld, Tp, trans ? 1 : 0);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   return KDQMC_OK;

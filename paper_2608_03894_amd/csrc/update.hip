@@ -49,14 +49,16 @@ __global__ void k_frame_scale(const int8_t* __restrict__ s, int n, double ea, do
 //   w_n = sum_q Z'[n][q] h_q,        Z'[n][q] = delta_nq - Cr[p][q],
 // and Gs, Cf, Cr receive rank-one updates on their live part (indices > p);
 // row p and column p of all three are never written again.
-// Register layout: thread t owns the WS x WS entries (x, y) with
-// x = t/16 + 16 i, y = t%16 + 16 k of each block.  Per accept the owners
+// Register layout: the NT threads form a GR x GR grid (GR = 8 for one wave,
+// 16 for four); thread t owns the WS x WS entries (x, y) with
+// x = t/GR + GR i, y = t%GR + GR k of each block.  Per accept the owners
 // publish row p / column p through LDS (barrier), everyone updates its
 // registers and the diagonal owners publish the new diagonal (barrier).  A
-// rejected flip reads one LDS word and needs no barrier.
+// rejected flip reads one LDS word and needs no barrier.  With a single wave
+// (windows of up to 32 sites) the barriers cost next to nothing.
 // ---------------------------------------------------------------------------
-template <typename T, int WS>
-__global__ void __launch_bounds__(256)
+template <typename T, int WS, int NT>
+__global__ void __launch_bounds__(NT)
 k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
          const double* __restrict__ evinv, int8_t* __restrict__ s_l,
          const double* __restrict__ u, const uint8_t* __restrict__ forced,
@@ -64,7 +66,8 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
          const double* __restrict__ Gs_in, double em2a, double ep2a, int win,
          int* __restrict__ win_a, int* __restrict__ win_p, double* __restrict__ Zg,
          double* __restrict__ Zpg) {
-  constexpr int WM = 16 * WS;  // largest window this instance handles
+  constexpr int GR = (NT == 64) ? 8 : 16;
+  constexpr int WM = GR * WS;  // largest window this instance handles
   // Everything the loop produces stays in LDS until the end: a barrier also
   // waits for outstanding global stores, so none are issued inside the loop.
   __shared__ double rowp[WM], colp[WM], cfp[WM], crp[WM], diagL[WM], ul[WM], rl[WM];
@@ -73,13 +76,13 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
   __shared__ int8_t sl[WM];
   __shared__ uint8_t fl[WM], al[WM];
   const int tid = threadIdx.x;
-  const int rx = tid >> 4, cy = tid & 15;
+  const int rx = tid / GR, cy = tid % GR;
   double gs[WS][WS], cf[WS][WS], cr[WS][WS];
 #pragma unroll
   for (int i = 0; i < WS; ++i)
 #pragma unroll
     for (int k = 0; k < WS; ++k) {
-      const int x = rx + 16 * i, y = cy + 16 * k;
+      const int x = rx + GR * i, y = cy + GR * k;
       double g = 0.0;
       if (x < wn && y < wn) {
         if (Gs_in) {
@@ -94,7 +97,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
       cr[i][k] = 0.0;
       if (x == y && x < wn) diagL[x] = g;
     }
-  for (int p = tid; p < wn; p += 256) {
+  for (int p = tid; p < wn; p += NT) {
     sl[p] = s_l[w0 + p];
     ul[p] = u ? u[w0 + p] : 0.0;
     fl[p] = forced ? forced[w0 + p] : 0;
@@ -117,7 +120,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     if (!a) continue;
     const double c = delta / R;
     const int n = na;
-    const int ip = p >> 4, pr = p & 15;
+    const int ip = p / GR, pr = p % GR;
     // phase A: publish row p of Gs and Cr, column p of Gs and Cf
     if (rx == pr) {
 #pragma unroll
@@ -129,8 +132,8 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
             g = gs[i][k];
             r = cr[i][k];
           }
-        rowp[cy + 16 * k] = g;
-        crp[cy + 16 * k] = r;
+        rowp[cy + GR * k] = g;
+        crp[cy + GR * k] = r;
       }
     }
     if (cy == pr) {
@@ -143,8 +146,8 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
             g = gs[i][k];
             f = cf[i][k];
           }
-        colp[rx + 16 * i] = g;
-        cfp[rx + 16 * i] = f;
+        colp[rx + GR * i] = g;
+        cfp[rx + GR * i] = f;
       }
     }
     if (tid == 0) {
@@ -156,13 +159,13 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     double cx[WS], qx[WS], ry[WS], zpy[WS];
 #pragma unroll
     for (int i = 0; i < WS; ++i) {
-      const int x = rx + 16 * i;
+      const int x = rx + GR * i;
       cx[i] = colp[x];
       qx[i] = -c * ((x == n ? 1.0 : 0.0) + cfp[x]);   // Z[x][n] (rows q = x of Cf)
     }
 #pragma unroll
     for (int k = 0; k < WS; ++k) {
-      const int y = cy + 16 * k;
+      const int y = cy + GR * k;
       ry[k] = rowp[y];
       zpy[k] = (y == n ? 1.0 : 0.0) - crp[y];        // Z'[n][y] (columns q = y of Cr)
     }
@@ -170,7 +173,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     for (int i = 0; i < WS; ++i)
 #pragma unroll
       for (int k = 0; k < WS; ++k) {
-        const int x = rx + 16 * i, y = cy + 16 * k;
+        const int x = rx + GR * i, y = cy + GR * k;
         if (x > p && y > p) gs[i][k] += c * cx[i] * ry[k];
         if (x <= n && y > p) cf[i][k] -= qx[i] * ry[k];
         if (x > p && y <= n) cr[i][k] -= c * cx[i] * zpy[k];
@@ -182,7 +185,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     if (rx == cy) {
 #pragma unroll
       for (int i = 0; i < WS; ++i) {
-        const int x = rx + 16 * i;
+        const int x = rx + GR * i;
         if (x > p && x < wn) diagL[x] = gs[i][i];
       }
     }
@@ -191,13 +194,13 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
   }
   __syncthreads();
   if (tid == 0) win_a[win] = na;
-  for (int n = tid; n < na; n += 256) win_p[win * W + n] = pl[n];
-  for (int p = tid; p < wn; p += 256) {
+  for (int n = tid; n < na; n += NT) win_p[win * W + n] = pl[n];
+  for (int p = tid; p < wn; p += NT) {
     s_l[w0 + p] = sl[p];
     if (ratio_out) ratio_out[w0 + p] = rl[p];
     if (acc_out) acc_out[w0 + p] = al[p];
   }
-  for (int idx = tid; idx < na * na; idx += 256) {
+  for (int idx = tid; idx < na * na; idx += NT) {
     const int q = idx / na, n = idx % na;
     if (q <= n) Zg[q * W + n] = Zs[q][n];
     if (n <= q) Zpg[q * W + n] = Zps[q][n];
@@ -455,15 +458,15 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
     // decide
     const int e_d = prof_mark(c);
     if (wn <= 16)
-      hipLaunchKernelGGL((k_decide<T, 1>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
+      hipLaunchKernelGGL((k_decide<T, 2, 64>), dim3(1), dim3(64), 0, c->stream, G, N, c->ev, c->evinv,
                          s_l, u, forced, acc, ratio, w0, wn, W, first_in_group ? nullptr : c->Gs,
                          em2a, ep2a, win, c->win_a, c->win_p, c->Xw, c->Yw);
     else if (wn <= 32)
-      hipLaunchKernelGGL((k_decide<T, 2>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
+      hipLaunchKernelGGL((k_decide<T, 4, 64>), dim3(1), dim3(64), 0, c->stream, G, N, c->ev, c->evinv,
                          s_l, u, forced, acc, ratio, w0, wn, W, first_in_group ? nullptr : c->Gs,
                          em2a, ep2a, win, c->win_a, c->win_p, c->Xw, c->Yw);
     else
-      hipLaunchKernelGGL((k_decide<T, 4>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
+      hipLaunchKernelGGL((k_decide<T, 4, 256>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
                          s_l, u, forced, acc, ratio, w0, wn, W, first_in_group ? nullptr : c->Gs,
                          em2a, ep2a, win, c->win_a, c->win_p, c->Xw, c->Yw);
     const int e_e = prof_mark(c);
