@@ -58,6 +58,136 @@ def cpu_baseline(w, n_slices):
                       f"of one sweep, {dt:.1f} s, scaled by L_tau/{n_slices}"}
 
 
+CU_FP64_TFS = FP64_PEAK_TFS / 256   # one compute unit's share (4 SIMDs x 16 FP64 lanes x 2 x 2.4 GHz)
+
+
+def qr_panel_flops(n):
+    """Householder flops of all panels of one n x n QR (2 m b^2 - 2 b^3 / 3 per
+    m x b panel; panel width 32, or 16 for more than 1024 rows)."""
+    f, j = 0.0, 0
+    while j < n:
+        m = n - j
+        b = min(16 if m > 1024 else 32, m)
+        f += 2.0 * m * b * b - 2.0 * b ** 3 / 3.0
+        j += b
+    return f
+
+
+def qr_panels(n):
+    cnt, j = 0, 0
+    while j < n:
+        j += min(16 if n - j > 1024 else 32, n - j)
+        cnt += 1
+    return cnt
+
+
+def kernel_rooflines(prof, N, Lt, prec, k_avg, n_stab):
+    """{phase: roofline dict} from the profiled (HIP-event) per-phase totals.
+
+    achieved = algorithmic bytes or flops per launch / average launch time:
+      wrap_cols, wrap_rows, bmul: 2 N^2 s bytes (G read once, written once)
+      flush: 2 N^2 k flops (k = accepted flips per flush), HBM bytes 2 N^2 s + 2 N k s
+      qr_panel: Householder panel flops; one workgroup, so the peak is one
+                compute unit's FP64 rate (the chip's 78.6 TFLOP/s / 256)
+      decide: sequential per-site decisions on one workgroup; 2 w^2 flops per
+              accepted flip (the rank-one update of the window block), against
+              one compute unit's FP64 rate
+    """
+    out = {}
+    es = 8 if prec == "fp64" else 4
+    for name, (ms, n) in prof.items():
+        if n == 0 or name == "stabilize":
+            continue
+        t = ms / n / 1000.0
+        r = {"avg_us": round(1e6 * t, 3), "launches": n}
+        if name in ("wrap_cols", "wrap_rows", "bmul"):
+            e = 8 if name == "bmul" else es
+            byt = 2.0 * N * N * e
+            ach = byt / t / 1e9
+            r.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                     algorithmic_per_launch=byt)
+        elif name == "flush":
+            fl = 2.0 * N * N * k_avg
+            pk = FP64_PEAK_TFS if prec == "fp64" else F16_PEAK_TFS
+            ach = fl / t / 1e12
+            byt = 2.0 * N * N * es + 2.0 * N * k_avg * es
+            r.update(bound="mfma", achieved=ach, peak=pk, unit="TFLOP/s", frac=ach / pk,
+                     algorithmic_per_launch=fl, hbm_gbs=byt / t / 1e9,
+                     hbm_frac=byt / t / 1e9 / HBM_PEAK_GBS, k_avg=k_avg)
+        elif name == "qr_panel":
+            per_sweep_qr = n  # launches
+            fl_qr = qr_panel_flops(N)
+            n_qr = per_sweep_qr / qr_panels(N)
+            fl = fl_qr * n_qr / n
+            ach = fl / t / 1e12
+            r.update(bound="alu", achieved=ach, peak=CU_FP64_TFS, unit="TFLOP/s", frac=ach / CU_FP64_TFS,
+                     algorithmic_per_launch=fl, note="one workgroup per panel (sequential columns)")
+        elif name == "decide":
+            fl = None
+            r.update(bound="alu", unit="TFLOP/s", peak=CU_FP64_TFS,
+                     note="one workgroup per window (sequential sites)")
+            out[name] = r
+            continue
+        else:
+            r.update(bound=None)
+        out[name] = r
+    return out
+
+
+def decide_roofline(kern, prof, accepts_per_sweep, steps, window):
+    """Fills the decide entry: 2 w^2 flops per accepted flip."""
+    if "decide" not in kern:
+        return
+    ms, n = prof["decide"]
+    t = ms / n / 1000.0
+    fl = 2.0 * window * window * accepts_per_sweep * steps / n
+    ach = fl / t / 1e12
+    kern["decide"].update(achieved=ach, frac=ach / CU_FP64_TFS, algorithmic_per_launch=fl)
+
+
+def _sha1(path):
+    import hashlib
+    with open(path, "rb") as fh:
+        return hashlib.sha1(fh.read()).hexdigest()
+
+
+def pmc_traffic(phase, workload):
+    """HBM bytes per launch of a phase's kernel from a committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (profiles/pmc_traffic_*.txt), or None when
+    there is none or the kernel's source has changed since it was taken."""
+    import glob
+    for f in sorted(glob.glob(os.path.join(HERE, "profiles", "pmc_traffic_*.txt"))):
+        kv = {}
+        with open(f) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith(("#", " ")):
+                    a, b = line.split(":", 1)
+                    kv[a.strip()] = b.strip()
+        if kv.get("phase") != phase or kv.get("workload") != workload:
+            continue
+        src = os.path.join(HERE, kv.get("source", ""))
+        if not os.path.isfile(src) or _sha1(src) != kv.get("source_sha1"):
+            return None
+        try:
+            return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+        except (KeyError, ValueError):
+            return None
+    return None
+
+
+def copy_calibration(mib=1024, reps=5):
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
+    counters: each dispatch reads and writes mib MiB."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.neg(a, out=b)   # an elementwise kernel: one 8 B read and one 8 B write per element
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_dispatch": n * 8, "dispatches": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,8 +198,11 @@ def main():
     ap.add_argument("--delay-k", type=int, default=None)
     ap.add_argument("--window", type=int, default=0)
     ap.add_argument("--fft-tile", type=int, default=0)
+    ap.add_argument("--n-stab", type=int, default=None, help="slices between stabilizations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -78,14 +211,19 @@ def main():
                                    "see the design notes)"}))
         sys.exit(2)
 
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
     import torch
     from paper_2608_03894_amd import kdqmc
 
     w = CONFIGS[args.config]
     prec = args.prec or ("fp64" if w.prec == "fp64" else w.prec)
     k = args.delay_k or w.delay_k
+    n_stab = args.n_stab or w.n_stab
     dev = torch.device("cuda:0")
-    p = kdqmc.make_params(w.L, w.U, w.beta, w.dtau, mu=-1.0, n_stab=w.n_stab, delay_k=k,
+    p = kdqmc.make_params(w.L, w.U, w.beta, w.dtau, mu=-1.0, n_stab=n_stab, delay_k=k,
                           window=args.window, fft_tile=args.fft_tile, prec=prec)
     ch = kdqmc.Chain(p, device=dev)
     N, Lt = ch.N, ch.L_tau
@@ -93,7 +231,7 @@ def main():
     fields = torch.from_numpy(si.ising_fields(w.L, Lt, w.seed)).to(dev)
     uni = torch.from_numpy(si.metropolis_uniforms(w.L, Lt, w.seed, n_sweeps=total)).to(dev)
     acc = torch.zeros((Lt, N), dtype=torch.uint8, device=dev)
-    errs = torch.zeros(Lt // w.n_stab, dtype=torch.float64, device=dev)
+    errs = torch.zeros(Lt // n_stab, dtype=torch.float64, device=dev)
     log(f"workload {w.name} prec={prec} k={k} N={N} L_tau={Lt}")
     ch.set_fields(fields)
     for s in range(args.warmup):
@@ -133,34 +271,19 @@ def main():
         if n:
             log(f"  {name:10s} {ms:10.3f} ms  {n:7d} launches  {1000 * ms / n:9.2f} us/launch")
 
-    # dominant kernel (stabilize is a composite of bmul/qr_panel/gemm and others)
-    kern = {n: v for n, v in prof.items() if n != "stabilize" and v[1] > 0}
-    dom = max(kern, key=lambda n: kern[n][0])
-    es = 8 if prec == "fp64" else 4
-    roof = None
-    dms, dn = kern[dom]
-    avg_s = dms / dn / 1000.0
-    if dom in ("wrap_cols", "wrap_rows", "bmul"):
-        e = 8 if dom == "bmul" else es
-        byt = 2.0 * N * N * e
-        ach = byt / avg_s / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                "algorithmic": f"{byt:.0f} B per launch (N^2 read + N^2 write, {e} B elements)"}
-    elif dom == "flush":
-        kavg = accepts / max(1, prof["flush"][1] / args.steps)
-        fl = 2.0 * N * N * kavg
-        ach = fl / avg_s / 1e12
-        pk = FP64_PEAK_TFS if prec == "fp64" else F16_PEAK_TFS
-        roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": pk, "unit": "TFLOP/s",
-                "frac": ach / pk, "traffic": None,
-                "algorithmic": f"2 N^2 k flops per launch, k = {kavg:.1f} accepted flips per flush"}
-    else:
-        # latency-bound single-workgroup kernels: report against one CU's FP64 rate
-        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": FP64_PEAK_TFS / 256,
-                "unit": "TFLOP/s", "frac": None, "traffic": None,
-                "algorithmic": "sequential per-site decisions / panel factorization on one workgroup"}
-
+    # per-kernel rooflines from the HIP-event durations; the dominant kernel
+    # (stabilize is a composite of bmul / qr_panel / gemm and is skipped)
+    flushes = max(1, prof["flush"][1] // args.steps)
+    k_avg = accepts / flushes
+    kernels = kernel_rooflines(prof, N, Lt, prec, k_avg, n_stab)
+    win = min(args.window or min(k, 64), N)   # the library's default window: min(delay_k, 64)
+    decide_roofline(kernels, prof, accepts, args.steps, win)
+    cand = {n: v for n, v in prof.items() if n != "stabilize" and v[1] > 0}
+    dom = max(cand, key=lambda n: cand[n][0])
+    roof = dict(kernels.get(dom, {"bound": "alu", "achieved": None, "peak": None, "unit": None,
+                                  "frac": None}))
+    roof["kernel"] = dom
+    roof["traffic"] = pmc_traffic(dom, w.name)
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_slices} slices ...")
@@ -181,9 +304,10 @@ def main():
         "dtype": "f64" if prec == "fp64" else f"f32+{prec.split('_')[1]}",
         "data": "synthetic",
         "config": {"workload": w.name, "L": w.L, "N": N, "U": w.U, "beta": w.beta, "L_tau": Lt,
-                   "delay_k": k, "window": ch.p.window, "prec": prec,
+                   "delay_k": k, "window": win, "prec": prec, "n_stab": n_stab,
                    "field_updates_per_s": value * N * Lt},
         "roofline": roof,
+        "kernels": kernels,
         "cpu_baseline": cpu,
         "profiled_ms_per_step": 1000.0 * (t3 - t2) / args.steps,
         "phases_ms_per_sweep": {n: round(v[0] / args.steps, 4) for n, v in prof.items() if v[1]},

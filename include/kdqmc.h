@@ -101,13 +101,17 @@ int kdqmc_get_fields(kdqmc_ctx* c, int8_t* s_dev);
 
 /* Loads an externally computed G(l) (FP64, N x N row-major) and sets the
  * current slice to l (0 <= l <= L_tau).  The stabilization stacks are not
- * touched (they must come from kdqmc_set_fields for kdqmc_stabilize). */
+ * touched (they must come from kdqmc_set_fields for kdqmc_stabilize); the
+ * next stabilization due becomes the first one after slice l if that is
+ * earlier than the one already due. */
 int kdqmc_set_G(kdqmc_ctx* c, const double* G_dev, int l);
 
 /* G(l) = B_l G(l-1) B_l^{-1} with unchanged fields: the column pass applies
  * exp(V_l) then exp(-dtau K) to every column (batched 2D FFTs, 3x3 block
  * multiply, inverse FFTs), the row pass applies exp(+dtau K) to every row
- * (exp(dtau K) is symmetric).  Requires l == current slice + 1. */
+ * (exp(dtau K) is symmetric).  Requires l == current slice + 1, and
+ * KDQMC_ESTATE if slice l - 1 is a multiple of n_stab whose kdqmc_stabilize
+ * call has not been made (the same holds for kdqmc_sweep_slice). */
 int kdqmc_wrap_slice(kdqmc_ctx* c, int l);
 
 /* One slice of the Monte Carlo sweep (requires l == current slice + 1):
@@ -124,7 +128,9 @@ int kdqmc_sweep_slice(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* f
                       uint8_t* accepted_dev, double* ratio_dev);
 
 /* Recomputes G(l) in FP64 for the current slice l (l must be a multiple of
- * n_stab, l > 0) from the QR-stabilized stacks (UDT form, pre-pivoted
+ * n_stab, l > 0, and every earlier multiple since kdqmc_set_fields or the
+ * last sweep end must have been stabilized, else KDQMC_ESTATE) from the
+ * QR-stabilized stacks (UDT form, pre-pivoted
  * Householder QR, Loh-Gubernatis scale separation), writes
  * max |G_current - G_fresh| to wrap_err_dev[0] (float64, optional) and
  * replaces G.  At l == L_tau it also rebuilds the left stack from the new

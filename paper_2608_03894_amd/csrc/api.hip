@@ -291,6 +291,7 @@ int kdqmc_set_fields(kdqmc_ctx* c, const int8_t* s_dev) {
   KDQMC_TRY(stab_green(c, 0, c->G64));
   KDQMC_TRY(copy_64_to_G(c, c->G64));
   c->l_cur = 0;
+  c->stab_next = 1;
   c->stacks_valid = true;
   return KDQMC_OK;
 }
@@ -308,6 +309,17 @@ int kdqmc_set_G(kdqmc_ctx* c, const double* G_dev, int l) {
   if (l < 0 || l > c->Ltau) return set_error(KDQMC_EINVAL, "slice index out of range");
   KDQMC_TRY(copy_64_to_G(c, G_dev));
   c->l_cur = l;
+  // stack entries up to slice l stay valid; later ones are rebuilt in order
+  c->stab_next = std::min(c->stab_next, l / c->p.n_stab + 1);
+  return KDQMC_OK;
+}
+
+// A slice step may not pass over a stabilization that is due: the right
+// stack entry it would build is needed by every later stabilization.
+static int check_stab_due(kdqmc_ctx* c, int l) {
+  const int lp = l - 1;
+  if (lp > 0 && lp % c->p.n_stab == 0 && lp / c->p.n_stab >= c->stab_next)
+    return set_error(KDQMC_ESTATE, "kdqmc_stabilize is due at the current slice");
   return KDQMC_OK;
 }
 
@@ -328,6 +340,7 @@ int kdqmc_wrap_slice(kdqmc_ctx* c, int l) {
   KDQMC_TRY(check_ctx(c));
   if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded (set_fields or set_G first)");
   if (l != c->l_cur + 1 || l > c->Ltau) return set_error(KDQMC_ESTATE, "wrap_slice needs l == current slice + 1");
+  KDQMC_TRY(check_stab_due(c, l));
   KDQMC_TRY(launch_frame_scale(c, l));
   KDQMC_TRY(wrap_pass(c));
   c->l_cur = l;
@@ -339,6 +352,7 @@ int kdqmc_sweep_slice(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* f
   KDQMC_TRY(check_ctx(c));
   if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded (set_fields or set_G first)");
   if (l != c->l_cur + 1 || l > c->Ltau) return set_error(KDQMC_ESTATE, "sweep_slice needs l == current slice + 1");
+  KDQMC_TRY(check_stab_due(c, l));
   if (!u_dev && !forced_dev) return set_error(KDQMC_EINVAL, "need uniforms or forced decisions");
   KDQMC_TRY(launch_frame_scale(c, l));
   KDQMC_TRY(run_slice_updates(c, l, u_dev, forced_dev, accepted_dev, ratio_dev));
@@ -360,13 +374,17 @@ static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev) {
   const int l = c->l_cur;
   if (l <= 0 || l % c->p.n_stab != 0) return set_error(KDQMC_ESTATE, "stabilize needs the current slice to be a positive multiple of n_stab");
   const int j = l / c->p.n_stab;
+  if (j != c->stab_next)
+    return set_error(KDQMC_ESTATE, "an earlier stabilization was skipped (each multiple of n_stab needs one, in order)");
   KDQMC_TRY(stab_right_step(c, j));
   KDQMC_TRY(stab_green(c, j, c->G64));
   if (wrap_err_dev) KDQMC_TRY(max_abs_diff(c, c->G64, c->N, wrap_err_dev));
   KDQMC_TRY(copy_64_to_G(c, c->G64));
+  c->stab_next = j + 1;
   if (j == c->nc) {
     KDQMC_TRY(stab_build_left(c));
     c->l_cur = 0;
+    c->stab_next = 1;
   }
   return KDQMC_OK;
 }
@@ -416,6 +434,7 @@ int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, ui
     if (rc != KDQMC_OK) {
       if (g) (void)hipGraphDestroy(g);
       c->l_cur = 0;
+      c->stab_next = 1;
       return rc;
     }
     if (ec != hipSuccess) return set_error(KDQMC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));

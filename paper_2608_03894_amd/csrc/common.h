@@ -145,6 +145,7 @@ struct kdqmc_ctx {
   hipStream_t stream = nullptr;
   int l_cur = -1;
   bool stacks_valid = false;
+  int stab_next = 1;        // index j of the next stabilization due (at slice j * n_stab)
   bool fp64 = true;
 
   // device buffers (carved from the caller's workspace)

@@ -100,8 +100,8 @@ int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, 
 // Householder QR, blocked (compact WY form).
 //
 // Panels of width nbp (32 while the panel has at most 1024 rows, else 16) are
-// factored by one workgroup of NT threads (128 for at most 512 rows, else 256)
-// holding the panel in registers (thread t owns rows j+t, j+t+NT, ...).  H_c = I - tau_c v_c v_c^T with
+// factored by one workgroup of NT = 256, 512 or 1024 threads holding the
+// panel in registers (thread t owns rows j+t and j+t+NT).  H_c = I - tau_c v_c v_c^T with
 // v_c[jc] = 1 (LAPACK convention); H_0 ... H_{nbp-1} = I - V T V^T.
 // Outputs: R in A (zeros below the diagonal), explicit V in Vq (unit diagonal,
 // zeros above), T in Tq (row stride 32), tau.
@@ -128,19 +128,44 @@ __device__ __forceinline__ double xchg_xor(double v, int mask) {
   return __shfl_xor(v, mask);
 }
 
+// Reads lane `src` (a compile-time constant) of a double held in a vector
+// register; the value is wave-uniform afterwards (scalar registers).
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// One panel of the Householder QR.  Column c (row jc = j + c) needs, over
+// the rows r >= jc, the dot products d_t = sum_r a_c[r] a_t[r] with every
+// column t of the panel, and the row jc itself.  With alpha = a_c[jc],
+// beta = -sign(alpha) sqrt(d_c) and u = a_c - beta e_jc (rows >= jc):
+//   v_c = u / (alpha - beta),   tau_c = (beta - alpha) / beta,
+//   v_c^T a_t = (d_t - beta a_t[jc]) / (alpha - beta),
+// the last being the Householder coefficient of a trailing column t and,
+// for an earlier column t (which holds v_t below its diagonal), the entry
+// (V^T V)[t][c] of the T factor.  So every column costs one workgroup-wide
+// reduction of NB sums and one barrier (the reduction buffers and the
+// published row are double-buffered).
+//
+// Register positions are static: the panel is processed in groups of U
+// columns, and after each group the per-thread register array is rotated by
+// U, so physical position p holds column g*U + p (mod NB) during group g.
 template <int RPT, int NB, int NT>
 __global__ void __launch_bounds__(NT)
 k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __restrict__ Vq,
            double* __restrict__ Tq, double* __restrict__ tau_out) {
   constexpr int NW = NT / 64;
-  __shared__ double red2[2][NW][2];   // (norm^2, diagonal) partials, double-buffered
-  __shared__ double redn[NW * NB];    // dot-product partials
-  __shared__ double dots[NB];
-  __shared__ double Sv[NB][NB + 1];   // V^T V (column cc of rows < cc)
+  constexpr int U = 4;
+  static_assert(NB % U == 0 && NB <= kNBmax && NT >= NB, "panel shape");
+  __shared__ double red[2][NW][NB];   // per-wave partial sums d_t
+  __shared__ double rowv[2][NB];      // row jc of the panel
+  __shared__ double Sv[NB][NB + 1];   // V^T V, strict upper part
   __shared__ double Ts[NB][NB + 1];
   __shared__ double betas[NB];
   __shared__ double taus[NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int pl = lane & (NB - 1);     // the sum this lane ends up holding
   double a[RPT][NB];
   int row[RPT];
 #pragma unroll
@@ -151,112 +176,110 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
       a[q][cc] = (row[q] < n && cc < nbp) ? A[(size_t)row[q] * lda + j + cc] : 0.0;
   }
 
-  // fully unrolled over the panel's columns: every register index is static
-  // (columns at or beyond nbp are skipped by a uniform branch)
+  const int ngroups = (nbp + U - 1) / U;
+#pragma unroll 1
+  for (int g = 0; g < ngroups; ++g) {
+    const int live = NB - g * U;  // positions below this hold columns not yet factored
 #pragma clang loop unroll(full)
-  for (int cc = 0; cc < NB; ++cc) {
-    if (cc < nbp) {
-    const int jc = j + cc;
-    // one reduction gives ||a[jc:, cc]||^2 and the diagonal value a[jc, cc]
-    double ss = 0.0, dg = 0.0;
+    for (int i = 0; i < U; ++i) {
+      const int c = g * U + i;
+      if (c < nbp) {
+        const int jc = j + c;
+        const int buf = c & 1;
+        if (tid == c) {  // owner of row jc (its first row)
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const double x = a[q][cc];
-      if (row[q] >= jc && row[q] < n) ss += x * x;
-      if (row[q] == jc) dg = x;
-    }
+          for (int p = 0; p < NB; ++p) rowv[buf][p] = a[0][p];
+        }
+        double x[RPT];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      ss += xchg_xor(ss, o);
-      dg += xchg_xor(dg, o);
-    }
-    const int buf = cc & 1;
-    if (lane == 0) {
-      red2[buf][wave][0] = ss;
-      red2[buf][wave][1] = dg;
-    }
-    __syncthreads();
-    ss = 0.0;
-    double alpha = 0.0;
+        for (int q = 0; q < RPT; ++q) x[q] = (row[q] >= jc && row[q] < n) ? a[q][i] : 0.0;
+        double part[NB];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      ss += red2[buf][w][0];
-      alpha += red2[buf][w][1];
-    }
-    const double sub = ss - alpha * alpha;
-    double tau_c, beta, scale;
-    if (!(sub > 0.0)) {  // nothing below the diagonal: H = I
-      tau_c = 0.0;
-      beta = alpha;
-      scale = 0.0;
-    } else {
-      const double nrm = sqrt(ss);
-      beta = (alpha >= 0.0) ? -nrm : nrm;
-      tau_c = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    double vq[RPT];
+        for (int p = 0; p < NB; ++p) {
+          double sacc = 0.0;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const double x = a[q][cc];
-      double v;
-      if (row[q] < jc || row[q] >= n) v = 0.0;
-      else if (row[q] == jc) v = 1.0;
-      else v = x * scale;
-      vq[q] = v;
-      if (row[q] >= jc) a[q][cc] = v;
-    }
-    // dots[t] = v^T (column t): earlier v's (t < cc) and trailing columns (t > cc)
-    double part[NB];
+          for (int q = 0; q < RPT; ++q) sacc = fma(x[q], a[q][p], sacc);
+          part[p] = sacc;
+        }
+        // reduce-scatter within the wave: lane l keeps sum number l % NB
+        {
+          int cnt = NB;
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
-      double s = 0.0;
+          for (int b = 0; (1 << b) < NB; ++b) {
+            const int bit = (lane >> b) & 1;
+            cnt >>= 1;
 #pragma unroll
-      for (int q = 0; q < RPT; ++q) s += vq[q] * a[q][t];
-      part[t] = s;
-    }
-    {
-      int cnt = NB;
+            for (int h = 0; h < NB / 2; ++h) {
+              if (h < cnt) {
+                const double keep = bit ? part[2 * h + 1] : part[2 * h];
+                const double send = bit ? part[2 * h] : part[2 * h + 1];
+                part[h] = keep + xchg_xor(send, 1 << b);
+              }
+            }
+          }
+          double v = part[0];
 #pragma unroll
-      for (int b = 0; (1 << b) < NB; ++b) {
-        const int bit = (lane >> b) & 1;
-        cnt >>= 1;
+          for (int o = NB; o < 64; o <<= 1) v += xchg_xor(v, o);
+          if (lane < NB) red[buf][wave][lane] = v;
+        }
+        __syncthreads();
+        double tot = 0.0;
 #pragma unroll
-        for (int i = 0; i < NB / 2; ++i) {
-          if (i < cnt) {
-            const double keep = bit ? part[2 * i + 1] : part[2 * i];
-            const double send = bit ? part[2 * i] : part[2 * i + 1];
-            part[i] = keep + xchg_xor(send, 1 << b);
+        for (int w = 0; w < NW; ++w) tot += red[buf][w][pl];
+        const double rv = rowv[buf][pl];
+        const double ss = lane_value(tot, i);
+        const double alpha = lane_value(rv, i);
+        double tau_c, beta, scale;
+        if (!(ss - alpha * alpha > 0.0)) {  // nothing below the diagonal: H = I
+          tau_c = 0.0;
+          beta = alpha;
+          scale = 0.0;
+        } else {
+          const double nrm = sqrt(ss);
+          beta = (alpha >= 0.0) ? -nrm : nrm;
+          tau_c = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
+        const double wv = (tot - beta * rv) * scale;  // v_c^T a_t, t at position pl
+        const double tw = -tau_c * wv;
+        if (wave == 0 && lane < NB) {
+          if (lane < i) Sv[g * U + lane][c] = wv;
+          else if (lane >= live) Sv[g * U + lane - NB][c] = wv;
+        }
+        if (tid == 0) {
+          betas[c] = beta;
+          taus[c] = tau_c;
+        }
+        double vq[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          const int r = row[q];
+          const double v = (r < jc || r >= n) ? 0.0 : (r == jc ? 1.0 : a[q][i] * scale);
+          vq[q] = v;
+          if (r >= jc) a[q][i] = v;
+        }
+#pragma clang loop unroll(full)
+        for (int p = i + 1; p < NB; ++p) {
+          if (p < live) {
+            const double f = lane_value(tw, p);
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) a[q][p] = fma(f, vq[q], a[q][p]);
           }
         }
       }
-      double v = part[0];
-#pragma unroll
-      for (int o = NB; o < 64; o <<= 1) v += xchg_xor(v, o);
-      if (lane < NB) redn[wave * NB + lane] = v;
     }
-    __syncthreads();
-    if (tid < NB) {
-      double sacc = 0.0;
 #pragma unroll
-      for (int w = 0; w < NW; ++w) sacc += redn[w * NB + tid];
-      dots[tid] = sacc;
-      if (tid < cc) Sv[tid][cc] = sacc;  // (V^T V)[tid][cc]
-    }
-    if (tid == 0) {
-      betas[cc] = beta;
-      taus[cc] = tau_c;
-    }
-    __syncthreads();
+    for (int q = 0; q < RPT; ++q) {
+      double keep[U];
 #pragma unroll
-    for (int t = cc + 1; t < NB; ++t) {
-      const double dt = tau_c * dots[t];
+      for (int u = 0; u < U; ++u) keep[u] = a[q][u];
 #pragma unroll
-      for (int q = 0; q < RPT; ++q)
-        if (row[q] >= jc && row[q] < n) a[q][t] -= vq[q] * dt;
-    }
+      for (int p = 0; p + U < NB; ++p) a[q][p] = a[q][p + U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) a[q][NB - U + u] = keep[u];
     }
   }
+  __syncthreads();
   // T of the block reflector from V^T V: T[cc][cc] = tau_cc,
   // T[0:cc, cc] = -tau_cc T[0:cc, 0:cc] (V^T V)[0:cc, cc]  (one wave, no barriers)
   if (wave == 0) {
@@ -274,19 +297,21 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
     }
   }
   __syncthreads();
+  const int rot = (ngroups * U) % NB;  // position p now holds column (p + rot) % NB
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = row[q];
     if (r >= n) continue;
 #pragma unroll
-    for (int cc = 0; cc < NB; ++cc) {
+    for (int p = 0; p < NB; ++p) {
+      const int cc = (p + rot < NB) ? p + rot : p + rot - NB;
       if (cc >= nbp) continue;
       const int jc = j + cc;
-      double rv, vv;
-      if (r < jc) { rv = a[q][cc]; vv = 0.0; }
-      else if (r == jc) { rv = betas[cc]; vv = 1.0; }
-      else { rv = 0.0; vv = a[q][cc]; }
-      A[(size_t)r * lda + jc] = rv;
+      double rvv, vv;
+      if (r < jc) { rvv = a[q][p]; vv = 0.0; }
+      else if (r == jc) { rvv = betas[cc]; vv = 1.0; }
+      else { rvv = 0.0; vv = a[q][p]; }
+      A[(size_t)r * lda + jc] = rvv;
       Vq[(size_t)r * lda + jc] = vv;
     }
   }
@@ -408,14 +433,13 @@ inline int panel_width(int rows) { return rows > 1024 ? 16 : 32; }
 int launch_panel(kdqmc_ctx* c, double* A, int ld, int n, int j, int nbp, double* Tp) {
   const int m = n - j;
   const int e0 = prof_mark(c);
-  if (nbp > 16) {
-    if (m <= 512)
-      hipLaunchKernelGGL((k_qr_panel<4, 32, 128>), dim3(1), dim3(128), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
-    else
-      hipLaunchKernelGGL((k_qr_panel<4, 32, 256>), dim3(1), dim3(256), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
-  } else {
-    hipLaunchKernelGGL((k_qr_panel<8, 16, 256>), dim3(1), dim3(256), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
-  }
+  // rows per thread: 2; the panel's rows fit in RPT * NT
+  if (m <= 512)
+    hipLaunchKernelGGL((k_qr_panel<2, 32, 256>), dim3(1), dim3(256), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+  else if (m <= 1024)
+    hipLaunchKernelGGL((k_qr_panel<2, 32, 512>), dim3(1), dim3(512), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+  else
+    hipLaunchKernelGGL((k_qr_panel<2, 16, 1024>), dim3(1), dim3(1024), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
   prof_pair(c, PH_QR_PANEL, e0, prof_mark(c));
   return KDQMC_OK;
 }

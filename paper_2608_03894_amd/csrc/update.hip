@@ -54,8 +54,9 @@ __global__ void k_frame_scale(const int8_t* __restrict__ s, int n, double ea, do
 // x = t/GR + GR i, y = t%GR + GR k of each block.  Per accept the owners
 // publish row p / column p through LDS (barrier), everyone updates its
 // registers and the diagonal owners publish the new diagonal (barrier).  A
-// rejected flip reads one LDS word and needs no barrier.  With a single wave
-// (windows of up to 32 sites) the barriers cost next to nothing.
+// rejected flip reads one LDS word and needs no barrier.  Four waves are used
+// for every window size: the per-accept updates are VALU bound and spread
+// better over four SIMDs than the barriers cost.
 // ---------------------------------------------------------------------------
 template <typename T, int WS, int NT>
 __global__ void __launch_bounds__(NT)
@@ -458,11 +459,11 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
     // decide
     const int e_d = prof_mark(c);
     if (wn <= 16)
-      hipLaunchKernelGGL((k_decide<T, 2, 64>), dim3(1), dim3(64), 0, c->stream, G, N, c->ev, c->evinv,
+      hipLaunchKernelGGL((k_decide<T, 1, 256>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
                          s_l, u, forced, acc, ratio, w0, wn, W, first_in_group ? nullptr : c->Gs,
                          em2a, ep2a, win, c->win_a, c->win_p, c->Xw, c->Yw);
     else if (wn <= 32)
-      hipLaunchKernelGGL((k_decide<T, 4, 64>), dim3(1), dim3(64), 0, c->stream, G, N, c->ev, c->evinv,
+      hipLaunchKernelGGL((k_decide<T, 2, 256>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
                          s_l, u, forced, acc, ratio, w0, wn, W, first_in_group ? nullptr : c->Gs,
                          em2a, ep2a, win, c->win_a, c->win_p, c->Xw, c->Yw);
     else

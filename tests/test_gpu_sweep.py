@@ -76,6 +76,20 @@ def test_l6_sweep_forced(gpu_lib):
     assert worst < TOL64
 
 
+@pytest.mark.parametrize("k,window", [(64, 64), (128, 64), (64, 48), (96, 32)])
+def test_l6_sweep_forced_wide_windows(gpu_lib, k, window):
+    """Windows above 32 sites (four register blocks per thread) and flush
+    groups of several windows, on N = 108 (two windows per slice, ragged)."""
+    say("L6 sweep k", k, "window", window)
+    m, f, g0, r, u = oracle_run(6, -4.0, 2.0, 6)
+    ch = chain(6, -4.0, 2.0, delay_k=k, window=window)
+    gs, ratio, acc, errs = run_forced_sweep(ch, f, r)
+    worst = max(np.abs(a - b).max() for a, b in zip(gs, r["G_slices"]))
+    say("L6 wide worst", worst)
+    assert worst < TOL64
+    assert np.abs(ratio - r["ratios"]).max() < 1e-9 * max(1.0, np.abs(r["ratios"]).max())
+
+
 def test_c2_ten_slices_forced(gpu_lib):
     """The benchmark lattice (L=12, N=432, U=-4, beta=8, k=32): first ten
     slices and the first stabilization, decisions replayed.
@@ -220,3 +234,23 @@ def test_state_errors(gpu_lib):
     with pytest.raises(kdqmc.KdqmcError) as e:
         ch.stabilize()
     assert e.value.code == kdqmc.ESTATE
+    for l in range(2, 11):
+        ch.wrap_slice(l)
+    # slice 10 needs its stabilization before slice 11
+    with pytest.raises(kdqmc.KdqmcError) as e:
+        ch.wrap_slice(11)
+    assert e.value.code == kdqmc.ESTATE
+    ch.stabilize()
+    ch.wrap_slice(11)
+    # going back re-opens the stabilizations after the new slice
+    G = ch.G()
+    ch.set_G(G, 5)
+    for l in range(6, 11):
+        ch.wrap_slice(l)
+    ch.stabilize()
+    ch.set_G(G, 15)
+    for l in range(16, 21):
+        ch.wrap_slice(l)
+    # slice 10 has been stabilized again, so slice 20's is the one due
+    ch.stabilize()
+    assert ch.current_slice() == 0
