@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFS = 78.6           # MI355X FP64 (vector and matrix)
 F16_PEAK_TFS = 2500.0          # MI355X dense FP16/BF16 MFMA
 
-CONFIGS = {"c1": si.C1, "c2": si.C2, "c3": si.C3, "c5": si.C5}
+CONFIGS = {"c1": si.C1, "c2": si.C2, "c3": si.C3, "c5": si.C5, "c4": None}
 
 
 def log(*a):
@@ -188,6 +188,64 @@ def copy_calibration(mib=1024, reps=5):
     print(json.dumps({"copy_calibration_bytes_per_dispatch": n * 8, "dispatches": reps}), flush=True)
 
 
+def bench_batch(args):
+    """64 independent chains of uneven L, U, beta (grouped by shape, one
+    batched context and stream per group); one step = one sweep of every
+    chain.  Value: aggregate chain-sweeps per second."""
+    import torch
+    from paper_2608_03894_amd import kdqmc
+    chains = si.batched_chains(64, 64)
+    prec = args.prec or "mixed_f16"
+    dev = torch.device("cuda:0")
+    params, fields, unis = [], [], []
+    total = args.warmup + args.steps
+    for w in chains:
+        k = args.delay_k or w.delay_k
+        params.append(kdqmc.make_params(w.L, w.U, w.beta, w.dtau, mu=-1.0, n_stab=args.n_stab or w.n_stab,
+                                        delay_k=k, window=args.window, fft_tile=args.fft_tile, prec=prec))
+        Lt = si.l_tau(w.beta, w.dtau)
+        fields.append(torch.from_numpy(si.ising_fields(w.L, Lt, w.seed)).to(dev))
+        unis.append(torch.from_numpy(si.metropolis_uniforms(w.L, Lt, w.seed, n_sweeps=total)).to(dev))
+    b = kdqmc.Batch(params, device=dev)
+    log(f"batch of {b.n_chains} chains in {len(b.groups)} shape groups, prec={prec}")
+    b.set_inputs(fields, unis)
+    for s in range(args.warmup):
+        b.sweep(s)
+        log(f"warmup sweep {s + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        b.sweep(args.warmup + s)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = b.n_chains * args.steps / elapsed
+    upd = b.field_updates_per_sweep()
+    log(f"timed {args.steps} batch sweeps in {elapsed:.3f} s -> {value:.2f} chain-sweeps/s")
+    groups = [{"L": g["chain"].p.L, "beta": g["chain"].p.beta, "chains": len(g["idx"])} for g in b.groups]
+    out = {
+        "metric": "HS-field sweeps/sec (batched, aggregate over chains)",
+        "value": value,
+        "unit": "chain-sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else f"f32+{prec.split('_')[1]}",
+        "data": "synthetic",
+        "config": {"workload": "kagome-batch-64-chains-L6-15-U3-5-beta4-8", "chains": b.n_chains,
+                   "groups": groups, "prec": prec, "field_updates_per_s": upd * args.steps / elapsed},
+        "roofline": None,
+        "cpu_baseline": None,
+        "acceptance": b.accepted() / upd,
+        "max_wrap_err": b.max_wrap_err(),
+    }
+    b.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +271,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.config == "c4":
+        bench_batch(args)
         return
 
     import torch

@@ -27,6 +27,14 @@
  *     the last error on the calling thread is kdqmc_last_error().  A failed
  *     call leaves the context usable unless it returns KDQMC_EHIP.
  *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Batched chains: a context made by kdqmc_init_batch holds n_chains
+ *     independent Markov chains of one shape (same parameters except U);
+ *     every call then acts on all of them at once (one launch per kernel,
+ *     chains along the grid's z dimension).  Each device array argument then
+ *     holds one record per chain, back to back, each laid out as documented
+ *     for a single chain (record sizes: fields L_tau*N bytes, G N*N doubles,
+ *     per-slice u/forced/accepted/ratio N elements, per-sweep ones L_tau*N,
+ *     wrap_err 1 (kdqmc_stabilize) or L_tau/n_stab (kdqmc_sweep)).
  */
 #ifndef KDQMC_H
 #define KDQMC_H
@@ -77,6 +85,10 @@ typedef struct kdqmc_ctx kdqmc_ctx;
  * Returns 0 for invalid parameters (kdqmc_last_error says why). */
 size_t kdqmc_workspace_bytes(const kdqmc_params* p);
 
+/* Bytes of device workspace for n_chains chains of one shape (1..65535):
+ * n_chains per-chain blocks.  0 for invalid parameters. */
+size_t kdqmc_workspace_bytes_batch(const kdqmc_params* p, int n_chains);
+
 /* Chemical potential at the Dirac energy of the kagome bands: the energy at
  * which the two dispersive bands of the 3x3 Bloch block (Eq. (4)) touch,
  * -t (exact; the Dirac filling rho = 2/3 of Sec. IV). */
@@ -89,6 +101,18 @@ double kdqmc_dirac_mu(int L, double t);
  * call kdqmc_set_fields (or kdqmc_set_G) next. */
 int kdqmc_init_lattice(kdqmc_ctx** out, const kdqmc_params* p, void* workspace_dev,
                        size_t workspace_bytes, void* hip_stream);
+
+/* As kdqmc_init_lattice for n_chains independent chains of the same shape
+ * (the batched Monte Carlo of many Markov chains): U_host[n_chains] (host
+ * memory, may be NULL = p->U for all) gives each chain's interaction, all
+ * other parameters are shared.  The workspace must hold
+ * kdqmc_workspace_bytes_batch(p, n_chains) bytes.  Array layouts of the
+ * other calls: see "Batched chains" above. */
+int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const double* U_host,
+                     void* workspace_dev, size_t workspace_bytes, void* hip_stream);
+
+/* Chains held by the context (1 unless made by kdqmc_init_batch). */
+int kdqmc_num_chains(const kdqmc_ctx* c);
 
 /* Copies the Ising fields s_dev[L_tau][N] (int8, each +1 or -1), builds the
  * left stabilization stack from the top slice down, computes G(0) in FP64
@@ -188,7 +212,9 @@ int kdqmc_profile_read(kdqmc_ctx* c, double* ms, int* launches);
 /* Name of a phase index ("" if out of range). */
 const char* kdqmc_phase_name(int phase);
 
-/* ---- kernel-level entry points (the building blocks, for tests/tuning) ---- */
+/* ---- kernel-level entry points (the building blocks, for tests/tuning) ----
+ * These act on caller matrices, not on chains: they need a single-chain
+ * context (KDQMC_EINVAL otherwise). */
 
 /* C(M x N) = alpha * op(A) op(B) + beta * C, FP64, row-major, on the
  * context's stream; op(X) = X or X^T (trans_* != 0).  lda/ldb/ldc are row

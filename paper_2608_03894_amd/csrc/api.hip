@@ -68,7 +68,8 @@ int derive(const kdqmc_params* p, Derived* d) {
   return KDQMC_OK;
 }
 
-// Carves the workspace; with c == nullptr only measures.  Returns bytes.
+// Carves one chain's block of the workspace; with c == nullptr only
+// measures.  Returns the block size (a multiple of 256 bytes).
 size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
@@ -111,6 +112,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   char* tau = take(N * 8);
   char* nrm = take(2 * N * 8);
   char* perm = take(N * 4);
+  char* sc = take(SC_COUNT * 8);
   if (c) {
     c->G = G;
     c->G64 = (double*)G64;
@@ -138,8 +140,14 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
     c->tau = (double*)tau;
     c->nrm = (double*)nrm;
     c->perm = (int*)perm;
+    c->sc = (double*)sc;
   }
-  return ((off + 255) & ~size_t(255)) + 256;  // slack for base alignment
+  return (off + 255) & ~size_t(255);
+}
+
+// Bytes for nch chains of one shape: nch blocks plus slack for aligning the base.
+size_t batch_bytes(const kdqmc_params* p, const Derived& d, int nch) {
+  return (size_t)nch * carve(p, d, nullptr, nullptr) + 256;
 }
 
 __global__ void k_check_fields(const int8_t* __restrict__ s, size_t n, int* __restrict__ bad) {
@@ -204,24 +212,46 @@ using namespace kdqmc;
 
 extern "C" {
 
-size_t kdqmc_workspace_bytes(const kdqmc_params* p) {
+size_t kdqmc_workspace_bytes(const kdqmc_params* p) { return kdqmc_workspace_bytes_batch(p, 1); }
+
+size_t kdqmc_workspace_bytes_batch(const kdqmc_params* p, int n_chains) {
+  if (n_chains < 1 || n_chains > 65535) {
+    set_error(KDQMC_EINVAL, "n_chains must be in 1..65535");
+    return 0;
+  }
   Derived d;
   if (derive(p, &d) != KDQMC_OK) return 0;
-  return carve(p, d, nullptr, nullptr);
+  return batch_bytes(p, d, n_chains);
 }
 
 double kdqmc_dirac_mu(int L, double t) { return kdqmc::dirac_mu(L, t); }
 
 int kdqmc_init_lattice(kdqmc_ctx** out, const kdqmc_params* p, void* workspace_dev,
                        size_t workspace_bytes, void* hip_stream) {
+  return kdqmc_init_batch(out, p, 1, nullptr, workspace_dev, workspace_bytes, hip_stream);
+}
+
+int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const double* U_host,
+                     void* workspace_dev, size_t workspace_bytes, void* hip_stream) {
   if (!out) return set_error(KDQMC_EINVAL, "out is NULL");
   *out = nullptr;
+  if (n_chains < 1 || n_chains > 65535) return set_error(KDQMC_EINVAL, "n_chains must be in 1..65535");
   Derived d;
   KDQMC_TRY(derive(p, &d));
+  std::vector<double> Uc(n_chains, p->U);
+  if (U_host) {
+    for (int z = 0; z < n_chains; ++z) {
+      kdqmc_params q = *p;
+      q.U = U_host[z];
+      Derived dq;
+      KDQMC_TRY(derive(&q, &dq));
+      Uc[z] = U_host[z];
+    }
+  }
   if (!workspace_dev) return set_error(KDQMC_EINVAL, "workspace is NULL");
-  const size_t need = carve(p, d, nullptr, nullptr);
+  const size_t need = batch_bytes(p, d, n_chains);
   if (workspace_bytes < need)
-    return set_error(KDQMC_ENOSPACE, "workspace smaller than kdqmc_workspace_bytes()");
+    return set_error(KDQMC_ENOSPACE, "workspace smaller than kdqmc_workspace_bytes_batch()");
   KDQMC_TRY(prepare_kinetic(p->L));
   KDQMC_TRY(prepare_updates());
   kdqmc_ctx* c = new kdqmc_ctx();
@@ -238,11 +268,12 @@ int kdqmc_init_lattice(kdqmc_ctx** out, const kdqmc_params* p, void* workspace_d
   c->P64 = d.P64;
   c->nb = 16;
   c->fp64 = d.fp64;
-  c->alpha = std::acosh(std::exp(p->dtau * std::fabs(p->U) / 2.0));
+  c->alpha = std::acosh(std::exp(p->dtau * std::fabs(Uc[0]) / 2.0));
   c->stream = static_cast<hipStream_t>(hip_stream);
+  c->nch = n_chains;
   char* base = static_cast<char*>(workspace_dev);
   base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(base) + 255) & ~uintptr_t(255));
-  carve(p, d, c, base);
+  c->zs = carve(p, d, c, base);
   // Bloch tables: exp(-dtau H(k)) and exp(+dtau H(k)) for the wrap (mu cancels),
   // exp(-dtau (H(k) - mu)) for the B-chains; 1/L^2 folded in.
   const size_t L2 = (size_t)p->L * p->L;
@@ -262,9 +293,22 @@ int kdqmc_init_lattice(kdqmc_ctx** out, const kdqmc_params* p, void* workspace_d
     }
     return KDQMC_OK;
   };
-  if ((rc = upload(c->tab_m, tm, !c->fp64)) != KDQMC_OK ||
-      (rc = upload(c->tab_p, tp, !c->fp64)) != KDQMC_OK ||
-      (rc = upload(c->tab_mu64, tmu, false)) != KDQMC_OK) {
+  // every chain holds its own copy of the tables and its decoupling scalars
+  for (int z = 0; z < n_chains && rc == KDQMC_OK; ++z) {
+    const size_t o = (size_t)z * c->zs;
+    const double a = std::acosh(std::exp(p->dtau * std::fabs(Uc[z]) / 2.0));
+    std::vector<double> scv(SC_COUNT);
+    scv[SC_EA] = std::exp(a);
+    scv[SC_EAINV] = std::exp(-a);
+    scv[SC_EM2A] = std::exp(-2.0 * a);
+    scv[SC_EP2A] = std::exp(2.0 * a);
+    if ((rc = upload(static_cast<char*>(c->tab_m) + o, tm, !c->fp64)) != KDQMC_OK ||
+        (rc = upload(static_cast<char*>(c->tab_p) + o, tp, !c->fp64)) != KDQMC_OK ||
+        (rc = upload(reinterpret_cast<char*>(c->tab_mu64) + o, tmu, false)) != KDQMC_OK ||
+        (rc = upload(reinterpret_cast<char*>(c->sc) + o, scv, false)) != KDQMC_OK)
+      break;
+  }
+  if (rc != KDQMC_OK) {
     delete c;
     return rc;
   }
@@ -279,13 +323,15 @@ int kdqmc_set_fields(kdqmc_ctx* c, const int8_t* s_dev) {
   KDQMC_TRY(check_ctx(c));
   if (!s_dev) return set_error(KDQMC_EINVAL, "fields pointer is NULL");
   const size_t n = (size_t)c->Ltau * c->N;
+  const size_t all = n * c->nch;  // chain z's fields at s_dev + z * n
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, c->stream, c->flag, 16);
-  hipLaunchKernelGGL(k_check_fields, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, s_dev, n, c->flag);
+  hipLaunchKernelGGL(k_check_fields, dim3((unsigned)((all + 255) / 256)), dim3(256), 0, c->stream, s_dev, all,
+                     c->flag);
   int bad = 0;
   KDQMC_HIP(hipMemcpyAsync(&bad, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   KDQMC_HIP(hipStreamSynchronize(c->stream));
   if (bad) return set_error(KDQMC_EINVAL, "fields must be +1 or -1");
-  KDQMC_HIP(hipMemcpyAsync(c->fields, s_dev, n, hipMemcpyDeviceToDevice, c->stream));
+  KDQMC_HIP(hipMemcpy2DAsync(c->fields, c->zs, s_dev, n, n, c->nch, hipMemcpyDeviceToDevice, c->stream));
   KDQMC_TRY(stab_build_left(c));
   KDQMC_TRY(stab_identity(c, false, 0));
   KDQMC_TRY(stab_green(c, 0, c->G64));
@@ -299,7 +345,8 @@ int kdqmc_set_fields(kdqmc_ctx* c, const int8_t* s_dev) {
 int kdqmc_get_fields(kdqmc_ctx* c, int8_t* s_dev) {
   KDQMC_TRY(check_ctx(c));
   if (!s_dev) return set_error(KDQMC_EINVAL, "fields pointer is NULL");
-  KDQMC_HIP(hipMemcpyAsync(s_dev, c->fields, (size_t)c->Ltau * c->N, hipMemcpyDeviceToDevice, c->stream));
+  const size_t n = (size_t)c->Ltau * c->N;
+  KDQMC_HIP(hipMemcpy2DAsync(s_dev, n, c->fields, c->zs, n, c->nch, hipMemcpyDeviceToDevice, c->stream));
   return KDQMC_OK;
 }
 
@@ -307,7 +354,7 @@ int kdqmc_set_G(kdqmc_ctx* c, const double* G_dev, int l) {
   KDQMC_TRY(check_ctx(c));
   if (!G_dev) return set_error(KDQMC_EINVAL, "G pointer is NULL");
   if (l < 0 || l > c->Ltau) return set_error(KDQMC_EINVAL, "slice index out of range");
-  KDQMC_TRY(copy_64_to_G(c, G_dev));
+  KDQMC_TRY(copy_64_to_G(c, G_dev, (size_t)c->N * c->N));
   c->l_cur = l;
   // stack entries up to slice l stay valid; later ones are rebuilt in order
   c->stab_next = std::min(c->stab_next, l / c->p.n_stab + 1);
@@ -323,7 +370,7 @@ static int check_stab_due(kdqmc_ctx* c, int l) {
   return KDQMC_OK;
 }
 
-static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev);
+static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev, size_t zn);
 
 static int wrap_pass(kdqmc_ctx* c) {
   if (c->fp64) {
@@ -347,29 +394,40 @@ int kdqmc_wrap_slice(kdqmc_ctx* c, int l) {
   return KDQMC_OK;
 }
 
-int kdqmc_sweep_slice(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* forced_dev,
-                      uint8_t* accepted_dev, double* ratio_dev) {
-  KDQMC_TRY(check_ctx(c));
+// zn: elements between consecutive chains' records of u, forced, accepted, ratio
+static int sweep_slice_impl(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* forced_dev,
+                            uint8_t* accepted_dev, double* ratio_dev, size_t zn) {
   if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded (set_fields or set_G first)");
   if (l != c->l_cur + 1 || l > c->Ltau) return set_error(KDQMC_ESTATE, "sweep_slice needs l == current slice + 1");
   KDQMC_TRY(check_stab_due(c, l));
   if (!u_dev && !forced_dev) return set_error(KDQMC_EINVAL, "need uniforms or forced decisions");
   KDQMC_TRY(launch_frame_scale(c, l));
-  KDQMC_TRY(run_slice_updates(c, l, u_dev, forced_dev, accepted_dev, ratio_dev));
+  KDQMC_TRY(run_slice_updates(c, l, u_dev, forced_dev, accepted_dev, ratio_dev, zn));
   KDQMC_TRY(wrap_pass(c));
   c->l_cur = l;
   return KDQMC_OK;
 }
 
-int kdqmc_stabilize(kdqmc_ctx* c, double* wrap_err_dev) {
+int kdqmc_sweep_slice(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* forced_dev,
+                      uint8_t* accepted_dev, double* ratio_dev) {
   KDQMC_TRY(check_ctx(c));
+  return sweep_slice_impl(c, l, u_dev, forced_dev, accepted_dev, ratio_dev, (size_t)c->N);
+}
+
+// zn: elements between consecutive chains' wrap-error records
+static int stabilize_timed(kdqmc_ctx* c, double* wrap_err_dev, size_t zn) {
   const int e0 = prof_mark(c);
-  const int rc = stabilize_impl(c, wrap_err_dev);
+  const int rc = stabilize_impl(c, wrap_err_dev, zn);
   prof_pair(c, PH_STABILIZE, e0, prof_mark(c));
   return rc;
 }
 
-static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev) {
+int kdqmc_stabilize(kdqmc_ctx* c, double* wrap_err_dev) {
+  KDQMC_TRY(check_ctx(c));
+  return stabilize_timed(c, wrap_err_dev, 1);
+}
+
+static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev, size_t zn) {
   if (!c->stacks_valid) return set_error(KDQMC_ESTATE, "stacks not built (call set_fields)");
   const int l = c->l_cur;
   if (l <= 0 || l % c->p.n_stab != 0) return set_error(KDQMC_ESTATE, "stabilize needs the current slice to be a positive multiple of n_stab");
@@ -378,7 +436,7 @@ static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev) {
     return set_error(KDQMC_ESTATE, "an earlier stabilization was skipped (each multiple of n_stab needs one, in order)");
   KDQMC_TRY(stab_right_step(c, j));
   KDQMC_TRY(stab_green(c, j, c->G64));
-  if (wrap_err_dev) KDQMC_TRY(max_abs_diff(c, c->G64, c->N, wrap_err_dev));
+  if (wrap_err_dev) KDQMC_TRY(max_abs_diff(c, c->G64, c->N, wrap_err_dev, zn));
   KDQMC_TRY(copy_64_to_G(c, c->G64));
   c->stab_next = j + 1;
   if (j == c->nc) {
@@ -392,12 +450,15 @@ static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev) {
 static int sweep_eager(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev,
                        uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev) {
   const size_t N = c->N;
+  const size_t zn = (size_t)c->Ltau * N;  // per-chain records of the sweep's caller arrays
   for (int l = 1; l <= c->Ltau; ++l) {
     const size_t o = (size_t)(l - 1) * N;
-    KDQMC_TRY(kdqmc_sweep_slice(c, l, u_dev ? u_dev + o : nullptr, forced_dev ? forced_dev + o : nullptr,
-                                accepted_dev ? accepted_dev + o : nullptr, ratio_dev ? ratio_dev + o : nullptr));
+    KDQMC_TRY(sweep_slice_impl(c, l, u_dev ? u_dev + o : nullptr, forced_dev ? forced_dev + o : nullptr,
+                               accepted_dev ? accepted_dev + o : nullptr, ratio_dev ? ratio_dev + o : nullptr,
+                               zn));
     if (l % c->p.n_stab == 0)
-      KDQMC_TRY(kdqmc_stabilize(c, wrap_err_dev ? wrap_err_dev + (l / c->p.n_stab - 1) : nullptr));
+      KDQMC_TRY(stabilize_timed(c, wrap_err_dev ? wrap_err_dev + (l / c->p.n_stab - 1) : nullptr,
+                                (size_t)c->nc));
   }
   return KDQMC_OK;
 }
@@ -461,11 +522,16 @@ int kdqmc_use_graphs(kdqmc_ctx* c, int on) {
   return KDQMC_OK;
 }
 
+int kdqmc_num_chains(const kdqmc_ctx* c) {
+  if (!c) return set_error(KDQMC_EINVAL, "context is NULL");
+  return c->nch;
+}
+
 int kdqmc_measure_G(kdqmc_ctx* c, double* G_dev) {
   KDQMC_TRY(check_ctx(c));
   if (!G_dev) return set_error(KDQMC_EINVAL, "G pointer is NULL");
   if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded");
-  return copy_G_to64(c, G_dev);
+  return copy_G_to64(c, G_dev, (size_t)c->N * c->N);
 }
 
 int kdqmc_current_slice(const kdqmc_ctx* c) {
@@ -533,6 +599,7 @@ int kdqmc_gemm_f64(kdqmc_ctx* c, int trans_a, int trans_b, int M, int N, int K, 
                    double* C_dev, int ldc) {
   KDQMC_TRY(check_ctx(c));
   if (!A_dev || !B_dev || !C_dev) return set_error(KDQMC_EINVAL, "NULL matrix");
+  if (c->nch != 1) return set_error(KDQMC_EINVAL, "building blocks need a single-chain context");
   if (M < 0 || N < 0 || K < 0) return set_error(KDQMC_EINVAL, "negative size");
   const int acols = trans_a ? M : K, bcols = trans_b ? K : N;
   if (lda < std::max(1, acols) || ldb < std::max(1, bcols) || ldc < std::max(1, N))
@@ -543,6 +610,7 @@ int kdqmc_gemm_f64(kdqmc_ctx* c, int trans_a, int trans_b, int M, int N, int K, 
 int kdqmc_qr_f64(kdqmc_ctx* c, int n, double* A_dev, double* Q_dev) {
   KDQMC_TRY(check_ctx(c));
   if (!A_dev || !Q_dev) return set_error(KDQMC_EINVAL, "NULL matrix");
+  if (c->nch != 1) return set_error(KDQMC_EINVAL, "building blocks need a single-chain context");
   if (n < 1 || n > c->N) return set_error(KDQMC_EINVAL, "QR order must be in 1..N");
   // the routine works with row stride N; callers pass N x N buffers
   return qr_f64(c, n, A_dev, Q_dev);

@@ -103,6 +103,27 @@ template <int N>
 inline constexpr TwiddleTable<N> kTw{};
 
 // ---------------------------------------------------------------------------
+// Batched chains.  A context may hold nch chains of one shape (same L, L_tau
+// and schedule; U may differ).  Every launch then has gridDim.z = nch and
+// chain z = blockIdx.z works on its own copy of the workspace, zs bytes after
+// chain z-1's: kernels receive chain 0's workspace pointers and shift them
+// with zw().  Caller arrays hold one record per chain, zn elements apart,
+// shifted with zc().  Null pointers stay null.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T* zw(T* p, size_t zs) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (size_t)blockIdx.z * zs) : p;
+}
+template <typename T>
+__device__ __forceinline__ T* zc(T* p, size_t zn) {
+  return p ? p + (size_t)blockIdx.z * zn : p;
+}
+
+// Per-chain scalars kept in the workspace (the decoupling constant differs
+// between chains of a batch): exp(alpha), exp(-alpha), exp(-2 alpha), exp(2 alpha).
+enum { SC_EA = 0, SC_EAINV, SC_EM2A, SC_EP2A, SC_COUNT };
+
+// ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
 struct Layout;  // workspace carving, see api.hip
@@ -141,7 +162,10 @@ struct kdqmc_ctx {
   int P64 = 0;                            // same for the FP64 stack products
   int kmax = 0;                           // columns of the pending factors (F * w)
   int nb = 32;                            // QR panel width
-  double alpha = 0.0;
+  double alpha = 0.0;                     // decoupling constant of chain 0
+  int nch = 1;                            // chains in this context
+  size_t zs = 0;                          // workspace bytes per chain
+  double* sc = nullptr;                   // SC_COUNT per-chain scalars
   hipStream_t stream = nullptr;
   int l_cur = -1;
   bool stacks_valid = false;
@@ -210,8 +234,9 @@ int launch_kinetic_f32(kdqmc_ctx* c, float* A, int lda, bool cols, const float* 
 int prepare_kinetic(int L);
 int prepare_updates();
 int launch_frame_scale(kdqmc_ctx* c, int l);
+// Caller arrays u, forced, acc, ratio: one record per chain, zn elements apart.
 int run_slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, uint8_t* acc,
-                      double* ratio);
+                      double* ratio, size_t zn);
 
 int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
              int lda, const double* B, int ldb, double beta, double* C, int ldc);
@@ -223,9 +248,12 @@ int stab_identity(kdqmc_ctx* c, bool left, int j);
 int stab_build_left(kdqmc_ctx* c);
 int stab_green(kdqmc_ctx* c, int j, double* out);   // G at checkpoint j into out (FP64)
 int stab_right_step(kdqmc_ctx* c, int j);           // right stack entry j from j-1
-int copy_G_to64(kdqmc_ctx* c, double* out);
-int copy_64_to_G(kdqmc_ctx* c, const double* in);
-int max_abs_diff(kdqmc_ctx* c, const double* a, int n, double* out);  // max |G - a|
+// in / out may be workspace arrays (zn = 0: shifted by the workspace stride)
+// or caller arrays (zn > 0: one N x N record per chain, zn elements apart).
+int copy_G_to64(kdqmc_ctx* c, double* out, size_t zn = 0);
+int copy_64_to_G(kdqmc_ctx* c, const double* in, size_t zn = 0);
+// max |G - a| (a in the workspace) into out[0] of each chain's record (zn apart).
+int max_abs_diff(kdqmc_ctx* c, const double* a, int n, double* out, size_t zn);
 
 // Device-to-device copy of n doubles as a kernel (graph-capture friendly).
 int copy_f64(kdqmc_ctx* c, double* dst, const double* src, size_t n);

@@ -203,8 +203,13 @@ template <typename T, int L, bool COLS>
 __global__ void __launch_bounds__(512)
 k_kinetic(T* __restrict__ A, int lda, int P, const T* __restrict__ tab,
           const double* __restrict__ pre_e, const double* __restrict__ pre_v,
-          const double* __restrict__ post_e) {
+          const double* __restrict__ post_e, size_t zs) {
   constexpr int NS = 3 * L * L;
+  A = zw(A, zs);
+  tab = zw(tab, zs);
+  pre_e = zw(pre_e, zs);
+  pre_v = zw(pre_v, zs);
+  post_e = zw(post_e, zs);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sre = reinterpret_cast<T*>(smem_raw);
   T* sim = sre + NS * P;
@@ -289,9 +294,11 @@ int launch_L(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double*
   if (threads < 64) threads = 64;
   const int e0 = prof_mark(c);
   if (cols)
-    hipLaunchKernelGGL((k_kinetic<T, L, true>), dim3(grid), dim3(threads), lds, c->stream, A, lda, P, tab, pre_e, pre_v, post_e);
+    hipLaunchKernelGGL((k_kinetic<T, L, true>), dim3(grid, 1, c->nch), dim3(threads), lds, c->stream, A, lda, P,
+                       tab, pre_e, pre_v, post_e, c->zs);
   else
-    hipLaunchKernelGGL((k_kinetic<T, L, false>), dim3(grid), dim3(threads), lds, c->stream, A, lda, P, tab, pre_e, pre_v, post_e);
+    hipLaunchKernelGGL((k_kinetic<T, L, false>), dim3(grid, 1, c->nch), dim3(threads), lds, c->stream, A, lda, P,
+                       tab, pre_e, pre_v, post_e, c->zs);
   prof_pair(c, (sizeof(T) == 8 && tab == (const T*)c->tab_mu64) ? PH_BMUL : (cols ? PH_WRAP_COLS : PH_WRAP_ROWS), e0, prof_mark(c));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;

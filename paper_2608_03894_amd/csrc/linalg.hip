@@ -17,8 +17,12 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256)
 k_gemm_f64(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
-           const double* __restrict__ B, int ldb, double beta, double* __restrict__ C, int ldc) {
+           const double* __restrict__ B, int ldb, double beta, double* __restrict__ C, int ldc,
+           size_t zs) {
   __shared__ double As[16][64 + 2];
+  A = zw(A, zs);
+  B = zw(B, zs);
+  C = zw(C, zs);
   __shared__ double Bs[16][64 + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
@@ -81,16 +85,16 @@ k_gemm_f64(int M, int N, int K, double alpha, const double* __restrict__ A, int 
 int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
              int lda, const double* B, int ldb, double beta, double* C, int ldc) {
   if (M <= 0 || N <= 0) return KDQMC_OK;
-  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  dim3 grid((N + 63) / 64, (M + 63) / 64, c->nch);
   const int e0 = prof_mark(c);
   if (!ta && !tb)
-    hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, c->zs);
   else if (ta && !tb)
-    hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, c->zs);
   else if (!ta && tb)
-    hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, c->zs);
   else
-    hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, c->zs);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
@@ -154,9 +158,13 @@ __device__ __forceinline__ double lane_value(double v, int src) {
 template <int RPT, int NB, int NT>
 __global__ void __launch_bounds__(NT)
 k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __restrict__ Vq,
-           double* __restrict__ Tq, double* __restrict__ tau_out) {
+           double* __restrict__ Tq, double* __restrict__ tau_out, size_t zs) {
   constexpr int NW = NT / 64;
   constexpr int U = 4;
+  A = zw(A, zs);
+  Vq = zw(Vq, zs);
+  Tq = zw(Tq, zs);
+  tau_out = zw(tau_out, zs);
   static_assert(NB % U == 0 && NB <= kNBmax && NT >= NB, "panel shape");
   __shared__ double red[2][NW][NB];   // per-wave partial sums d_t
   __shared__ double rowv[2][NB];      // row jc of the panel
@@ -330,7 +338,11 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
 // C -= V W2 with the waves splitting the rows.
 __global__ void __launch_bounds__(512)
 k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
-           const double* __restrict__ V, int ldv, const double* __restrict__ T, int trans) {
+           const double* __restrict__ V, int ldv, const double* __restrict__ T, int trans,
+           size_t zs) {
+  C = zw(C, zs);
+  V = zw(V, zs);
+  T = zw(T, zs);
   constexpr int NW = 8;
   __shared__ double Wp[NW][32][33];
   __shared__ double W2[32][33];
@@ -413,7 +425,8 @@ k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
   }
 }
 
-__global__ void k_set_identity(double* __restrict__ Q, int n, int ld) {
+__global__ void k_set_identity(double* __restrict__ Q, int n, int ld, size_t zs) {
+  Q = zw(Q, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)n * n) {
     const int r = idx / n, cc = idx % n;
@@ -421,7 +434,8 @@ __global__ void k_set_identity(double* __restrict__ Q, int n, int ld) {
   }
 }
 
-__global__ void k_zero(double* __restrict__ X, size_t count) {
+__global__ void k_zero(double* __restrict__ X, size_t count, size_t zs) {
+  X = zw(X, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < count) X[idx] = 0.0;
 }
@@ -435,11 +449,14 @@ int launch_panel(kdqmc_ctx* c, double* A, int ld, int n, int j, int nbp, double*
   const int e0 = prof_mark(c);
   // rows per thread: 2; the panel's rows fit in RPT * NT
   if (m <= 512)
-    hipLaunchKernelGGL((k_qr_panel<2, 32, 256>), dim3(1), dim3(256), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+    hipLaunchKernelGGL((k_qr_panel<2, 32, 256>), dim3(1, 1, c->nch), dim3(256), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp,
+                       c->tau, c->zs);
   else if (m <= 1024)
-    hipLaunchKernelGGL((k_qr_panel<2, 32, 512>), dim3(1), dim3(512), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+    hipLaunchKernelGGL((k_qr_panel<2, 32, 512>), dim3(1, 1, c->nch), dim3(512), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp,
+                       c->tau, c->zs);
   else
-    hipLaunchKernelGGL((k_qr_panel<2, 16, 1024>), dim3(1), dim3(1024), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp, c->tau);
+    hipLaunchKernelGGL((k_qr_panel<2, 16, 1024>), dim3(1, 1, c->nch), dim3(1024), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp,
+                       c->tau, c->zs);
   prof_pair(c, PH_QR_PANEL, e0, prof_mark(c));
   return KDQMC_OK;
 }
@@ -450,8 +467,8 @@ int launch_apply(kdqmc_ctx* c, double* C, int ld, int n, int j, int nbp, int col
   const int e0 = prof_mark(c);
   const int stripes = (ncols - col0 + 31) / 32;
   // the kernel indexes columns from C's base: shift the base to col0
-  hipLaunchKernelGGL(k_apply_wy, dim3(stripes), dim3(512), 0, c->stream, C + col0, ld, n, j, nbp,
-                     ncols - col0, c->Vq, ld, Tp, trans ? 1 : 0);
+  hipLaunchKernelGGL(k_apply_wy, dim3(stripes, 1, c->nch), dim3(512), 0, c->stream, C + col0, ld, n, j,
+                     nbp, ncols - col0, c->Vq, ld, Tp, trans ? 1 : 0, c->zs);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   return KDQMC_OK;
 }
@@ -464,7 +481,7 @@ int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q) {
   const int ld = c->N;
   if (n > 2048) return set_error(KDQMC_EUNSUPPORTED, "QR order above 2048");
   const size_t nn = (size_t)n * ld;
-  hipLaunchKernelGGL(k_zero, dim3((nn + 255) / 256), dim3(256), 0, c->stream, c->Vq, nn);
+  hipLaunchKernelGGL(k_zero, dim3((nn + 255) / 256, 1, c->nch), dim3(256), 0, c->stream, c->Vq, nn, c->zs);
   int npan = 0;
   for (int j = 0; j < n; ++npan) {
     const int nbp = std::min(panel_width(n - j), n - j);
@@ -477,7 +494,8 @@ int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q) {
   }
   c->qr_npan = npan;
   if (Q) {
-    hipLaunchKernelGGL(k_set_identity, dim3((n * n + 255) / 256), dim3(256), 0, c->stream, Q, n, ld);
+    hipLaunchKernelGGL(k_set_identity, dim3((n * n + 255) / 256, 1, c->nch), dim3(256), 0, c->stream, Q, n,
+                       ld, c->zs);
     for (int p = npan - 1; p >= 0; --p) {
       const int j = c->qr_panel_start[p];
       KDQMC_TRY(launch_apply(c, Q, ld, n, j, c->qr_panel_width[p], j, n,
@@ -508,8 +526,11 @@ int apply_qt_f64(kdqmc_ctx* c, int n, double* X) {
 // ---------------------------------------------------------------------------
 constexpr int kTB = 32;
 
-__global__ void k_trinv_blocks(const double* __restrict__ R, int n, int ld, double* __restrict__ Rinv) {
+__global__ void k_trinv_blocks(const double* __restrict__ R, int n, int ld, double* __restrict__ Rinv,
+                               size_t zs) {
   __shared__ double Rb[kTB][kTB + 1];
+  R = zw(R, zs);
+  Rinv = zw(Rinv, zs);
   const int b = blockIdx.x;
   const int b0 = b * kTB;
   const int nbp = min(kTB, n - b0);
@@ -538,8 +559,11 @@ __global__ void k_trinv_blocks(const double* __restrict__ R, int n, int ld, doub
 // partials summed in LDS), then X_b = Rinv_bb (X_b - acc).
 __global__ void __launch_bounds__(256)
 k_trsm_upper(const double* __restrict__ R, const double* __restrict__ Rinv, double* __restrict__ X,
-             int n, int ld) {
+             int n, int ld, size_t zs) {
   __shared__ double Wp[4][32][33];
+  R = zw(R, zs);
+  Rinv = zw(Rinv, zs);
+  X = zw(X, zs);
   __shared__ double Rb[32][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -605,8 +629,9 @@ int trsm_upper_f64(kdqmc_ctx* c, int n, const double* R, double* X) {
   const int nblk = (n + kTB - 1) / kTB;
   double* Rinv = c->Tq;  // nblk * 32 * 32 (the QR's T factors are no longer needed)
   const int e0 = prof_mark(c);
-  hipLaunchKernelGGL(k_trinv_blocks, dim3(nblk), dim3(64), 0, c->stream, R, n, ld, Rinv);
-  hipLaunchKernelGGL(k_trsm_upper, dim3((n + 31) / 32), dim3(256), 0, c->stream, R, Rinv, X, n, ld);
+  hipLaunchKernelGGL(k_trinv_blocks, dim3(nblk, 1, c->nch), dim3(64), 0, c->stream, R, n, ld, Rinv, c->zs);
+  hipLaunchKernelGGL(k_trsm_upper, dim3((n + 31) / 32, 1, c->nch), dim3(256), 0, c->stream, R, Rinv, X, n, ld,
+                     c->zs);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;

@@ -19,13 +19,20 @@
 
 namespace kdqmc {
 
-__global__ void k_ev_slice(const int8_t* __restrict__ s, int n, double ea, double eainv,
-                           double* __restrict__ ev) {
+__global__ void k_ev_slice(const int8_t* __restrict__ s, int n, const double* __restrict__ sc,
+                           double* __restrict__ ev, size_t zs) {
+  s = zw(s, zs);
+  ev = zw(ev, zs);
+  const double ea = zw(sc, zs)[SC_EA], eainv = zw(sc, zs)[SC_EAINV];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) ev[i] = s[i] > 0 ? ea : eainv;
 }
 
-__global__ void k_identity_udt(double* __restrict__ U, double* __restrict__ D, double* __restrict__ T, int n) {
+__global__ void k_identity_udt(double* __restrict__ U, double* __restrict__ D, double* __restrict__ T, int n,
+                               size_t zs) {
+  U = zw(U, zs);
+  D = zw(D, zs);
+  T = zw(T, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)n * n) {
     const int r = idx / n, c = idx % n;
@@ -35,15 +42,20 @@ __global__ void k_identity_udt(double* __restrict__ U, double* __restrict__ D, d
   }
 }
 
-__global__ void k_scale_cols(double* __restrict__ C, int n, const double* __restrict__ d) {
+__global__ void k_scale_cols(double* __restrict__ C, int n, const double* __restrict__ d, size_t zs) {
+  C = zw(C, zs);
+  d = zw(d, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)n * n) C[idx] *= d[idx % n];
 }
 
 // squared column norms: a workgroup owns 64 columns, its 4 waves split the
 // rows (lanes over columns: coalesced), partial sums combined in LDS
-__global__ void __launch_bounds__(256) k_colnorm2(const double* __restrict__ C, int n, double* __restrict__ nrm) {
+__global__ void __launch_bounds__(256) k_colnorm2(const double* __restrict__ C, int n, double* __restrict__ nrm,
+                                                  size_t zs) {
   __shared__ double part[4][64];
+  C = zw(C, zs);
+  nrm = zw(nrm, zs);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + lane;
   double s = 0.0;
@@ -60,7 +72,9 @@ __global__ void __launch_bounds__(256) k_colnorm2(const double* __restrict__ C, 
 }
 
 // perm[rank] = column, descending norm, ties by column index (stable); n <= 2048
-__global__ void k_rank_perm(const double* __restrict__ nrm, int n, int* __restrict__ perm) {
+__global__ void k_rank_perm(const double* __restrict__ nrm, int n, int* __restrict__ perm, size_t zs) {
+  nrm = zw(nrm, zs);
+  perm = zw(perm, zs);
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     const double v = nrm[c];
     int rank = 0;
@@ -73,7 +87,10 @@ __global__ void k_rank_perm(const double* __restrict__ nrm, int n, int* __restri
 }
 
 __global__ void k_gather_cols(double* __restrict__ dst, const double* __restrict__ src, int n,
-                              const int* __restrict__ perm) {
+                              const int* __restrict__ perm, size_t zs) {
+  dst = zw(dst, zs);
+  src = zw(src, zs);
+  perm = zw(perm, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)n * n) {
     const int r = idx / n, c = idx % n;
@@ -82,7 +99,10 @@ __global__ void k_gather_cols(double* __restrict__ dst, const double* __restrict
 }
 
 __global__ void k_gather_rows(double* __restrict__ dst, const double* __restrict__ src, int n,
-                              const int* __restrict__ perm) {
+                              const int* __restrict__ perm, size_t zs) {
+  dst = zw(dst, zs);
+  src = zw(src, zs);
+  perm = zw(perm, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)n * n) {
     const int r = idx / n, c = idx % n;
@@ -91,19 +111,27 @@ __global__ void k_gather_rows(double* __restrict__ dst, const double* __restrict
 }
 
 // R <- D^{-1} R (rows), D = |diag R| computed beforehand by k_diag_abs
-__global__ void k_diag_normalize(double* __restrict__ R, int n, const double* __restrict__ D) {
+__global__ void k_diag_normalize(double* __restrict__ R, int n, const double* __restrict__ D, size_t zs) {
+  R = zw(R, zs);
+  D = zw(D, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)n * n) R[idx] /= D[idx / n];
 }
 
-__global__ void k_diag_abs(const double* __restrict__ R, int n, double* __restrict__ D) {
+__global__ void k_diag_abs(const double* __restrict__ R, int n, double* __restrict__ D, size_t zs) {
+  R = zw(R, zs);
+  D = zw(D, zs);
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n) D[r] = fabs(R[(size_t)r * n + r]);
 }
 
 // M = Db_R^{-1} X1 Db_L^{-1} + Ds_R X2 Ds_L (in place in X1)
 __global__ void k_combine_M(double* __restrict__ X1, const double* __restrict__ X2, int n,
-                            const double* __restrict__ DR, const double* __restrict__ DL) {
+                            const double* __restrict__ DR, const double* __restrict__ DL, size_t zs) {
+  X1 = zw(X1, zs);
+  X2 = zw(X2, zs);
+  DR = zw(DR, zs);
+  DL = zw(DL, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)n * n) {
     const int r = idx / n, c = idx % n;
@@ -116,7 +144,10 @@ __global__ void k_combine_M(double* __restrict__ X1, const double* __restrict__ 
 
 // dst = Db^{-1} src^T
 __global__ void k_transpose_scale(double* __restrict__ dst, const double* __restrict__ src, int n,
-                                  const double* __restrict__ D) {
+                                  const double* __restrict__ D, size_t zs) {
+  dst = zw(dst, zs);
+  src = zw(src, zs);
+  D = zw(D, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)n * n) {
     const int r = idx / n, c = idx % n;
@@ -125,15 +156,20 @@ __global__ void k_transpose_scale(double* __restrict__ dst, const double* __rest
 }
 
 // X <- Db^{-1} X (rows)
-__global__ void k_scale_rows_big(double* __restrict__ X, int n, const double* __restrict__ D) {
+__global__ void k_scale_rows_big(double* __restrict__ X, int n, const double* __restrict__ D, size_t zs) {
+  X = zw(X, zs);
+  D = zw(D, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)n * n) X[idx] /= fmax(D[idx / n], 1.0);
 }
 
 template <typename T>
 __global__ void k_maxabs_partial(const T* __restrict__ G, const double* __restrict__ F, size_t count,
-                                 double* __restrict__ part) {
+                                 double* __restrict__ part, size_t zs) {
   __shared__ double red[16];
+  G = zw(G, zs);
+  F = zw(F, zs);
+  part = zw(part, zs);
   double m = 0.0;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count;
        idx += (size_t)gridDim.x * blockDim.x) {
@@ -153,34 +189,50 @@ __global__ void k_maxabs_partial(const T* __restrict__ G, const double* __restri
   }
 }
 
-__global__ void k_max_final(const double* __restrict__ part, int n, double* __restrict__ out) {
-  if (threadIdx.x == 0) {
-    double r = 0.0;
-    for (int i = 0; i < n; ++i) r = (part[i] > r || part[i] != part[i]) ? part[i] : r;
-    out[0] = r;
+// out[0] = max of n partial maxima (one wave; NaN propagates); out is a
+// caller array with records zo bytes apart
+__global__ void k_max_final(const double* __restrict__ part, int n, double* __restrict__ out, size_t zs,
+                            size_t zo) {
+  part = zw(part, zs);
+  out = zw(out, zo);
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 64) m = (part[i] > m || part[i] != part[i]) ? part[i] : m;
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double x = __shfl_xor(m, o);
+    m = (x > m || x != x) ? x : m;
   }
+  if (threadIdx.x == 0) out[0] = m;
 }
 
+// dst and src records are zd and zsrc bytes apart between chains
 template <typename TO, typename TI>
-__global__ void k_convert(TO* __restrict__ dst, const TI* __restrict__ src, size_t count) {
+__global__ void k_convert(TO* __restrict__ dst, const TI* __restrict__ src, size_t count, size_t zd,
+                          size_t zsrc) {
+  dst = zw(dst, zd);
+  src = zw(src, zsrc);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < count) dst[idx] = TO(src[idx]);
 }
 
-__global__ void k_copy_f64(double* __restrict__ dst, const double* __restrict__ src, size_t n) {
+__global__ void k_copy_f64(double* __restrict__ dst, const double* __restrict__ src, size_t n, size_t zs) {
+  dst = zw(dst, zs);
+  src = zw(src, zs);
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
 }
 
 int copy_f64(kdqmc_ctx* c, double* dst, const double* src, size_t n) {
-  hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, dst, src, n);
+  hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((n + 255) / 256), 1, c->nch), dim3(256), 0, c->stream, dst,
+                     src, n, c->zs);
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
 
 namespace {
 
-inline dim3 grid_for(size_t count) { return dim3((unsigned)((count + 255) / 256)); }
+inline dim3 grid_for(kdqmc_ctx* c, size_t count) {
+  return dim3((unsigned)((count + 255) / 256), 1, (unsigned)c->nch);
+}
 
 double* stackU(kdqmc_ctx* c, bool left, int j) { return (left ? c->LU : c->RU) + (size_t)j * c->N * c->N; }
 double* stackT(kdqmc_ctx* c, bool left, int j) { return (left ? c->LT : c->RT) + (size_t)j * c->N * c->N; }
@@ -197,24 +249,24 @@ int udt_step(kdqmc_ctx* c, const double* Uin, const double* Din, const double* T
   double* Tp = c->S[3];
   double* evs = c->nrm + n;  // second half of the norm buffer holds the slice scale
   KDQMC_TRY(copy_f64(c, C, Uin, nn));
-  const double ea = std::exp(c->alpha), eainv = std::exp(-c->alpha);
+  const size_t zs = c->zs;
   for (int q = 0; q < nsl; ++q) {
     const int l = slices[q];
-    hipLaunchKernelGGL(k_ev_slice, dim3((n + 255) / 256), dim3(256), 0, c->stream,
-                       c->fields + (size_t)(l - 1) * n, n, ea, eainv, evs);
+    hipLaunchKernelGGL(k_ev_slice, grid_for(c, n), dim3(256), 0, c->stream,
+                       c->fields + (size_t)(l - 1) * n, n, c->sc, evs, zs);
     if (transposed)
       KDQMC_TRY(launch_kinetic_f64(c, C, n, true, c->tab_mu64, nullptr, nullptr, evs));
     else
       KDQMC_TRY(launch_kinetic_f64(c, C, n, true, c->tab_mu64, evs, nullptr, nullptr));
   }
-  hipLaunchKernelGGL(k_scale_cols, grid_for(nn), dim3(256), 0, c->stream, C, n, Din);
-  hipLaunchKernelGGL(k_colnorm2, dim3((n + 63) / 64), dim3(256), 0, c->stream, C, n, c->nrm);
-  hipLaunchKernelGGL(k_rank_perm, dim3(1), dim3(1024), 0, c->stream, c->nrm, n, c->perm);
-  hipLaunchKernelGGL(k_gather_cols, grid_for(nn), dim3(256), 0, c->stream, Cp, C, n, c->perm);
+  hipLaunchKernelGGL(k_scale_cols, grid_for(c, nn), dim3(256), 0, c->stream, C, n, Din, zs);
+  hipLaunchKernelGGL(k_colnorm2, dim3((n + 63) / 64, 1, c->nch), dim3(256), 0, c->stream, C, n, c->nrm, zs);
+  hipLaunchKernelGGL(k_rank_perm, dim3(1, 1, c->nch), dim3(1024), 0, c->stream, c->nrm, n, c->perm, zs);
+  hipLaunchKernelGGL(k_gather_cols, grid_for(c, nn), dim3(256), 0, c->stream, Cp, C, n, c->perm, zs);
   KDQMC_TRY(qr_f64(c, n, Cp, Uout));
-  hipLaunchKernelGGL(k_diag_abs, dim3((n + 255) / 256), dim3(256), 0, c->stream, Cp, n, Dout);
-  hipLaunchKernelGGL(k_diag_normalize, grid_for(nn), dim3(256), 0, c->stream, Cp, n, Dout);
-  hipLaunchKernelGGL(k_gather_rows, grid_for(nn), dim3(256), 0, c->stream, Tp, Tin, n, c->perm);
+  hipLaunchKernelGGL(k_diag_abs, grid_for(c, n), dim3(256), 0, c->stream, Cp, n, Dout, zs);
+  hipLaunchKernelGGL(k_diag_normalize, grid_for(c, nn), dim3(256), 0, c->stream, Cp, n, Dout, zs);
+  hipLaunchKernelGGL(k_gather_rows, grid_for(c, nn), dim3(256), 0, c->stream, Tp, Tin, n, c->perm, zs);
   KDQMC_TRY(gemm_f64(c, false, false, n, n, n, 1.0, Cp, n, Tp, n, 0.0, Tout, n));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
@@ -224,8 +276,8 @@ int udt_step(kdqmc_ctx* c, const double* Uin, const double* Din, const double* T
 
 int stab_identity(kdqmc_ctx* c, bool left, int j) {
   const size_t nn = (size_t)c->N * c->N;
-  hipLaunchKernelGGL(k_identity_udt, grid_for(nn), dim3(256), 0, c->stream, stackU(c, left, j),
-                     stackD(c, left, j), stackT(c, left, j), c->N);
+  hipLaunchKernelGGL(k_identity_udt, grid_for(c, nn), dim3(256), 0, c->stream, stackU(c, left, j),
+                     stackD(c, left, j), stackT(c, left, j), c->N, c->zs);
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
@@ -267,52 +319,56 @@ int stab_green(kdqmc_ctx* c, int j, double* out) {
   double* Y = c->S[4];
   KDQMC_TRY(gemm_f64(c, true, false, n, n, n, 1.0, UR, n, UL, n, 0.0, X1, n));
   KDQMC_TRY(gemm_f64(c, false, true, n, n, n, 1.0, TR, n, TL, n, 0.0, X2, n));
-  hipLaunchKernelGGL(k_combine_M, grid_for(nn), dim3(256), 0, c->stream, X1, X2, n, DR, DL);
+  hipLaunchKernelGGL(k_combine_M, grid_for(c, nn), dim3(256), 0, c->stream, X1, X2, n, DR, DL, c->zs);
   KDQMC_TRY(qr_f64(c, n, X1, nullptr));
-  hipLaunchKernelGGL(k_transpose_scale, grid_for(nn), dim3(256), 0, c->stream, Y, UR, n, DR);
+  hipLaunchKernelGGL(k_transpose_scale, grid_for(c, nn), dim3(256), 0, c->stream, Y, UR, n, DR, c->zs);
   KDQMC_TRY(apply_qt_f64(c, n, Y));
   KDQMC_TRY(trsm_upper_f64(c, n, X1, Y));
-  hipLaunchKernelGGL(k_scale_rows_big, grid_for(nn), dim3(256), 0, c->stream, Y, n, DL);
+  hipLaunchKernelGGL(k_scale_rows_big, grid_for(c, nn), dim3(256), 0, c->stream, Y, n, DL, c->zs);
   KDQMC_TRY(gemm_f64(c, false, false, n, n, n, 1.0, UL, n, Y, n, 0.0, out, n));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
 
-int copy_G_to64(kdqmc_ctx* c, double* out) {
+int copy_G_to64(kdqmc_ctx* c, double* out, size_t zn) {
   const size_t nn = (size_t)c->N * c->N;
-  if (c->fp64) {
-    KDQMC_TRY(copy_f64(c, out, (const double*)c->G, nn));
-  } else {
-    hipLaunchKernelGGL((k_convert<double, float>), grid_for(nn), dim3(256), 0, c->stream, out,
-                       (const float*)c->G, nn);
-    KDQMC_HIP(hipGetLastError());
-  }
+  const size_t zd = zn ? zn * sizeof(double) : c->zs;
+  if (c->fp64)
+    hipLaunchKernelGGL((k_convert<double, double>), grid_for(c, nn), dim3(256), 0, c->stream, out,
+                       (const double*)c->G, nn, zd, c->zs);
+  else
+    hipLaunchKernelGGL((k_convert<double, float>), grid_for(c, nn), dim3(256), 0, c->stream, out,
+                       (const float*)c->G, nn, zd, c->zs);
+  KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
 
-int copy_64_to_G(kdqmc_ctx* c, const double* in) {
+int copy_64_to_G(kdqmc_ctx* c, const double* in, size_t zn) {
   const size_t nn = (size_t)c->N * c->N;
+  const size_t zsrc = zn ? zn * sizeof(double) : c->zs;
   if (c->fp64) {
     if (in != c->G)
-      KDQMC_TRY(copy_f64(c, (double*)c->G, in, nn));
+      hipLaunchKernelGGL((k_convert<double, double>), grid_for(c, nn), dim3(256), 0, c->stream,
+                         (double*)c->G, in, nn, c->zs, zsrc);
   } else {
-    hipLaunchKernelGGL((k_convert<float, double>), grid_for(nn), dim3(256), 0, c->stream,
-                       (float*)c->G, in, nn);
-    KDQMC_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_convert<float, double>), grid_for(c, nn), dim3(256), 0, c->stream,
+                       (float*)c->G, in, nn, c->zs, zsrc);
   }
+  KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
 
-int max_abs_diff(kdqmc_ctx* c, const double* a, int /*n*/, double* out) {
+int max_abs_diff(kdqmc_ctx* c, const double* a, int /*n*/, double* out, size_t zn) {
   const size_t nn = (size_t)c->N * c->N;
   const int nblk = 256;
   if (c->fp64)
-    hipLaunchKernelGGL((k_maxabs_partial<double>), dim3(nblk), dim3(256), 0, c->stream,
-                       (const double*)c->G, a, nn, c->err);
+    hipLaunchKernelGGL((k_maxabs_partial<double>), dim3(nblk, 1, c->nch), dim3(256), 0, c->stream,
+                       (const double*)c->G, a, nn, c->err, c->zs);
   else
-    hipLaunchKernelGGL((k_maxabs_partial<float>), dim3(nblk), dim3(256), 0, c->stream,
-                       (const float*)c->G, a, nn, c->err);
-  hipLaunchKernelGGL(k_max_final, dim3(1), dim3(64), 0, c->stream, c->err, nblk, out);
+    hipLaunchKernelGGL((k_maxabs_partial<float>), dim3(nblk, 1, c->nch), dim3(256), 0, c->stream,
+                       (const float*)c->G, a, nn, c->err, c->zs);
+  hipLaunchKernelGGL(k_max_final, dim3(1, 1, c->nch), dim3(64), 0, c->stream, c->err, nblk, out, c->zs,
+                     zn * sizeof(double));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }

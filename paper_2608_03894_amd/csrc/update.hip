@@ -27,8 +27,12 @@ typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // ev = exp(alpha s), evinv = exp(-alpha s) for the fields of one slice.
-__global__ void k_frame_scale(const int8_t* __restrict__ s, int n, double ea, double eainv,
-                              double* __restrict__ ev, double* __restrict__ evinv) {
+__global__ void k_frame_scale(const int8_t* __restrict__ s, int n, const double* __restrict__ sc,
+                              double* __restrict__ ev, double* __restrict__ evinv, size_t zs) {
+  s = zw(s, zs);
+  ev = zw(ev, zs);
+  evinv = zw(evinv, zs);
+  const double ea = zw(sc, zs)[SC_EA], eainv = zw(sc, zs)[SC_EAINV];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const bool up = s[i] > 0;
@@ -64,10 +68,24 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
          const double* __restrict__ evinv, int8_t* __restrict__ s_l,
          const double* __restrict__ u, const uint8_t* __restrict__ forced,
          uint8_t* __restrict__ acc_out, double* __restrict__ ratio_out, int w0, int wn, int W,
-         const double* __restrict__ Gs_in, double em2a, double ep2a, int win,
+         const double* __restrict__ Gs_in, const double* __restrict__ sc, int win,
          int* __restrict__ win_a, int* __restrict__ win_p, double* __restrict__ Zg,
-         double* __restrict__ Zpg) {
+         double* __restrict__ Zpg, size_t zs, size_t zn) {
   constexpr int GR = (NT == 64) ? 8 : 16;
+  G = zw(G, zs);
+  ev = zw(ev, zs);
+  evinv = zw(evinv, zs);
+  s_l = zw(s_l, zs);
+  u = zc(u, zn);
+  forced = zc(forced, zn);
+  acc_out = zc(acc_out, zn);
+  ratio_out = zc(ratio_out, zn);
+  Gs_in = zw(Gs_in, zs);
+  win_a = zw(win_a, zs);
+  win_p = zw(win_p, zs);
+  Zg = zw(Zg, zs);
+  Zpg = zw(Zpg, zs);
+  const double em2a = zw(sc, zs)[SC_EM2A], ep2a = zw(sc, zs)[SC_EP2A];
   constexpr int WM = GR * WS;  // largest window this instance handles
   // Everything the loop produces stays in LDS until the end: a barrier also
   // waits for outstanding global stores, so none are issued inside the loop.
@@ -220,8 +238,18 @@ __global__ void __launch_bounds__(256)
 k_extend(const T* __restrict__ G, int N, const double* __restrict__ ev,
          const double* __restrict__ evinv, T* __restrict__ Up, T* __restrict__ Wp,
          const int* __restrict__ win_a, int win, int grp0, const int* __restrict__ win_p,
-         const double* __restrict__ Zg, const double* __restrict__ Zpg, int W, int w0, int RB) {
+         const double* __restrict__ Zg, const double* __restrict__ Zpg, int W, int w0, int RB,
+         size_t zs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  G = zw(G, zs);
+  ev = zw(ev, zs);
+  evinv = zw(evinv, zs);
+  Up = zw(Up, zs);
+  Wp = zw(Wp, zs);
+  win_a = zw(win_a, zs);
+  win_p = zw(win_p, zs);
+  Zg = zw(Zg, zs);
+  Zpg = zw(Zpg, zs);
   const int a = win_a[win];
   if (a == 0) return;
   int m = 0;
@@ -277,7 +305,14 @@ template <typename T>
 __global__ void k_prep(const T* __restrict__ G, int N, const double* __restrict__ ev,
                        const double* __restrict__ evinv, const T* __restrict__ Up,
                        const T* __restrict__ Wp, const int* __restrict__ win_a, int grp0,
-                       int upto, int w0, int wn, int W, double* __restrict__ Gs) {
+                       int upto, int w0, int wn, int W, double* __restrict__ Gs, size_t zs) {
+  G = zw(G, zs);
+  ev = zw(ev, zs);
+  evinv = zw(evinv, zs);
+  Up = zw(Up, zs);
+  Wp = zw(Wp, zs);
+  win_a = zw(win_a, zs);
+  Gs = zw(Gs, zs);
   int m = 0;
   for (int j = grp0; j <= upto; ++j) m += win_a[j];
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -297,7 +332,12 @@ __global__ void k_prep(const T* __restrict__ G, int N, const double* __restrict_
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_flush_f64(double* __restrict__ G, int N, const double* __restrict__ Up,
-            const double* __restrict__ Wp, const int* __restrict__ win_a, int grp0, int grp1) {
+            const double* __restrict__ Wp, const int* __restrict__ win_a, int grp0, int grp1,
+            size_t zs) {
+  G = zw(G, zs);
+  Up = zw(Up, zs);
+  Wp = zw(Wp, zs);
+  win_a = zw(win_a, zs);
   int K = 0;
   for (int j = grp0; j < grp1; ++j) K += win_a[j];
   if (K == 0) return;
@@ -370,7 +410,12 @@ struct SplitTraits<__bf16> {
 template <typename H>
 __global__ void __launch_bounds__(256)
 k_flush_split(float* __restrict__ G, int N, const float* __restrict__ Up,
-              const float* __restrict__ Wp, const int* __restrict__ win_a, int grp0, int grp1) {
+              const float* __restrict__ Wp, const int* __restrict__ win_a, int grp0, int grp1,
+              size_t zs) {
+  G = zw(G, zs);
+  Up = zw(Up, zs);
+  Wp = zw(Wp, zs);
+  win_a = zw(win_a, zs);
   typedef SplitTraits<H> Tr;
   typedef typename Tr::vec vec;
   int K = 0;
@@ -443,14 +488,15 @@ int set_lds_limits() {
 
 template <typename T>
 int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, uint8_t* acc,
-                  double* ratio) {
+                  double* ratio, size_t zn) {
   const int N = c->N, W = c->w;
   T* G = static_cast<T*>(c->G);
   T* Up = static_cast<T*>(c->Upend);
   T* Wp = static_cast<T*>(c->Wpend);
   int8_t* s_l = c->fields + (size_t)(l - 1) * N;
-  const double em2a = std::exp(-2.0 * c->alpha), ep2a = std::exp(2.0 * c->alpha);
   const int RB = 32;
+  const unsigned Z = (unsigned)c->nch;
+  const size_t zs = c->zs;
   for (int win = 0; win < c->nw; ++win) {
     const int w0 = win * W;
     const int wn = std::min(W, N - w0);
@@ -459,47 +505,50 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
     // decide
     const int e_d = prof_mark(c);
     if (wn <= 16)
-      hipLaunchKernelGGL((k_decide<T, 1, 256>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
-                         s_l, u, forced, acc, ratio, w0, wn, W, first_in_group ? nullptr : c->Gs,
-                         em2a, ep2a, win, c->win_a, c->win_p, c->Xw, c->Yw);
+      hipLaunchKernelGGL((k_decide<T, 1, 256>), dim3(1, 1, Z), dim3(256), 0, c->stream, G, N, c->ev,
+                         c->evinv, s_l, u, forced, acc, ratio, w0, wn, W,
+                         first_in_group ? nullptr : c->Gs, c->sc, win, c->win_a, c->win_p, c->Xw,
+                         c->Yw, zs, zn);
     else if (wn <= 32)
-      hipLaunchKernelGGL((k_decide<T, 2, 256>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
-                         s_l, u, forced, acc, ratio, w0, wn, W, first_in_group ? nullptr : c->Gs,
-                         em2a, ep2a, win, c->win_a, c->win_p, c->Xw, c->Yw);
+      hipLaunchKernelGGL((k_decide<T, 2, 256>), dim3(1, 1, Z), dim3(256), 0, c->stream, G, N, c->ev,
+                         c->evinv, s_l, u, forced, acc, ratio, w0, wn, W,
+                         first_in_group ? nullptr : c->Gs, c->sc, win, c->win_a, c->win_p, c->Xw,
+                         c->Yw, zs, zn);
     else
-      hipLaunchKernelGGL((k_decide<T, 4, 256>), dim3(1), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
-                         s_l, u, forced, acc, ratio, w0, wn, W, first_in_group ? nullptr : c->Gs,
-                         em2a, ep2a, win, c->win_a, c->win_p, c->Xw, c->Yw);
+      hipLaunchKernelGGL((k_decide<T, 4, 256>), dim3(1, 1, Z), dim3(256), 0, c->stream, G, N, c->ev,
+                         c->evinv, s_l, u, forced, acc, ratio, w0, wn, W,
+                         first_in_group ? nullptr : c->Gs, c->sc, win, c->win_a, c->win_p, c->Xw,
+                         c->Yw, zs, zn);
     const int e_e = prof_mark(c);
     prof_pair(c, PH_DECIDE, e_d, e_e);
     // extend
     const size_t lds_e = 2 * size_t(W) * W * 8 + 2 * size_t(RB) * W * 8 + size_t(W) * 4 + 16;
-    hipLaunchKernelGGL(k_extend<T>, dim3((N + RB - 1) / RB), dim3(256), lds_e, c->stream, G, N,
+    hipLaunchKernelGGL(k_extend<T>, dim3((N + RB - 1) / RB, 1, Z), dim3(256), lds_e, c->stream, G, N,
                        c->ev, c->evinv, Up, Wp, c->win_a, win, grp0, c->win_p, c->Xw, c->Yw, W,
-                       w0, RB);
+                       w0, RB, zs);
     const int e_x = prof_mark(c);
     prof_pair(c, PH_EXTEND, e_e, e_x);
     const bool last_in_group = (win - grp0 == c->F - 1) || (win == c->nw - 1);
     if (last_in_group) {
-      dim3 grid((N + 63) / 64, (N + 63) / 64);
+      dim3 grid((N + 63) / 64, (N + 63) / 64, Z);
       if constexpr (sizeof(T) == 8) {
         hipLaunchKernelGGL(k_flush_f64, grid, dim3(256), 0, c->stream, (double*)G, N,
-                           (const double*)Up, (const double*)Wp, c->win_a, grp0, win + 1);
+                           (const double*)Up, (const double*)Wp, c->win_a, grp0, win + 1, zs);
       } else {
         if (c->p.prec == KDQMC_MIXED_BF16)
           hipLaunchKernelGGL(k_flush_split<__bf16>, grid, dim3(256), 0, c->stream, (float*)G, N,
-                             (const float*)Up, (const float*)Wp, c->win_a, grp0, win + 1);
+                             (const float*)Up, (const float*)Wp, c->win_a, grp0, win + 1, zs);
         else
           hipLaunchKernelGGL(k_flush_split<_Float16>, grid, dim3(256), 0, c->stream, (float*)G, N,
-                             (const float*)Up, (const float*)Wp, c->win_a, grp0, win + 1);
+                             (const float*)Up, (const float*)Wp, c->win_a, grp0, win + 1, zs);
       }
       prof_pair(c, PH_FLUSH, e_x, prof_mark(c));
     } else {
       const int nx = win + 1;
       const int nw0 = nx * W;
       const int nwn = std::min(W, N - nw0);
-      hipLaunchKernelGGL(k_prep<T>, dim3((nwn * nwn + 255) / 256), dim3(256), 0, c->stream, G, N,
-                         c->ev, c->evinv, Up, Wp, c->win_a, grp0, win, nw0, nwn, W, c->Gs);
+      hipLaunchKernelGGL(k_prep<T>, dim3((nwn * nwn + 255) / 256, 1, Z), dim3(256), 0, c->stream, G,
+                         N, c->ev, c->evinv, Up, Wp, c->win_a, grp0, win, nw0, nwn, W, c->Gs, zs);
       prof_pair(c, PH_PREP, e_x, prof_mark(c));
     }
   }
@@ -515,17 +564,17 @@ int prepare_updates() {
 }
 
 int launch_frame_scale(kdqmc_ctx* c, int l) {
-  const double ea = std::exp(c->alpha), eainv = std::exp(-c->alpha);
-  hipLaunchKernelGGL(k_frame_scale, dim3((c->N + 255) / 256), dim3(256), 0, c->stream,
-                     c->fields + (size_t)(l - 1) * c->N, c->N, ea, eainv, c->ev, c->evinv);
+  hipLaunchKernelGGL(k_frame_scale, dim3((c->N + 255) / 256, 1, (unsigned)c->nch), dim3(256), 0,
+                     c->stream, c->fields + (size_t)(l - 1) * c->N, c->N, c->sc, c->ev, c->evinv,
+                     c->zs);
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
 
 int run_slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, uint8_t* acc,
-                      double* ratio) {
-  if (c->fp64) return slice_updates<double>(c, l, u, forced, acc, ratio);
-  return slice_updates<float>(c, l, u, forced, acc, ratio);
+                      double* ratio, size_t zn) {
+  if (c->fp64) return slice_updates<double>(c, l, u, forced, acc, ratio, zn);
+  return slice_updates<float>(c, l, u, forced, acc, ratio, zn);
 }
 
 }  // namespace kdqmc

@@ -46,6 +46,10 @@ _lib = None
 _vp = ctypes.c_void_p
 _SIGS = {
     "kdqmc_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Params)]),
+    "kdqmc_workspace_bytes_batch": (ctypes.c_size_t, [ctypes.POINTER(Params), ctypes.c_int]),
+    "kdqmc_init_batch": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(Params), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_double), _vp, ctypes.c_size_t, _vp]),
+    "kdqmc_num_chains": (ctypes.c_int, [_vp]),
     "kdqmc_dirac_mu": (ctypes.c_double, [ctypes.c_int, ctypes.c_double]),
     "kdqmc_init_lattice": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.POINTER(Params), _vp,
                                           ctypes.c_size_t, _vp]),
@@ -120,8 +124,8 @@ def make_params(L, U, beta, dtau=0.1, t=1.0, mu=None, n_stab=10, delay_k=32, win
                   window=window, fft_tile=fft_tile, prec=prec)
 
 
-def workspace_bytes(p: Params) -> int:
-    return int(load().kdqmc_workspace_bytes(ctypes.byref(p)))
+def workspace_bytes(p: Params, n_chains: int = 1) -> int:
+    return int(load().kdqmc_workspace_bytes_batch(ctypes.byref(p), n_chains))
 
 
 def dirac_mu(L: int, t: float = 1.0) -> float:
@@ -135,9 +139,13 @@ def _ptr(x):
 
 
 class Chain:
-    """One Markov chain: a context, its workspace tensor and its stream."""
+    """A context with its workspace tensor and stream: one Markov chain, or
+    n_chains chains of one shape (per-chain interaction U) run together.
 
-    def __init__(self, params: Params, device="cuda:0", stream=None):
+    For n_chains > 1 every array argument holds one record per chain (leading
+    dimension n_chains), each shaped as for a single chain."""
+
+    def __init__(self, params: Params, device="cuda:0", stream=None, n_chains=1, U=None):
         import torch
         self.torch = torch
         self.p = params
@@ -145,15 +153,21 @@ class Chain:
         self.device = torch.device(device)
         self.N = 3 * params.L * params.L
         self.L_tau = int(round(params.beta / params.dtau))
-        nbytes = workspace_bytes(params)
+        self.n_chains = int(n_chains)
+        nbytes = workspace_bytes(params, self.n_chains)
         if nbytes == 0:
             raise KdqmcError(EINVAL, last_error())
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
-        _check(self.lib.kdqmc_init_lattice(ctypes.byref(ctx), ctypes.byref(params),
-                                           _ptr(self.ws), nbytes,
-                                           ctypes.c_void_p(self.stream.cuda_stream)))
+        u_arr = None
+        if U is not None:
+            if len(U) != self.n_chains:
+                raise KdqmcError(EINVAL, "need one U per chain")
+            u_arr = (ctypes.c_double * self.n_chains)(*[float(x) for x in U])
+        _check(self.lib.kdqmc_init_batch(ctypes.byref(ctx), ctypes.byref(params), self.n_chains,
+                                         u_arr, _ptr(self.ws), nbytes,
+                                         ctypes.c_void_p(self.stream.cuda_stream)))
         self.ctx = ctx
 
     # -- the calls of the C ABI, same names ---------------------------------
@@ -214,7 +228,8 @@ class Chain:
 
     # -- conveniences ---------------------------------------------------------
     def G(self):
-        out = self.torch.empty((self.N, self.N), dtype=self.torch.float64, device=self.device)
+        shape = (self.N, self.N) if self.n_chains == 1 else (self.n_chains, self.N, self.N)
+        out = self.torch.empty(shape, dtype=self.torch.float64, device=self.device)
         self.measure_G(out)
         self.sync()
         return out
@@ -229,3 +244,72 @@ class Chain:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Independent Markov chains of uneven shape (L, beta, U may all differ).
+
+    Chains whose parameters agree except for U form one batched context
+    (one launch per kernel for all of them); each such group runs on its own
+    HIP stream, so the groups' sweeps overlap on the GPU.  Inputs are given
+    per chain in the caller's order and packed per group once (set_inputs);
+    sweep() then enqueues every group's sweep and makes the caller's current
+    stream wait for all of them."""
+
+    def __init__(self, params_list, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = list(params_list)
+        groups = {}
+        for i, p in enumerate(self.params):
+            key = (p.L, p.t, p.mu, p.beta, p.dtau, p.n_stab, p.delay_k, p.window, p.fft_tile, p.prec)
+            groups.setdefault(key, []).append(i)
+        self.groups = []
+        for key, idx in groups.items():
+            stream = torch.cuda.Stream(self.device)
+            ch = Chain(self.params[idx[0]], device=self.device, stream=stream, n_chains=len(idx),
+                       U=[self.params[i].U for i in idx])
+            self.groups.append({"idx": idx, "chain": ch, "stream": stream})
+        self.n_chains = len(self.params)
+
+    def set_inputs(self, fields, uniforms):
+        """fields[c]: int8 (L_tau, N) device tensor; uniforms[c]: float64
+        (n_sweeps, L_tau, N) device tensor of the chain's Metropolis draws."""
+        t = self.torch
+        cur = t.cuda.current_stream(self.device)
+        for g in self.groups:
+            idx = g["idx"]
+            g["fields"] = t.stack([fields[i] for i in idx]).contiguous()
+            g["u"] = t.stack([uniforms[i] for i in idx], dim=1).contiguous()  # (sweeps, chains, L_tau, N)
+            ch = g["chain"]
+            g["acc"] = t.zeros((len(idx), ch.L_tau, ch.N), dtype=t.uint8, device=self.device)
+            g["err"] = t.zeros((len(idx), ch.L_tau // ch.p.n_stab), dtype=t.float64, device=self.device)
+            g["stream"].wait_stream(cur)
+            with t.cuda.stream(g["stream"]):
+                ch.set_fields(g["fields"])
+        for g in self.groups:
+            cur.wait_stream(g["stream"])
+
+    def sweep(self, s):
+        """One sweep of every chain with its uniforms of sweep s."""
+        t = self.torch
+        cur = t.cuda.current_stream(self.device)
+        for g in self.groups:
+            g["stream"].wait_stream(cur)
+            g["chain"].sweep(g["u"][s], None, g["acc"], None, g["err"])
+        for g in self.groups:
+            cur.wait_stream(g["stream"])
+
+    def accepted(self):
+        return sum(int(g["acc"].sum().item()) for g in self.groups)
+
+    def max_wrap_err(self):
+        return max(float(g["err"].max().item()) for g in self.groups)
+
+    def field_updates_per_sweep(self):
+        return sum(3 * p.L * p.L * int(round(p.beta / p.dtau)) for p in self.params)
+
+    def close(self):
+        for g in self.groups:
+            g["chain"].close()

@@ -1,0 +1,137 @@
+"""Batched chains: one context running several independent Markov chains of
+one shape (chains along the launch grid's z dimension), and uneven batches
+grouped by shape onto streams.  A chain computed in a batch must equal the
+same chain computed alone bit for bit (same kernels, same arithmetic order),
+and each chain's own U must reach its decoupling constant (checked against
+the oracle for a chain whose U differs from the first chain's)."""
+import numpy as np
+import pytest
+
+import seeded_inputs as si
+from gpu_helpers import dev, oracle_run, say, torch
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def _params(L, U, beta, prec="fp64", delay_k=16):
+    from paper_2608_03894_amd import kdqmc
+    return kdqmc.make_params(L, U, beta, 0.1, mu=-1.0, n_stab=10, delay_k=delay_k, prec=prec)
+
+
+def _run_single(L, U, beta, f, u, prec):
+    from paper_2608_03894_amd import kdqmc
+    t = torch()
+    ch = kdqmc.Chain(_params(L, U, beta, prec))
+    ch.set_fields(dev(f))
+    acc = t.zeros(f.shape, dtype=t.uint8, device="cuda:0")
+    ratio = t.zeros(f.shape, dtype=t.float64, device="cuda:0")
+    err = t.zeros(f.shape[0] // 10, dtype=t.float64, device="cuda:0")
+    ch.sweep(dev(u), None, acc, ratio, err)
+    g = ch.G().cpu().numpy()
+    out = (g, acc.cpu().numpy(), ratio.cpu().numpy(), err.cpu().numpy())
+    ch.close()
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_f16"])
+def test_batched_chains_equal_single_chains(gpu_lib, prec):
+    from paper_2608_03894_amd import kdqmc
+    t = torch()
+    L, beta = 6, 2.0
+    Us = [-3.0, -4.0, -5.0]
+    seeds = [61, 62, 63]
+    Lt = 20
+    fs = [si.ising_fields(L, Lt, s) for s in seeds]
+    us = [si.metropolis_uniforms(L, Lt, s)[0] for s in seeds]
+    say("batch of 3, L6", prec)
+    b = kdqmc.Chain(_params(L, Us[0], beta, prec), n_chains=3, U=Us)
+    assert b.n_chains == 3
+    b.set_fields(dev(np.stack(fs)))
+    acc = t.zeros((3, Lt, 3 * L * L), dtype=t.uint8, device="cuda:0")
+    ratio = t.zeros((3, Lt, 3 * L * L), dtype=t.float64, device="cuda:0")
+    err = t.zeros((3, Lt // 10), dtype=t.float64, device="cuda:0")
+    b.sweep(dev(np.stack(us)), None, acc, ratio, err)
+    G = b.G().cpu().numpy()
+    acc, ratio, err = acc.cpu().numpy(), ratio.cpu().numpy(), err.cpu().numpy()
+    fields = t.zeros((3, Lt, 3 * L * L), dtype=t.int8, device="cuda:0")
+    b.get_fields(fields)
+    fields = fields.cpu().numpy()
+    b.close()
+    for z in range(3):
+        say("single chain", z, "U", Us[z])
+        g1, a1, r1, e1 = _run_single(L, Us[z], beta, fs[z], us[z], prec)
+        assert np.array_equal(G[z], g1)
+        assert np.array_equal(acc[z], a1)
+        assert np.array_equal(ratio[z], r1)
+        assert np.array_equal(err[z], e1)
+        assert np.array_equal(fields[z] == fs[z], a1 == 0)
+    if prec == "fp64":
+        # chain 2 has U = -5 while the context's parameters carry U = -3
+        m, f, g0, r, u = oracle_run(L, -5.0, beta, seeds[2])
+        assert np.array_equal(acc[2].astype(bool), r["accepted"])
+        assert np.abs(G[2] - r["G"]).max() < TOL64
+        assert np.abs(ratio[2] - r["ratios"]).max() < 1e-9 * np.abs(r["ratios"]).max()
+
+
+def test_batched_slice_calls_and_measure(gpu_lib):
+    """Per-slice calls, stabilize and set_G on a batch (records N, 1 and N*N apart)."""
+    from paper_2608_03894_amd import kdqmc
+    t = torch()
+    L, beta, Lt = 3, 2.0, 20
+    Us = [-4.0, -3.0]
+    seeds = [71, 72]
+    fs = [si.ising_fields(L, Lt, s) for s in seeds]
+    us = [si.metropolis_uniforms(L, Lt, s)[0] for s in seeds]
+    say("batch slice calls")
+    b = kdqmc.Chain(_params(L, Us[0], beta, delay_k=4), n_chains=2, U=Us)
+    b.set_fields(dev(np.stack(fs)))
+    U = dev(np.stack(us))
+    e = t.zeros((2, 1), dtype=t.float64, device="cuda:0")
+    for l in range(1, Lt + 1):
+        b.sweep_slice(l, U[:, l - 1].contiguous())
+        if l % 10 == 0:
+            b.stabilize(e)
+    G = b.G().cpu().numpy()
+    for z in range(2):
+        g1, _, _, e1 = _run_single(L, Us[z], beta, fs[z], us[z], "fp64")
+        assert np.abs(G[z] - g1).max() < TOL64
+        assert abs(float(e.cpu()[z, 0]) - e1[-1]) < 1e-12
+    # set_G takes one N x N record per chain
+    Gin = np.stack([np.eye(27), 2.0 * np.eye(27)])
+    b.set_G(dev(Gin), 0)
+    assert np.array_equal(b.G().cpu().numpy(), Gin)
+    b.close()
+
+
+def test_uneven_batch_groups(gpu_lib):
+    """Chains of different L and beta: grouped by shape, run on several streams,
+    each chain equal to the same chain alone."""
+    from paper_2608_03894_amd import kdqmc
+    specs = [(3, -4.0, 2.0, 81), (6, -3.0, 2.0, 82), (3, -5.0, 3.0, 83), (6, -5.0, 2.0, 84),
+             (3, -3.0, 2.0, 85)]
+    params = [_params(L, U, beta, delay_k=8) for (L, U, beta, _) in specs]
+    fs = [si.ising_fields(L, int(round(beta * 10)), s) for (L, U, beta, s) in specs]
+    us = [si.metropolis_uniforms(L, int(round(beta * 10)), s, n_sweeps=2) for (L, U, beta, s) in specs]
+    say("uneven batch", len(specs))
+    b = kdqmc.Batch(params)
+    assert len(b.groups) == 3
+    b.set_inputs([dev(f) for f in fs], [dev(u) for u in us])
+    b.sweep(0)
+    b.sweep(1)
+    torch().cuda.synchronize()
+    for g in b.groups:
+        G = g["chain"].G().cpu().numpy()
+        if G.ndim == 2:
+            G = G[None]
+        for k, i in enumerate(g["idx"]):
+            L, U, beta, s = specs[i]
+            from paper_2608_03894_amd import kdqmc as kd
+            ch = kd.Chain(_params(L, U, beta, delay_k=8))
+            ch.set_fields(dev(fs[i]))
+            ch.sweep(dev(us[i][0]))
+            ch.sweep(dev(us[i][1]))
+            assert np.array_equal(G[k], ch.G().cpu().numpy()), (i, specs[i])
+            ch.close()
+    b.close()
