@@ -89,3 +89,27 @@ def autotune(L, U, beta, dtau=0.1, prec="fp64", n_stab=10, seed=0, sweeps=2, dev
             json.dump(table, fh, indent=1, sort_keys=True)
         os.replace(tmp, cache)
     return best
+
+
+def main(argv=None):
+    """python -m paper_2608_03894_amd.autotune --L 12 --U -4 --beta 8 [--prec fp64]"""
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--L", type=int, required=True)
+    ap.add_argument("--U", type=float, required=True)
+    ap.add_argument("--beta", type=float, required=True)
+    ap.add_argument("--dtau", type=float, default=0.1)
+    ap.add_argument("--prec", default="fp64")
+    ap.add_argument("--n-stab", type=int, default=10)
+    ap.add_argument("--sweeps", type=int, default=2)
+    ap.add_argument("--refresh", action="store_true")
+    ap.add_argument("--cache", default=DEFAULT_CACHE)
+    a = ap.parse_args(argv)
+    best = autotune(a.L, a.U, a.beta, a.dtau, a.prec, a.n_stab, sweeps=a.sweeps, cache=a.cache,
+                    refresh=a.refresh, log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(best))
+
+
+if __name__ == "__main__":
+    main()
