@@ -447,11 +447,13 @@ static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev, size_t zn) {
   return KDQMC_OK;
 }
 
-static int sweep_eager(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev,
+// Slices lo..hi of a sweep (caller records L_tau * N apart per chain), then
+// the stabilization that is due at hi, if any.
+static int sweep_range(kdqmc_ctx* c, int lo, int hi, const double* u_dev, const uint8_t* forced_dev,
                        uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev) {
   const size_t N = c->N;
   const size_t zn = (size_t)c->Ltau * N;  // per-chain records of the sweep's caller arrays
-  for (int l = 1; l <= c->Ltau; ++l) {
+  for (int l = lo; l <= hi; ++l) {
     const size_t o = (size_t)(l - 1) * N;
     KDQMC_TRY(sweep_slice_impl(c, l, u_dev ? u_dev + o : nullptr, forced_dev ? forced_dev + o : nullptr,
                                accepted_dev ? accepted_dev + o : nullptr, ratio_dev ? ratio_dev + o : nullptr,
@@ -461,6 +463,22 @@ static int sweep_eager(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_
                                 (size_t)c->nc));
   }
   return KDQMC_OK;
+}
+
+static int sweep_eager(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev,
+                       uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev) {
+  return sweep_range(c, 1, c->Ltau, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
+}
+
+static void drop_graphs(kdqmc_ctx* c) {
+  for (hipGraphExec_t e : c->sweep_exec) (void)hipGraphExecDestroy(e);
+  c->sweep_exec.clear();
+}
+
+// Slices per captured graph: never across a stabilization, and at most
+// about 4096 decision windows, so that no graph grows beyond some 15k nodes.
+static int graph_segment_slices(const kdqmc_ctx* c) {
+  return std::max(1, std::min(c->p.n_stab, 4096 / std::max(1, c->nw)));
 }
 
 int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, uint8_t* accepted_dev,
@@ -473,41 +491,50 @@ int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, ui
   if (!c->use_graphs || c->prof_on)
     return sweep_eager(c, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
   const void* key[6] = {u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev, nullptr};
-  bool same = c->sweep_exec != nullptr;
+  bool same = !c->sweep_exec.empty();
   for (int i = 0; i < 6 && same; ++i) same = (key[i] == c->sweep_key[i]);
   if (!same) {
-    if (c->sweep_exec) {
-      (void)hipGraphExecDestroy(c->sweep_exec);
-      c->sweep_exec = nullptr;
-    }
+    drop_graphs(c);
     if (!c->cap_stream) KDQMC_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     c->graph_next = 0;
     c->graph_triples.clear();
+    const int seg = graph_segment_slices(c);
     hipStream_t user = c->stream;
-    KDQMC_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    c->stream = c->cap_stream;
-    c->capturing = true;
-    const int rc = sweep_eager(c, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
-    c->capturing = false;
-    c->stream = user;
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
-    if (rc != KDQMC_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      c->l_cur = 0;
-      c->stab_next = 1;
-      return rc;
-    }
-    if (ec != hipSuccess) return set_error(KDQMC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
-    const hipError_t ei = hipGraphInstantiate(&c->sweep_exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ei != hipSuccess) {
-      c->sweep_exec = nullptr;
-      return set_error(KDQMC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    for (int lo = 1; lo <= c->Ltau;) {
+      // a segment ends at the next stabilization point at the latest
+      const int next_stab = ((lo - 1) / c->p.n_stab + 1) * c->p.n_stab;
+      const int hi = std::min(next_stab, lo + seg - 1);
+      KDQMC_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      c->stream = c->cap_stream;
+      c->capturing = true;
+      const int rc = sweep_range(c, lo, hi, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
+      c->capturing = false;
+      c->stream = user;
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+      if (rc != KDQMC_OK || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        drop_graphs(c);
+        c->l_cur = 0;
+        c->stab_next = 1;
+        if (rc != KDQMC_OK) return rc;
+        return set_error(KDQMC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+      }
+      hipGraphExec_t ex = nullptr;
+      const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        drop_graphs(c);
+        c->l_cur = 0;
+        c->stab_next = 1;
+        return set_error(KDQMC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+      }
+      c->sweep_exec.push_back(ex);
+      lo = hi + 1;
     }
     for (int i = 0; i < 6; ++i) c->sweep_key[i] = key[i];
   }
-  KDQMC_HIP(hipGraphLaunch(c->sweep_exec, c->stream));
+  for (hipGraphExec_t ex : c->sweep_exec) KDQMC_HIP(hipGraphLaunch(ex, c->stream));
   c->l_cur = 0;  // a whole sweep ends at slice 0 (stabilized G(L_tau) = G(0))
   return KDQMC_OK;
 }
@@ -515,10 +542,7 @@ int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, ui
 int kdqmc_use_graphs(kdqmc_ctx* c, int on) {
   KDQMC_TRY(check_ctx(c));
   c->use_graphs = (on != 0);
-  if (!c->use_graphs && c->sweep_exec) {
-    (void)hipGraphExecDestroy(c->sweep_exec);
-    c->sweep_exec = nullptr;
-  }
+  if (!c->use_graphs) drop_graphs(c);
   return KDQMC_OK;
 }
 
@@ -547,7 +571,7 @@ int kdqmc_sync(kdqmc_ctx* c) {
 
 void kdqmc_destroy(kdqmc_ctx* c) {
   if (!c) return;
-  if (c->sweep_exec) (void)hipGraphExecDestroy(c->sweep_exec);
+  drop_graphs(c);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->graph_events) (void)hipEventDestroy(e);

@@ -149,7 +149,7 @@ struct kdqmc_ctx {
   bool use_graphs = true;
   bool capturing = false;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t sweep_exec = nullptr;
+  std::vector<hipGraphExec_t> sweep_exec;  // one graph per segment of the sweep
   const void* sweep_key[6] = {nullptr};
   std::vector<hipEvent_t> graph_events;   // events that are nodes of the captured graph
   int graph_next = 0;

@@ -330,12 +330,14 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
   if (tid < nbp) tau_out[j + tid] = taus[tid];
 }
 
-// C[j:n, s0:s0+32] -= V op(T) (V^T C[j:n, s0:s0+32]) for the panel at column
+// C[j:n, s0:s0+SW] -= V op(T) (V^T C[j:n, s0:s0+SW]) for the panel at column
 // j (width nbp <= 32): op(T) = T^T applies H^T = H_{nbp-1} ... H_0 (the
 // factorization / Q^T direction), op(T) = T applies H = H_0 ... H_{nbp-1}.
-// One workgroup (8 waves) per 32-column stripe.  W = V^T C: the waves split
-// the rows and their partial 32 x 32 products are summed in LDS; then
-// C -= V W2 with the waves splitting the rows.
+// One workgroup (8 waves) per SW-column stripe (SW = 16 or 32; narrow stripes
+// give more workgroups for the few-hundred-column matrices here).
+// W = V^T C: the waves split the rows and their partial 32 x SW products are
+// summed in LDS; then C -= V W2 with the waves splitting the rows.
+template <int SW>
 __global__ void __launch_bounds__(512)
 k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
            const double* __restrict__ V, int ldv, const double* __restrict__ T, int trans,
@@ -344,49 +346,53 @@ k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
   V = zw(V, zs);
   T = zw(T, zs);
   constexpr int NW = 8;
-  __shared__ double Wp[NW][32][33];
-  __shared__ double W2[32][33];
+  constexpr int BJ = SW / 16;
+  __shared__ double Wp[NW][32][SW + 1];
+  __shared__ double W2[32][SW + 1];
   __shared__ double Tl[32][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int s0 = blockIdx.x * 32;
+  const int s0 = blockIdx.x * SW;
   const int m = n - j;
   for (int idx = tid; idx < 32 * 32; idx += 512) {
     const int r = idx >> 5, cc = idx & 31;
     Tl[r][cc] = (r < nbp && cc < nbp) ? T[r * kNBmax + cc] : 0.0;
   }
-  // W = V^T C (32 x 32), rows split over waves in chunks of 4
-  v4d acc[2][2];
+  // W = V^T C (32 x SW), rows split over waves in chunks of 4
+  v4d acc[2][BJ];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
   for (int kb = wave * 4; kb < m; kb += 4 * NW) {
     const int r = j + kb + lk;
-    double av[2], bv[2];
+    double av[2], bv[BJ];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
       const int vc = bi * 16 + lr;
       av[bi] = (r < n && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
-      const int cc = s0 + bi * 16 + lr;
-      bv[bi] = (r < n && cc < ncols) ? C[(size_t)r * ldc + cc] : 0.0;
+    }
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) {
+      const int cc = s0 + bj * 16 + lr;
+      bv[bj] = (r < n && cc < ncols) ? C[(size_t)r * ldc + cc] : 0.0;
     }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
+      for (int bj = 0; bj < BJ; ++bj)
         acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
       for (int e = 0; e < 4; ++e) Wp[wave][bi * 16 + lk + 4 * e][bj * 16 + lr] = acc[bi][bj][e];
   __syncthreads();
-  for (int idx = tid; idx < 32 * 32; idx += 512) {
-    const int r = idx >> 5, cc = idx & 31;
+  for (int idx = tid; idx < 32 * SW; idx += 512) {
+    const int r = idx / SW, cc = idx % SW;
     double sacc = 0.0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) sacc += Wp[w][r][cc];
@@ -394,8 +400,8 @@ k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
   }
   __syncthreads();
   // W2 = op(T) W
-  for (int idx = tid; idx < 32 * 32; idx += 512) {
-    const int r = idx >> 5, cc = idx & 31;
+  for (int idx = tid; idx < 32 * SW; idx += 512) {
+    const int r = idx / SW, cc = idx % SW;
     double sacc = 0.0;
     for (int t = 0; t < 32; ++t) sacc += (trans ? Tl[t][r] : Tl[r][t]) * Wp[0][t][cc];
     W2[r][cc] = sacc;
@@ -404,19 +410,19 @@ k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
   // C -= V W2, 16-row blocks split over waves
 #pragma unroll 2
   for (int rb = wave * 16; rb < m; rb += 16 * NW) {
-    v4d d[2];
+    v4d d[BJ];
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) d[bj] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int bj = 0; bj < BJ; ++bj) d[bj] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int kk = 0; kk < 32; kk += 4) {
       const int r = j + rb + lr, vc = kk + lk;
       const double av = (r < n && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
+      for (int bj = 0; bj < BJ; ++bj)
         d[bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W2[kk + lk][bj * 16 + lr], d[bj], 0, 0, 0);
     }
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = j + rb + lk + 4 * e, cc = s0 + bj * 16 + lr;
@@ -465,9 +471,10 @@ int launch_apply(kdqmc_ctx* c, double* C, int ld, int n, int j, int nbp, int col
                  const double* Tp, bool trans) {
   if (ncols <= col0) return KDQMC_OK;
   const int e0 = prof_mark(c);
-  const int stripes = (ncols - col0 + 31) / 32;
   // the kernel indexes columns from C's base: shift the base to col0
-  hipLaunchKernelGGL(k_apply_wy, dim3(stripes, 1, c->nch), dim3(512), 0, c->stream, C + col0, ld, n, j,
+  constexpr int SW = 16;
+  const int stripes = (ncols - col0 + SW - 1) / SW;
+  hipLaunchKernelGGL(k_apply_wy<SW>, dim3(stripes, 1, c->nch), dim3(512), 0, c->stream, C + col0, ld, n, j,
                      nbp, ncols - col0, c->Vq, ld, Tp, trans ? 1 : 0, c->zs);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   return KDQMC_OK;

@@ -71,19 +71,25 @@ __global__ void __launch_bounds__(256) k_colnorm2(const double* __restrict__ C, 
   if (wave == 0 && c < n) nrm[c] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
 }
 
-// perm[rank] = column, descending norm, ties by column index (stable); n <= 2048
-__global__ void k_rank_perm(const double* __restrict__ nrm, int n, int* __restrict__ perm, size_t zs) {
+// perm[rank] = column, descending norm, ties by column index (stable); n <= 2048.
+// Each workgroup ranks 256 columns against all n norms staged in LDS (every
+// lane reads the same LDS word at a time: broadcast).
+__global__ void __launch_bounds__(256) k_rank_perm(const double* __restrict__ nrm, int n, int* __restrict__ perm,
+                                                   size_t zs) {
+  __shared__ double sn[2048];
   nrm = zw(nrm, zs);
   perm = zw(perm, zs);
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    const double v = nrm[c];
-    int rank = 0;
-    for (int q = 0; q < n; ++q) {
-      const double w = nrm[q];
-      rank += (w > v) || (w == v && q < c);
-    }
-    perm[rank] = c;
+  for (int q = threadIdx.x; q < n; q += 256) sn[q] = nrm[q];
+  __syncthreads();
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= n) return;
+  const double v = sn[c];
+  int rank = 0;
+  for (int q = 0; q < n; ++q) {
+    const double w = sn[q];
+    rank += (w > v) || (w == v && q < c);
   }
+  perm[rank] = c;
 }
 
 __global__ void k_gather_cols(double* __restrict__ dst, const double* __restrict__ src, int n,
@@ -261,7 +267,8 @@ int udt_step(kdqmc_ctx* c, const double* Uin, const double* Din, const double* T
   }
   hipLaunchKernelGGL(k_scale_cols, grid_for(c, nn), dim3(256), 0, c->stream, C, n, Din, zs);
   hipLaunchKernelGGL(k_colnorm2, dim3((n + 63) / 64, 1, c->nch), dim3(256), 0, c->stream, C, n, c->nrm, zs);
-  hipLaunchKernelGGL(k_rank_perm, dim3(1, 1, c->nch), dim3(1024), 0, c->stream, c->nrm, n, c->perm, zs);
+  hipLaunchKernelGGL(k_rank_perm, dim3((n + 255) / 256, 1, c->nch), dim3(256), 0, c->stream, c->nrm, n, c->perm,
+                     zs);
   hipLaunchKernelGGL(k_gather_cols, grid_for(c, nn), dim3(256), 0, c->stream, Cp, C, n, c->perm, zs);
   KDQMC_TRY(qr_f64(c, n, Cp, Uout));
   hipLaunchKernelGGL(k_diag_abs, grid_for(c, n), dim3(256), 0, c->stream, Cp, n, Dout, zs);

@@ -184,25 +184,28 @@ def test_fp64_deterministic(gpu_lib):
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed_f16"])
-def test_graph_replay_matches_eager(gpu_lib, prec):
-    """Two sweeps replayed from the captured HIP graph give bitwise the same
-    G, decisions, ratios and wrap errors as two sweeps of direct launches."""
-    say("graph vs eager", prec)
+@pytest.mark.parametrize("prec,L,k,window", [("fp64", 6, 16, 0), ("mixed_f16", 6, 16, 0),
+                                              ("fp64", 12, 1, 1)])
+def test_graph_replay_matches_eager(gpu_lib, prec, L, k, window):
+    """Two sweeps replayed from the captured HIP graphs give bitwise the same
+    G, decisions, ratios and wrap errors as two sweeps of direct launches.
+    With one-site windows at L = 12 (432 windows per slice) a stabilization
+    interval is captured as two graphs (9 + 1 slices)."""
+    say("graph vs eager", prec, L, k, window)
     t = torch()
-    w = si.C2
-    f = si.ising_fields(6, 20, 6)
-    u = dev(si.metropolis_uniforms(6, 20, 6, n_sweeps=2))
+    N = 3 * L * L
+    f = si.ising_fields(L, 20, 6)
+    u = dev(si.metropolis_uniforms(L, 20, 6, n_sweeps=2))
     outs = []
     for graphs in (False, True):
-        ch = chain(6, -4.0, 2.0, delay_k=16, prec=prec)
+        ch = chain(L, -4.0, 2.0, delay_k=k, window=window, prec=prec)
         ch.use_graphs(graphs)
         ch.set_fields(dev(f))
         res = []
         # fixed buffers: the second sweep replays the graph captured by the first
-        ub = t.zeros((20, 108), dtype=t.float64, device="cuda:0")
-        acc = t.zeros((20, 108), dtype=t.uint8, device="cuda:0")
-        rat = t.zeros((20, 108), dtype=t.float64, device="cuda:0")
+        ub = t.zeros((20, N), dtype=t.float64, device="cuda:0")
+        acc = t.zeros((20, N), dtype=t.uint8, device="cuda:0")
+        rat = t.zeros((20, N), dtype=t.float64, device="cuda:0")
         err = t.zeros(2, dtype=t.float64, device="cuda:0")
         for s in range(2):
             ub.copy_(u[s])
