@@ -30,6 +30,21 @@ FP64_PEAK_TFS = 78.6           # MI355X FP64 (vector and matrix)
 F16_PEAK_TFS = 2500.0          # MI355X dense FP16/BF16 MFMA
 
 CONFIGS = {"c1": si.C1, "c2": si.C2, "c3": si.C3, "c5": si.C5, "c4": None}
+AUTOTUNED = ("c4", "c5")   # workloads whose delay rank and FFT tile come from the autotuner
+
+
+def schedule(args, w, prec, n_stab, autotuned):
+    """(delay_k, window, fft_tile, from_autotuner): command-line values win;
+    for autotuned workloads the cached autotuner choice (same lattice, beta,
+    precision and interval) is used when present, else the workload default."""
+    t = None
+    if autotuned and not args.delay_k:
+        from paper_2608_03894_amd import autotune
+        t = autotune.lookup(w.L, w.U, w.beta, w.dtau, prec, n_stab, any_U=True)
+    k = args.delay_k or (t["delay_k"] if t else w.delay_k)
+    window = args.window or (t["window"] if t else 0)
+    tile = args.fft_tile or (t["fft_tile"] if t else 0)
+    return k, window, tile, t is not None
 
 
 def log(*a):
@@ -199,10 +214,13 @@ def bench_batch(args):
     dev = torch.device("cuda:0")
     params, fields, unis = [], [], []
     total = args.warmup + args.steps
+    n_tuned = 0
     for w in chains:
-        k = args.delay_k or w.delay_k
-        params.append(kdqmc.make_params(w.L, w.U, w.beta, w.dtau, mu=-1.0, n_stab=args.n_stab or w.n_stab,
-                                        delay_k=k, window=args.window, fft_tile=args.fft_tile, prec=prec))
+        n_stab = args.n_stab or w.n_stab
+        k, window, tile, tuned = schedule(args, w, prec, n_stab, True)
+        n_tuned += tuned
+        params.append(kdqmc.make_params(w.L, w.U, w.beta, w.dtau, mu=-1.0, n_stab=n_stab,
+                                        delay_k=k, window=window, fft_tile=tile, prec=prec))
         Lt = si.l_tau(w.beta, w.dtau)
         fields.append(torch.from_numpy(si.ising_fields(w.L, Lt, w.seed)).to(dev))
         unis.append(torch.from_numpy(si.metropolis_uniforms(w.L, Lt, w.seed, n_sweeps=total)).to(dev))
@@ -221,7 +239,8 @@ def bench_batch(args):
     value = b.n_chains * args.steps / elapsed
     upd = b.field_updates_per_sweep()
     log(f"timed {args.steps} batch sweeps in {elapsed:.3f} s -> {value:.2f} chain-sweeps/s")
-    groups = [{"L": g["chain"].p.L, "beta": g["chain"].p.beta, "chains": len(g["idx"])} for g in b.groups]
+    groups = [{"L": g["chain"].p.L, "beta": g["chain"].p.beta, "chains": len(g["idx"]),
+               "delay_k": g["chain"].p.delay_k, "window": g["chain"].p.window} for g in b.groups]
     out = {
         "metric": "HS-field sweeps/sec (batched, aggregate over chains)",
         "value": value,
@@ -236,7 +255,8 @@ def bench_batch(args):
         "dtype": "f64" if prec == "fp64" else f"f32+{prec.split('_')[1]}",
         "data": "synthetic",
         "config": {"workload": "kagome-batch-64-chains-L6-15-U3-5-beta4-8", "chains": b.n_chains,
-                   "groups": groups, "prec": prec, "field_updates_per_s": upd * args.steps / elapsed},
+                   "groups": groups, "prec": prec, "autotuned_chains": n_tuned,
+                   "field_updates_per_s": upd * args.steps / elapsed},
         "roofline": None,
         "cpu_baseline": None,
         "acceptance": b.accepted() / upd,
@@ -244,6 +264,65 @@ def bench_batch(args):
     }
     b.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_wrap(args):
+    """The FFT wrap alone (both passes of kdqmc_wrap_slice) on a resident G, at
+    L = 12, 18, 24 in FP64 and FP32: GB/s = 2 N^2 s bytes per pass / average
+    pass time (HIP events).  'resident' is one chain (its G stays in the
+    256 MB Infinity Cache between passes); 'batch' runs enough chains in one
+    batched context that their G matrices exceed 256 MB, so every pass
+    streams from HBM."""
+    import torch
+    from paper_2608_03894_amd import kdqmc
+    dev = torch.device("cuda:0")
+    res = []
+    beta, dtau = 10.0, 0.1
+    Lt = si.l_tau(beta, dtau)
+    for L in (int(x) for x in args.wrap_L.split(",")):
+        for prec in ("fp64", "mixed_f16"):
+            N = 3 * L * L
+            es = 8 if prec == "fp64" else 4
+            for mode in ("resident", "batch"):
+                nch = 1 if mode == "resident" else max(2, int(np.ceil(320e6 / (N * N * es))))
+                p = kdqmc.make_params(L, -4.0, beta, dtau, mu=-1.0, n_stab=Lt, delay_k=32,
+                                      fft_tile=args.fft_tile, prec=prec)
+                try:
+                    ch = kdqmc.Chain(p, device=dev, n_chains=nch)
+                except kdqmc.KdqmcError as e:
+                    log(f"wrap L={L} {prec} {mode}: {e}")
+                    continue
+                g = torch.eye(N, dtype=torch.float64, device=dev).expand(nch, N, N).contiguous()
+                g += 1e-3 * torch.rand(nch, N, N, dtype=torch.float64, device=dev)
+                ch.set_fields(torch.ones((nch, Lt, N), dtype=torch.int8, device=dev))
+                ch.set_G(g, 0)
+                for l in range(1, 4):
+                    ch.wrap_slice(l)
+                ch.profile_enable(True)
+                ch.set_G(g, 0)
+                prof = None
+                reps = max(4, min(Lt - 1, args.wrap_reps))
+                for l in range(1, reps + 1):
+                    ch.wrap_slice(l)
+                ch.sync()
+                prof = ch.profile_read()
+                ch.profile_enable(False)
+                byt = 2.0 * N * N * es * nch
+                row = {"L": L, "N": N, "prec": prec, "mode": mode, "chains": nch}
+                for ph in ("wrap_cols", "wrap_rows"):
+                    ms, n = prof[ph]
+                    t = ms / n / 1000.0
+                    row[ph + "_us"] = round(1e6 * t, 2)
+                    row[ph + "_GBs"] = round(byt / t / 1e9, 1)
+                    row[ph + "_frac"] = round(byt / t / 1e9 / HBM_PEAK_GBS, 4)
+                log(json.dumps(row))
+                res.append(row)
+                ch.close()
+                del g
+                torch.cuda.synchronize()
+    print(json.dumps({"metric": "FFT wrap HBM GB/s", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                      "algorithmic": "2 N^2 s bytes per pass per chain (G read once, written once)",
+                      "results": res}), flush=True)
 
 
 def main():
@@ -259,6 +338,10 @@ def main():
     ap.add_argument("--n-stab", type=int, default=None, help="slices between stabilizations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=20)
+    ap.add_argument("--wrap-only", action="store_true",
+                    help="only time the FFT wrap passes at the lattice sizes of --wrap-L and exit")
+    ap.add_argument("--wrap-L", default="12,18,24")
+    ap.add_argument("--wrap-reps", type=int, default=50)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -275,17 +358,20 @@ def main():
     if args.config == "c4":
         bench_batch(args)
         return
+    if args.wrap_only:
+        bench_wrap(args)
+        return
 
     import torch
     from paper_2608_03894_amd import kdqmc
 
     w = CONFIGS[args.config]
     prec = args.prec or ("fp64" if w.prec == "fp64" else w.prec)
-    k = args.delay_k or w.delay_k
     n_stab = args.n_stab or w.n_stab
+    k, window, tile, tuned = schedule(args, w, prec, n_stab, args.config in AUTOTUNED)
     dev = torch.device("cuda:0")
     p = kdqmc.make_params(w.L, w.U, w.beta, w.dtau, mu=-1.0, n_stab=n_stab, delay_k=k,
-                          window=args.window, fft_tile=args.fft_tile, prec=prec)
+                          window=window, fft_tile=tile, prec=prec)
     ch = kdqmc.Chain(p, device=dev)
     N, Lt = ch.N, ch.L_tau
     total = args.warmup + args.steps
@@ -337,7 +423,7 @@ def main():
     flushes = max(1, prof["flush"][1] // args.steps)
     k_avg = accepts / flushes
     kernels = kernel_rooflines(prof, N, Lt, prec, k_avg, n_stab)
-    win = min(args.window or min(k, 64), N)   # the library's default window: min(delay_k, 64)
+    win = min(window or min(k, 64), N)   # the library's default window: min(delay_k, 64)
     decide_roofline(kernels, prof, accepts, args.steps, win)
     cand = {n: v for n, v in prof.items() if n != "stabilize" and v[1] > 0}
     dom = max(cand, key=lambda n: cand[n][0])
@@ -365,7 +451,8 @@ def main():
         "dtype": "f64" if prec == "fp64" else f"f32+{prec.split('_')[1]}",
         "data": "synthetic",
         "config": {"workload": w.name, "L": w.L, "N": N, "U": w.U, "beta": w.beta, "L_tau": Lt,
-                   "delay_k": k, "window": win, "prec": prec, "n_stab": n_stab,
+                   "delay_k": k, "window": win, "fft_tile": tile, "autotuned": tuned,
+                   "prec": prec, "n_stab": n_stab,
                    "field_updates_per_s": value * N * Lt},
         "roofline": roof,
         "kernels": kernels,

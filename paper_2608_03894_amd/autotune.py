@@ -27,6 +27,26 @@ def _key(L, U, beta, dtau, prec, n_stab):
     return f"L{L}_U{U:g}_b{beta:g}_d{dtau:g}_{prec}_s{n_stab}"
 
 
+def lookup(L, U, beta, dtau=0.1, prec="fp64", n_stab=10, cache=DEFAULT_CACHE, any_U=False):
+    """The cached choice for a workload, or None.  With any_U, an entry for the
+    same lattice, beta, precision and interval but another U also serves (the
+    schedule depends on N and L_tau, not on the coupling)."""
+    if not (cache and os.path.exists(cache)):
+        return None
+    with open(cache) as fh:
+        table = json.load(fh)
+    key = _key(L, U, beta, dtau, prec, n_stab)
+    if key in table:
+        return table[key]
+    if any_U:
+        tail = _key(L, 0.0, beta, dtau, prec, n_stab).split("_U0_")[1]
+        head = f"L{L}_U"
+        for k, v in sorted(table.items()):
+            if k.startswith(head) and k.endswith("_" + tail):
+                return v
+    return None
+
+
 def _time_sweeps(params, fields, uni, sweeps, device):
     import torch
     ch = kdqmc.Chain(params, device=device)
