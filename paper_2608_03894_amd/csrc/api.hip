@@ -19,17 +19,19 @@ struct Derived {
 };
 
 // Complex vectors per wrap workgroup: at least one workgroup per compute
-// unit (256) where the matrix allows, within 64 KB of LDS and 512 threads.
-int auto_tile(int L, size_t elem, int requested) {
+// unit (256) over all chains of the context where the matrices allow, at most
+// 4 (wider tiles coalesce the column pass but leave fewer workgroups), within
+// 64 KB of LDS and 512 threads.
+int auto_tile(int L, size_t elem, int requested, int nch) {
   if (requested > 0) return requested;
   const int N = 3 * L * L;
   const int ncomplex = (N + 1) / 2;
-  int P = std::max(1, ncomplex / 256);
-  while (P > 1 && (2 * (size_t)N * P * elem > 64 * 1024 || 3 * L * P > 512)) --P;
+  int P = std::max(1, std::min(4, (int)((size_t)nch * ncomplex / 256)));
+  while (P > 1 && (2 * (size_t)(N + L) * P * elem > 64 * 1024 || 3 * L * P > 512)) --P;
   return P;
 }
 
-int derive(const kdqmc_params* p, Derived* d) {
+int derive(const kdqmc_params* p, Derived* d, int nch = 1) {
   if (!p) return set_error(KDQMC_EINVAL, "params is NULL");
   if (!lattice_supported(p->L))
     return set_error(KDQMC_EUNSUPPORTED, "L must be one of 3, 6, 9, 12, 15, 18, 24");
@@ -61,9 +63,9 @@ int derive(const kdqmc_params* p, Derived* d) {
   d->kmax = d->F * d->w;
   d->fp64 = (p->prec == KDQMC_FP64);
   const size_t es = d->fp64 ? 8 : 4;
-  d->P = auto_tile(p->L, es, p->fft_tile);
-  d->P64 = d->fp64 ? d->P : auto_tile(p->L, 8, 0);
-  if (2 * (size_t)d->N * d->P * es > 160 * 1024 || 3 * p->L * d->P > 512)
+  d->P = auto_tile(p->L, es, p->fft_tile, nch);
+  d->P64 = d->fp64 ? d->P : auto_tile(p->L, 8, 0, nch);
+  if (2 * (size_t)(d->N + p->L) * d->P * es > 160 * 1024 || 3 * p->L * d->P > 512)
     return set_error(KDQMC_EINVAL, "fft_tile exceeds LDS or thread limits");
   return KDQMC_OK;
 }
@@ -237,7 +239,7 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
   *out = nullptr;
   if (n_chains < 1 || n_chains > 65535) return set_error(KDQMC_EINVAL, "n_chains must be in 1..65535");
   Derived d;
-  KDQMC_TRY(derive(p, &d));
+  KDQMC_TRY(derive(p, &d, n_chains));
   std::vector<double> Uc(n_chains, p->U);
   if (U_host) {
     for (int z = 0; z < n_chains; ++z) {

@@ -5,8 +5,11 @@
 // vector (the operator is real, so the real and imaginary parts do not mix).
 //
 // One workgroup owns P complex vectors (2P real columns or rows), staged in
-// LDS as separate real/imaginary planes [element][vector]; the FFT lines are
-// processed in registers, one line per thread.
+// LDS as separate real/imaginary planes [slot][vector]; the FFT lines are
+// processed in registers, one line per thread.  Element e = (x1 L + x2) 3 + s
+// sits in slot e + x1: every x1 row of 3L elements is padded by one slot, so
+// that the lanes of an x2-direction stage (one x1 row each, 3L + 1 slots
+// apart) spread over the LDS banks instead of sharing one.
 #include "common.h"
 
 namespace kdqmc {
@@ -142,9 +145,16 @@ struct FFT {
   }
 };
 
+// LDS slot of element e (row x1 = e / 3L padded by one slot).
+template <int L>
+__device__ __forceinline__ int slot_of(int e) {
+  return e + e / (3 * L);
+}
+
 // One FFT stage over all lines of the tile: line (a, s, c) for a in [0, L),
-// s in [0, 3), c in [0, P): elements e = base(a, s) + m * stride, m in [0, L).
-// AXIS == 2: lines along x2 (a = x1, stride 3); AXIS == 1: along x1 (a = x2, stride 3L).
+// s in [0, 3), c in [0, P): slots base(a, s) + m * stride, m in [0, L).
+// AXIS == 2: lines along x2 (a = x1, stride 3); AXIS == 1: along x1 (a = x2,
+// stride 3L + 1, the padded row).
 template <typename T, int L, int AXIS, int SIGN>
 __device__ __forceinline__ void fft_stage(T* sre, T* sim, int P) {
   const int nlines = 3 * L * P;
@@ -153,8 +163,8 @@ __device__ __forceinline__ void fft_stage(T* sre, T* sim, int P) {
     const int q = idx / P;  // q = a*3 + s
     const int s = q % 3;
     const int a = q / 3;
-    const int base = (AXIS == 2) ? (a * L * 3 + s) : (a * 3 + s);
-    constexpr int stride = (AXIS == 2) ? 3 : 3 * L;
+    const int base = (AXIS == 2) ? (a * (3 * L + 1) + s) : (a * 3 + s);
+    constexpr int stride = (AXIS == 2) ? 3 : 3 * L + 1;
     T re[L], im[L];
 #pragma unroll
     for (int m = 0; m < L; ++m) {
@@ -178,11 +188,12 @@ __device__ __forceinline__ void mix_stage(T* sre, T* sim, int P, const T* __rest
     const int c = idx % P;
     const int k = idx / P;
     const T* tk = tab + 18 * k;
+    const int b = (k / L) * (3 * L + 1) + 3 * (k % L);  // slot of (k, s = 0)
     T xr[3], xi[3];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-      xr[s] = sre[(3 * k + s) * P + c];
-      xi[s] = sim[(3 * k + s) * P + c];
+      xr[s] = sre[(b + s) * P + c];
+      xi[s] = sim[(b + s) * P + c];
     }
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
@@ -193,8 +204,8 @@ __device__ __forceinline__ void mix_stage(T* sre, T* sim, int P, const T* __rest
         yr += ar * xr[t] - ai * xi[t];
         yi += ar * xi[t] + ai * xr[t];
       }
-      sre[(3 * k + s) * P + c] = yr;
-      sim[(3 * k + s) * P + c] = yi;
+      sre[(b + s) * P + c] = yr;
+      sim[(b + s) * P + c] = yi;
     }
   }
 }
@@ -212,7 +223,8 @@ k_kinetic(T* __restrict__ A, int lda, int P, const T* __restrict__ tab,
   post_e = zw(post_e, zs);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sre = reinterpret_cast<T*>(smem_raw);
-  T* sim = sre + NS * P;
+  constexpr int NSP = NS + L;  // padded slots
+  T* sim = sre + NSP * P;
   const int vbase = 2 * blockIdx.x * P;      // first real vector of this workgroup
   const int nreal = min(2 * P, NS - vbase);  // real vectors present (ragged tail)
 
@@ -225,8 +237,9 @@ k_kinetic(T* __restrict__ A, int lda, int P, const T* __restrict__ tab,
       T x0 = T(0), x1 = T(0);
       if (r0 < nreal) x0 = T(double(A[(size_t)e * lda + vbase + r0]) * se * (pre_v ? pre_v[vbase + r0] : 1.0));
       if (r1 < nreal) x1 = T(double(A[(size_t)e * lda + vbase + r1]) * se * (pre_v ? pre_v[vbase + r1] : 1.0));
-      sre[e * P + c] = x0;
-      sim[e * P + c] = x1;
+      const int se_ = slot_of<L>(e);
+      sre[se_ * P + c] = x0;
+      sim[se_ * P + c] = x1;
     }
   } else {
     for (int idx = threadIdx.x; idx < NS * 2 * P; idx += blockDim.x) {
@@ -238,9 +251,9 @@ k_kinetic(T* __restrict__ A, int lda, int P, const T* __restrict__ tab,
           x = T(double(x) * (pre_e ? pre_e[e] : 1.0) * (pre_v ? pre_v[vbase + r] : 1.0));
       }
       if (r & 1)
-        sim[e * P + (r >> 1)] = x;
+        sim[slot_of<L>(e) * P + (r >> 1)] = x;
       else
-        sre[e * P + (r >> 1)] = x;
+        sre[slot_of<L>(e) * P + (r >> 1)] = x;
     }
   }
   __syncthreads();
@@ -260,14 +273,16 @@ k_kinetic(T* __restrict__ A, int lda, int P, const T* __restrict__ tab,
       const int c = idx % P, e = idx / P;
       const int r0 = 2 * c, r1 = 2 * c + 1;
       const double se = post_e ? post_e[e] : 1.0;
-      if (r0 < nreal) A[(size_t)e * lda + vbase + r0] = T(double(sre[e * P + c]) * se);
-      if (r1 < nreal) A[(size_t)e * lda + vbase + r1] = T(double(sim[e * P + c]) * se);
+      const int so = slot_of<L>(e);
+      if (r0 < nreal) A[(size_t)e * lda + vbase + r0] = T(double(sre[so * P + c]) * se);
+      if (r1 < nreal) A[(size_t)e * lda + vbase + r1] = T(double(sim[so * P + c]) * se);
     }
   } else {
     for (int idx = threadIdx.x; idx < NS * 2 * P; idx += blockDim.x) {
       const int e = idx % NS, r = idx / NS;
       if (r < nreal) {
-        T x = (r & 1) ? sim[e * P + (r >> 1)] : sre[e * P + (r >> 1)];
+        const int so = slot_of<L>(e);
+        T x = (r & 1) ? sim[so * P + (r >> 1)] : sre[so * P + (r >> 1)];
         if (post_e) x = T(double(x) * post_e[e]);
         A[(size_t)(vbase + r) * lda + e] = x;
       }
@@ -283,7 +298,7 @@ int launch_L(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double*
   constexpr int NS = 3 * L * L;
   int P = (sizeof(T) == 8) ? c->P64 : c->P;
   if (P <= 0) P = 1;
-  const size_t lds = size_t(2) * NS * P * sizeof(T);
+  const size_t lds = size_t(2) * (NS + L) * P * sizeof(T);
   if (lds > 160 * 1024)
     return set_error(KDQMC_EINVAL, "fft_tile too large for LDS");
   const int ncomplex = (NS + 1) / 2;
