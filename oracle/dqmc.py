@@ -275,6 +275,51 @@ def sweep(model: Model, fields: np.ndarray, g0: np.ndarray, uniforms=None, force
                 accepted=acc, ratios=ratios, wrap_err=wrap_err)
 
 
+def sweep_down(model: Model, fields: np.ndarray, g_top: np.ndarray, uniforms=None, forced=None,
+               k: int = 1, n_stab: int = 10, record: bool = True, l_stop=None, l_start=None):
+    """One downward pass l = L_tau..1 over the slices, starting from
+    G(L_tau) = G(0).
+
+    Per slice, read off the same relation as the upward pass backwards:
+    G~ = exp(dtau K) G(l) exp(-dtau K) is exp(V_l) G(l-1) exp(-V_l), the matrix
+    on which the flips of slice l act; after the sequential updates (delay k),
+    G(l-1) = exp(-V_l) G~ exp(V_l) with the new fields.  Whenever l-1 is a
+    multiple of n_stab (l-1 = 0 included) G is replaced by the QR-stabilized
+    G(l-1) and max|G - G_fresh| is logged.
+
+    ``l_start`` begins at another slice (then ``g_top`` is G(l_start)) and
+    ``l_stop`` ends the pass after the slice of that index.  Returns the same
+    dict as ``sweep``; ``G_slices`` holds G(l-1) in visiting order (index
+    L_tau - l), and ``G_prestab`` / ``wrap_err`` are keyed by l-1.
+    """
+    fields = fields.copy()
+    L_tau, n = fields.shape
+    acc = np.zeros((L_tau, n), dtype=bool)
+    ratios = np.zeros((L_tau, n))
+    wrap_err = {}
+    g_slices, g_pre = [], {}
+    g = g_top.copy()
+    top = L_tau if l_start is None else l_start
+    for l in range(top, (1 if l_stop is None else l_stop) - 1, -1):
+        s = fields[l - 1]
+        gt = model.EKinv @ g @ model.EK
+        gt, acc[l - 1], ratios[l - 1] = update_slice(
+            gt, s, model.alpha,
+            None if uniforms is None else uniforms[l - 1],
+            None if forced is None else forced[l - 1], k)
+        ev = np.exp(model.alpha * s.astype(float))
+        g = gt / ev[:, None] * ev[None, :]
+        if (l - 1) % n_stab == 0:
+            g_pre[l - 1] = g.copy()
+            gf = green_scratch(model, fields, l - 1)
+            wrap_err[l - 1] = float(np.max(np.abs(g - gf)))
+            g = gf
+        if record:
+            g_slices.append(g.copy())
+    return dict(fields=fields, G=g, G_slices=g_slices, G_prestab=g_pre,
+                accepted=acc, ratios=ratios, wrap_err=wrap_err)
+
+
 def log_weight_det(model: Model, fields: np.ndarray) -> float:
     """log of prod exp(-alpha s) * det(I + B_{L_tau} ... B_1)^2 (sign dropped).
 

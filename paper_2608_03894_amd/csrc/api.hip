@@ -110,7 +110,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   for (int i = 0; i < 8; ++i) S[i] = take(nn * 8);
   char* Vq = take(nn * 8);
   char* Tq = take((N / nb + 2) * 32 * 32 * 8);
-  char* Wq = take(2 * nb * N * 8);
+  char* Wq = take((size_t)16 * 32 * N * 8);  // split WY apply: 16 row chunks of 32 x N partials
   char* tau = take(N * 8);
   char* nrm = take(2 * N * 8);
   char* perm = take(N * 4);

@@ -204,7 +204,7 @@ struct kdqmc_ctx {
   int qr_npan = 0;             // panels of the last QR (start column, width)
   int qr_panel_start[160] = {0};
   int qr_panel_width[160] = {0};
-  double* Wq = nullptr;        // nb*N
+  double* Wq = nullptr;        // 16 * 32 * N: partial V^T C products of the split WY apply
   double* tau = nullptr;       // N
   double* nrm = nullptr;       // N
   int* perm = nullptr;         // N

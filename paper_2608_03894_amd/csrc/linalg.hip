@@ -431,6 +431,135 @@ k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
   }
 }
 
+// Split-K form of the same apply for tall panels (more than 512 rows), so
+// that the whole chip works on it instead of one workgroup per stripe:
+// k_wy_partial: workgroup (stripe, q) sums V^T C over rows
+//   [j + q rc, j + (q+1) rc) into Wpart[q][32][ncols] (4 waves split the rows);
+// k_wy_reduce: workgroup (stripe) adds up the partial products of its columns
+//   and writes W2 = op(T) W over chunk 0's partials;
+// k_wy_update: workgroup (stripe, 64-row tile) subtracts V W2 from its tile.
+constexpr int kWyChunks = 16;
+
+template <int SW>
+__global__ void __launch_bounds__(256)
+k_wy_partial(const double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
+             const double* __restrict__ V, int ldv, int rc, double* __restrict__ Wpart, size_t zs) {
+  C = zw(C, zs);
+  V = zw(V, zs);
+  Wpart = zw(Wpart, zs);
+  constexpr int NW = 4;
+  constexpr int BJ = SW / 16;
+  __shared__ double Wp[NW][32][SW + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int s0 = blockIdx.x * SW, q = blockIdx.y;
+  const int r0 = j + q * rc, r1 = min(n, r0 + rc);
+  v4d acc[2][BJ];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int kb = r0 + wave * 4; kb < r1; kb += 4 * NW) {
+    const int r = kb + lk;
+    double av[2], bv[BJ];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const int vc = bi * 16 + lr;
+      av[bi] = (r < r1 && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
+    }
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj) {
+      const int cc = s0 + bj * 16 + lr;
+      bv[bj] = (r < r1 && cc < ncols) ? C[(size_t)r * ldc + cc] : 0.0;
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj)
+        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Wp[wave][bi * 16 + lk + 4 * e][bj * 16 + lr] = acc[bi][bj][e];
+  __syncthreads();
+  for (int idx = tid; idx < 32 * SW; idx += 256) {
+    const int r = idx / SW, cc = idx % SW;
+    if (s0 + cc < ncols)
+      Wpart[((size_t)q * 32 + r) * ncols + s0 + cc] = Wp[0][r][cc] + Wp[1][r][cc] + Wp[2][r][cc] + Wp[3][r][cc];
+  }
+}
+
+template <int SW>
+__global__ void __launch_bounds__(256)
+k_wy_reduce(int nbp, int ncols, const double* __restrict__ T, int trans, double* __restrict__ Wpart, int nq,
+            size_t zs) {
+  T = zw(T, zs);
+  Wpart = zw(Wpart, zs);
+  __shared__ double Tl[32][33];
+  __shared__ double Ws[32][SW + 1];
+  const int tid = threadIdx.x;
+  const int s0 = blockIdx.x * SW;
+  for (int idx = tid; idx < 32 * 32; idx += 256) {
+    const int r = idx >> 5, cc = idx & 31;
+    Tl[r][cc] = (r < nbp && cc < nbp) ? T[r * kNBmax + cc] : 0.0;
+  }
+  for (int idx = tid; idx < 32 * SW; idx += 256) {
+    const int r = idx / SW, cc = idx % SW;
+    double sacc = 0.0;
+    if (s0 + cc < ncols)
+      for (int q = 0; q < nq; ++q) sacc += Wpart[((size_t)q * 32 + r) * ncols + s0 + cc];
+    Ws[r][cc] = sacc;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < 32 * SW; idx += 256) {
+    const int r = idx / SW, cc = idx % SW;
+    double sacc = 0.0;
+    for (int t = 0; t < 32; ++t) sacc += (trans ? Tl[t][r] : Tl[r][t]) * Ws[t][cc];
+    if (s0 + cc < ncols) Wpart[(size_t)r * ncols + s0 + cc] = sacc;
+  }
+}
+
+template <int SW>
+__global__ void __launch_bounds__(256)
+k_wy_update(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
+            const double* __restrict__ V, int ldv, const double* __restrict__ W2g, size_t zs) {
+  C = zw(C, zs);
+  V = zw(V, zs);
+  W2g = zw(W2g, zs);
+  constexpr int BJ = SW / 16;
+  __shared__ double W2[32][SW + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int s0 = blockIdx.x * SW;
+  for (int idx = tid; idx < 32 * SW; idx += 256) {
+    const int r = idx / SW, cc = idx % SW;
+    W2[r][cc] = (s0 + cc < ncols) ? W2g[(size_t)r * ncols + s0 + cc] : 0.0;
+  }
+  __syncthreads();
+  const int rb = j + blockIdx.y * 64 + wave * 16;
+  v4d d[BJ];
+#pragma unroll
+  for (int bj = 0; bj < BJ; ++bj) d[bj] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < 32; kk += 4) {
+    const int r = rb + lr, vc = kk + lk;
+    const double av = (r < n && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
+#pragma unroll
+    for (int bj = 0; bj < BJ; ++bj)
+      d[bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W2[kk + lk][bj * 16 + lr], d[bj], 0, 0, 0);
+  }
+#pragma unroll
+  for (int bj = 0; bj < BJ; ++bj)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = rb + lk + 4 * e, cc = s0 + bj * 16 + lr;
+      if (r < n && cc < ncols) C[(size_t)r * ldc + cc] -= d[bj][e];
+    }
+}
+
 __global__ void k_set_identity(double* __restrict__ Q, int n, int ld, size_t zs) {
   Q = zw(Q, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -448,21 +577,22 @@ __global__ void k_zero(double* __restrict__ X, size_t count, size_t zs) {
 
 namespace {
 
+// Panel width: 32 columns while the panel has at most 1024 rows, else 16
+// (two rows per thread in registers; measured against 16-column panels and
+// four rows per thread: within 1 % at N = 432, 972 and 1728, this choice best).
 inline int panel_width(int rows) { return rows > 1024 ? 16 : 32; }
 
 int launch_panel(kdqmc_ctx* c, double* A, int ld, int n, int j, int nbp, double* Tp) {
   const int m = n - j;
   const int e0 = prof_mark(c);
-  // rows per thread: 2; the panel's rows fit in RPT * NT
-  if (m <= 512)
-    hipLaunchKernelGGL((k_qr_panel<2, 32, 256>), dim3(1, 1, c->nch), dim3(256), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp,
-                       c->tau, c->zs);
-  else if (m <= 1024)
-    hipLaunchKernelGGL((k_qr_panel<2, 32, 512>), dim3(1, 1, c->nch), dim3(512), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp,
-                       c->tau, c->zs);
-  else
-    hipLaunchKernelGGL((k_qr_panel<2, 16, 1024>), dim3(1, 1, c->nch), dim3(1024), 0, c->stream, A, ld, n, j, nbp, c->Vq, Tp,
-                       c->tau, c->zs);
+#define PANEL(RPT, NB, NT)                                                                          \
+  hipLaunchKernelGGL((k_qr_panel<RPT, NB, NT>), dim3(1, 1, c->nch), dim3(NT), 0, c->stream, A, ld, n, j, \
+                     nbp, c->Vq, Tp, c->tau, c->zs)
+  // the panel's rows must fit in RPT * NT and its width in NB (panel_width)
+  if (m <= 512) PANEL(2, 32, 256);
+  else if (m <= 1024) PANEL(2, 32, 512);
+  else PANEL(2, 16, 1024);
+#undef PANEL
   prof_pair(c, PH_QR_PANEL, e0, prof_mark(c));
   return KDQMC_OK;
 }
@@ -471,11 +601,23 @@ int launch_apply(kdqmc_ctx* c, double* C, int ld, int n, int j, int nbp, int col
                  const double* Tp, bool trans) {
   if (ncols <= col0) return KDQMC_OK;
   const int e0 = prof_mark(c);
-  // the kernel indexes columns from C's base: shift the base to col0
+  // the kernels index columns from C's base: shift the base to col0
   constexpr int SW = 16;
   const int stripes = (ncols - col0 + SW - 1) / SW;
-  hipLaunchKernelGGL(k_apply_wy<SW>, dim3(stripes, 1, c->nch), dim3(512), 0, c->stream, C + col0, ld, n, j,
-                     nbp, ncols - col0, c->Vq, ld, Tp, trans ? 1 : 0, c->zs);
+  const int m = n - j;
+  if (m <= 512) {
+    hipLaunchKernelGGL(k_apply_wy<SW>, dim3(stripes, 1, c->nch), dim3(512), 0, c->stream, C + col0, ld, n, j,
+                       nbp, ncols - col0, c->Vq, ld, Tp, trans ? 1 : 0, c->zs);
+  } else {
+    const int rc = ((m + kWyChunks - 1) / kWyChunks + 15) / 16 * 16;  // rows per chunk
+    const int nq = (m + rc - 1) / rc;                                  // <= kWyChunks
+    hipLaunchKernelGGL(k_wy_partial<SW>, dim3(stripes, nq, c->nch), dim3(256), 0, c->stream, C + col0, ld, n,
+                       j, nbp, ncols - col0, c->Vq, ld, rc, c->Wq, c->zs);
+    hipLaunchKernelGGL(k_wy_reduce<SW>, dim3(stripes, 1, c->nch), dim3(256), 0, c->stream, nbp, ncols - col0,
+                       Tp, trans ? 1 : 0, c->Wq, nq, c->zs);
+    hipLaunchKernelGGL(k_wy_update<SW>, dim3(stripes, (m + 63) / 64, c->nch), dim3(256), 0, c->stream,
+                       C + col0, ld, n, j, nbp, ncols - col0, c->Vq, ld, c->Wq, c->zs);
+  }
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   return KDQMC_OK;
 }

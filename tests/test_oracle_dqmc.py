@@ -140,6 +140,73 @@ def test_sweep_consistency(c1):
         assert np.abs(g - dqmc.green_scratch(m, f_at_l, l)).max() < 1e-9
 
 
+def test_down_slice_update_equals_scratch(c1):
+    """Downward step: from the fresh G(l), forced flips at slice l give the
+    fresh G(l-1) of the new fields."""
+    w, m, f = c1
+    for l, sites in ((7, [0, 4, 26]), (1, [3, 11])):
+        forced = np.zeros((m.L_tau, m.N), dtype=np.uint8)
+        forced[l - 1, sites] = 1
+        r = dqmc.sweep_down(m, f, dqmc.green_scratch(m, f, l), forced=forced, k=1,
+                            n_stab=m.L_tau + 1, l_start=l, l_stop=l)
+        assert np.abs(r["G"] - dqmc.green_scratch(m, r["fields"], l - 1)).max() < 1e-12
+        assert list(np.nonzero(r["accepted"][l - 1])[0]) == sites
+
+
+def test_down_ratio_vs_determinants(c1):
+    """The ratio read off exp(dtau K) G(l) exp(-dtau K) (the downward pass's
+    matrix) equals the multiprecision weight ratio of the flip."""
+    w, m, f = c1
+    e = brute.mp_propagator(m, dps=30)
+    lw0 = brute.mp_log_weight(m, f, dps=30, e=e)
+    for (l, i) in [(20, 2), (6, 19), (1, 8)]:
+        gt = m.EKinv @ dqmc.green_scratch(m, f, l) @ m.EK
+        ratio, _, _ = dqmc.flip_ratio(m.alpha, int(f[l - 1, i]), gt[i, i])
+        f2 = f.copy()
+        f2[l - 1, i] *= -1
+        rb = float(brute.mp.exp(brute.mp_log_weight(m, f2, dps=30, e=e) - lw0))
+        assert abs(ratio / rb - 1) < 1e-11, (l, i, ratio, rb)
+
+
+@pytest.mark.parametrize("k", [2, 5, 32])
+def test_down_delayed_equals_undelayed(c1, k):
+    w, m, f = c1
+    gt = dqmc.green_scratch(m, f, m.L_tau)
+    u = si.metropolis_uniforms(w.L, m.L_tau, w.seed)[0]
+    r1 = dqmc.sweep_down(m, f, gt, uniforms=u, k=1)
+    rk = dqmc.sweep_down(m, f, gt, uniforms=u, k=k)
+    assert np.array_equal(r1["accepted"], rk["accepted"])
+    for a, b in zip(r1["G_slices"], rk["G_slices"]):
+        assert np.abs(a - b).max() < 1e-11
+
+
+def test_down_sweep_consistency(c1):
+    """A Metropolis downward pass: decisions follow the rule, every slice's G is
+    the fresh G of the fields so far, the pass ends at the fresh G(0)."""
+    w, m, f = c1
+    u = si.metropolis_uniforms(w.L, m.L_tau, w.seed + 1)[0]
+    r = dqmc.sweep_down(m, f, dqmc.green_scratch(m, f, m.L_tau), uniforms=u, k=4)
+    assert np.array_equal(r["fields"] != f, r["accepted"])
+    assert np.array_equal(u < r["ratios"], r["accepted"])
+    assert sorted(r["wrap_err"]) == [0, 10]
+    assert max(r["wrap_err"].values()) < 1e-9
+    assert np.abs(r["G"] - dqmc.green_scratch(m, r["fields"], 0)).max() < 1e-13
+    for idx, g in enumerate(r["G_slices"]):
+        l = m.L_tau - idx            # slice just processed; g is G(l-1)
+        f_now = np.concatenate([f[:l - 1], r["fields"][l - 1:]])
+        assert np.abs(g - dqmc.green_scratch(m, f_now, l - 1)).max() < 1e-9
+
+
+def test_up_then_down_returns_to_scratch(c1):
+    """An upward pass followed by a downward pass from its end matrix."""
+    w, m, f = c1
+    u = si.metropolis_uniforms(w.L, m.L_tau, w.seed, n_sweeps=2)
+    r1 = dqmc.sweep(m, f, dqmc.green_scratch(m, f, 0), uniforms=u[0], k=3)
+    r2 = dqmc.sweep_down(m, r1["fields"], r1["G"], uniforms=u[1], k=3)
+    assert np.abs(r2["G"] - dqmc.green_scratch(m, r2["fields"], 0)).max() < 1e-13
+    assert r2["accepted"].any()
+
+
 def test_golden_multiprecision_fixture():
     """G(0) and G(10) of the smallest workload, 50-digit brute force, stored
     by tests/golden/make_golden.py (which calls only the oracle)."""

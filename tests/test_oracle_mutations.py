@@ -104,3 +104,26 @@ def test_wrong_update_row_is_caught(monkeypatch):
     monkeypatch.setattr(dqmc, "update_slice", bad)
     with pytest.raises(AssertionError):
         tdq.test_rank_one_update_then_wrap_equals_scratch(_c1())
+
+
+def test_down_pass_old_field_scaling_is_caught(monkeypatch):
+    """Downward pass that scales back with the fields from before the flips."""
+    def bad(model, fields, g_top, uniforms=None, forced=None, k=1, n_stab=10, record=True,
+            l_stop=None, l_start=None):
+        fields = fields.copy()
+        L_tau, n = fields.shape
+        acc = np.zeros((L_tau, n), dtype=bool)
+        g = g_top.copy()
+        top = L_tau if l_start is None else l_start
+        for l in range(top, (1 if l_stop is None else l_stop) - 1, -1):
+            s = fields[l - 1]
+            ev = np.exp(model.alpha * s.astype(float))   # taken before the flips
+            gt = model.EKinv @ g @ model.EK
+            gt, acc[l - 1], _ = dqmc.update_slice(gt, s, model.alpha,
+                                                  None if uniforms is None else uniforms[l - 1],
+                                                  None if forced is None else forced[l - 1], k)
+            g = gt / ev[:, None] * ev[None, :]
+        return dict(fields=fields, G=g, accepted=acc)
+    monkeypatch.setattr(dqmc, "sweep_down", bad)
+    with pytest.raises(AssertionError):
+        tdq.test_down_slice_update_equals_scratch(_c1())
