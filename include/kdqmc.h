@@ -124,10 +124,11 @@ int kdqmc_set_fields(kdqmc_ctx* c, const int8_t* s_dev);
 int kdqmc_get_fields(kdqmc_ctx* c, int8_t* s_dev);
 
 /* Loads an externally computed G(l) (FP64, N x N row-major) and sets the
- * current slice to l (0 <= l <= L_tau).  The stabilization stacks are not
- * touched (they must come from kdqmc_set_fields for kdqmc_stabilize); the
- * next stabilization due becomes the first one after slice l if that is
- * earlier than the one already due. */
+ * current slice to l (0 <= l <= L_tau); for l > 0 an upward pass is then in
+ * progress at slice l.  The stabilization stacks are not touched (they come
+ * from kdqmc_set_fields and the passes); the next stabilization due becomes
+ * the first one after slice l when the right stack holds the entries before
+ * it, else the first of the pass. */
 int kdqmc_set_G(kdqmc_ctx* c, const double* G_dev, int l);
 
 /* G(l) = B_l G(l-1) B_l^{-1} with unchanged fields: the column pass applies
@@ -151,23 +152,48 @@ int kdqmc_wrap_slice(kdqmc_ctx* c, int l);
 int kdqmc_sweep_slice(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* forced_dev,
                       uint8_t* accepted_dev, double* ratio_dev);
 
-/* Recomputes G(l) in FP64 for the current slice l (l must be a multiple of
- * n_stab, l > 0, and every earlier multiple since kdqmc_set_fields or the
- * last sweep end must have been stabilized, else KDQMC_ESTATE) from the
- * QR-stabilized stacks (UDT form, pre-pivoted
- * Householder QR, Loh-Gubernatis scale separation), writes
- * max |G_current - G_fresh| to wrap_err_dev[0] (float64, optional) and
- * replaces G.  At l == L_tau it also rebuilds the left stack from the new
- * fields and sets the current slice to 0 (G(0) = G(L_tau)). */
+/* One slice of a downward pass (the same update read backwards, Eq. (5)'s
+ * product traversed from slice L_tau to 1).  From G(l):
+ * G~ = exp(dtau K) G(l) exp(-dtau K) = exp(V_l) G(l-1) exp(-V_l), the sites of
+ * slice l are visited as in kdqmc_sweep_slice, then
+ * G(l-1) = exp(-V_l') G~ exp(V_l') with the new fields V_l'.  A downward pass
+ * starts from slice 0 (G(L_tau) = G(0)) with l = L_tau and continues with
+ * l == current slice; afterwards the current slice is l - 1.  Arguments as in
+ * kdqmc_sweep_slice.  KDQMC_ESTATE during an upward pass or when a
+ * stabilization is due. */
+int kdqmc_sweep_slice_down(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* forced_dev,
+                           uint8_t* accepted_dev, double* ratio_dev);
+
+/* Recomputes G(l) in FP64 for the current slice l of a pass from the
+ * QR-stabilized stacks (UDT form, pre-pivoted Householder QR, Loh-Gubernatis
+ * scale separation), writes max |G_current - G_fresh| to wrap_err_dev[0]
+ * (float64, optional) and replaces G.  l must be a multiple of n_stab
+ * reached by the pass (upward: n_stab..L_tau, downward: L_tau - n_stab..0),
+ * with every earlier one of the pass stabilized, else KDQMC_ESTATE.  An
+ * upward pass extends the right stack (B_l ... B_1) by one entry, a downward
+ * pass the left stack ((B_{L_tau} ... B_{l+1})^T); the last stabilization of
+ * a pass (l == L_tau upward, l == 0 downward) ends it at slice 0.  A stack
+ * left stale by a pass in the other direction's absence (two upward passes
+ * in a row) is rebuilt here from the current fields. */
 int kdqmc_stabilize(kdqmc_ctx* c, double* wrap_err_dev);
 
-/* A full sweep: kdqmc_sweep_slice for l = 1..L_tau with the uniforms
+/* A full upward sweep: kdqmc_sweep_slice for l = 1..L_tau with the uniforms
  * u_dev[L_tau][N] (float64) or forced_dev[L_tau][N], and kdqmc_stabilize
  * after every n_stab slices.  Optional outputs accepted_dev[L_tau][N],
- * ratio_dev[L_tau][N] and wrap_err_dev[L_tau / n_stab].  Requires the
- * current slice to be 0. */
+ * ratio_dev[L_tau][N] and wrap_err_dev[L_tau / n_stab] (entry j - 1 for the
+ * stabilization at slice j n_stab).  Requires the current slice to be 0
+ * with no pass in progress. */
 int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev,
                 uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev);
+
+/* A full downward sweep: kdqmc_sweep_slice_down for l = L_tau..1 (the
+ * uniforms and decisions of slice l at row l - 1 as above), kdqmc_stabilize
+ * at every l - 1 that is a multiple of n_stab; wrap_err_dev[L_tau / n_stab]
+ * has entry j for the stabilization at slice j n_stab.  Alternating upward
+ * and downward sweeps keeps both stabilization stacks current without
+ * rebuilding either. */
+int kdqmc_sweep_down(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev,
+                     uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev);
 
 /* Graph mode (default on): kdqmc_sweep captures its whole launch sequence
  * once per distinct set of pointer arguments into a HIP graph (on a

@@ -339,7 +339,10 @@ int kdqmc_set_fields(kdqmc_ctx* c, const int8_t* s_dev) {
   KDQMC_TRY(stab_green(c, 0, c->G64));
   KDQMC_TRY(copy_64_to_G(c, c->G64));
   c->l_cur = 0;
+  c->dir = 0;
   c->stab_next = 1;
+  c->left_valid = true;
+  c->right_valid = false;
   c->stacks_valid = true;
   return KDQMC_OK;
 }
@@ -357,14 +360,22 @@ int kdqmc_set_G(kdqmc_ctx* c, const double* G_dev, int l) {
   if (!G_dev) return set_error(KDQMC_EINVAL, "G pointer is NULL");
   if (l < 0 || l > c->Ltau) return set_error(KDQMC_EINVAL, "slice index out of range");
   KDQMC_TRY(copy_64_to_G(c, G_dev, (size_t)c->N * c->N));
+  // positions an upward pass at slice l: right stack entries up to slice l
+  // stay usable when this pass (or a complete earlier one) built them
+  if (l == 0) {
+    c->dir = 0;
+    c->stab_next = 1;
+  } else {
+    if (c->dir == 1) c->stab_next = std::min(c->stab_next, l / c->p.n_stab + 1);
+    else c->stab_next = c->right_valid ? l / c->p.n_stab + 1 : 1;
+    c->dir = 1;
+  }
   c->l_cur = l;
-  // stack entries up to slice l stay valid; later ones are rebuilt in order
-  c->stab_next = std::min(c->stab_next, l / c->p.n_stab + 1);
   return KDQMC_OK;
 }
 
-// A slice step may not pass over a stabilization that is due: the right
-// stack entry it would build is needed by every later stabilization.
+// A slice step may not pass over a stabilization that is due: the stack entry
+// it would build is needed by every later stabilization of the pass.
 static int check_stab_due(kdqmc_ctx* c, int l) {
   const int lp = l - 1;
   if (lp > 0 && lp % c->p.n_stab == 0 && lp / c->p.n_stab >= c->stab_next)
@@ -372,8 +383,15 @@ static int check_stab_due(kdqmc_ctx* c, int l) {
   return KDQMC_OK;
 }
 
+static int check_stab_due_down(kdqmc_ctx* c, int l) {
+  if (l < c->Ltau && l % c->p.n_stab == 0 && l / c->p.n_stab <= c->stab_next)
+    return set_error(KDQMC_ESTATE, "kdqmc_stabilize is due at the current slice");
+  return KDQMC_OK;
+}
+
 static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev, size_t zn);
 
+// Upward wrap G(l) = exp(-dtau K) [D G_store D^{-1}] exp(dtau K) (D = ev).
 static int wrap_pass(kdqmc_ctx* c) {
   if (c->fp64) {
     KDQMC_TRY(launch_kinetic_f64(c, (double*)c->G, c->N, true, (const double*)c->tab_m, c->ev, c->evinv, nullptr));
@@ -385,11 +403,35 @@ static int wrap_pass(kdqmc_ctx* c) {
   return KDQMC_OK;
 }
 
+// Downward wrap into the store frame: G_store = D^{-1} exp(dtau K) G(l)
+// exp(-dtau K) D (D = ev): the column pass applies exp(dtau K), the row pass
+// exp(-dtau K) with the row scale D^{-1} and the column scale D.
+static int wrap_pass_down(kdqmc_ctx* c) {
+  if (c->fp64) {
+    KDQMC_TRY(launch_kinetic_f64(c, (double*)c->G, c->N, true, (const double*)c->tab_p, nullptr, nullptr, nullptr));
+    KDQMC_TRY(launch_kinetic_f64(c, (double*)c->G, c->N, false, (const double*)c->tab_m, nullptr, c->evinv, c->ev));
+  } else {
+    KDQMC_TRY(launch_kinetic_f32(c, (float*)c->G, c->N, true, (const float*)c->tab_p, nullptr, nullptr, nullptr));
+    KDQMC_TRY(launch_kinetic_f32(c, (float*)c->G, c->N, false, (const float*)c->tab_m, nullptr, c->evinv, c->ev));
+  }
+  return KDQMC_OK;
+}
+
+// Starts an upward pass at slice 1 from slice 0, or continues one.
+static int enter_up(kdqmc_ctx* c, int l, const char* what) {
+  if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded (set_fields or set_G first)");
+  if (c->dir < 0) return set_error(KDQMC_ESTATE, "a downward pass is in progress");
+  if (l != c->l_cur + 1 || l > c->Ltau) return set_error(KDQMC_ESTATE, std::string(what) + " needs l == current slice + 1");
+  if (c->dir == 0) {
+    c->dir = 1;
+    c->stab_next = 1;
+  }
+  return check_stab_due(c, l);
+}
+
 int kdqmc_wrap_slice(kdqmc_ctx* c, int l) {
   KDQMC_TRY(check_ctx(c));
-  if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded (set_fields or set_G first)");
-  if (l != c->l_cur + 1 || l > c->Ltau) return set_error(KDQMC_ESTATE, "wrap_slice needs l == current slice + 1");
-  KDQMC_TRY(check_stab_due(c, l));
+  KDQMC_TRY(enter_up(c, l, "wrap_slice"));
   KDQMC_TRY(launch_frame_scale(c, l));
   KDQMC_TRY(wrap_pass(c));
   c->l_cur = l;
@@ -399,10 +441,8 @@ int kdqmc_wrap_slice(kdqmc_ctx* c, int l) {
 // zn: elements between consecutive chains' records of u, forced, accepted, ratio
 static int sweep_slice_impl(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* forced_dev,
                             uint8_t* accepted_dev, double* ratio_dev, size_t zn) {
-  if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded (set_fields or set_G first)");
-  if (l != c->l_cur + 1 || l > c->Ltau) return set_error(KDQMC_ESTATE, "sweep_slice needs l == current slice + 1");
-  KDQMC_TRY(check_stab_due(c, l));
   if (!u_dev && !forced_dev) return set_error(KDQMC_EINVAL, "need uniforms or forced decisions");
+  KDQMC_TRY(enter_up(c, l, "sweep_slice"));
   KDQMC_TRY(launch_frame_scale(c, l));
   KDQMC_TRY(run_slice_updates(c, l, u_dev, forced_dev, accepted_dev, ratio_dev, zn));
   KDQMC_TRY(wrap_pass(c));
@@ -414,6 +454,35 @@ int kdqmc_sweep_slice(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* f
                       uint8_t* accepted_dev, double* ratio_dev) {
   KDQMC_TRY(check_ctx(c));
   return sweep_slice_impl(c, l, u_dev, forced_dev, accepted_dev, ratio_dev, (size_t)c->N);
+}
+
+static int sweep_slice_down_impl(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* forced_dev,
+                                 uint8_t* accepted_dev, double* ratio_dev, size_t zn) {
+  if (!u_dev && !forced_dev) return set_error(KDQMC_EINVAL, "need uniforms or forced decisions");
+  if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded (set_fields or set_G first)");
+  if (!c->stacks_valid) return set_error(KDQMC_ESTATE, "stacks not built (call set_fields)");
+  if (c->dir > 0) return set_error(KDQMC_ESTATE, "an upward pass is in progress");
+  if (c->dir == 0) {
+    if (c->l_cur != 0 || l != c->Ltau)
+      return set_error(KDQMC_ESTATE, "a downward pass starts at slice L_tau from slice 0");
+    c->dir = -1;
+    c->l_cur = c->Ltau;  // G(L_tau) = G(0)
+    c->stab_next = c->nc - 1;
+  }
+  if (l != c->l_cur) return set_error(KDQMC_ESTATE, "sweep_slice_down needs l == current slice");
+  KDQMC_TRY(check_stab_due_down(c, l));
+  KDQMC_TRY(launch_frame_scale(c, l));
+  KDQMC_TRY(wrap_pass_down(c));
+  KDQMC_TRY(run_slice_updates(c, l, u_dev, forced_dev, accepted_dev, ratio_dev, zn));
+  KDQMC_TRY(launch_down_reframe(c, l));
+  c->l_cur = l - 1;
+  return KDQMC_OK;
+}
+
+int kdqmc_sweep_slice_down(kdqmc_ctx* c, int l, const double* u_dev, const uint8_t* forced_dev,
+                           uint8_t* accepted_dev, double* ratio_dev) {
+  KDQMC_TRY(check_ctx(c));
+  return sweep_slice_down_impl(c, l, u_dev, forced_dev, accepted_dev, ratio_dev, (size_t)c->N);
 }
 
 // zn: elements between consecutive chains' wrap-error records
@@ -429,52 +498,85 @@ int kdqmc_stabilize(kdqmc_ctx* c, double* wrap_err_dev) {
   return stabilize_timed(c, wrap_err_dev, 1);
 }
 
+// The state at the end of a whole pass: slice 0; an upward pass leaves the
+// right stack matching the new fields, a downward pass the left stack.
+static void end_of_pass(kdqmc_ctx* c, int dir) {
+  c->l_cur = 0;
+  c->dir = 0;
+  c->stab_next = 1;
+  c->left_valid = dir < 0;
+  c->right_valid = dir > 0;
+}
+
 static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev, size_t zn) {
   if (!c->stacks_valid) return set_error(KDQMC_ESTATE, "stacks not built (call set_fields)");
   const int l = c->l_cur;
-  if (l <= 0 || l % c->p.n_stab != 0) return set_error(KDQMC_ESTATE, "stabilize needs the current slice to be a positive multiple of n_stab");
+  if (c->dir == 0) return set_error(KDQMC_ESTATE, "no pass in progress");
+  if (l % c->p.n_stab != 0 || (c->dir > 0 && l == 0) || (c->dir < 0 && l == c->Ltau))
+    return set_error(KDQMC_ESTATE, "stabilize needs the current slice to be a multiple of n_stab inside a pass");
   const int j = l / c->p.n_stab;
   if (j != c->stab_next)
     return set_error(KDQMC_ESTATE, "an earlier stabilization was skipped (each multiple of n_stab needs one, in order)");
-  KDQMC_TRY(stab_right_step(c, j));
+  if (c->dir > 0) {
+    // the left entries used from here on depend only on slices not yet
+    // visited in this pass, so a stale left stack is rebuilt from the fields
+    if (!c->left_valid) {
+      KDQMC_TRY(stab_build_left(c));
+      c->left_valid = true;
+    }
+    KDQMC_TRY(stab_right_step(c, j));
+  } else {
+    if (!c->right_valid) {
+      KDQMC_TRY(stab_build_right(c));
+      c->right_valid = true;
+    }
+    KDQMC_TRY(stab_left_step(c, j));
+  }
   KDQMC_TRY(stab_green(c, j, c->G64));
   if (wrap_err_dev) KDQMC_TRY(max_abs_diff(c, c->G64, c->N, wrap_err_dev, zn));
   KDQMC_TRY(copy_64_to_G(c, c->G64));
-  c->stab_next = j + 1;
-  if (j == c->nc) {
-    KDQMC_TRY(stab_build_left(c));
-    c->l_cur = 0;
-    c->stab_next = 1;
+  if (c->dir > 0) {
+    c->stab_next = j + 1;
+    if (j == c->nc) end_of_pass(c, 1);
+  } else {
+    c->stab_next = j - 1;
+    if (j == 0) end_of_pass(c, -1);
   }
   return KDQMC_OK;
 }
 
-// Slices lo..hi of a sweep (caller records L_tau * N apart per chain), then
-// the stabilization that is due at hi, if any.
-static int sweep_range(kdqmc_ctx* c, int lo, int hi, const double* u_dev, const uint8_t* forced_dev,
-                       uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev) {
+// Slices a..b of a pass (upward: a <= b, downward: a >= b), each followed by
+// the stabilization that is due after it; caller records are L_tau * N apart
+// per chain, wrap errors L_tau / n_stab apart.
+static int pass_range(kdqmc_ctx* c, int dir, int a, int b, const double* u_dev, const uint8_t* forced_dev,
+                      uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev) {
   const size_t N = c->N;
-  const size_t zn = (size_t)c->Ltau * N;  // per-chain records of the sweep's caller arrays
-  for (int l = lo; l <= hi; ++l) {
+  const size_t zn = (size_t)c->Ltau * N;
+  const int ns = c->p.n_stab;
+  for (int l = a; dir > 0 ? l <= b : l >= b; l += dir) {
     const size_t o = (size_t)(l - 1) * N;
-    KDQMC_TRY(sweep_slice_impl(c, l, u_dev ? u_dev + o : nullptr, forced_dev ? forced_dev + o : nullptr,
-                               accepted_dev ? accepted_dev + o : nullptr, ratio_dev ? ratio_dev + o : nullptr,
-                               zn));
-    if (l % c->p.n_stab == 0)
-      KDQMC_TRY(stabilize_timed(c, wrap_err_dev ? wrap_err_dev + (l / c->p.n_stab - 1) : nullptr,
-                                (size_t)c->nc));
+    const double* u = u_dev ? u_dev + o : nullptr;
+    const uint8_t* f = forced_dev ? forced_dev + o : nullptr;
+    uint8_t* acc = accepted_dev ? accepted_dev + o : nullptr;
+    double* rat = ratio_dev ? ratio_dev + o : nullptr;
+    if (dir > 0) {
+      KDQMC_TRY(sweep_slice_impl(c, l, u, f, acc, rat, zn));
+      if (l % ns == 0)
+        KDQMC_TRY(stabilize_timed(c, wrap_err_dev ? wrap_err_dev + (l / ns - 1) : nullptr, (size_t)c->nc));
+    } else {
+      KDQMC_TRY(sweep_slice_down_impl(c, l, u, f, acc, rat, zn));
+      if ((l - 1) % ns == 0)
+        KDQMC_TRY(stabilize_timed(c, wrap_err_dev ? wrap_err_dev + (l - 1) / ns : nullptr, (size_t)c->nc));
+    }
   }
   return KDQMC_OK;
-}
-
-static int sweep_eager(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev,
-                       uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev) {
-  return sweep_range(c, 1, c->Ltau, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
 }
 
 static void drop_graphs(kdqmc_ctx* c) {
-  for (hipGraphExec_t e : c->sweep_exec) (void)hipGraphExecDestroy(e);
-  c->sweep_exec.clear();
+  for (int g = 0; g < 2; ++g) {
+    for (hipGraphExec_t e : c->sweep_exec[g]) (void)hipGraphExecDestroy(e);
+    c->sweep_exec[g].clear();
+  }
 }
 
 // Slices per captured graph: never across a stabilization, and at most
@@ -483,62 +585,84 @@ static int graph_segment_slices(const kdqmc_ctx* c) {
   return std::max(1, std::min(c->p.n_stab, 4096 / std::max(1, c->nw)));
 }
 
-int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, uint8_t* accepted_dev,
-                double* ratio_dev, double* wrap_err_dev) {
+// A whole pass (dir = +1 upward, -1 downward), from and back to slice 0.
+static int run_pass(kdqmc_ctx* c, int dir, const double* u_dev, const uint8_t* forced_dev,
+                    uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev) {
   KDQMC_TRY(check_ctx(c));
-  if (c->l_cur != 0) return set_error(KDQMC_ESTATE, "sweep needs the current slice to be 0");
+  if (c->l_cur != 0 || c->dir != 0) return set_error(KDQMC_ESTATE, "a pass needs the current slice to be 0");
   if (!c->stacks_valid) return set_error(KDQMC_ESTATE, "stacks not built (call set_fields)");
   if (!u_dev && !forced_dev) return set_error(KDQMC_EINVAL, "need uniforms or forced decisions");
+  const int first = dir > 0 ? 1 : c->Ltau, last = dir > 0 ? c->Ltau : 1;
   // events recorded inside a captured graph cannot be timed: profiling runs eager
   if (!c->use_graphs || c->prof_on)
-    return sweep_eager(c, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
-  const void* key[6] = {u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev, nullptr};
-  bool same = !c->sweep_exec.empty();
-  for (int i = 0; i < 6 && same; ++i) same = (key[i] == c->sweep_key[i]);
+    return pass_range(c, dir, first, last, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
+  const int gi = dir > 0 ? 0 : 1;
+  // what the captured launches depend on: the caller's buffers and whether
+  // the stack the pass reads must be rebuilt first
+  const bool stale = dir > 0 ? !c->left_valid : !c->right_valid;
+  const bool left0 = c->left_valid, right0 = c->right_valid;
+  const void* key[7] = {u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev,
+                        reinterpret_cast<const void*>(uintptr_t(stale ? 2 : 1)), nullptr};
+  bool same = !c->sweep_exec[gi].empty();
+  for (int i = 0; i < 7 && same; ++i) same = (key[i] == c->sweep_key[gi][i]);
   if (!same) {
-    drop_graphs(c);
+    for (hipGraphExec_t e : c->sweep_exec[gi]) (void)hipGraphExecDestroy(e);
+    c->sweep_exec[gi].clear();
     if (!c->cap_stream) KDQMC_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     c->graph_next = 0;
     c->graph_triples.clear();
     const int seg = graph_segment_slices(c);
+    const int ns = c->p.n_stab;
     hipStream_t user = c->stream;
-    for (int lo = 1; lo <= c->Ltau;) {
+    for (int a = first; dir > 0 ? a <= last : a >= last;) {
       // a segment ends at the next stabilization point at the latest
-      const int next_stab = ((lo - 1) / c->p.n_stab + 1) * c->p.n_stab;
-      const int hi = std::min(next_stab, lo + seg - 1);
+      int b;
+      if (dir > 0) b = std::min(((a - 1) / ns + 1) * ns, a + seg - 1);
+      else b = std::max(((a - 1) / ns) * ns + 1, a - seg + 1);
       KDQMC_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
       c->stream = c->cap_stream;
       c->capturing = true;
-      const int rc = sweep_range(c, lo, hi, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
+      const int rc = pass_range(c, dir, a, b, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
       c->capturing = false;
       c->stream = user;
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
-      if (rc != KDQMC_OK || ec != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        drop_graphs(c);
-        c->l_cur = 0;
-        c->stab_next = 1;
-        if (rc != KDQMC_OK) return rc;
-        return set_error(KDQMC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
-      }
       hipGraphExec_t ex = nullptr;
-      const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (ei != hipSuccess) {
-        drop_graphs(c);
+      hipError_t ei = hipSuccess;
+      if (rc == KDQMC_OK && ec == hipSuccess) ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (rc != KDQMC_OK || ec != hipSuccess || ei != hipSuccess) {
+        for (hipGraphExec_t e : c->sweep_exec[gi]) (void)hipGraphExecDestroy(e);
+        c->sweep_exec[gi].clear();
+        // nothing of the pass has run: the stacks and G are as before it
         c->l_cur = 0;
+        c->dir = 0;
         c->stab_next = 1;
+        c->left_valid = left0;
+        c->right_valid = right0;
+        if (rc != KDQMC_OK) return rc;
+        if (ec != hipSuccess)
+          return set_error(KDQMC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
         return set_error(KDQMC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
       }
-      c->sweep_exec.push_back(ex);
-      lo = hi + 1;
+      c->sweep_exec[gi].push_back(ex);
+      a = b + dir;
     }
-    for (int i = 0; i < 6; ++i) c->sweep_key[i] = key[i];
+    for (int i = 0; i < 7; ++i) c->sweep_key[gi][i] = key[i];
   }
-  for (hipGraphExec_t ex : c->sweep_exec) KDQMC_HIP(hipGraphLaunch(ex, c->stream));
-  c->l_cur = 0;  // a whole sweep ends at slice 0 (stabilized G(L_tau) = G(0))
+  for (hipGraphExec_t ex : c->sweep_exec[gi]) KDQMC_HIP(hipGraphLaunch(ex, c->stream));
+  end_of_pass(c, dir);
   return KDQMC_OK;
+}
+
+int kdqmc_sweep(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, uint8_t* accepted_dev,
+                double* ratio_dev, double* wrap_err_dev) {
+  return run_pass(c, 1, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
+}
+
+int kdqmc_sweep_down(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_dev, uint8_t* accepted_dev,
+                     double* ratio_dev, double* wrap_err_dev) {
+  return run_pass(c, -1, u_dev, forced_dev, accepted_dev, ratio_dev, wrap_err_dev);
 }
 
 int kdqmc_use_graphs(kdqmc_ctx* c, int on) {

@@ -149,8 +149,9 @@ struct kdqmc_ctx {
   bool use_graphs = true;
   bool capturing = false;
   hipStream_t cap_stream = nullptr;
-  std::vector<hipGraphExec_t> sweep_exec;  // one graph per segment of the sweep
-  const void* sweep_key[6] = {nullptr};
+  // captured passes, [0] upward and [1] downward: one graph per segment
+  std::vector<hipGraphExec_t> sweep_exec[2];
+  const void* sweep_key[2][7] = {{nullptr}};
   std::vector<hipEvent_t> graph_events;   // events that are nodes of the captured graph
   int graph_next = 0;
   std::vector<int> graph_triples;
@@ -170,6 +171,9 @@ struct kdqmc_ctx {
   int l_cur = -1;
   bool stacks_valid = false;
   int stab_next = 1;        // index j of the next stabilization due (at slice j * n_stab)
+  int dir = 0;              // pass in progress: +1 upward, -1 downward, 0 none (at slice 0)
+  bool left_valid = false;  // left stack entries match the current fields
+  bool right_valid = false; // right stack entries match the current fields
   bool fp64 = true;
 
   // device buffers (carved from the caller's workspace)
@@ -234,6 +238,9 @@ int launch_kinetic_f32(kdqmc_ctx* c, float* A, int lda, bool cols, const float* 
 int prepare_kinetic(int L);
 int prepare_updates();
 int launch_frame_scale(kdqmc_ctx* c, int l);
+// Downward pass: after the flips of slice l, G <- F G F^{-1} with
+// F = diag(exp(alpha (s_old - s_new))) (ev holds exp(alpha s_old)).
+int launch_down_reframe(kdqmc_ctx* c, int l);
 // Caller arrays u, forced, acc, ratio: one record per chain, zn elements apart.
 int run_slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, uint8_t* acc,
                       double* ratio, size_t zn);
@@ -245,7 +252,9 @@ int apply_qt_f64(kdqmc_ctx* c, int n, double* X);
 int trsm_upper_f64(kdqmc_ctx* c, int n, const double* R, double* X);
 
 int stab_identity(kdqmc_ctx* c, bool left, int j);
-int stab_build_left(kdqmc_ctx* c);
+int stab_build_left(kdqmc_ctx* c);                  // all left entries from the current fields
+int stab_build_right(kdqmc_ctx* c);                 // all right entries from the current fields
+int stab_left_step(kdqmc_ctx* c, int j);            // left stack entry j from j+1
 int stab_green(kdqmc_ctx* c, int j, double* out);   // G at checkpoint j into out (FP64)
 int stab_right_step(kdqmc_ctx* c, int j);           // right stack entry j from j-1
 // in / out may be workspace arrays (zn = 0: shifted by the workspace stride)

@@ -289,17 +289,25 @@ int stab_identity(kdqmc_ctx* c, bool left, int j) {
   return KDQMC_OK;
 }
 
+int stab_left_step(kdqmc_ctx* c, int j) {
+  // L_j^T-chain: B_{c_j+1}^T ... B_{c_{j+1}}^T applied to L_{j+1}: rightmost first
+  int sl[1024];
+  const int lo = j * c->p.n_stab + 1, hi = (j + 1) * c->p.n_stab;
+  int ns = 0;
+  for (int l = hi; l >= lo; --l) sl[ns++] = l;
+  return udt_step(c, stackU(c, true, j + 1), stackD(c, true, j + 1), stackT(c, true, j + 1), sl, ns, true,
+                  stackU(c, true, j), stackD(c, true, j), stackT(c, true, j));
+}
+
 int stab_build_left(kdqmc_ctx* c) {
   KDQMC_TRY(stab_identity(c, true, c->nc));
-  int sl[1024];
-  for (int j = c->nc - 1; j >= 0; --j) {
-    // L_j^T-chain: B_{c_j+1}^T ... B_{c_{j+1}}^T applied to L_{j+1}: rightmost first
-    const int lo = j * c->p.n_stab + 1, hi = (j + 1) * c->p.n_stab;
-    int ns = 0;
-    for (int l = hi; l >= lo; --l) sl[ns++] = l;
-    KDQMC_TRY(udt_step(c, stackU(c, true, j + 1), stackD(c, true, j + 1), stackT(c, true, j + 1), sl,
-                       ns, true, stackU(c, true, j), stackD(c, true, j), stackT(c, true, j)));
-  }
+  for (int j = c->nc - 1; j >= 0; --j) KDQMC_TRY(stab_left_step(c, j));
+  return KDQMC_OK;
+}
+
+int stab_build_right(kdqmc_ctx* c) {
+  KDQMC_TRY(stab_identity(c, false, 0));
+  for (int j = 1; j <= c->nc; ++j) KDQMC_TRY(stab_right_step(c, j));
   return KDQMC_OK;
 }
 

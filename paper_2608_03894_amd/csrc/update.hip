@@ -41,6 +41,26 @@ __global__ void k_frame_scale(const int8_t* __restrict__ s, int n, const double*
   }
 }
 
+// Downward pass: G <- F G F^{-1}, F_i = exp(alpha s_old,i) exp(-alpha s_new,i)
+// (1 where the site was not flipped), element by element.
+template <typename T>
+__global__ void k_down_reframe(T* __restrict__ G, int n, const double* __restrict__ ev,
+                               const double* __restrict__ evinv, const int8_t* __restrict__ s,
+                               const double* __restrict__ sc, size_t zs) {
+  G = zw(G, zs);
+  ev = zw(ev, zs);
+  evinv = zw(evinv, zs);
+  s = zw(s, zs);
+  const double ea = zw(sc, zs)[SC_EA], eainv = zw(sc, zs)[SC_EAINV];
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < (size_t)n * n) {
+    const int r = (int)(idx / n), cc = (int)(idx % n);
+    const double fr = ev[r] * (s[r] > 0 ? eainv : ea);
+    const double fci = evinv[cc] * (s[cc] > 0 ? ea : eainv);
+    if (fr != 1.0 || fci != 1.0) G[idx] = T(double(G[idx]) * fr * fci);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Sequential decisions of one window (single workgroup of 256 threads).
 // Three wn x wn blocks are kept: the window submatrix Gs (tilde frame) and two
@@ -567,6 +587,20 @@ int launch_frame_scale(kdqmc_ctx* c, int l) {
   hipLaunchKernelGGL(k_frame_scale, dim3((c->N + 255) / 256, 1, (unsigned)c->nch), dim3(256), 0,
                      c->stream, c->fields + (size_t)(l - 1) * c->N, c->N, c->sc, c->ev, c->evinv,
                      c->zs);
+  KDQMC_HIP(hipGetLastError());
+  return KDQMC_OK;
+}
+
+int launch_down_reframe(kdqmc_ctx* c, int l) {
+  const size_t nn = (size_t)c->N * c->N;
+  const dim3 grid((unsigned)((nn + 255) / 256), 1, (unsigned)c->nch);
+  const int8_t* s = c->fields + (size_t)(l - 1) * c->N;
+  if (c->fp64)
+    hipLaunchKernelGGL(k_down_reframe<double>, grid, dim3(256), 0, c->stream, (double*)c->G, c->N, c->ev,
+                       c->evinv, s, c->sc, c->zs);
+  else
+    hipLaunchKernelGGL(k_down_reframe<float>, grid, dim3(256), 0, c->stream, (float*)c->G, c->N, c->ev,
+                       c->evinv, s, c->sc, c->zs);
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }

@@ -60,6 +60,8 @@ _SIGS = {
     "kdqmc_sweep_slice": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
     "kdqmc_stabilize": (ctypes.c_int, [_vp, _vp]),
     "kdqmc_sweep": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "kdqmc_sweep_slice_down": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp, _vp]),
+    "kdqmc_sweep_down": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "kdqmc_measure_G": (ctypes.c_int, [_vp, _vp]),
     "kdqmc_current_slice": (ctypes.c_int, [_vp]),
     "kdqmc_sync": (ctypes.c_int, [_vp]),
@@ -187,6 +189,14 @@ class Chain:
         _check(self.lib.kdqmc_sweep_slice(self.ctx, l, _ptr(u), _ptr(forced), _ptr(accepted),
                                           _ptr(ratio)))
 
+    def sweep_slice_down(self, l, u=None, forced=None, accepted=None, ratio=None):
+        _check(self.lib.kdqmc_sweep_slice_down(self.ctx, l, _ptr(u), _ptr(forced), _ptr(accepted),
+                                               _ptr(ratio)))
+
+    def sweep_down(self, u=None, forced=None, accepted=None, ratio=None, wrap_err=None):
+        _check(self.lib.kdqmc_sweep_down(self.ctx, _ptr(u), _ptr(forced), _ptr(accepted), _ptr(ratio),
+                                         _ptr(wrap_err)))
+
     def stabilize(self, wrap_err=None):
         _check(self.lib.kdqmc_stabilize(self.ctx, _ptr(wrap_err)))
 
@@ -291,13 +301,15 @@ class Batch:
         for g in self.groups:
             cur.wait_stream(g["stream"])
 
-    def sweep(self, s):
-        """One sweep of every chain with its uniforms of sweep s."""
+    def sweep(self, s, down=False):
+        """One pass of every chain with its uniforms of sweep s (upward, or
+        downward with down=True)."""
         t = self.torch
         cur = t.cuda.current_stream(self.device)
         for g in self.groups:
             g["stream"].wait_stream(cur)
-            g["chain"].sweep(g["u"][s], None, g["acc"], None, g["err"])
+            fn = g["chain"].sweep_down if down else g["chain"].sweep
+            fn(g["u"][s], None, g["acc"], None, g["err"])
         for g in self.groups:
             cur.wait_stream(g["stream"])
 

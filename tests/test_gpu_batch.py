@@ -9,6 +9,7 @@ import pytest
 
 import seeded_inputs as si
 from gpu_helpers import dev, oracle_run, say, torch
+from oracle import dqmc
 
 pytestmark = pytest.mark.gpu
 
@@ -20,7 +21,7 @@ def _params(L, U, beta, prec="fp64", delay_k=16):
     return kdqmc.make_params(L, U, beta, 0.1, mu=-1.0, n_stab=10, delay_k=delay_k, prec=prec)
 
 
-def _run_single(L, U, beta, f, u, prec):
+def _run_single(L, U, beta, f, u, prec, u_down=None):
     from paper_2608_03894_amd import kdqmc
     t = torch()
     ch = kdqmc.Chain(_params(L, U, beta, prec))
@@ -29,10 +30,14 @@ def _run_single(L, U, beta, f, u, prec):
     ratio = t.zeros(f.shape, dtype=t.float64, device="cuda:0")
     err = t.zeros(f.shape[0] // 10, dtype=t.float64, device="cuda:0")
     ch.sweep(dev(u), None, acc, ratio, err)
-    g = ch.G().cpu().numpy()
-    out = (g, acc.cpu().numpy(), ratio.cpu().numpy(), err.cpu().numpy())
+    out = [None, acc.cpu().numpy(), ratio.cpu().numpy(), err.cpu().numpy()]
+    if u_down is not None:
+        acc2 = t.zeros(f.shape, dtype=t.uint8, device="cuda:0")
+        ch.sweep_down(dev(u_down), None, acc2, None, None)
+        out.append(acc2.cpu().numpy())
+    out[0] = ch.G().cpu().numpy()
     ch.close()
-    return out
+    return tuple(out)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed_f16"])
@@ -53,7 +58,11 @@ def test_batched_chains_equal_single_chains(gpu_lib, prec):
     ratio = t.zeros((3, Lt, 3 * L * L), dtype=t.float64, device="cuda:0")
     err = t.zeros((3, Lt // 10), dtype=t.float64, device="cuda:0")
     b.sweep(dev(np.stack(us)), None, acc, ratio, err)
+    us2 = [si.metropolis_uniforms(L, Lt, s + 100)[0] for s in seeds]
+    acc2 = t.zeros((3, Lt, 3 * L * L), dtype=t.uint8, device="cuda:0")
+    b.sweep_down(dev(np.stack(us2)), None, acc2, None, None)
     G = b.G().cpu().numpy()
+    acc2 = acc2.cpu().numpy()
     acc, ratio, err = acc.cpu().numpy(), ratio.cpu().numpy(), err.cpu().numpy()
     fields = t.zeros((3, Lt, 3 * L * L), dtype=t.int8, device="cuda:0")
     b.get_fields(fields)
@@ -61,18 +70,21 @@ def test_batched_chains_equal_single_chains(gpu_lib, prec):
     b.close()
     for z in range(3):
         say("single chain", z, "U", Us[z])
-        g1, a1, r1, e1 = _run_single(L, Us[z], beta, fs[z], us[z], prec)
+        g1, a1, r1, e1, a2 = _run_single(L, Us[z], beta, fs[z], us[z], prec, us2[z])
         assert np.array_equal(G[z], g1)
         assert np.array_equal(acc[z], a1)
         assert np.array_equal(ratio[z], r1)
         assert np.array_equal(err[z], e1)
-        assert np.array_equal(fields[z] == fs[z], a1 == 0)
+        assert np.array_equal(acc2[z], a2)
+        assert np.array_equal(fields[z] == fs[z], (a1 ^ a2) == 0)
     if prec == "fp64":
         # chain 2 has U = -5 while the context's parameters carry U = -3
         m, f, g0, r, u = oracle_run(L, -5.0, beta, seeds[2])
         assert np.array_equal(acc[2].astype(bool), r["accepted"])
-        assert np.abs(G[2] - r["G"]).max() < TOL64
         assert np.abs(ratio[2] - r["ratios"]).max() < 1e-9 * np.abs(r["ratios"]).max()
+        rd = dqmc.sweep_down(m, r["fields"], r["G"], uniforms=us2[2], k=1)
+        assert np.array_equal(acc2[2].astype(bool), rd["accepted"])
+        assert np.abs(G[2] - rd["G"]).max() < TOL64
 
 
 def test_batched_slice_calls_and_measure(gpu_lib):
@@ -106,8 +118,8 @@ def test_batched_slice_calls_and_measure(gpu_lib):
 
 
 def test_uneven_batch_groups(gpu_lib):
-    """Chains of different L and beta: grouped by shape, run on several streams,
-    each chain equal to the same chain alone."""
+    """Chains of different L and beta: grouped by shape, run on several streams
+    (an upward then a downward pass), each chain equal to the same chain alone."""
     from paper_2608_03894_amd import kdqmc
     specs = [(3, -4.0, 2.0, 81), (6, -3.0, 2.0, 82), (3, -5.0, 3.0, 83), (6, -5.0, 2.0, 84),
              (3, -3.0, 2.0, 85)]
@@ -119,7 +131,7 @@ def test_uneven_batch_groups(gpu_lib):
     assert len(b.groups) == 3
     b.set_inputs([dev(f) for f in fs], [dev(u) for u in us])
     b.sweep(0)
-    b.sweep(1)
+    b.sweep(1, down=True)
     torch().cuda.synchronize()
     for g in b.groups:
         G = g["chain"].G().cpu().numpy()
@@ -131,7 +143,7 @@ def test_uneven_batch_groups(gpu_lib):
             ch = kd.Chain(_params(L, U, beta, delay_k=8))
             ch.set_fields(dev(fs[i]))
             ch.sweep(dev(us[i][0]))
-            ch.sweep(dev(us[i][1]))
+            ch.sweep_down(dev(us[i][1]))
             assert np.array_equal(G[k], ch.G().cpu().numpy()), (i, specs[i])
             ch.close()
     b.close()

@@ -257,3 +257,140 @@ def test_state_errors(gpu_lib):
     # slice 10 has been stabilized again, so slice 20's is the one due
     ch.stabilize()
     assert ch.current_slice() == 0
+
+
+def _down_replay(ch, f_start, r_down, n_stab=10):
+    """Replays a downward pass slice by slice; returns per-slice G, ratios,
+    wrap errors and the G before each stabilization."""
+    t = torch()
+    L_tau, N = f_start.shape
+    forced = dev(r_down["accepted"].astype(np.uint8))
+    ratio = t.zeros((L_tau, N), dtype=t.float64, device="cuda:0")
+    errs, pre = {}, {}
+    gs = []
+    for l in range(L_tau, 0, -1):
+        ch.sweep_slice_down(l, None, forced[l - 1], None, ratio[l - 1])
+        if (l - 1) % n_stab == 0:
+            pre[l - 1] = ch.G().cpu().numpy()
+            e = t.zeros(1, dtype=t.float64, device="cuda:0")
+            ch.stabilize(e)
+            errs[l - 1] = float(e.cpu()[0])
+        gs.append(ch.G().cpu().numpy())
+    return gs, ratio.cpu().numpy(), errs, pre
+
+
+@pytest.mark.parametrize("L,k,window", [(3, 1, 1), (3, 5, 5), (3, 32, 0), (6, 16, 0)])
+def test_down_sweep_forced(gpu_lib, L, k, window):
+    """An upward pass, then a downward pass slice by slice, both with the
+    oracle's decisions replayed: every G(l-1), ratio and wrap error of the
+    downward pass against the oracle's downward pass."""
+    say("down sweep", L, k, window)
+    m, f, g0, r_up, u = oracle_run(L, -4.0, 2.0, 3 if L == 3 else 6)
+    u2 = si.metropolis_uniforms(L, m.L_tau, 77)[0]
+    r_dn = dqmc.sweep_down(m, r_up["fields"], r_up["G"], uniforms=u2, k=1)
+    ch = chain(L, -4.0, 2.0, delay_k=k, window=window)
+    ch.set_fields(dev(f))
+    ch.sweep(None, dev(r_up["accepted"].astype(np.uint8)))
+    assert np.abs(ch.G().cpu().numpy() - r_up["G"]).max() < TOL64
+    gs, ratio, errs, pre = _down_replay(ch, r_up["fields"], r_dn)
+    worst = max(np.abs(a - b).max() for a, b in zip(gs, r_dn["G_slices"]))
+    say("down worst", worst)
+    assert worst < TOL64
+    assert np.abs(ratio - r_dn["ratios"]).max() < 1e-9 * np.abs(r_dn["ratios"]).max()
+    # Before a stabilization each side has drifted from the fresh G by its own
+    # wrap error; the two wrapped matrices agree within the sum of the drifts,
+    # and the GPU's drift stays within a few times the oracle's.
+    for j, e in errs.items():
+        e_or = r_dn["wrap_err"][j]
+        say("down wrap error at", j, "gpu", e, "oracle", e_or)
+        assert np.abs(pre[j] - r_dn["G_prestab"][j]).max() < max(TOL64, e + e_or) + 1e-12
+        assert e < max(5 * TOL64, 4 * e_or)
+    assert ch.current_slice() == 0
+    fields = torch().zeros(f.shape, dtype=torch().int8, device="cuda:0")
+    ch.get_fields(fields)
+    assert np.array_equal(fields.cpu().numpy(), r_dn["fields"])
+
+
+def test_down_sweep_after_set_fields(gpu_lib):
+    """A downward pass straight after set_fields (the right stack is built at
+    its first stabilization), then an upward pass (no rebuild), then an upward
+    pass again (the left stack is rebuilt): all against the oracle."""
+    say("down after set_fields")
+    L, Lt = 3, 20
+    m = model(L, -4.0, 2.0)
+    f = si.ising_fields(L, Lt, 5)
+    u = si.metropolis_uniforms(L, Lt, 5, n_sweeps=3)
+    r1 = dqmc.sweep_down(m, f, dqmc.green_scratch(m, f, 0), uniforms=u[0], k=1)
+    r2 = dqmc.sweep(m, r1["fields"], r1["G"], uniforms=u[1], k=1)
+    r3 = dqmc.sweep(m, r2["fields"], r2["G"], uniforms=u[2], k=1)
+    ch = chain(L, -4.0, 2.0, delay_k=8)
+    ch.set_fields(dev(f))
+    t = torch()
+    errs = t.zeros(2, dtype=t.float64, device="cuda:0")
+    for r, down in ((r1, True), (r2, False), (r3, False)):
+        forced = dev(r["accepted"].astype(np.uint8))
+        (ch.sweep_down if down else ch.sweep)(None, forced, None, None, errs)
+        assert np.abs(ch.G().cpu().numpy() - r["G"]).max() < TOL64
+        e = errs.cpu().numpy()
+        keys = sorted(r["wrap_err"])
+        for i, key in enumerate(keys):
+            assert e[i] < max(5 * TOL64, 4 * r["wrap_err"][key])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_f16"])
+def test_alternating_passes_graph_equals_eager(gpu_lib, prec):
+    """Up, down, up, down from captured graphs equals the same passes of direct
+    launches bit for bit."""
+    say("alternating graph vs eager", prec)
+    t = torch()
+    L, Lt = 6, 20
+    N = 3 * L * L
+    f = si.ising_fields(L, Lt, 9)
+    u = dev(si.metropolis_uniforms(L, Lt, 9, n_sweeps=4))
+    outs = []
+    for graphs in (False, True):
+        ch = chain(L, -4.0, 2.0, delay_k=16, prec=prec)
+        ch.use_graphs(graphs)
+        ch.set_fields(dev(f))
+        ub = t.zeros((Lt, N), dtype=t.float64, device="cuda:0")
+        acc = t.zeros((Lt, N), dtype=t.uint8, device="cuda:0")
+        err = t.zeros(2, dtype=t.float64, device="cuda:0")
+        res = []
+        for s in range(4):
+            ub.copy_(u[s])
+            (ch.sweep_down if s % 2 else ch.sweep)(ub, None, acc, None, err)
+            res.append((ch.G().cpu().numpy(), acc.cpu().numpy(), err.cpu().numpy()))
+        outs.append(res)
+        ch.close()
+    for a, b in zip(outs[0], outs[1]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_down_state_errors(gpu_lib):
+    from paper_2608_03894_amd import kdqmc
+    say("down state errors")
+    t = torch()
+    ch = chain(3, -4.0, 2.0)
+    ch.set_fields(dev(np.ones((20, 27), dtype=np.int8)))
+    forced = t.zeros(27, dtype=t.uint8, device="cuda:0")
+    with pytest.raises(kdqmc.KdqmcError) as e:
+        ch.sweep_slice_down(19, None, forced)        # a downward pass starts at L_tau
+    assert e.value.code == kdqmc.ESTATE
+    ch.sweep_slice_down(20, None, forced)
+    with pytest.raises(kdqmc.KdqmcError) as e:
+        ch.sweep_slice(1, None, forced)              # upward step inside a downward pass
+    assert e.value.code == kdqmc.ESTATE
+    for l in range(19, 10, -1):
+        ch.sweep_slice_down(l, None, forced)
+    with pytest.raises(kdqmc.KdqmcError) as e:
+        ch.sweep_slice_down(10, None, forced)        # slice 10 needs its stabilization first
+    assert e.value.code == kdqmc.ESTATE
+    ch.stabilize()
+    for l in range(10, 0, -1):
+        ch.sweep_slice_down(l, None, forced)
+    ch.stabilize()
+    assert ch.current_slice() == 0
+    with pytest.raises(kdqmc.KdqmcError) as e:
+        ch.stabilize()                               # no pass in progress
+    assert e.value.code == kdqmc.ESTATE
