@@ -1,9 +1,12 @@
 """Benchmark: HS-field sweeps per second of the kagome DQMC hot path on one GPU.
 
-One step = one full sweep (L_tau slices of window decisions, delayed rank-k
-flushes and FFT wraps, plus a QR-stabilization every n_stab slices and the
-left-stack rebuild at the end), on seeded synthetic fields and uniforms that
-are resident in device memory before the timed region starts.
+One step = one full sweep: a pass over all L_tau slices (window decisions,
+delayed rank-k flushes and FFT wraps, a QR-stabilization every n_stab
+slices), on seeded synthetic fields and uniforms that are resident in device
+memory before the timed region starts.  Passes alternate upward and downward
+(the standard sweep order of DQMC; each pass keeps the stabilization stack
+the next one needs), or are all upward with --passes up (then every pass
+ends by rebuilding the left stack).
 
 Prints ONE JSON line.  `roofline` is for the dominant kernel (largest share
 of the timed region's kernel time, from HIP events recorded by the library
@@ -227,13 +230,14 @@ def bench_batch(args):
     b = kdqmc.Batch(params, device=dev)
     log(f"batch of {b.n_chains} chains in {len(b.groups)} shape groups, prec={prec}")
     b.set_inputs(fields, unis)
+    alt = args.passes == "alternate"
     for s in range(args.warmup):
-        b.sweep(s)
+        b.sweep(s, down=alt and s % 2 == 1)
         log(f"warmup sweep {s + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        b.sweep(args.warmup + s)
+        b.sweep(args.warmup + s, down=alt and (args.warmup + s) % 2 == 1)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = b.n_chains * args.steps / elapsed
@@ -255,7 +259,7 @@ def bench_batch(args):
         "dtype": "f64" if prec == "fp64" else f"f32+{prec.split('_')[1]}",
         "data": "synthetic",
         "config": {"workload": "kagome-batch-64-chains-L6-15-U3-5-beta4-8", "chains": b.n_chains,
-                   "groups": groups, "prec": prec, "autotuned_chains": n_tuned,
+                   "groups": groups, "prec": prec, "autotuned_chains": n_tuned, "passes": args.passes,
                    "field_updates_per_s": upd * args.steps / elapsed},
         "roofline": None,
         "cpu_baseline": None,
@@ -336,6 +340,8 @@ def main():
     ap.add_argument("--window", type=int, default=0)
     ap.add_argument("--fft-tile", type=int, default=0)
     ap.add_argument("--n-stab", type=int, default=None, help="slices between stabilizations")
+    ap.add_argument("--passes", default="alternate", choices=["alternate", "up"],
+                    help="sweep directions: alternating upward/downward passes, or upward only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=20)
     ap.add_argument("--wrap-only", action="store_true",
@@ -381,16 +387,24 @@ def main():
     errs = torch.zeros(Lt // n_stab, dtype=torch.float64, device=dev)
     log(f"workload {w.name} prec={prec} k={k} N={N} L_tau={Lt}")
     ch.set_fields(fields)
+    alt = args.passes == "alternate"
+
+    def one_pass(s):
+        if alt and s % 2 == 1:
+            ch.sweep_down(uni[s], None, acc, None, errs)
+        else:
+            ch.sweep(uni[s], None, acc, None, errs)
+
     for s in range(args.warmup):
-        ch.sweep(uni[s], None, acc, None, errs)
+        one_pass(s)
         log(f"warmup sweep {s + 1}/{args.warmup} done")
     torch.cuda.synchronize()
 
-    # timed region: K sweeps replayed from the captured HIP graph
+    # timed region: K sweeps replayed from the captured HIP graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        ch.sweep(uni[args.warmup + s], None, acc, None, errs)
+        one_pass(args.warmup + s)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     accepts = int(acc.sum().item())  # last sweep's accepts
@@ -403,12 +417,12 @@ def main():
     # (direct launches: events inside a graph are not timed)
     ch.set_fields(fields)
     for s in range(args.warmup):
-        ch.sweep(uni[s], None, acc, None, errs)
+        one_pass(s)
     ch.profile_enable(True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for s in range(args.steps):
-        ch.sweep(uni[args.warmup + s], None, acc, None, errs)
+        one_pass(args.warmup + s)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     prof = ch.profile_read()
@@ -452,7 +466,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "L": w.L, "N": N, "U": w.U, "beta": w.beta, "L_tau": Lt,
                    "delay_k": k, "window": win, "fft_tile": tile, "autotuned": tuned,
-                   "prec": prec, "n_stab": n_stab,
+                   "prec": prec, "n_stab": n_stab, "passes": args.passes,
                    "field_updates_per_s": value * N * Lt},
         "roofline": roof,
         "kernels": kernels,
