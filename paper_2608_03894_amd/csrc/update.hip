@@ -76,9 +76,11 @@ __global__ void k_down_reframe(T* __restrict__ G, int n, const double* __restric
 // Register layout: the NT threads form a GR x GR grid (GR = 8 for one wave,
 // 16 for four); thread t owns the WS x WS entries (x, y) with
 // x = t/GR + GR i, y = t%GR + GR k of each block.  Per accept the owners
-// publish row p / column p through LDS (barrier), everyone updates its
-// registers and the diagonal owners publish the new diagonal (barrier).  A
-// rejected flip reads one LDS word and needs no barrier.  Four waves are used
+// publish row p / column p through LDS (one barrier), everyone updates its
+// registers and the diagonal owners publish the new diagonal for the
+// decisions after the next accept.  A decision reads three LDS words (the
+// diagonal entry and the latest accept's row/column entries) and needs no
+// barrier.  Four waves are used
 // for every window size: the per-accept updates are VALU bound and spread
 // better over four SIMDs than the barriers cost.
 // ---------------------------------------------------------------------------
@@ -109,7 +111,15 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
   constexpr int WM = GR * WS;  // largest window this instance handles
   // Everything the loop produces stays in LDS until the end: a barrier also
   // waits for outstanding global stores, so none are issued inside the loop.
-  __shared__ double rowp[WM], colp[WM], cfp[WM], crp[WM], diagL[WM], ul[WM], rl[WM];
+  // The published row / column of the latest accept and the diagonal of G~cur
+  // are double-buffered by accept parity, so one barrier per accept suffices:
+  // buffer n & 1 is written by accept n before its barrier and read until the
+  // barrier of accept n + 1, after which nobody reads it before accept n + 2
+  // overwrites it.  diagB[k & 1] holds the diagonal after k accepts (entries
+  // past the k-th accepted site); a decision after accept n adds accept n's
+  // rank-one term to diagB[n & 1] itself, exactly as the owners do.
+  __shared__ double rowp[2][WM], colp[2][WM], cfp[2][WM], crp[2][WM], diagB[2][WM];
+  __shared__ double ul[WM], rl[WM];
   __shared__ double Zs[WM][WM + 1], Zps[WM][WM + 1];
   __shared__ int pl[WM];
   __shared__ int8_t sl[WM];
@@ -134,7 +144,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
       gs[i][k] = g;
       cf[i][k] = 0.0;
       cr[i][k] = 0.0;
-      if (x == y && x < wn) diagL[x] = g;
+      if (x == y && x < wn) diagB[0][x] = g;
     }
   for (int p = tid; p < wn; p += NT) {
     sl[p] = s_l[w0 + p];
@@ -144,9 +154,16 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
   __syncthreads();
 
   int na = 0;
+  double c_last = 0.0;  // c of the latest accept (the same in every thread)
   for (int p = 0; p < wn; ++p) {
     const int s = sl[p];
-    const double gpp = diagL[p];
+    double gpp;
+    if (na == 0) {
+      gpp = diagB[0][p];
+    } else {
+      const int bl = (na - 1) & 1;
+      gpp = fma(c_last * colp[bl][p], rowp[bl][p], diagB[bl][p]);
+    }
     const double delta = (s > 0 ? em2a : ep2a) - 1.0;
     const double e2as = s > 0 ? ep2a : em2a;
     const double R = 1.0 + delta * (1.0 - gpp);
@@ -159,6 +176,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     if (!a) continue;
     const double c = delta / R;
     const int n = na;
+    const int b = n & 1;
     const int ip = p / GR, pr = p % GR;
     // phase A: publish row p of Gs and Cr, column p of Gs and Cf
     if (rx == pr) {
@@ -171,8 +189,8 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
             g = gs[i][k];
             r = cr[i][k];
           }
-        rowp[cy + GR * k] = g;
-        crp[cy + GR * k] = r;
+        rowp[b][cy + GR * k] = g;
+        crp[b][cy + GR * k] = r;
       }
     }
     if (cy == pr) {
@@ -185,57 +203,54 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
             g = gs[i][k];
             f = cf[i][k];
           }
-        colp[rx + GR * i] = g;
-        cfp[rx + GR * i] = f;
+        colp[b][rx + GR * i] = g;
+        cfp[b][rx + GR * i] = f;
       }
     }
-    if (tid == 0) {
-      sl[p] = int8_t(-s);
-      pl[n] = p;
-    }
+    if (tid == 0) pl[n] = p;
     __syncthreads();
     // phase B: rank-one updates of the live parts; publish the accept's factors
     double cx[WS], qx[WS], ry[WS], zpy[WS];
 #pragma unroll
     for (int i = 0; i < WS; ++i) {
       const int x = rx + GR * i;
-      cx[i] = colp[x];
-      qx[i] = -c * ((x == n ? 1.0 : 0.0) + cfp[x]);   // Z[x][n] (rows q = x of Cf)
+      cx[i] = colp[b][x];
+      qx[i] = -c * ((x == n ? 1.0 : 0.0) + cfp[b][x]);   // Z[x][n] (rows q = x of Cf)
     }
 #pragma unroll
     for (int k = 0; k < WS; ++k) {
       const int y = cy + GR * k;
-      ry[k] = rowp[y];
-      zpy[k] = (y == n ? 1.0 : 0.0) - crp[y];        // Z'[n][y] (columns q = y of Cr)
+      ry[k] = rowp[b][y];
+      zpy[k] = (y == n ? 1.0 : 0.0) - crp[b][y];        // Z'[n][y] (columns q = y of Cr)
     }
 #pragma unroll
     for (int i = 0; i < WS; ++i)
 #pragma unroll
       for (int k = 0; k < WS; ++k) {
         const int x = rx + GR * i, y = cy + GR * k;
-        if (x > p && y > p) gs[i][k] += c * cx[i] * ry[k];
+        if (x > p && y > p) gs[i][k] = fma(c * cx[i], ry[k], gs[i][k]);
         if (x <= n && y > p) cf[i][k] -= qx[i] * ry[k];
         if (x > p && y <= n) cr[i][k] -= c * cx[i] * zpy[k];
       }
     if (tid <= n) {
-      Zs[tid][n] = -c * ((tid == n ? 1.0 : 0.0) + cfp[tid]);
-      Zps[n][tid] = (tid == n ? 1.0 : 0.0) - crp[tid];
+      Zs[tid][n] = -c * ((tid == n ? 1.0 : 0.0) + cfp[b][tid]);
+      Zps[n][tid] = (tid == n ? 1.0 : 0.0) - crp[b][tid];
     }
     if (rx == cy) {
 #pragma unroll
       for (int i = 0; i < WS; ++i) {
         const int x = rx + GR * i;
-        if (x > p && x < wn) diagL[x] = gs[i][i];
+        if (x > p && x < wn) diagB[b ^ 1][x] = gs[i][i];
       }
     }
+    c_last = c;
     ++na;
-    __syncthreads();
   }
   __syncthreads();
   if (tid == 0) win_a[win] = na;
   for (int n = tid; n < na; n += NT) win_p[win * W + n] = pl[n];
   for (int p = tid; p < wn; p += NT) {
-    s_l[w0 + p] = sl[p];
+    s_l[w0 + p] = al[p] ? int8_t(-sl[p]) : sl[p];   // the loop never writes sl: other waves read it
     if (ratio_out) ratio_out[w0 + p] = rl[p];
     if (acc_out) acc_out[w0 + p] = al[p];
   }
