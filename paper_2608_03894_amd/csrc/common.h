@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -110,9 +111,12 @@ inline constexpr TwiddleTable<N> kTw{};
 // with zw().  Caller arrays hold one record per chain, zn elements apart,
 // shifted with zc().  Null pointers stay null.
 // ---------------------------------------------------------------------------
+// (byte arithmetic on a char pointer, not on an integer: the compiler then
+// still knows the result points to global memory and emits global loads)
 template <typename T>
 __device__ __forceinline__ T* zw(T* p, size_t zs) {
-  return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (size_t)blockIdx.z * zs) : p;
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (size_t)blockIdx.z * zs) : p;
 }
 template <typename T>
 __device__ __forceinline__ T* zc(T* p, size_t zn) {
