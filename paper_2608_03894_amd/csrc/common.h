@@ -123,6 +123,14 @@ __device__ __forceinline__ T* zc(T* p, size_t zn) {
   return p ? p + (size_t)blockIdx.z * zn : p;
 }
 
+// Lane `src` (wave-uniform) of a double held in a vector register; the value
+// is wave-uniform afterwards (scalar registers).
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
 // Per-chain scalars kept in the workspace (the decoupling constant differs
 // between chains of a batch): exp(alpha), exp(-alpha), exp(-2 alpha), exp(2 alpha).
 enum { SC_EA = 0, SC_EAINV, SC_EM2A, SC_EP2A, SC_COUNT };

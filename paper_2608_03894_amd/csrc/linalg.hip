@@ -132,14 +132,6 @@ __device__ __forceinline__ double xchg_xor(double v, int mask) {
   return __shfl_xor(v, mask);
 }
 
-// Reads lane `src` (a compile-time constant) of a double held in a vector
-// register; the value is wave-uniform afterwards (scalar registers).
-__device__ __forceinline__ double lane_value(double v, int src) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-  return __hiloint2double(hi, lo);
-}
-
 // One panel of the Householder QR.  Column c (row jc = j + c) needs, over
 // the rows r >= jc, the dot products d_t = sum_r a_c[r] a_t[r] with every
 // column t of the panel, and the row jc itself.  With alpha = a_c[jc],

@@ -153,27 +153,44 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
   }
   __syncthreads();
 
+  // A rejected proposal leaves G~cur unchanged, so every proposal between two
+  // accepts sees the same matrix: lane x of each wave tests site x of the
+  // window against the state after the latest accept, and the lowest
+  // accepting site past the previous accept (a ballot) is the next accept;
+  // the sites before it are rejections with exactly the ratios the one by one
+  // scan computes.  Every wave evaluates the same tests, so all agree on the
+  // accept without a barrier.
+  const int lane = tid & 63;
+  const bool xin = lane < wn;
+  const int sx = xin ? sl[lane] : 1;
+  const double ux = xin ? ul[lane] : 0.0;
+  const bool fx = xin && fl[lane] != 0;
+  const double delta_x = (sx > 0 ? em2a : ep2a) - 1.0;
+  const double e2as_x = sx > 0 ? ep2a : em2a;
   int na = 0;
+  int p0 = 0;           // first site not yet decided
   double c_last = 0.0;  // c of the latest accept (the same in every thread)
-  for (int p = 0; p < wn; ++p) {
-    const int s = sl[p];
-    double gpp;
+  while (p0 < wn) {
+    double gxx;
     if (na == 0) {
-      gpp = diagB[0][p];
+      gxx = xin ? diagB[0][lane] : 0.0;
     } else {
       const int bl = (na - 1) & 1;
-      gpp = fma(c_last * colp[bl][p], rowp[bl][p], diagB[bl][p]);
+      gxx = xin ? fma(c_last * colp[bl][lane], rowp[bl][lane], diagB[bl][lane]) : 0.0;
     }
-    const double delta = (s > 0 ? em2a : ep2a) - 1.0;
-    const double e2as = s > 0 ? ep2a : em2a;
-    const double R = 1.0 + delta * (1.0 - gpp);
-    const double ratio = e2as * R * R;
-    const bool a = forced ? (fl[p] != 0) : (ul[p] < ratio);
-    if (tid == 0) {
-      rl[p] = ratio;
-      al[p] = a ? 1 : 0;
+    const double Rx = 1.0 + delta_x * (1.0 - gxx);
+    const double ratio_x = e2as_x * Rx * Rx;
+    const bool ax = forced ? fx : (ux < ratio_x);
+    const unsigned long long hits = __ballot(xin && lane >= p0 && ax);
+    const int p = hits ? __builtin_ctzll(hits) : wn;
+    if (tid < 64 && lane >= p0 && lane <= p && xin) {
+      rl[lane] = ratio_x;
+      al[lane] = lane == p ? 1 : 0;
     }
-    if (!a) continue;
+    if (p >= wn) break;
+    p0 = p + 1;
+    const double R = lane_value(Rx, p);
+    const double delta = lane_value(delta_x, p);
     const double c = delta / R;
     const int n = na;
     const int b = n & 1;
@@ -258,6 +275,148 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     const int q = idx / na, n = idx % na;
     if (q <= n) Zg[q * W + n] = Zs[q][n];
     if (n <= q) Zpg[q * W + n] = Zps[q][n];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sequential decisions of one window of at most 32 sites in a single wave
+// (no barriers).  Accept n at site p adds u_n w_n^T to the window, with
+//   u_n = -c G~cur[:, p] = -c (G0[:, p] + sum_{r<n} u_r w_r[p]),
+//   w_n = e_p - G~cur[p, :] = e_p - G0[p, :] - sum_{r<n} u_r[p] w_r,
+// so lane x (site x of the window) rebuilds column and row p from G0 (LDS)
+// and the factors of the earlier accepts (a lane-private history in LDS),
+// and keeps only its own diagonal entry current.  Rejections leave G~cur
+// unchanged: all sites past the latest accept are tested at once against
+// that state and a ballot names the next accept (the sites before it are
+// rejections with the ratios a one-by-one scan computes).  Lanes 32 + q run
+// the same recursion for the coefficient row q of Z and column q of Z'
+// (u_n = sum_q G0[:, i_q] Z[q][n], w_n = sum_q Z'[n][q] h_q with
+// h_q = e_{i_q} - G0[i_q, :]):
+//   Z[q][n]  = -c (delta_qn + sum_{r<n} Z[q][r] w_r[p]),
+//   Z'[n][q] = delta_nq - sum_{r<n} u_r[p] Z'[r][q],
+// with the same remote values w_r[p], u_r[p] as the sites use.
+// ---------------------------------------------------------------------------
+template <typename T, int WM>
+__global__ void __launch_bounds__(64)
+k_decide_wave(const T* __restrict__ G, int N, const double* __restrict__ ev,
+              const double* __restrict__ evinv, int8_t* __restrict__ s_l,
+              const double* __restrict__ u, const uint8_t* __restrict__ forced,
+              uint8_t* __restrict__ acc_out, double* __restrict__ ratio_out, int w0, int wn, int W,
+              const double* __restrict__ Gs_in, const double* __restrict__ sc, int win,
+              int* __restrict__ win_a, int* __restrict__ win_p, double* __restrict__ Zg,
+              double* __restrict__ Zpg, size_t zs, size_t zn) {
+  static_assert(WM <= 32, "one wave holds the sites in lanes 0..31 and Z in lanes 32..63");
+  G = zw(G, zs);
+  ev = zw(ev, zs);
+  evinv = zw(evinv, zs);
+  s_l = zw(s_l, zs);
+  u = zc(u, zn);
+  forced = zc(forced, zn);
+  acc_out = zc(acc_out, zn);
+  ratio_out = zc(ratio_out, zn);
+  Gs_in = zw(Gs_in, zs);
+  win_a = zw(win_a, zs);
+  win_p = zw(win_p, zs);
+  Zg = zw(Zg, zs);
+  Zpg = zw(Zpg, zs);
+  const double em2a = zw(sc, zs)[SC_EM2A], ep2a = zw(sc, zs)[SC_EP2A];
+  __shared__ double g0s[WM][WM + 1];
+  __shared__ double2 hist[WM][64];  // hist[r][lane]: (u_r[x], w_r[x]) or (Z[q][r], Z'[r][q])
+  __shared__ double rl[WM];
+  __shared__ uint8_t al[WM];
+  __shared__ int pl[WM];
+  const int lane = threadIdx.x;
+  // window submatrix G0 (tilde frame): all loads issued before any is used
+  const bool site = lane < WM;
+  const bool xin = lane < wn;
+  const bool zlane = lane >= 32;  // coefficient lanes (q = lane - 32)
+  const int q = lane - 32;
+  const int xs = w0 + min(lane, wn - 1);
+  const int s_raw = s_l[xs];
+  const double u_raw = u ? u[xs] : 0.0;
+  const bool f_raw = forced ? forced[xs] != 0 : false;
+  // (addresses clamped into the window instead of branches, so that every
+  // load is in flight before the first wait)
+  constexpr int PER = (WM * WM + 63) / 64;
+  double gv[PER];
+  if (Gs_in) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int idx = lane + 64 * j;
+      const int x = min(idx / WM, wn - 1), y = min(idx % WM, wn - 1);
+      gv[j] = Gs_in[x * W + y];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int idx = lane + 64 * j;
+      const int gx = w0 + min(idx / WM, wn - 1), gy = w0 + min(idx % WM, wn - 1);
+      gv[j] = double(G[(size_t)gx * N + gy]) * ev[gx] * evinv[gy];
+    }
+  }
+  const int sx = xin ? s_raw : 1;
+  const double ux = xin ? u_raw : 0.0;
+  const bool fx = xin && f_raw;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int idx = lane + 64 * j;
+    const bool ok = idx / WM < wn && idx % WM < wn;
+    if (idx < WM * WM) g0s[idx / WM][idx % WM] = ok ? gv[j] : 0.0;
+  }
+  __syncthreads();
+  const double delta_x = (sx > 0 ? em2a : ep2a) - 1.0;
+  const double e2as_x = sx > 0 ? ep2a : em2a;
+  double diag = xin ? g0s[lane][lane] : 0.0;
+  int na = 0, p0 = 0;
+  while (p0 < wn) {
+    const double Rx = 1.0 + delta_x * (1.0 - diag);
+    const double ratio_x = e2as_x * Rx * Rx;
+    const bool ax = forced ? fx : (ux < ratio_x);
+    const unsigned long long hits = __ballot(xin && lane >= p0 && ax);
+    const int p = hits ? __builtin_ctzll(hits) : wn;
+    if (xin && lane >= p0 && lane <= p) {
+      rl[lane] = ratio_x;
+      al[lane] = lane == p ? 1 : 0;
+    }
+    if (p >= wn) break;
+    p0 = p + 1;
+    const double c = lane_value(delta_x, p) / lane_value(Rx, p);
+    const int n = na;
+    double A, B;
+    if (site) {
+      A = g0s[lane][p];
+      B = g0s[p][lane];
+    } else {  // coefficient lanes; lanes WM..31 (16-site windows) compute unused values
+      A = (q == n) ? 1.0 : 0.0;
+      B = 0.0;
+    }
+    for (int r = 0; r < n; ++r) {
+      const double2 own = hist[r][lane];
+      const double2 rem = hist[r][p];  // (u_r[p], w_r[p]), the same for every lane
+      A = fma(own.x, rem.y, A);
+      B = fma(rem.x, own.y, B);
+    }
+    const double Xn = -c * A;
+    const double Yn = ((site ? lane == p : q == n) ? 1.0 : 0.0) - B;
+    hist[n][lane] = make_double2(Xn, Yn);
+    if (site) diag = fma(Xn, Yn, diag);
+    if (lane == 0) pl[n] = p;
+    ++na;
+  }
+  __syncthreads();
+  if (lane == 0) win_a[win] = na;
+  for (int n = lane; n < na; n += 64) win_p[win * W + n] = pl[n];
+  if (xin) {
+    s_l[w0 + lane] = al[lane] ? int8_t(-sx) : int8_t(sx);
+    if (ratio_out) ratio_out[w0 + lane] = rl[lane];
+    if (acc_out) acc_out[w0 + lane] = al[lane];
+  }
+  if (zlane && q < na) {
+    for (int n = q; n < na; ++n) {
+      const double2 h = hist[n][lane];
+      Zg[q * W + n] = h.x;   // Z[q][n], q <= n
+      Zpg[n * W + q] = h.y;  // Z'[n][q], q <= n
+    }
   }
 }
 
@@ -540,12 +699,12 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
     // decide
     const int e_d = prof_mark(c);
     if (wn <= 16)
-      hipLaunchKernelGGL((k_decide<T, 1, 256>), dim3(1, 1, Z), dim3(256), 0, c->stream, G, N, c->ev,
+      hipLaunchKernelGGL((k_decide_wave<T, 16>), dim3(1, 1, Z), dim3(64), 0, c->stream, G, N, c->ev,
                          c->evinv, s_l, u, forced, acc, ratio, w0, wn, W,
                          first_in_group ? nullptr : c->Gs, c->sc, win, c->win_a, c->win_p, c->Xw,
                          c->Yw, zs, zn);
     else if (wn <= 32)
-      hipLaunchKernelGGL((k_decide<T, 2, 256>), dim3(1, 1, Z), dim3(256), 0, c->stream, G, N, c->ev,
+      hipLaunchKernelGGL((k_decide_wave<T, 32>), dim3(1, 1, Z), dim3(64), 0, c->stream, G, N, c->ev,
                          c->evinv, s_l, u, forced, acc, ratio, w0, wn, W,
                          first_in_group ? nullptr : c->Gs, c->sc, win, c->win_a, c->win_p, c->Xw,
                          c->Yw, zs, zn);
