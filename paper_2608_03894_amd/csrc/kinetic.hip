@@ -210,6 +210,123 @@ __device__ __forceinline__ void mix_stage(T* sre, T* sim, int P, const T* __rest
   }
 }
 
+// Loads of the tile, B items per thread in flight at a time: item indices
+// are clamped into range (an item past the end repeats the last item, whose
+// value it writes again to the same slot) and values of vectors past the
+// ragged tail replaced by zeros, so no branch separates one load from the next.  HE / HV: scale by pre_e[e] (element)
+// and pre_v[v] (vector) on the way in.
+constexpr int kWrapBatch = 16;
+
+template <typename T, int L, bool COLS, bool HE, bool HV>
+__device__ __forceinline__ void load_tile(const T* __restrict__ A, int lda, int P, int vbase,
+                                          int nreal, const double* __restrict__ pre_e,
+                                          const double* __restrict__ pre_v, T* sre, T* sim) {
+  constexpr int NS = 3 * L * L;
+  constexpr int B = kWrapBatch;
+  const int nt = blockDim.x;
+  if constexpr (COLS) {
+    // item (e, j): column vbase + j of row e; the 2P columns of a row are
+    // read by consecutive lanes (one contiguous segment per row)
+    const int w = 2 * P;
+    const int total = NS * w;
+    for (int base = threadIdx.x; base < total; base += B * nt) {
+      T x[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int idx = min(base + k * nt, total - 1);
+        const int j = idx % w, e = idx / w;
+        const int v = vbase + min(j, nreal - 1);
+        const T a = A[(size_t)e * lda + v];
+        T y = a;
+        if constexpr (HE || HV)
+          y = T(double(a) * (HE ? pre_e[e] : 1.0) * (HV ? pre_v[v] : 1.0));
+        x[k] = j < nreal ? y : T(0);
+      }
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int idx = min(base + k * nt, total - 1);
+        const int j = idx % w, e = idx / w;
+        ((j & 1) ? sim : sre)[slot_of<L>(e) * P + (j >> 1)] = x[k];
+      }
+    }
+  } else {
+    // item (r, e): element e of real vector r (contiguous in e)
+    const int total = NS * 2 * P;
+    for (int base = threadIdx.x; base < total; base += B * nt) {
+      T x[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int idx = min(base + k * nt, total - 1);
+        const int e = idx % NS, r = idx / NS;
+        const int v = vbase + min(r, nreal - 1);
+        const T a = A[(size_t)v * lda + e];
+        T y = a;
+        if constexpr (HE || HV)
+          y = T(double(a) * (HE ? pre_e[e] : 1.0) * (HV ? pre_v[v] : 1.0));
+        x[k] = r < nreal ? y : T(0);
+      }
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int idx = min(base + k * nt, total - 1);
+        const int e = idx % NS, r = idx / NS;
+        ((r & 1) ? sim : sre)[slot_of<L>(e) * P + (r >> 1)] = x[k];
+      }
+    }
+  }
+}
+
+// Stores of the tile (LDS reads batched ahead of the stores, clamped item
+// indices as in load_tile: a repeated last item stores the same value again);
+// HP: scale by post_e[e] on the way out.
+template <typename T, int L, bool COLS, bool HP>
+__device__ __forceinline__ void store_tile(T* __restrict__ A, int lda, int P, int vbase, int nreal,
+                                           const double* __restrict__ post_e, const T* sre,
+                                           const T* sim) {
+  constexpr int NS = 3 * L * L;
+  constexpr int B = kWrapBatch;
+  const int nt = blockDim.x;
+  if constexpr (COLS) {
+    const int w = 2 * P;
+    const int total = NS * w;
+    for (int base = threadIdx.x; base < total; base += B * nt) {
+      T x[B];
+      double se[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int idx = min(base + k * nt, total - 1);
+        const int j = idx % w, e = idx / w, so = slot_of<L>(e);
+        x[k] = (j & 1) ? sim[so * P + (j >> 1)] : sre[so * P + (j >> 1)];
+        se[k] = HP ? post_e[e] : 1.0;
+      }
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int idx = min(base + k * nt, total - 1);
+        const int j = idx % w, e = idx / w;
+        if (j < nreal) A[(size_t)e * lda + vbase + j] = HP ? T(double(x[k]) * se[k]) : x[k];
+      }
+    }
+  } else {
+    const int total = NS * 2 * P;
+    for (int base = threadIdx.x; base < total; base += B * nt) {
+      T x[B];
+      double se[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int idx = min(base + k * nt, total - 1);
+        const int e = idx % NS, r = idx / NS, so = slot_of<L>(e);
+        x[k] = (r & 1) ? sim[so * P + (r >> 1)] : sre[so * P + (r >> 1)];
+        se[k] = HP ? post_e[e] : 1.0;
+      }
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int idx = min(base + k * nt, total - 1);
+        const int e = idx % NS, r = idx / NS;
+        if (r < nreal) A[(size_t)(vbase + r) * lda + e] = HP ? T(double(x[k]) * se[k]) : x[k];
+      }
+    }
+  }
+}
+
 template <typename T, int L, bool COLS>
 __global__ void __launch_bounds__(512)
 k_kinetic(T* __restrict__ A, int lda, int P, const T* __restrict__ tab,
@@ -225,36 +342,25 @@ k_kinetic(T* __restrict__ A, int lda, int P, const T* __restrict__ tab,
   T* sre = reinterpret_cast<T*>(smem_raw);
   constexpr int NSP = NS + L;  // padded slots
   T* sim = sre + NSP * P;
-  const int vbase = 2 * blockIdx.x * P;      // first real vector of this workgroup
+  // Workgroups are dealt to the 8 XCDs in turn (by linear id, so by
+  // blockIdx.x % 8 within every chain); tile t is renumbered so that each XCD
+  // owns a contiguous range of vectors and the column pass's short row
+  // segments of neighbouring tiles meet in the same L2.
+  const int gx = gridDim.x, xk = blockIdx.x % 8, xq = gx / 8, xr = gx % 8;
+  const int tile = xk * xq + min(xk, xr) + blockIdx.x / 8;
+  const int vbase = 2 * tile * P;            // first real vector of this workgroup
   const int nreal = min(2 * P, NS - vbase);  // real vectors present (ragged tail)
 
-  // ---- load (with optional scaling) ----
-  if constexpr (COLS) {
-    for (int idx = threadIdx.x; idx < NS * P; idx += blockDim.x) {
-      const int c = idx % P, e = idx / P;
-      const int r0 = 2 * c, r1 = 2 * c + 1;
-      const double se = pre_e ? pre_e[e] : 1.0;
-      T x0 = T(0), x1 = T(0);
-      if (r0 < nreal) x0 = T(double(A[(size_t)e * lda + vbase + r0]) * se * (pre_v ? pre_v[vbase + r0] : 1.0));
-      if (r1 < nreal) x1 = T(double(A[(size_t)e * lda + vbase + r1]) * se * (pre_v ? pre_v[vbase + r1] : 1.0));
-      const int se_ = slot_of<L>(e);
-      sre[se_ * P + c] = x0;
-      sim[se_ * P + c] = x1;
-    }
+  if (pre_e) {
+    if (pre_v)
+      load_tile<T, L, COLS, true, true>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
+    else
+      load_tile<T, L, COLS, true, false>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
   } else {
-    for (int idx = threadIdx.x; idx < NS * 2 * P; idx += blockDim.x) {
-      const int e = idx % NS, r = idx / NS;
-      T x = T(0);
-      if (r < nreal) {
-        x = A[(size_t)(vbase + r) * lda + e];
-        if (pre_e || pre_v)
-          x = T(double(x) * (pre_e ? pre_e[e] : 1.0) * (pre_v ? pre_v[vbase + r] : 1.0));
-      }
-      if (r & 1)
-        sim[slot_of<L>(e) * P + (r >> 1)] = x;
-      else
-        sre[slot_of<L>(e) * P + (r >> 1)] = x;
-    }
+    if (pre_v)
+      load_tile<T, L, COLS, false, true>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
+    else
+      load_tile<T, L, COLS, false, false>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
   }
   __syncthreads();
   fft_stage<T, L, 2, -1>(sre, sim, P);
@@ -267,27 +373,10 @@ k_kinetic(T* __restrict__ A, int lda, int P, const T* __restrict__ tab,
   __syncthreads();
   fft_stage<T, L, 2, +1>(sre, sim, P);
   __syncthreads();
-  // ---- store ----
-  if constexpr (COLS) {
-    for (int idx = threadIdx.x; idx < NS * P; idx += blockDim.x) {
-      const int c = idx % P, e = idx / P;
-      const int r0 = 2 * c, r1 = 2 * c + 1;
-      const double se = post_e ? post_e[e] : 1.0;
-      const int so = slot_of<L>(e);
-      if (r0 < nreal) A[(size_t)e * lda + vbase + r0] = T(double(sre[so * P + c]) * se);
-      if (r1 < nreal) A[(size_t)e * lda + vbase + r1] = T(double(sim[so * P + c]) * se);
-    }
-  } else {
-    for (int idx = threadIdx.x; idx < NS * 2 * P; idx += blockDim.x) {
-      const int e = idx % NS, r = idx / NS;
-      if (r < nreal) {
-        const int so = slot_of<L>(e);
-        T x = (r & 1) ? sim[so * P + (r >> 1)] : sre[so * P + (r >> 1)];
-        if (post_e) x = T(double(x) * post_e[e]);
-        A[(size_t)(vbase + r) * lda + e] = x;
-      }
-    }
-  }
+  if (post_e)
+    store_tile<T, L, COLS, true>(A, lda, P, vbase, nreal, post_e, sre, sim);
+  else
+    store_tile<T, L, COLS, false>(A, lda, P, vbase, nreal, post_e, sre, sim);
 }
 
 namespace {
