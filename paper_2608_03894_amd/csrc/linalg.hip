@@ -103,7 +103,7 @@ int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, 
 // ---------------------------------------------------------------------------
 // Householder QR, blocked (compact WY form).
 //
-// Panels of width nbp (32 while the panel has at most 1024 rows, else 16) are
+// Panels of width nbp (16 up to 512 rows, 32 up to 1024 rows, else 16) are
 // factored by one workgroup of NT = 256, 512 or 1024 threads holding the
 // panel in registers (thread t owns rows j+t and j+t+NT).  H_c = I - tau_c v_c v_c^T with
 // v_c[jc] = 1 (LAPACK convention); H_0 ... H_{nbp-1} = I - V T V^T.
@@ -572,7 +572,10 @@ namespace {
 // Panel width: 32 columns while the panel has at most 1024 rows, else 16
 // (two rows per thread in registers; measured against 16-column panels and
 // four rows per thread: within 1 % at N = 432, 972 and 1728, this choice best).
-inline int panel_width(int rows) { return rows > 1024 ? 16 : 32; }
+// Width 16 at most 512 rows (the per-column reduction and update of a panel
+// scale with its width, and there the extra WY applies are cheap), 32 up to
+// 1024 rows, 16 beyond (registers).
+inline int panel_width(int rows) { return rows <= 512 ? 16 : rows <= 1024 ? 32 : 16; }
 
 int launch_panel(kdqmc_ctx* c, double* A, int ld, int n, int j, int nbp, double* Tp) {
   const int m = n - j;
@@ -581,7 +584,7 @@ int launch_panel(kdqmc_ctx* c, double* A, int ld, int n, int j, int nbp, double*
   hipLaunchKernelGGL((k_qr_panel<RPT, NB, NT>), dim3(1, 1, c->nch), dim3(NT), 0, c->stream, A, ld, n, j, \
                      nbp, c->Vq, Tp, c->tau, c->zs)
   // the panel's rows must fit in RPT * NT and its width in NB (panel_width)
-  if (m <= 512) PANEL(2, 32, 256);
+  if (m <= 512) PANEL(2, 16, 256);
   else if (m <= 1024) PANEL(2, 32, 512);
   else PANEL(2, 16, 1024);
 #undef PANEL
