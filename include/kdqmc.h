@@ -72,7 +72,7 @@ typedef struct {
   double dtau;    /* imaginary-time step */
   int n_stab;     /* slices between stabilizations; must divide L_tau */
   int delay_k;    /* largest rank of one delayed flush, 1..512 */
-  int window;     /* sites per decision window, 0 = min(delay_k, 64) */
+  int window;     /* sites per decision window (at most 64), 0 = min(delay_k, 32) */
   int fft_tile;   /* complex vectors per wrap workgroup, 0 = automatic */
   int prec;       /* kdqmc_prec */
 } kdqmc_params;

@@ -51,7 +51,7 @@ int derive(const kdqmc_params* p, Derived* d, int nch = 1) {
   if (p->delay_k < 1 || p->delay_k > 512) return set_error(KDQMC_EINVAL, "delay_k must be in 1..512");
   if (p->prec != KDQMC_FP64 && p->prec != KDQMC_MIXED_F16 && p->prec != KDQMC_MIXED_BF16)
     return set_error(KDQMC_EINVAL, "unknown precision");
-  int w = p->window > 0 ? p->window : std::min(p->delay_k, 64);
+  int w = p->window > 0 ? p->window : std::min(p->delay_k, 32);
   if (w > 64) return set_error(KDQMC_EINVAL, "window above 64");
   if (w > p->delay_k) return set_error(KDQMC_EINVAL, "window larger than delay_k");
   d->N = 3 * p->L * p->L;
@@ -95,8 +95,10 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   char* Wp = take((size_t)d.kmax * N * es);
   char* win_a = take((size_t)d.nw * 4);
   char* win_p = take((size_t)d.nw * d.w * 4);
-  char* Zg = take((size_t)d.w * d.w * 8);
-  char* Zpg = take((size_t)d.w * d.w * 8);
+  char* Zg = take(2 * (size_t)d.w * d.w * 8);
+  char* Zpg = take(2 * (size_t)d.w * d.w * 8);
+  char* snapc = take(2 * N * d.w * 8);
+  char* snapr = take(2 * N * d.w * 8);
   char* Gs = take((size_t)d.w * d.w * 8);
   char* flag = take(64);
   char* err = take(1024 * 8);
@@ -130,6 +132,8 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
     c->win_p = (int*)win_p;
     c->Xw = (double*)Zg;
     c->Yw = (double*)Zpg;
+    c->snapc = (double*)snapc;
+    c->snapr = (double*)snapr;
     c->Gs = (double*)Gs;
     c->flag = (int*)flag;
     c->err = (double*)err;
@@ -265,6 +269,7 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
   c->w = d.w;
   c->nw = d.nw;
   c->F = d.F;
+  c->fused = d.fp64 && d.F == 1 && d.w <= 32 && (64 % d.w == 0 || d.nw == 1);
   c->kmax = d.kmax;
   c->P = d.P;
   c->P64 = d.P64;

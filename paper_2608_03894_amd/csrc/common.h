@@ -205,8 +205,11 @@ struct kdqmc_ctx {
   int* win_a = nullptr;        // nw: accepted count per window
   int* win_p = nullptr;        // nw*w: window-local positions of the accepts
   double* win_c = nullptr;     // nw*w: Delta/R of the accepts
-  double* Xw = nullptr;        // w*w: -Gs[p_n][q] at the time of accept n
-  double* Yw = nullptr;        // w*w: -c_n Gs[q][p_n] at the time of accept n
+  double* Xw = nullptr;        // 2*w*w: Z of a window (two buffers by window parity)
+  double* Yw = nullptr;        // 2*w*w: Z' of a window
+  double* snapc = nullptr;     // 2*N*w: G[:, S] of a window (fused schedule, by parity)
+  double* snapr = nullptr;     // 2*w*N: G[S, :] of a window
+  bool fused = false;          // FP64, one window per flush, windows inside 64 x 64 tiles
   double* Gs = nullptr;        // w*w: G~cur[S,S] of the next window
   int* flag = nullptr;         // small device status words
   double* err = nullptr;       // reduction scratch

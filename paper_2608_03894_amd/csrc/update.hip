@@ -296,16 +296,137 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
 //   Z'[n][q] = delta_nq - sum_{r<n} u_r[p] Z'[r][q],
 // with the same remote values w_r[p], u_r[p] as the sites use.
 // ---------------------------------------------------------------------------
-template <typename T, int WM>
-__global__ void __launch_bounds__(64)
-k_decide_wave(const T* __restrict__ G, int N, const double* __restrict__ ev,
-              const double* __restrict__ evinv, int8_t* __restrict__ s_l,
-              const double* __restrict__ u, const uint8_t* __restrict__ forced,
-              uint8_t* __restrict__ acc_out, double* __restrict__ ratio_out, int w0, int wn, int W,
-              const double* __restrict__ Gs_in, const double* __restrict__ sc, int win,
-              int* __restrict__ win_a, int* __restrict__ win_p, double* __restrict__ Zg,
-              double* __restrict__ Zpg, size_t zs, size_t zn) {
+// Wave-level ordering of LDS accesses (one wave runs the decisions; its LDS
+// operations complete in order, the fence keeps the compiler from moving
+// them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// The decisions of one window whose submatrix G0 (tilde frame, zero outside
+// wn x wn) is in g0s, run by the calling wave alone.  sx, ux, fx: field,
+// uniform and forced flag of site `lane` (lanes < wn).  Writes the flipped
+// fields, the accept flags and ratios, win_a[win], win_p and Z, Z'.
+template <int WM>
+__device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, int win,
+                                              double (*g0s)[WM + 1], double2 (*hist)[64], int sx,
+                                              double ux, bool fx, bool use_forced, double em2a,
+                                              double ep2a,
+                                              int8_t* __restrict__ s_l, uint8_t* __restrict__ acc_out,
+                                              double* __restrict__ ratio_out, int* __restrict__ win_a,
+                                              int* __restrict__ win_p, double* __restrict__ Zg,
+                                              double* __restrict__ Zpg) {
   static_assert(WM <= 32, "one wave holds the sites in lanes 0..31 and Z in lanes 32..63");
+  static_assert(WM % 8 == 0, "history rows are read in blocks of 8");
+  const bool site = lane < WM;
+  const bool xin = lane < wn;
+  const bool zlane = lane >= 32;  // coefficient lanes (q = lane - 32)
+  const int q = lane - 32;
+  const double delta_x = (sx > 0 ? em2a : ep2a) - 1.0;
+  const double e2as_x = sx > 0 ? ep2a : em2a;
+  double diag = xin ? g0s[lane][lane] : 0.0;
+  // history rows not yet written hold zeros, so the dot products below run
+  // over whole blocks of 8 rows without tests (a zero row adds exactly 0)
+#pragma unroll
+  for (int r = 0; r < WM; ++r) hist[r][lane] = make_double2(0.0, 0.0);
+  wave_sync();
+  // the ratio and decision of site `lane` and the position of accept number
+  // `lane` stay in registers until the end (no LDS traffic but the history)
+  double my_ratio = 0.0;
+  bool my_acc = false;
+  int my_pos = 0;
+  int na = 0, p0 = 0;
+  while (p0 < wn) {
+    const double Rx = 1.0 + delta_x * (1.0 - diag);
+    double cx = delta_x / Rx;  // c of every candidate, off the ballot's path
+    const double ratio_x = e2as_x * Rx * Rx;
+    const bool ax = use_forced ? fx : (ux < ratio_x);
+    const unsigned long long hits = __ballot(xin && lane >= p0 && ax);
+    asm volatile("" : "+v"(cx));  // (the division is issued before the branch below)
+    const int p = hits ? __builtin_ctzll(hits) : wn;
+    if (lane >= p0 && lane <= p) {
+      my_ratio = ratio_x;
+      my_acc = lane == p;
+    }
+    if (p >= wn) break;
+    p0 = p + 1;
+    const double c = lane_value(cx, p);
+    const int n = na;
+    if (lane == n) my_pos = p;
+    double A, B;
+    if (site) {
+      A = g0s[lane][p];
+      B = g0s[p][lane];
+    } else {  // coefficient lanes; lanes WM..31 (16-site windows) compute unused values
+      A = (q == n) ? 1.0 : 0.0;
+      B = 0.0;
+    }
+    // blocks of 8 history rows read at once (rows n.. of the last block are zero)
+    for (int r0 = 0; r0 < n; r0 += 8) {
+      double2 own[8], rem[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        own[j] = hist[r0 + j][lane];
+        rem[j] = hist[r0 + j][p];  // (u_r[p], w_r[p]), the same for every lane
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        A = fma(own[j].x, rem[j].y, A);
+        B = fma(rem[j].x, own[j].y, B);
+      }
+    }
+    const double Xn = -c * A;
+    const double Yn = ((site ? lane == p : q == n) ? 1.0 : 0.0) - B;
+    hist[n][lane] = make_double2(Xn, Yn);
+    if (site) diag = fma(Xn, Yn, diag);
+    ++na;
+  }
+  wave_sync();
+  if (lane == 0) win_a[win] = na;
+  if (lane < na) win_p[win * W + lane] = my_pos;
+  if (xin) {
+    s_l[w0 + lane] = my_acc ? int8_t(-sx) : int8_t(sx);
+    if (ratio_out) ratio_out[w0 + lane] = my_ratio;
+    if (acc_out) acc_out[w0 + lane] = my_acc ? 1 : 0;
+  }
+  if (zlane && q < na) {
+    for (int n = q; n < na; ++n) {
+      const double2 h = hist[n][lane];
+      Zg[q * W + n] = h.x;   // Z[q][n], q <= n
+      Zpg[n * W + q] = h.y;  // Z'[n][q], q <= n
+    }
+  }
+}
+
+// Field, uniform and forced flag of site `lane` of the window at w0 (loads
+// clamped into the window; lanes >= wn get neutral values).
+__device__ __forceinline__ void site_inputs(int lane, int w0, int wn, const int8_t* __restrict__ s_l,
+                                            const double* __restrict__ u,
+                                            const uint8_t* __restrict__ forced, int& sx, double& ux,
+                                            bool& fx) {
+  const int xs = w0 + min(lane, wn - 1);
+  const int s_raw = s_l[xs];
+  const double u_raw = u ? u[xs] : 0.0;
+  const bool f_raw = forced ? forced[xs] != 0 : false;
+  const bool xin = lane < wn;
+  sx = xin ? s_raw : 1;
+  ux = xin ? u_raw : 0.0;
+  fx = xin && f_raw;
+}
+
+// Loads the window submatrix (from G, or from the prepared Gs_in) and runs
+// its decisions in the calling wave (64 threads).
+template <typename T, int WM>
+__device__ __forceinline__ void
+decide_wave_body(const T* __restrict__ G, int N, const double* __restrict__ ev,
+                 const double* __restrict__ evinv, int8_t* __restrict__ s_l,
+                 const double* __restrict__ u, const uint8_t* __restrict__ forced,
+                 uint8_t* __restrict__ acc_out, double* __restrict__ ratio_out, int w0, int wn, int W,
+                 const double* __restrict__ Gs_in, const double* __restrict__ sc, int win,
+                 int* __restrict__ win_a, int* __restrict__ win_p, double* __restrict__ Zg,
+                 double* __restrict__ Zpg, size_t zs, size_t zn) {
   G = zw(G, zs);
   ev = zw(ev, zs);
   evinv = zw(evinv, zs);
@@ -322,21 +443,13 @@ k_decide_wave(const T* __restrict__ G, int N, const double* __restrict__ ev,
   const double em2a = zw(sc, zs)[SC_EM2A], ep2a = zw(sc, zs)[SC_EP2A];
   __shared__ double g0s[WM][WM + 1];
   __shared__ double2 hist[WM][64];  // hist[r][lane]: (u_r[x], w_r[x]) or (Z[q][r], Z'[r][q])
-  __shared__ double rl[WM];
-  __shared__ uint8_t al[WM];
-  __shared__ int pl[WM];
   const int lane = threadIdx.x;
+  int sx;
+  double ux;
+  bool fx;
+  site_inputs(lane, w0, wn, s_l, u, forced, sx, ux, fx);
   // window submatrix G0 (tilde frame): all loads issued before any is used
-  const bool site = lane < WM;
-  const bool xin = lane < wn;
-  const bool zlane = lane >= 32;  // coefficient lanes (q = lane - 32)
-  const int q = lane - 32;
-  const int xs = w0 + min(lane, wn - 1);
-  const int s_raw = s_l[xs];
-  const double u_raw = u ? u[xs] : 0.0;
-  const bool f_raw = forced ? forced[xs] != 0 : false;
-  // (addresses clamped into the window instead of branches, so that every
-  // load is in flight before the first wait)
+  // (addresses clamped into the window instead of branches)
   constexpr int PER = (WM * WM + 63) / 64;
   double gv[PER];
   if (Gs_in) {
@@ -354,70 +467,271 @@ k_decide_wave(const T* __restrict__ G, int N, const double* __restrict__ ev,
       gv[j] = double(G[(size_t)gx * N + gy]) * ev[gx] * evinv[gy];
     }
   }
-  const int sx = xin ? s_raw : 1;
-  const double ux = xin ? u_raw : 0.0;
-  const bool fx = xin && f_raw;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     const int idx = lane + 64 * j;
     const bool ok = idx / WM < wn && idx % WM < wn;
     if (idx < WM * WM) g0s[idx / WM][idx % WM] = ok ? gv[j] : 0.0;
   }
+  wave_sync();
+  decide_window<WM>(lane, wn, w0, W, win, g0s, hist, sx, ux, fx, forced != nullptr, em2a, ep2a, s_l,
+                    acc_out, ratio_out, win_a, win_p, Zg, Zpg);
+}
+
+template <typename T, int WM>
+__global__ void __launch_bounds__(64)
+k_decide_wave(const T* __restrict__ G, int N, const double* __restrict__ ev,
+              const double* __restrict__ evinv, int8_t* __restrict__ s_l,
+              const double* __restrict__ u, const uint8_t* __restrict__ forced,
+              uint8_t* __restrict__ acc_out, double* __restrict__ ratio_out, int w0, int wn, int W,
+              const double* __restrict__ Gs_in, const double* __restrict__ sc, int win,
+              int* __restrict__ win_a, int* __restrict__ win_p, double* __restrict__ Zg,
+              double* __restrict__ Zpg, size_t zs, size_t zn) {
+  decide_wave_body<T, WM>(G, N, ev, evinv, s_l, u, forced, acc_out, ratio_out, w0, wn, W, Gs_in, sc,
+                          win, win_a, win_p, Zg, Zpg, zs, zn);
+}
+
+// ---------------------------------------------------------------------------
+// Fused schedule (FP64, a flush after every window, windows of at most 32
+// sites that never straddle a 64 x 64 tile).  Per slice: k_window_start runs
+// the decisions of window 0 (workgroup 0) and copies window 0's columns
+// G[:, S] and rows G[S, :] into the snapshot buffers (the other workgroups);
+// then per window one k_flush_decide:
+//   * every 64 x 64 tile (R, C) forms its own rows of the window's new
+//     factors, U[R, n] = sum_{q<=n} G~[R, i_q] Z[q][n] and
+//     W[n, C] = sum_{q<=n} Z'[n][q] (e_{i_q} - G~[i_q, C]), from the
+//     snapshots (other tiles update G[R, S] and G[S, C] in the same launch)
+//     in the same arithmetic as k_extend, and adds U W to its tile in the
+//     MFMA order of k_flush_f64;
+//   * the tiles crossing the next window's columns / rows copy them into the
+//     other snapshot buffer;
+//   * the tile holding the next window's diagonal block runs that window's
+//     decisions on its freshly updated block (one wave), writing Z, Z' to
+//     the other coefficient buffer.
+// Snapshots and coefficients alternate between two buffers by window parity.
+// ---------------------------------------------------------------------------
+template <int WM>
+__global__ void __launch_bounds__(64)
+k_window_start(const double* __restrict__ G, int N, const double* __restrict__ ev,
+               const double* __restrict__ evinv, int8_t* __restrict__ s_l,
+               const double* __restrict__ u, const uint8_t* __restrict__ forced,
+               uint8_t* __restrict__ acc_out, double* __restrict__ ratio_out, int wn, int W,
+               const double* __restrict__ sc, int* __restrict__ win_a, int* __restrict__ win_p,
+               double* __restrict__ Zg, double* __restrict__ Zpg, double* __restrict__ csn,
+               double* __restrict__ rsn, size_t zs, size_t zn) {
+  if (blockIdx.x == 0) {
+    decide_wave_body<double, WM>(G, N, ev, evinv, s_l, u, forced, acc_out, ratio_out, 0, wn, W,
+                                 nullptr, sc, 0, win_a, win_p, Zg, Zpg, zs, zn);
+    return;
+  }
+  G = zw(G, zs);
+  csn = zw(csn, zs);
+  rsn = zw(rsn, zs);
+  // column snapshot csn[r][y] = G[r][y], row snapshot rsn[x][c] = G[x][c]
+  // (x, y < wn): 8 elements per thread, loads before stores
+  constexpr int B = 8;
+  const int nc = N * wn, total = 2 * nc;
+  const int base = (blockIdx.x - 1) * 64 * B + threadIdx.x;
+  double v[B];
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    const int e = min(base + 64 * k, total - 1);
+    const size_t off = e < nc ? (size_t)(e / wn) * N + e % wn : (size_t)((e - nc) / N) * N + (e - nc) % N;
+    v[k] = G[off];
+  }
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    const int e = base + 64 * k;
+    if (e < nc)
+      csn[(size_t)(e / wn) * W + e % wn] = v[k];
+    else if (e < total)
+      rsn[(size_t)((e - nc) / N) * N + (e - nc) % N] = v[k];
+  }
+}
+
+template <int WM>
+__global__ void __launch_bounds__(256)
+k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
+               const double* __restrict__ evinv, int8_t* __restrict__ s_l,
+               const double* __restrict__ u, const uint8_t* __restrict__ forced,
+               uint8_t* __restrict__ acc_out, double* __restrict__ ratio_out,
+               const double* __restrict__ sc, int win, int W, int nw, int* __restrict__ win_a,
+               int* __restrict__ win_p, const double* __restrict__ Zc, const double* __restrict__ Zpc,
+               double* __restrict__ Zn, double* __restrict__ Zpn, const double* __restrict__ csc,
+               const double* __restrict__ rsc, double* __restrict__ csn, double* __restrict__ rsn,
+               size_t zs, size_t zn) {
+  G = zw(G, zs);
+  ev = zw(ev, zs);
+  evinv = zw(evinv, zs);
+  s_l = zw(s_l, zs);
+  u = zc(u, zn);
+  forced = zc(forced, zn);
+  acc_out = zc(acc_out, zn);
+  ratio_out = zc(ratio_out, zn);
+  win_a = zw(win_a, zs);
+  win_p = zw(win_p, zs);
+  Zc = zw(Zc, zs);
+  Zpc = zw(Zpc, zs);
+  Zn = zw(Zn, zs);
+  Zpn = zw(Zpn, zs);
+  csc = zw(csc, zs);
+  rsc = zw(rsc, zs);
+  csn = zw(csn, zs);
+  rsn = zw(rsn, zs);
+  // LDS: Zs, Zps (WM x (WM+1) each); R2 = gl [64][WM+1], later Ul [WM][64];
+  // R3 = hl [WM][65], later Wl [WM][64].  The decisions reuse Zs (window
+  // block) and R2..R3 (history).
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* lds = reinterpret_cast<double*>(smem_raw);
+  double(*Zs)[WM + 1] = reinterpret_cast<double(*)[WM + 1]>(lds);
+  double(*Zps)[WM + 1] = reinterpret_cast<double(*)[WM + 1]>(lds + WM * (WM + 1));
+  double* R2 = lds + 2 * WM * (WM + 1);
+  double* R3 = R2 + 64 * (WM + 1);
+  __shared__ int il[WM];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int R0 = blockIdx.y * 64, C0 = blockIdx.x * 64;
+  const int row0 = R0 + (wave >> 1) * 32, col0 = C0 + (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int w0 = win * W;
+  const int a = win_a[win];
+  const bool has_next = win + 1 < nw;
+  const int w1 = (win + 1) * W;
+  const int wn1 = has_next ? min(W, N - w1) : 0;
+  const bool diag_wg = has_next && (w1 >> 6) == (int)blockIdx.x && (w1 >> 6) == (int)blockIdx.y;
+  // the G tile (clamped loads, in flight during the factor work)
+  v4d acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = min(row0 + 16 * bi + lk + 4 * j, N - 1), cc = min(col0 + 16 * bj + lr, N - 1);
+        acc[bi][bj][j] = G[(size_t)r * N + cc];
+      }
+  int sx = 1;
+  double ux = 0.0;
+  bool fx = false;
+  if (diag_wg && wave == 0) site_inputs(lane, w1, wn1, s_l, u, forced, sx, ux, fx);
+  if (a > 0) {
+    for (int idx = tid; idx < a * a; idx += 256) {
+      const int q = idx / a, n = idx % a;
+      Zs[q][n] = Zc[q * W + n];
+      Zps[q][n] = Zpc[q * W + n];
+    }
+    for (int n = tid; n < a; n += 256) il[n] = w0 + win_p[win * W + n];
+    __syncthreads();
+    double(*gl)[WM + 1] = reinterpret_cast<double(*)[WM + 1]>(R2);
+    double(*hl)[65] = reinterpret_cast<double(*)[65]>(R3);
+    for (int idx = tid; idx < 64 * a; idx += 256) {
+      const int rr = idx / a, q = idx % a;
+      const int r = R0 + rr, i = il[q];
+      gl[rr][q] = r < N ? csc[(size_t)r * W + (i - w0)] * ev[r] * evinv[i] : 0.0;
+    }
+    for (int idx = tid; idx < a * 64; idx += 256) {
+      const int q = idx / 64, cc = idx % 64;
+      const int cg = C0 + cc, i = il[q];
+      hl[q][cc] = cg < N ? ((cg == i) ? 1.0 : 0.0) - rsc[(size_t)(i - w0) * N + cg] * ev[i] * evinv[cg] : 0.0;
+    }
+    __syncthreads();
+    // thread (lane, wave): row / column lane of the tile, factors n = wave + 4 k2;
+    // its row of gl and column of hl are read once into registers
+    constexpr int PERU = WM / 4;
+    double gr[WM], hr[WM];
+#pragma unroll
+    for (int q = 0; q < WM; ++q) {
+      gr[q] = gl[lane][q];
+      hr[q] = hl[q][lane];
+    }
+    double uvals[PERU], wvals[PERU];
+#pragma unroll
+    for (int k2 = 0; k2 < PERU; ++k2) {
+      const int n = wave + 4 * k2;
+      double uv = 0.0, wv = 0.0;
+#pragma unroll
+      for (int q = 0; q < WM; ++q) {
+        if (q <= n) {
+          uv += gr[q] * Zs[q][n];
+          wv += Zps[n][q] * hr[q];
+        }
+      }
+      uvals[k2] = R0 + lane < N ? uv * evinv[R0 + lane] : 0.0;
+      wvals[k2] = C0 + lane < N ? wv * ev[C0 + lane] : 0.0;
+    }
+    __syncthreads();
+    double(*Ul)[64] = reinterpret_cast<double(*)[64]>(R2);
+    double(*Wl)[64] = reinterpret_cast<double(*)[64]>(R3);
+#pragma unroll
+    for (int k2 = 0; k2 < PERU; ++k2) {
+      const int n = wave + 4 * k2;
+      if (n < a) {
+        Ul[n][lane] = uvals[k2];
+        Wl[n][lane] = wvals[k2];
+      }
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < a; k0 += 4) {
+      const int k = k0 + lk;
+      double av[2], bv[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        av[bi] = k < a ? Ul[k < a ? k : 0][row0 - R0 + 16 * bi + lr] : 0.0;
+        bv[bi] = k < a ? Wl[k < a ? k : 0][col0 - C0 + 16 * bi + lr] : 0.0;
+      }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
+          if (r < N && cc < N) G[(size_t)r * N + cc] = acc[bi][bj][j];
+        }
+  }
+  if (has_next) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
+          if (r < N && cc < N) {
+            if (cc >= w1 && cc < w1 + wn1) csn[(size_t)r * W + (cc - w1)] = acc[bi][bj][j];
+            if (r >= w1 && r < w1 + wn1) rsn[(size_t)(r - w1) * N + cc] = acc[bi][bj][j];
+          }
+        }
+  }
+  if (!diag_wg) return;  // uniform over the workgroup
+  __syncthreads();       // the factor buffers are free again
+  for (int idx = tid; idx < WM * (WM + 1); idx += 256) lds[idx] = 0.0;
   __syncthreads();
-  const double delta_x = (sx > 0 ? em2a : ep2a) - 1.0;
-  const double e2as_x = sx > 0 ? ep2a : em2a;
-  double diag = xin ? g0s[lane][lane] : 0.0;
-  int na = 0, p0 = 0;
-  while (p0 < wn) {
-    const double Rx = 1.0 + delta_x * (1.0 - diag);
-    const double ratio_x = e2as_x * Rx * Rx;
-    const bool ax = forced ? fx : (ux < ratio_x);
-    const unsigned long long hits = __ballot(xin && lane >= p0 && ax);
-    const int p = hits ? __builtin_ctzll(hits) : wn;
-    if (xin && lane >= p0 && lane <= p) {
-      rl[lane] = ratio_x;
-      al[lane] = lane == p ? 1 : 0;
-    }
-    if (p >= wn) break;
-    p0 = p + 1;
-    const double c = lane_value(delta_x, p) / lane_value(Rx, p);
-    const int n = na;
-    double A, B;
-    if (site) {
-      A = g0s[lane][p];
-      B = g0s[p][lane];
-    } else {  // coefficient lanes; lanes WM..31 (16-site windows) compute unused values
-      A = (q == n) ? 1.0 : 0.0;
-      B = 0.0;
-    }
-    for (int r = 0; r < n; ++r) {
-      const double2 own = hist[r][lane];
-      const double2 rem = hist[r][p];  // (u_r[p], w_r[p]), the same for every lane
-      A = fma(own.x, rem.y, A);
-      B = fma(rem.x, own.y, B);
-    }
-    const double Xn = -c * A;
-    const double Yn = ((site ? lane == p : q == n) ? 1.0 : 0.0) - B;
-    hist[n][lane] = make_double2(Xn, Yn);
-    if (site) diag = fma(Xn, Yn, diag);
-    if (lane == 0) pl[n] = p;
-    ++na;
-  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
+        if (r >= w1 && r < w1 + wn1 && cc >= w1 && cc < w1 + wn1)
+          Zs[r - w1][cc - w1] = acc[bi][bj][j] * ev[r] * evinv[cc];
+      }
   __syncthreads();
-  if (lane == 0) win_a[win] = na;
-  for (int n = lane; n < na; n += 64) win_p[win * W + n] = pl[n];
-  if (xin) {
-    s_l[w0 + lane] = al[lane] ? int8_t(-sx) : int8_t(sx);
-    if (ratio_out) ratio_out[w0 + lane] = rl[lane];
-    if (acc_out) acc_out[w0 + lane] = al[lane];
-  }
-  if (zlane && q < na) {
-    for (int n = q; n < na; ++n) {
-      const double2 h = hist[n][lane];
-      Zg[q * W + n] = h.x;   // Z[q][n], q <= n
-      Zpg[n * W + q] = h.y;  // Z'[n][q], q <= n
-    }
-  }
+  if (wave != 0) return;
+  const double em2a = zw(sc, zs)[SC_EM2A], ep2a = zw(sc, zs)[SC_EP2A];
+  decide_window<WM>(lane, wn1, w1, W, win + 1, Zs, reinterpret_cast<double2(*)[64]>(R2), sx, ux, fx,
+                    forced != nullptr, em2a, ep2a, s_l, acc_out, ratio_out, win_a, win_p, Zn, Zpn);
+}
+
+template <int WM>
+constexpr size_t flush_decide_lds() {
+  return size_t(2 * WM * (WM + 1) + 64 * (WM + 1) + WM * 65) * 8;
 }
 
 // ---------------------------------------------------------------------------
@@ -680,9 +994,48 @@ int set_lds_limits() {
   return KDQMC_OK;
 }
 
+// The fused schedule of one slice (see k_flush_decide): 1 + nw launches.
+template <int WM>
+int fused_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, uint8_t* acc,
+                  double* ratio, size_t zn) {
+  const int N = c->N, W = c->w;
+  double* G = static_cast<double*>(c->G);
+  int8_t* s_l = c->fields + (size_t)(l - 1) * N;
+  const unsigned Z = (unsigned)c->nch;
+  const size_t zs = c->zs;
+  const size_t ww = (size_t)W * W, nwv = (size_t)N * W;
+  const int wn0 = std::min(W, N);
+  const int nsnap = (2 * N * wn0 + 64 * 8 - 1) / (64 * 8);
+  const int e0 = prof_mark(c);
+  hipLaunchKernelGGL((k_window_start<WM>), dim3(1 + nsnap, 1, Z), dim3(64), 0, c->stream, G, N, c->ev,
+                     c->evinv, s_l, u, forced, acc, ratio, wn0, W, c->sc, c->win_a, c->win_p, c->Xw,
+                     c->Yw, c->snapc, c->snapr, zs, zn);
+  int e1 = prof_mark(c);
+  prof_pair(c, PH_DECIDE, e0, e1);
+  const dim3 grid((N + 63) / 64, (N + 63) / 64, Z);
+  for (int win = 0; win < c->nw; ++win) {
+    const size_t cur = win & 1, nxt = cur ^ 1;
+    hipLaunchKernelGGL((k_flush_decide<WM>), grid, dim3(256), flush_decide_lds<WM>(), c->stream, G, N,
+                       c->ev, c->evinv, s_l, u, forced, acc, ratio, c->sc, win, W, c->nw, c->win_a,
+                       c->win_p, c->Xw + cur * ww, c->Yw + cur * ww, c->Xw + nxt * ww, c->Yw + nxt * ww,
+                       c->snapc + cur * nwv, c->snapr + cur * nwv, c->snapc + nxt * nwv,
+                       c->snapr + nxt * nwv, zs, zn);
+    const int e2 = prof_mark(c);
+    prof_pair(c, PH_FLUSH, e1, e2);
+    e1 = e2;
+  }
+  KDQMC_HIP(hipGetLastError());
+  return KDQMC_OK;
+}
+
 template <typename T>
 int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, uint8_t* acc,
                   double* ratio, size_t zn) {
+  if constexpr (sizeof(T) == 8) {
+    if (c->fused)
+      return c->w <= 16 ? fused_updates<16>(c, l, u, forced, acc, ratio, zn)
+                        : fused_updates<32>(c, l, u, forced, acc, ratio, zn);
+  }
   const int N = c->N, W = c->w;
   T* G = static_cast<T*>(c->G);
   T* Up = static_cast<T*>(c->Upend);
