@@ -79,13 +79,18 @@ def cpu_baseline(w, n_slices):
 CU_FP64_TFS = FP64_PEAK_TFS / 256   # one compute unit's share (4 SIMDs x 16 FP64 lanes x 2 x 2.4 GHz)
 
 
+def panel_width(m):
+    """The library's QR panel width for a panel of m rows."""
+    return 16 if m <= 512 else 32 if m <= 1024 else 16
+
+
 def qr_panel_flops(n):
     """Householder flops of all panels of one n x n QR (2 m b^2 - 2 b^3 / 3 per
-    m x b panel; panel width 32, or 16 for more than 1024 rows)."""
+    m x b panel)."""
     f, j = 0.0, 0
     while j < n:
         m = n - j
-        b = min(16 if m > 1024 else 32, m)
+        b = min(panel_width(m), m)
         f += 2.0 * m * b * b - 2.0 * b ** 3 / 3.0
         j += b
     return f
@@ -94,7 +99,7 @@ def qr_panel_flops(n):
 def qr_panels(n):
     cnt, j = 0, 0
     while j < n:
-        j += min(16 if n - j > 1024 else 32, n - j)
+        j += min(panel_width(n - j), n - j)
         cnt += 1
     return cnt
 
@@ -110,6 +115,10 @@ def kernel_rooflines(prof, N, Lt, prec, k_avg, n_stab):
       decide: sequential per-site decisions on one workgroup; 2 w^2 flops per
               accepted flip (the rank-one update of the window block), against
               one compute unit's FP64 rate
+      flush_decide: the fused window launch (factors, flush, next window's
+              decisions); its duration is set by the decisions on one compute
+              unit, so it is rated like decide, with the flush's MFMA rate
+              (2 N^2 k flops per launch) beside it
     """
     out = {}
     es = 8 if prec == "fp64" else 4
@@ -140,10 +149,15 @@ def kernel_rooflines(prof, N, Lt, prec, k_avg, n_stab):
             ach = fl / t / 1e12
             r.update(bound="alu", achieved=ach, peak=CU_FP64_TFS, unit="TFLOP/s", frac=ach / CU_FP64_TFS,
                      algorithmic_per_launch=fl, note="one workgroup per panel (sequential columns)")
-        elif name == "decide":
-            fl = None
+        elif name in ("decide", "flush_decide"):
             r.update(bound="alu", unit="TFLOP/s", peak=CU_FP64_TFS,
                      note="one workgroup per window (sequential sites)")
+            if name == "flush_decide":
+                fl = 2.0 * N * N * k_avg
+                r.update(mfma_achieved=fl / t / 1e12, mfma_peak=FP64_PEAK_TFS,
+                         mfma_frac=fl / t / 1e12 / FP64_PEAK_TFS, k_avg=k_avg,
+                         note="one launch per window: factors and flush on every tile, the "
+                              "next window's sequential decisions on one workgroup")
             out[name] = r
             continue
         else:
@@ -153,14 +167,18 @@ def kernel_rooflines(prof, N, Lt, prec, k_avg, n_stab):
 
 
 def decide_roofline(kern, prof, accepts_per_sweep, steps, window):
-    """Fills the decide entry: 2 w^2 flops per accepted flip."""
-    if "decide" not in kern:
+    """Fills the decide and flush_decide entries: 2 w^2 flops per accepted flip,
+    the accepts spread evenly over the launches that make decisions."""
+    names = [x for x in ("decide", "flush_decide") if x in kern]
+    launches = sum(prof[x][1] for x in names)
+    if not launches:
         return
-    ms, n = prof["decide"]
-    t = ms / n / 1000.0
-    fl = 2.0 * window * window * accepts_per_sweep * steps / n
-    ach = fl / t / 1e12
-    kern["decide"].update(achieved=ach, frac=ach / CU_FP64_TFS, algorithmic_per_launch=fl)
+    fl = 2.0 * window * window * accepts_per_sweep * steps / launches
+    for x in names:
+        ms, n = prof[x]
+        t = ms / n / 1000.0
+        ach = fl / t / 1e12
+        kern[x].update(achieved=ach, frac=ach / CU_FP64_TFS, algorithmic_per_launch=fl)
 
 
 def _sha1(path):
@@ -434,10 +452,10 @@ def main():
 
     # per-kernel rooflines from the HIP-event durations; the dominant kernel
     # (stabilize is a composite of bmul / qr_panel / gemm and is skipped)
-    flushes = max(1, prof["flush"][1] // args.steps)
+    flushes = max(1, (prof["flush"][1] + prof.get("flush_decide", (0, 0))[1]) // args.steps)
     k_avg = accepts / flushes
     kernels = kernel_rooflines(prof, N, Lt, prec, k_avg, n_stab)
-    win = min(window or min(k, 64), N)   # the library's default window: min(delay_k, 64)
+    win = min(window or min(k, 32), N)   # the library's default window: min(delay_k, 32)
     decide_roofline(kernels, prof, accepts, args.steps, win)
     cand = {n: v for n, v in prof.items() if n != "stabilize" and v[1] > 0}
     dom = max(cand, key=lambda n: cand[n][0])

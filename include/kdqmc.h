@@ -220,12 +220,14 @@ const char* kdqmc_last_error(void);
 
 /* ---- profiling: HIP events around every kernel launch of the context ---- */
 
-#define KDQMC_NPHASE 10
+#define KDQMC_NPHASE 11
 /* Phases: 0 wrap_cols, 1 wrap_rows (the two FFT passes of the wrap),
  * 2 decide, 3 extend, 4 prep (window decisions and delayed factors),
  * 5 flush (rank-k MFMA update), 6 bmul (B-chain products of the stacks),
  * 7 qr_panel, 8 gemm (stabilization linear algebra), 9 stabilize (whole
- * kdqmc_stabilize calls, which contain phases 6-8). */
+ * kdqmc_stabilize calls, which contain phases 6-8), 10 flush_decide (FP64
+ * with a flush after every window: one launch per window that forms the
+ * window's factors, flushes them and runs the next window's decisions). */
 
 /* on != 0 starts recording (clearing earlier records); 0 stops. */
 int kdqmc_profile_enable(kdqmc_ctx* c, int on);

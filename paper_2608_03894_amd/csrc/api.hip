@@ -742,8 +742,9 @@ int kdqmc_profile_read(kdqmc_ctx* c, double* ms, int* launches) {
 }
 
 const char* kdqmc_phase_name(int phase) {
-  static const char* names[KDQMC_NPHASE] = {"wrap_cols", "wrap_rows", "decide", "extend", "prep",
-                                            "flush", "bmul", "qr_panel", "gemm", "stabilize"};
+  static const char* names[KDQMC_NPHASE] = {"wrap_cols", "wrap_rows", "decide",  "extend",
+                                            "prep",      "flush",     "bmul",    "qr_panel",
+                                            "gemm",      "stabilize", "flush_decide"};
   return (phase >= 0 && phase < KDQMC_NPHASE) ? names[phase] : "";
 }
 

@@ -146,7 +146,7 @@ namespace kdqmc {
 // Phases timed by the optional HIP-event profiler (kdqmc_profile_*).
 enum Phase {
   PH_WRAP_COLS = 0, PH_WRAP_ROWS, PH_DECIDE, PH_EXTEND, PH_PREP, PH_FLUSH, PH_BMUL, PH_QR_PANEL,
-  PH_GEMM, PH_STABILIZE, PH_COUNT
+  PH_GEMM, PH_STABILIZE, PH_FLUSH_DECIDE, PH_COUNT
 };
 }  // namespace kdqmc
 

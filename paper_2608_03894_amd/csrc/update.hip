@@ -1021,7 +1021,7 @@ int fused_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
                        c->snapc + cur * nwv, c->snapr + cur * nwv, c->snapc + nxt * nwv,
                        c->snapr + nxt * nwv, zs, zn);
     const int e2 = prof_mark(c);
-    prof_pair(c, PH_FLUSH, e1, e2);
+    prof_pair(c, PH_FLUSH_DECIDE, e1, e2);
     e1 = e2;
   }
   KDQMC_HIP(hipGetLastError());

@@ -78,7 +78,7 @@ _SIGS = {
     "kdqmc_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
 }
 
-NPHASE = 10
+NPHASE = 11
 
 
 def load():
