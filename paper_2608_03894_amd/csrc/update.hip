@@ -402,14 +402,22 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
 
 // Field, uniform and forced flag of site `lane` of the window at w0 (loads
 // clamped into the window; lanes >= wn get neutral values).
+// (absent inputs are read from stand-ins -- any double array `dfl` and the
+// field array -- and discarded, so that no branch separates these loads from
+// the caller's)
 __device__ __forceinline__ void site_inputs(int lane, int w0, int wn, const int8_t* __restrict__ s_l,
                                             const double* __restrict__ u,
-                                            const uint8_t* __restrict__ forced, int& sx, double& ux,
+                                            const uint8_t* __restrict__ forced,
+                                            const double* __restrict__ dfl, int& sx, double& ux,
                                             bool& fx) {
   const int xs = w0 + min(lane, wn - 1);
   const int s_raw = s_l[xs];
-  const double u_raw = u ? u[xs] : 0.0;
-  const bool f_raw = forced ? forced[xs] != 0 : false;
+  const double* ud = u ? u : dfl;
+  const double u_ld = ud[u ? xs : 0];
+  const uint8_t* fd = forced ? forced : reinterpret_cast<const uint8_t*>(s_l);
+  const uint8_t f_ld = fd[xs];
+  const double u_raw = u ? u_ld : 0.0;
+  const bool f_raw = forced ? f_ld != 0 : false;
   const bool xin = lane < wn;
   sx = xin ? s_raw : 1;
   ux = xin ? u_raw : 0.0;
@@ -447,7 +455,7 @@ decide_wave_body(const T* __restrict__ G, int N, const double* __restrict__ ev,
   int sx;
   double ux;
   bool fx;
-  site_inputs(lane, w0, wn, s_l, u, forced, sx, ux, fx);
+  site_inputs(lane, w0, wn, s_l, u, forced, ev, sx, ux, fx);
   // window submatrix G0 (tilde frame): all loads issued before any is used
   // (addresses clamped into the window instead of branches)
   constexpr int PER = (WM * WM + 63) / 64;
@@ -589,15 +597,29 @@ k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
   double* R3 = R2 + 64 * (WM + 1);
   __shared__ int il[WM];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int R0 = blockIdx.y * 64, C0 = blockIdx.x * 64;
-  const int row0 = R0 + (wave >> 1) * 32, col0 = C0 + (wave & 1) * 32;
-  const int lr = lane & 15, lk = lane >> 4;
   const int w0 = win * W;
   const int a = win_a[win];
   const bool has_next = win + 1 < nw;
   const int w1 = (win + 1) * W;
   const int wn1 = has_next ? min(W, N - w1) : 0;
-  const bool diag_wg = has_next && (w1 >> 6) == (int)blockIdx.x && (w1 >> 6) == (int)blockIdx.y;
+  // the tile holding the next window's diagonal block is given to the first
+  // workgroup dispatched (and its tile to that one), so that the decisions
+  // start at once and overlap the other tiles' work
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (has_next) {
+    const int t = w1 >> 6;
+    if (bx == 0 && by == 0) {
+      bx = t;
+      by = t;
+    } else if (bx == t && by == t) {
+      bx = 0;
+      by = 0;
+    }
+  }
+  const bool diag_wg = has_next && (w1 >> 6) == bx && (w1 >> 6) == by;
+  const int R0 = by * 64, C0 = bx * 64;
+  const int row0 = R0 + (wave >> 1) * 32, col0 = C0 + (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
   // the G tile (clamped loads, in flight during the factor work)
   v4d acc[2][2];
 #pragma unroll
@@ -609,10 +631,12 @@ k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
         const int r = min(row0 + 16 * bi + lk + 4 * j, N - 1), cc = min(col0 + 16 * bj + lr, N - 1);
         acc[bi][bj][j] = G[(size_t)r * N + cc];
       }
-  int sx = 1;
-  double ux = 0.0;
-  bool fx = false;
-  if (diag_wg && wave == 0) site_inputs(lane, w1, wn1, s_l, u, forced, sx, ux, fx);
+  // the next window's site inputs (used by the deciding wave; loaded by all,
+  // at clamped addresses, so that no branch waits on them)
+  int sx;
+  double ux;
+  bool fx;
+  site_inputs(lane, min(w1, N - 1), max(wn1, 1), s_l, u, forced, ev, sx, ux, fx);
   if (a > 0) {
     for (int idx = tid; idx < a * a; idx += 256) {
       const int q = idx / a, n = idx % a;
@@ -637,26 +661,34 @@ k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
     // thread (lane, wave): row / column lane of the tile, factors n = wave + 4 k2;
     // its row of gl and column of hl are read once into registers
     constexpr int PERU = WM / 4;
-    double gr[WM], hr[WM];
-#pragma unroll
-    for (int q = 0; q < WM; ++q) {
-      gr[q] = gl[lane][q];
-      hr[q] = hl[q][lane];
-    }
     double uvals[PERU], wvals[PERU];
+    {
+      double gr[WM];
 #pragma unroll
-    for (int k2 = 0; k2 < PERU; ++k2) {
-      const int n = wave + 4 * k2;
-      double uv = 0.0, wv = 0.0;
+      for (int q = 0; q < WM; ++q) gr[q] = gl[lane][q];
 #pragma unroll
-      for (int q = 0; q < WM; ++q) {
-        if (q <= n) {
-          uv += gr[q] * Zs[q][n];
-          wv += Zps[n][q] * hr[q];
-        }
+      for (int k2 = 0; k2 < PERU; ++k2) {
+        const int n = wave + 4 * k2;
+        double uv = 0.0;
+#pragma unroll
+        for (int q = 0; q < WM; ++q)
+          if (q <= n) uv += gr[q] * Zs[q][n];
+        uvals[k2] = R0 + lane < N ? uv * evinv[R0 + lane] : 0.0;
       }
-      uvals[k2] = R0 + lane < N ? uv * evinv[R0 + lane] : 0.0;
-      wvals[k2] = C0 + lane < N ? wv * ev[C0 + lane] : 0.0;
+    }
+    {
+      double hr[WM];
+#pragma unroll
+      for (int q = 0; q < WM; ++q) hr[q] = hl[q][lane];
+#pragma unroll
+      for (int k2 = 0; k2 < PERU; ++k2) {
+        const int n = wave + 4 * k2;
+        double wv = 0.0;
+#pragma unroll
+        for (int q = 0; q < WM; ++q)
+          if (q <= n) wv += Zps[n][q] * hr[q];
+        wvals[k2] = C0 + lane < N ? wv * ev[C0 + lane] : 0.0;
+      }
     }
     __syncthreads();
     double(*Ul)[64] = reinterpret_cast<double(*)[64]>(R2);
