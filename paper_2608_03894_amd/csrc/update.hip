@@ -638,24 +638,30 @@ k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
   bool fx;
   site_inputs(lane, min(w1, N - 1), max(wn1, 1), s_l, u, forced, ev, sx, ux, fx);
   if (a > 0) {
-    for (int idx = tid; idx < a * a; idx += 256) {
-      const int q = idx / a, n = idx % a;
-      Zs[q][n] = Zc[q * W + n];
-      Zps[q][n] = Zpc[q * W + n];
+    // Z (upper) and Z' (lower) triangles of the a accepts, zeros elsewhere in
+    // WM x WM, and g, h zero past the a accepts: the sums below then run over
+    // all WM terms without tests (the extra terms are exact zeros)
+    for (int idx = tid; idx < WM * WM; idx += 256) {
+      const int q = idx / WM, n = idx % WM;
+      const bool in = q < a && n < a;
+      Zs[q][n] = (in && q <= n) ? Zc[q * W + n] : 0.0;
+      Zps[q][n] = (in && n <= q) ? Zpc[q * W + n] : 0.0;
     }
     for (int n = tid; n < a; n += 256) il[n] = w0 + win_p[win * W + n];
     __syncthreads();
     double(*gl)[WM + 1] = reinterpret_cast<double(*)[WM + 1]>(R2);
     double(*hl)[65] = reinterpret_cast<double(*)[65]>(R3);
-    for (int idx = tid; idx < 64 * a; idx += 256) {
-      const int rr = idx / a, q = idx % a;
-      const int r = R0 + rr, i = il[q];
-      gl[rr][q] = r < N ? csc[(size_t)r * W + (i - w0)] * ev[r] * evinv[i] : 0.0;
+    for (int idx = tid; idx < 64 * WM; idx += 256) {
+      const int rr = idx / WM, q = idx % WM;
+      const int r = R0 + rr, i = il[q < a ? q : 0];
+      gl[rr][q] = (r < N && q < a) ? csc[(size_t)r * W + (i - w0)] * ev[r] * evinv[i] : 0.0;
     }
-    for (int idx = tid; idx < a * 64; idx += 256) {
+    for (int idx = tid; idx < WM * 64; idx += 256) {
       const int q = idx / 64, cc = idx % 64;
-      const int cg = C0 + cc, i = il[q];
-      hl[q][cc] = cg < N ? ((cg == i) ? 1.0 : 0.0) - rsc[(size_t)(i - w0) * N + cg] * ev[i] * evinv[cg] : 0.0;
+      const int cg = C0 + cc, i = il[q < a ? q : 0];
+      hl[q][cc] = (cg < N && q < a)
+                      ? ((cg == i) ? 1.0 : 0.0) - rsc[(size_t)(i - w0) * N + cg] * ev[i] * evinv[cg]
+                      : 0.0;
     }
     __syncthreads();
     // thread (lane, wave): row / column lane of the tile, factors n = wave + 4 k2;
@@ -671,8 +677,7 @@ k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
         const int n = wave + 4 * k2;
         double uv = 0.0;
 #pragma unroll
-        for (int q = 0; q < WM; ++q)
-          if (q <= n) uv += gr[q] * Zs[q][n];
+        for (int q = 0; q < WM; ++q) uv += gr[q] * Zs[q][n];
         uvals[k2] = R0 + lane < N ? uv * evinv[R0 + lane] : 0.0;
       }
     }
@@ -685,8 +690,7 @@ k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
         const int n = wave + 4 * k2;
         double wv = 0.0;
 #pragma unroll
-        for (int q = 0; q < WM; ++q)
-          if (q <= n) wv += Zps[n][q] * hr[q];
+        for (int q = 0; q < WM; ++q) wv += Zps[n][q] * hr[q];
         wvals[k2] = C0 + lane < N ? wv * ev[C0 + lane] : 0.0;
       }
     }
