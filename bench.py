@@ -33,7 +33,7 @@ FP64_PEAK_TFS = 78.6           # MI355X FP64 (vector and matrix)
 F16_PEAK_TFS = 2500.0          # MI355X dense FP16/BF16 MFMA
 
 CONFIGS = {"c1": si.C1, "c2": si.C2, "c3": si.C3, "c5": si.C5, "c4": None}
-AUTOTUNED = ("c4", "c5")   # workloads whose delay rank and FFT tile come from the autotuner
+AUTOTUNED = ("c3", "c4", "c5")   # workloads whose delay rank and FFT tile come from the autotuner
 
 
 def schedule(args, w, prec, n_stab, autotuned):
