@@ -99,6 +99,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   char* Zpg = take(2 * (size_t)d.w * d.w * 8);
   char* snapc = take(2 * N * d.w * 8);
   char* snapr = take(2 * N * d.w * 8);
+  char* snapb = take(2 * (size_t)d.w * d.w * 8);
   char* Gs = take((size_t)d.w * d.w * 8);
   char* flag = take(64);
   char* err = take(1024 * 8);
@@ -134,6 +135,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
     c->Yw = (double*)Zpg;
     c->snapc = (double*)snapc;
     c->snapr = (double*)snapr;
+    c->snapb = (double*)snapb;
     c->Gs = (double*)Gs;
     c->flag = (int*)flag;
     c->err = (double*)err;

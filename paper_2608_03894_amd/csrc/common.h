@@ -122,6 +122,16 @@ template <typename T>
 __device__ __forceinline__ T* zc(T* p, size_t zn) {
   return p ? p + (size_t)blockIdx.z * zn : p;
 }
+// The same for an explicit chain z (kernels that number their workgroups themselves).
+template <typename T>
+__device__ __forceinline__ T* zw_at(T* p, size_t zs, int z) {
+  using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (size_t)z * zs) : p;
+}
+template <typename T>
+__device__ __forceinline__ T* zc_at(T* p, size_t zn, int z) {
+  return p ? p + (size_t)z * zn : p;
+}
 
 // Lane `src` (wave-uniform) of a double held in a vector register; the value
 // is wave-uniform afterwards (scalar registers).
@@ -209,6 +219,7 @@ struct kdqmc_ctx {
   double* Yw = nullptr;        // 2*w*w: Z' of a window
   double* snapc = nullptr;     // 2*N*w: G[:, S] of a window (fused schedule, by parity)
   double* snapr = nullptr;     // 2*w*N: G[S, :] of a window
+  double* snapb = nullptr;     // 2*w*w: G[S, S] of the window after next
   bool fused = false;          // FP64, one window per flush, windows inside 64 x 64 tiles
   double* Gs = nullptr;        // w*w: G~cur[S,S] of the next window
   int* flag = nullptr;         // small device status words

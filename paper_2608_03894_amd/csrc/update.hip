@@ -526,7 +526,7 @@ k_window_start(const double* __restrict__ G, int N, const double* __restrict__ e
                uint8_t* __restrict__ acc_out, double* __restrict__ ratio_out, int wn, int W,
                const double* __restrict__ sc, int* __restrict__ win_a, int* __restrict__ win_p,
                double* __restrict__ Zg, double* __restrict__ Zpg, double* __restrict__ csn,
-               double* __restrict__ rsn, size_t zs, size_t zn) {
+               double* __restrict__ rsn, double* __restrict__ bk1, size_t zs, size_t zn) {
   if (blockIdx.x == 0) {
     decide_wave_body<double, WM>(G, N, ev, evinv, s_l, u, forced, acc_out, ratio_out, 0, wn, W,
                                  nullptr, sc, 0, win_a, win_p, Zg, Zpg, zs, zn);
@@ -535,16 +535,25 @@ k_window_start(const double* __restrict__ G, int N, const double* __restrict__ e
   G = zw(G, zs);
   csn = zw(csn, zs);
   rsn = zw(rsn, zs);
+  bk1 = zw(bk1, zs);
   // column snapshot csn[r][y] = G[r][y], row snapshot rsn[x][c] = G[x][c]
-  // (x, y < wn): 8 elements per thread, loads before stores
+  // (x, y < wn), and window 1's diagonal block bk1[x][y] = G[W + x][W + y]
+  // (x, y < wn1): 8 elements per thread, loads before stores
   constexpr int B = 8;
-  const int nc = N * wn, total = 2 * nc;
+  const int wn1 = max(min(W, N - W), 0);
+  const int nc = N * wn, total = 2 * nc + wn1 * wn1;
   const int base = (blockIdx.x - 1) * 64 * B + threadIdx.x;
   double v[B];
 #pragma unroll
   for (int k = 0; k < B; ++k) {
     const int e = min(base + 64 * k, total - 1);
-    const size_t off = e < nc ? (size_t)(e / wn) * N + e % wn : (size_t)((e - nc) / N) * N + (e - nc) % N;
+    size_t off;
+    if (e < nc)
+      off = (size_t)(e / wn) * N + e % wn;
+    else if (e < 2 * nc)
+      off = (size_t)((e - nc) / N) * N + (e - nc) % N;
+    else
+      off = (size_t)(W + (e - 2 * nc) / wn1) * N + W + (e - 2 * nc) % wn1;
     v[k] = G[off];
   }
 #pragma unroll
@@ -552,14 +561,16 @@ k_window_start(const double* __restrict__ G, int N, const double* __restrict__ e
     const int e = base + 64 * k;
     if (e < nc)
       csn[(size_t)(e / wn) * W + e % wn] = v[k];
-    else if (e < total)
+    else if (e < 2 * nc)
       rsn[(size_t)((e - nc) / N) * N + (e - nc) % N] = v[k];
+    else if (e < total)
+      bk1[(size_t)((e - 2 * nc) / wn1) * W + (e - 2 * nc) % wn1] = v[k];
   }
 }
 
 template <int WM>
 __global__ void __launch_bounds__(256)
-k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
+k_flush_decide(double* __restrict__ G, int N, int gxt, const double* __restrict__ ev,
                const double* __restrict__ evinv, int8_t* __restrict__ s_l,
                const double* __restrict__ u, const uint8_t* __restrict__ forced,
                uint8_t* __restrict__ acc_out, double* __restrict__ ratio_out,
@@ -567,25 +578,45 @@ k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
                int* __restrict__ win_p, const double* __restrict__ Zc, const double* __restrict__ Zpc,
                double* __restrict__ Zn, double* __restrict__ Zpn, const double* __restrict__ csc,
                const double* __restrict__ rsc, double* __restrict__ csn, double* __restrict__ rsn,
-               size_t zs, size_t zn) {
-  G = zw(G, zs);
-  ev = zw(ev, zs);
-  evinv = zw(evinv, zs);
-  s_l = zw(s_l, zs);
-  u = zc(u, zn);
-  forced = zc(forced, zn);
-  acc_out = zc(acc_out, zn);
-  ratio_out = zc(ratio_out, zn);
-  win_a = zw(win_a, zs);
-  win_p = zw(win_p, zs);
-  Zc = zw(Zc, zs);
-  Zpc = zw(Zpc, zs);
-  Zn = zw(Zn, zs);
-  Zpn = zw(Zpn, zs);
-  csc = zw(csc, zs);
-  rsc = zw(rsc, zs);
-  csn = zw(csn, zs);
-  rsn = zw(rsn, zs);
+               const double* __restrict__ bkc, double* __restrict__ bkn, size_t zs, size_t zn) {
+  // Roles: with a next window, workgroup z < nch (the first dispatched)
+  // decides chain z's next window; the others take the gxt x gxt tiles.
+  const int w1 = (win + 1) * W, w2 = (win + 2) * W;
+  const bool has_next = win + 1 < nw;
+  const int T = gxt * gxt, nz = gridDim.z;
+  const int lin = blockIdx.x + gridDim.x * blockIdx.z;
+  const bool decider = has_next && lin < nz;
+  int z, t;
+  if (decider) {
+    z = lin;
+    t = (w1 >> 6) * gxt + (w1 >> 6);  // the tile holding the next window's block
+  } else {
+    const int j = lin - (has_next ? nz : 0);
+    z = j / T;
+    t = j % T;
+  }
+  const int bx = t % gxt, by = t / gxt;
+  G = zw_at(G, zs, z);
+  ev = zw_at(ev, zs, z);
+  evinv = zw_at(evinv, zs, z);
+  s_l = zw_at(s_l, zs, z);
+  u = zc_at(u, zn, z);
+  forced = zc_at(forced, zn, z);
+  acc_out = zc_at(acc_out, zn, z);
+  ratio_out = zc_at(ratio_out, zn, z);
+  win_a = zw_at(win_a, zs, z);
+  win_p = zw_at(win_p, zs, z);
+  Zc = zw_at(Zc, zs, z);
+  Zpc = zw_at(Zpc, zs, z);
+  Zn = zw_at(Zn, zs, z);
+  Zpn = zw_at(Zpn, zs, z);
+  csc = zw_at(csc, zs, z);
+  rsc = zw_at(rsc, zs, z);
+  csn = zw_at(csn, zs, z);
+  rsn = zw_at(rsn, zs, z);
+  bkc = zw_at(bkc, zs, z);
+  bkn = zw_at(bkn, zs, z);
+  sc = zw_at(sc, zs, z);
   // LDS: Zs, Zps (WM x (WM+1) each); R2 = gl [64][WM+1], later Ul [WM][64];
   // R3 = hl [WM][65], later Wl [WM][64].  The decisions reuse Zs (window
   // block) and R2..R3 (history).
@@ -599,28 +630,180 @@ k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int w0 = win * W;
   const int a = win_a[win];
-  const bool has_next = win + 1 < nw;
-  const int w1 = (win + 1) * W;
   const int wn1 = has_next ? min(W, N - w1) : 0;
-  // the tile holding the next window's diagonal block is given to the first
-  // workgroup dispatched (and its tile to that one), so that the decisions
-  // start at once and overlap the other tiles' work
-  int bx = blockIdx.x, by = blockIdx.y;
-  if (has_next) {
-    const int t = w1 >> 6;
-    if (bx == 0 && by == 0) {
-      bx = t;
-      by = t;
-    } else if (bx == t && by == t) {
-      bx = 0;
-      by = 0;
-    }
-  }
-  const bool diag_wg = has_next && (w1 >> 6) == bx && (w1 >> 6) == by;
+  const int wn2 = win + 2 < nw ? min(W, N - w2) : 0;
   const int R0 = by * 64, C0 = bx * 64;
   const int row0 = R0 + (wave >> 1) * 32, col0 = C0 + (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
-  // the G tile (clamped loads, in flight during the factor work)
+  if (decider) {
+    // The decider: the next window's block only.  Every input is requested
+    // at once (Z, Z' whole, the block's rows of window k's columns and window
+    // k's rows at the block's columns, the scales, the block before this
+    // window's flush); the accepts are picked in LDS.  Per element the
+    // arithmetic is the tile's (same sums in the same order, same 16 x 16
+    // MFMA blocks), so the block equals the one written to G bit for bit.
+    const int Q0 = w1 & ~31;  // the 32 x 32 quadrant holding the block
+    constexpr int PZ = (WM * WM + 255) / 256;
+    double zv[PZ], zpv[PZ];
+#pragma unroll
+    for (int j = 0; j < PZ; ++j) {
+      const int idx = tid + 256 * j;
+      const int q = min(idx / WM, W - 1), n = min(idx % WM, W - 1);
+      zv[j] = Zc[q * W + n];
+      zpv[j] = Zpc[q * W + n];
+    }
+    // quadrant rows x (32) by window-k column y (WM): g source; window-k row y
+    // by quadrant column x: h source (4 + 4 per thread at WM = 32)
+    constexpr int PG = 32 * WM / 256;
+    double gsv[PG], hsv[PG];
+#pragma unroll
+    for (int j = 0; j < PG; ++j) {
+      const int idx = tid + 256 * j;
+      const int x = idx / WM, y = min(idx % WM, W - 1);
+      gsv[j] = csc[(size_t)min(Q0 + x, N - 1) * W + y];
+      hsv[j] = rsc[(size_t)y * N + min(Q0 + x, N - 1)];
+    }
+    const int pv = win_p[win * W + min(tid, W - 1)];
+    const int qs = min(Q0 + (tid & 31), N - 1);  // quadrant site
+    const double evq = ev[qs], evinvq = evinv[qs];
+    const int ks = min(w0 + (tid & (WM - 1)), N - 1);  // window-k site
+    const double evk = ev[ks], evinvk = evinv[ks];
+    v4d bacc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = Q0 + 16 * bi + lk + 4 * j, cc = Q0 + 16 * bj + lr;
+          const bool in = r >= w1 && r < w1 + wn1 && cc >= w1 && cc < w1 + wn1;
+          const double v = bkc[(size_t)min(max(r - w1, 0), W - 1) * W + min(max(cc - w1, 0), W - 1)];
+          bacc[bi][bj][j] = in ? v : 0.0;
+        }
+    int sx;
+    double ux;
+    bool fx;
+    site_inputs(lane, min(w1, N - 1), max(wn1, 1), s_l, u, forced, ev, sx, ux, fx);
+    __shared__ double evs[32], evinvs[32], evks[WM], evinvks[WM];
+    double(*gs)[WM + 1] = reinterpret_cast<double(*)[WM + 1]>(R2);  // [32][WM+1]
+    double(*hs)[33] = reinterpret_cast<double(*)[33]>(R3);          // [WM][33]
+    if (a > 0) {
+#pragma unroll
+      for (int j = 0; j < PZ; ++j) {
+        const int idx = tid + 256 * j;
+        if (idx < WM * WM) {
+          const int q = idx / WM, n = idx % WM;
+          const bool in = q < a && n < a;
+          Zs[q][n] = (in && q <= n) ? zv[j] : 0.0;
+          Zps[q][n] = (in && n <= q) ? zpv[j] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < PG; ++j) {
+        const int idx = tid + 256 * j;
+        gs[idx / WM][idx % WM] = gsv[j];
+        hs[idx % WM][idx / WM] = hsv[j];
+      }
+      if (tid < WM) il[tid] = tid < a ? pv : 0;  // window-local accept positions
+      if (tid < 32) {
+        evs[tid] = evq;
+        evinvs[tid] = evinvq;
+      }
+      if (tid < WM) {
+        evks[tid] = evk;
+        evinvks[tid] = evinvk;
+      }
+      __syncthreads();
+      // thread (lane < 32, wave): quadrant row / column lane, factors n = wave + 4 k2
+      constexpr int PERU = WM / 4;
+      double uvals[PERU], wvals[PERU];
+      const int x = lane & 31;
+      const int r = Q0 + x;
+      {
+        double gr[WM];
+#pragma unroll
+        for (int q = 0; q < WM; ++q) {
+          const int pq = il[q];
+          gr[q] = (r < N && q < a) ? gs[x][pq] * evs[x] * evinvks[pq] : 0.0;
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < PERU; ++k2) {
+          const int n = wave + 4 * k2;
+          double uv = 0.0;
+#pragma unroll
+          for (int q = 0; q < WM; ++q) uv += gr[q] * Zs[q][n];
+          uvals[k2] = r < N ? uv * evinvs[x] : 0.0;
+        }
+      }
+      {
+        double hr[WM];
+#pragma unroll
+        for (int q = 0; q < WM; ++q) {
+          const int pq = il[q];
+          hr[q] = (r < N && q < a) ? ((r == w0 + pq) ? 1.0 : 0.0) - hs[pq][x] * evks[pq] * evinvs[x] : 0.0;
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < PERU; ++k2) {
+          const int n = wave + 4 * k2;
+          double wv = 0.0;
+#pragma unroll
+          for (int q = 0; q < WM; ++q) wv += Zps[n][q] * hr[q];
+          wvals[k2] = r < N ? wv * evs[x] : 0.0;
+        }
+      }
+      __syncthreads();
+      double(*Ul)[32] = reinterpret_cast<double(*)[32]>(R2);
+      double(*Wl)[32] = reinterpret_cast<double(*)[32]>(R3);
+      if (lane < 32) {
+#pragma unroll
+        for (int k2 = 0; k2 < PERU; ++k2) {
+          const int n = wave + 4 * k2;
+          if (n < a) {
+            Ul[n][x] = uvals[k2];
+            Wl[n][x] = wvals[k2];
+          }
+        }
+      }
+      __syncthreads();
+      if (wave == 0) {
+        for (int k0 = 0; k0 < a; k0 += 4) {
+          const int k = k0 + lk;
+          double av[2], bv[2];
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi) {
+            av[bi] = k < a ? Ul[k < a ? k : 0][16 * bi + lr] : 0.0;
+            bv[bi] = k < a ? Wl[k < a ? k : 0][16 * bi + lr] : 0.0;
+          }
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+              bacc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], bacc[bi][bj], 0, 0, 0);
+        }
+      }
+      __syncthreads();  // the factor buffers are free again
+    }
+    if (wave != 0) return;
+    // the window block (tilde frame), zero outside wn1 x wn1
+    for (int idx = lane; idx < WM * (WM + 1); idx += 64) lds[idx] = 0.0;
+    wave_sync();
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = Q0 + 16 * bi + lk + 4 * j, cc = Q0 + 16 * bj + lr;
+          if (r >= w1 && r < w1 + wn1 && cc >= w1 && cc < w1 + wn1)
+            Zs[r - w1][cc - w1] = bacc[bi][bj][j] * ev[r] * evinv[cc];
+        }
+    wave_sync();
+    const double em2a = sc[SC_EM2A], ep2a = sc[SC_EP2A];
+    decide_window<WM>(lane, wn1, w1, W, win + 1, Zs, reinterpret_cast<double2(*)[64]>(R2), sx, ux, fx,
+                      forced != nullptr, em2a, ep2a, s_l, acc_out, ratio_out, win_a, win_p, Zn, Zpn);
+    return;
+  }
+  // a tile: the G tile (clamped loads, in flight during the factor work)
   v4d acc[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -628,15 +811,9 @@ k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = min(row0 + 16 * bi + lk + 4 * j, N - 1), cc = min(col0 + 16 * bj + lr, N - 1);
-        acc[bi][bj][j] = G[(size_t)r * N + cc];
+        const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
+        acc[bi][bj][j] = G[(size_t)min(r, N - 1) * N + min(cc, N - 1)];
       }
-  // the next window's site inputs (used by the deciding wave; loaded by all,
-  // at clamped addresses, so that no branch waits on them)
-  int sx;
-  double ux;
-  bool fx;
-  site_inputs(lane, min(w1, N - 1), max(wn1, 1), s_l, u, forced, ev, sx, ux, fx);
   if (a > 0) {
     // Z (upper) and Z' (lower) triangles of the a accepts, zeros elsewhere in
     // WM x WM, and g, h zero past the a accepts: the sums below then run over
@@ -730,7 +907,9 @@ k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
           if (r < N && cc < N) G[(size_t)r * N + cc] = acc[bi][bj][j];
         }
   }
-  if (has_next) {
+  {
+    // copies for the next launches: the next window's columns and rows, and
+    // the diagonal block of the window after next
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -741,28 +920,11 @@ k_flush_decide(double* __restrict__ G, int N, const double* __restrict__ ev,
           if (r < N && cc < N) {
             if (cc >= w1 && cc < w1 + wn1) csn[(size_t)r * W + (cc - w1)] = acc[bi][bj][j];
             if (r >= w1 && r < w1 + wn1) rsn[(size_t)(r - w1) * N + cc] = acc[bi][bj][j];
+            if (r >= w2 && r < w2 + wn2 && cc >= w2 && cc < w2 + wn2)
+              bkn[(size_t)(r - w2) * W + (cc - w2)] = acc[bi][bj][j];
           }
         }
   }
-  if (!diag_wg) return;  // uniform over the workgroup
-  __syncthreads();       // the factor buffers are free again
-  for (int idx = tid; idx < WM * (WM + 1); idx += 256) lds[idx] = 0.0;
-  __syncthreads();
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
-        if (r >= w1 && r < w1 + wn1 && cc >= w1 && cc < w1 + wn1)
-          Zs[r - w1][cc - w1] = acc[bi][bj][j] * ev[r] * evinv[cc];
-      }
-  __syncthreads();
-  if (wave != 0) return;
-  const double em2a = zw(sc, zs)[SC_EM2A], ep2a = zw(sc, zs)[SC_EP2A];
-  decide_window<WM>(lane, wn1, w1, W, win + 1, Zs, reinterpret_cast<double2(*)[64]>(R2), sx, ux, fx,
-                    forced != nullptr, em2a, ep2a, s_l, acc_out, ratio_out, win_a, win_p, Zn, Zpn);
 }
 
 template <int WM>
@@ -1040,22 +1202,24 @@ int fused_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
   const unsigned Z = (unsigned)c->nch;
   const size_t zs = c->zs;
   const size_t ww = (size_t)W * W, nwv = (size_t)N * W;
-  const int wn0 = std::min(W, N);
-  const int nsnap = (2 * N * wn0 + 64 * 8 - 1) / (64 * 8);
+  const int wn0 = std::min(W, N), wn1 = std::max(std::min(W, N - W), 0);
+  const int nsnap = (2 * N * wn0 + wn1 * wn1 + 64 * 8 - 1) / (64 * 8);
   const int e0 = prof_mark(c);
   hipLaunchKernelGGL((k_window_start<WM>), dim3(1 + nsnap, 1, Z), dim3(64), 0, c->stream, G, N, c->ev,
                      c->evinv, s_l, u, forced, acc, ratio, wn0, W, c->sc, c->win_a, c->win_p, c->Xw,
-                     c->Yw, c->snapc, c->snapr, zs, zn);
+                     c->Yw, c->snapc, c->snapr, c->snapb + ww, zs, zn);
   int e1 = prof_mark(c);
   prof_pair(c, PH_DECIDE, e0, e1);
-  const dim3 grid((N + 63) / 64, (N + 63) / 64, Z);
+  const int gxt = (N + 63) / 64;
   for (int win = 0; win < c->nw; ++win) {
     const size_t cur = win & 1, nxt = cur ^ 1;
+    // the tiles, and with a next window one deciding workgroup per chain
+    const dim3 grid(gxt * gxt + (win + 1 < c->nw ? 1 : 0), 1, Z);
     hipLaunchKernelGGL((k_flush_decide<WM>), grid, dim3(256), flush_decide_lds<WM>(), c->stream, G, N,
-                       c->ev, c->evinv, s_l, u, forced, acc, ratio, c->sc, win, W, c->nw, c->win_a,
+                       gxt, c->ev, c->evinv, s_l, u, forced, acc, ratio, c->sc, win, W, c->nw, c->win_a,
                        c->win_p, c->Xw + cur * ww, c->Yw + cur * ww, c->Xw + nxt * ww, c->Yw + nxt * ww,
                        c->snapc + cur * nwv, c->snapr + cur * nwv, c->snapc + nxt * nwv,
-                       c->snapr + nxt * nwv, zs, zn);
+                       c->snapr + nxt * nwv, c->snapb + nxt * ww, c->snapb + cur * ww, zs, zn);
     const int e2 = prof_mark(c);
     prof_pair(c, PH_FLUSH_DECIDE, e1, e2);
     e1 = e2;
