@@ -271,7 +271,10 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
   c->w = d.w;
   c->nw = d.nw;
   c->F = d.F;
-  c->fused = d.fp64 && d.F == 1 && d.w <= 32 && (64 % d.w == 0 || d.nw == 1);
+  // the fused window launch for one chain; batched chains (whose shape groups
+  // run on concurrent streams, hiding launch gaps) take the three-kernel
+  // schedule, which forms each window's factors once instead of per tile
+  c->fused = d.fp64 && d.F == 1 && d.w <= 32 && (64 % d.w == 0 || d.nw == 1) && n_chains == 1;
   c->kmax = d.kmax;
   c->P = d.P;
   c->P64 = d.P64;
