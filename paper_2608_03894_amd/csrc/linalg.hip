@@ -330,21 +330,25 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
 // W = V^T C: the waves split the rows and their partial 32 x SW products are
 // summed in LDS; then C -= V W2 with the waves splitting the rows.
 template <int SW>
-__global__ void __launch_bounds__(512)
-k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
-           const double* __restrict__ V, int ldv, const double* __restrict__ T, int trans,
-           size_t zs) {
-  C = zw(C, zs);
-  V = zw(V, zs);
-  T = zw(T, zs);
+struct WyLds {
+  double Wp[8][32][SW + 1];
+  double W2[32][SW + 1];
+  double Tl[32][33];
+};
+
+// One panel applied to the stripe s0 of C (the body of k_apply_wy; 512 threads).
+template <int SW>
+__device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restrict__ C, int ldc, int n,
+                                                int j, int nbp, int ncols, int s0,
+                                                const double* __restrict__ V, int ldv,
+                                                const double* __restrict__ T, int trans) {
   constexpr int NW = 8;
   constexpr int BJ = SW / 16;
-  __shared__ double Wp[NW][32][SW + 1];
-  __shared__ double W2[32][SW + 1];
-  __shared__ double Tl[32][33];
+  auto& Wp = sh.Wp;
+  auto& W2 = sh.W2;
+  auto& Tl = sh.Tl;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int s0 = blockIdx.x * SW;
   const int m = n - j;
   for (int idx = tid; idx < 32 * 32; idx += 512) {
     const int r = idx >> 5, cc = idx & 31;
@@ -420,6 +424,45 @@ k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
         const int r = j + rb + lk + 4 * e, cc = s0 + bj * 16 + lr;
         if (r < n && cc < ncols) C[(size_t)r * ldc + cc] -= d[bj][e];
       }
+  }
+}
+
+template <int SW>
+__global__ void __launch_bounds__(512)
+k_apply_wy(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
+           const double* __restrict__ V, int ldv, const double* __restrict__ T, int trans,
+           size_t zs) {
+  __shared__ WyLds<SW> sh;
+  apply_wy_stripe<SW>(sh, zw(C, zs), ldc, n, j, nbp, ncols, blockIdx.x * SW, zw(V, zs), ldv, zw(T, zs),
+                      trans);
+}
+
+// All panels of a factorization applied in turn to each SW-column stripe of C
+// (one workgroup per stripe, no launch per panel): forward order with
+// H^T (trans, op(T) = T^T) over all columns, as in applying Q^T; or backward
+// order with H over the columns right of each panel's start, as in forming Q
+// from the identity.  The panel table is the host's.
+struct PanelTable {
+  int start[160];
+  int width[160];
+};
+
+template <int SW>
+__global__ void __launch_bounds__(512)
+k_apply_wy_all(double* __restrict__ C, int ldc, int n, const double* __restrict__ V, int ldv,
+               const double* __restrict__ Tq, PanelTable pt, int npan, int backward, size_t zs) {
+  __shared__ WyLds<SW> sh;
+  C = zw(C, zs);
+  V = zw(V, zs);
+  Tq = zw(Tq, zs);
+  const int s0 = blockIdx.x * SW;
+  for (int i = 0; i < npan; ++i) {
+    const int p = backward ? npan - 1 - i : i;
+    const int j = pt.start[p];
+    if (backward && j > s0) continue;  // columns left of the panel are untouched
+    apply_wy_stripe<SW>(sh, C, ldc, n, j, pt.width[p], n, s0, V, ldv, Tq + (size_t)p * kNBmax * kNBmax,
+                        backward ? 0 : 1);
+    __syncthreads();  // this panel's update is read by the next one
   }
 }
 
@@ -619,6 +662,23 @@ int launch_apply(kdqmc_ctx* c, double* C, int ld, int n, int j, int nbp, int col
 
 }  // namespace
 
+// All panels of the last factorization applied to C, one launch: backward
+// (forming Q from the identity) or forward with H^T (applying Q^T).
+int launch_apply_all(kdqmc_ctx* c, double* C, int ld, int n, bool backward) {
+  static_assert(sizeof(PanelTable) <= 2048, "kernel argument size");
+  PanelTable pt;
+  for (int p = 0; p < c->qr_npan; ++p) {
+    pt.start[p] = c->qr_panel_start[p];
+    pt.width[p] = c->qr_panel_width[p];
+  }
+  constexpr int SW = 16;
+  const int e0 = prof_mark(c);
+  hipLaunchKernelGGL(k_apply_wy_all<SW>, dim3((n + SW - 1) / SW, 1, c->nch), dim3(512), 0, c->stream, C, ld, n,
+                     c->Vq, ld, c->Tq, pt, c->qr_npan, backward ? 1 : 0, c->zs);
+  prof_pair(c, PH_GEMM, e0, prof_mark(c));
+  return KDQMC_OK;
+}
+
 // A (n x n, leading dimension N) = Q R.  With Q != nullptr, Q is formed
 // explicitly; the panels' V and T stay in Vq / Tq for apply_qt_f64.
 int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q) {
@@ -640,11 +700,7 @@ int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q) {
   if (Q) {
     hipLaunchKernelGGL(k_set_identity, dim3((n * n + 255) / 256, 1, c->nch), dim3(256), 0, c->stream, Q, n,
                        ld, c->zs);
-    for (int p = npan - 1; p >= 0; --p) {
-      const int j = c->qr_panel_start[p];
-      KDQMC_TRY(launch_apply(c, Q, ld, n, j, c->qr_panel_width[p], j, n,
-                             c->Tq + (size_t)p * kNBmax * kNBmax, false));
-    }
+    KDQMC_TRY(launch_apply_all(c, Q, ld, n, true));
   }
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
@@ -652,12 +708,7 @@ int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q) {
 
 // X <- Q^T X for the Q of the last qr_f64 call (n x n, ld = N).
 int apply_qt_f64(kdqmc_ctx* c, int n, double* X) {
-  const int ld = c->N;
-  for (int p = 0; p < c->qr_npan; ++p) {
-    const int j = c->qr_panel_start[p];
-    KDQMC_TRY(launch_apply(c, X, ld, n, j, c->qr_panel_width[p], 0, n,
-                           c->Tq + (size_t)p * kNBmax * kNBmax, true));
-  }
+  KDQMC_TRY(launch_apply_all(c, X, c->N, n, false));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
