@@ -147,3 +147,41 @@ def test_uneven_batch_groups(gpu_lib):
             assert np.array_equal(G[k], ch.G().cpu().numpy()), (i, specs[i])
             ch.close()
     b.close()
+
+
+def test_fused_window_launch_equals_three_kernel_schedule(gpu_lib):
+    """One FP64 chain runs the fused window launch (factors, flush and the next
+    window's decisions in one launch, the decisions on a copy of the window
+    block); a batch of two takes decide / extend / flush.  Both do the same
+    arithmetic in the same order, so G, the decisions and the ratios must agree
+    bit for bit, here at L = 12 (7 x 7 tiles, 32-site windows) over an upward
+    and a downward pass."""
+    from paper_2608_03894_amd import kdqmc
+    t = torch()
+    L, U, beta, seed = 12, -4.0, 2.0, 91
+    Lt = 20
+    f = si.ising_fields(L, Lt, seed)
+    us = si.metropolis_uniforms(L, Lt, seed, n_sweeps=2)
+    say("fused vs three-kernel, L12")
+    p = kdqmc.make_params(L, U, beta, 0.1, mu=-1.0, n_stab=10, delay_k=32)
+    one = kdqmc.Chain(p)
+    one.set_fields(dev(f))
+    a1 = t.zeros((Lt, 3 * L * L), dtype=t.uint8, device="cuda:0")
+    r1 = t.zeros((Lt, 3 * L * L), dtype=t.float64, device="cuda:0")
+    one.sweep(dev(us[0]), None, a1, r1, None)
+    one.sweep_down(dev(us[1]), None, None, None, None)
+    G1 = one.G().cpu().numpy()
+    one.close()
+    two = kdqmc.Chain(p, n_chains=2)
+    two.set_fields(dev(np.stack([f, f])))
+    a2 = t.zeros((2, Lt, 3 * L * L), dtype=t.uint8, device="cuda:0")
+    r2 = t.zeros((2, Lt, 3 * L * L), dtype=t.float64, device="cuda:0")
+    two.sweep(dev(np.stack([us[0], us[0]])), None, a2, r2, None)
+    two.sweep_down(dev(np.stack([us[1], us[1]])), None, None, None, None)
+    G2 = two.G().cpu().numpy()
+    two.close()
+    assert a1.sum().item() > 0
+    for z in range(2):
+        assert np.array_equal(a1.cpu().numpy(), a2[z].cpu().numpy())
+        assert np.array_equal(r1.cpu().numpy(), r2[z].cpu().numpy())
+        assert np.array_equal(G1, G2[z])
