@@ -147,16 +147,14 @@ __device__ __forceinline__ double xchg_xor(double v, int mask) {
 // Register positions are static: the panel is processed in groups of U
 // columns, and after each group the per-thread register array is rotated by
 // U, so physical position p holds column g*U + p (mod NB) during group g.
+// The panel factorization by threads 0 .. NT-1 of a workgroup (pointers
+// already shifted to the chain).
 template <int RPT, int NB, int NT>
-__global__ void __launch_bounds__(NT)
-k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __restrict__ Vq,
-           double* __restrict__ Tq, double* __restrict__ tau_out, size_t zs) {
+__device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, int n, int j, int nbp,
+                                              double* __restrict__ Vq, double* __restrict__ Tq,
+                                              double* __restrict__ tau_out) {
   constexpr int NW = NT / 64;
   constexpr int U = 4;
-  A = zw(A, zs);
-  Vq = zw(Vq, zs);
-  Tq = zw(Tq, zs);
-  tau_out = zw(tau_out, zs);
   static_assert(NB % U == 0 && NB <= kNBmax && NT >= NB, "panel shape");
   __shared__ double red[2][NW][NB];   // per-wave partial sums d_t
   __shared__ double rowv[2][NB];      // row jc of the panel
@@ -322,6 +320,13 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
   if (tid < nbp) tau_out[j + tid] = taus[tid];
 }
 
+template <int RPT, int NB, int NT>
+__global__ void __launch_bounds__(NT)
+k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __restrict__ Vq,
+           double* __restrict__ Tq, double* __restrict__ tau_out, size_t zs) {
+  qr_panel_body<RPT, NB, NT>(zw(A, zs), lda, n, j, nbp, zw(Vq, zs), zw(Tq, zs), zw(tau_out, zs));
+}
+
 // C[j:n, s0:s0+SW] -= V op(T) (V^T C[j:n, s0:s0+SW]) for the panel at column
 // j (width nbp <= 32): op(T) = T^T applies H^T = H_{nbp-1} ... H_0 (the
 // factorization / Q^T direction), op(T) = T applies H = H_0 ... H_{nbp-1}.
@@ -463,6 +468,34 @@ k_apply_wy_all(double* __restrict__ C, int ldc, int n, const double* __restrict_
     apply_wy_stripe<SW>(sh, C, ldc, n, j, pt.width[p], n, s0, V, ldv, Tq + (size_t)p * kNBmax * kNBmax,
                         backward ? 0 : 1);
     __syncthreads();  // this panel's update is read by the next one
+  }
+}
+
+// One step of the factorization with look-ahead: workgroup 0 applies panel
+// p's reflector (columns jp.., width nbp, factor Tp) to the next panel's
+// columns and then factors that panel (threads 0 .. NT-1); the other
+// workgroups apply panel p's reflector to the 16-column stripes beyond the
+// next panel, concurrently.  Both read only panel p's V and T and write
+// disjoint columns.
+template <int RPT, int NB, int NT>
+__global__ void __launch_bounds__(512)
+k_qr_step(double* __restrict__ A, int lda, int n, int jp, int nbp, const double* __restrict__ Tp,
+          int jn, int nbn, double* __restrict__ Vq, double* __restrict__ Tn, double* __restrict__ tau,
+          size_t zs) {
+  static_assert(NT <= 512, "the panel runs inside a 512-thread workgroup");
+  __shared__ WyLds<16> sh;
+  A = zw(A, zs);
+  Vq = zw(Vq, zs);
+  Tp = zw(Tp, zs);
+  if (blockIdx.x == 0) {
+    for (int s0 = jn; s0 < jn + nbn; s0 += 16) {
+      apply_wy_stripe<16>(sh, A, lda, n, jp, nbp, n, s0, Vq, lda, Tp, 1);
+      __syncthreads();
+    }
+    if (threadIdx.x >= NT) return;  // waves past the panel's leave; barriers count the rest
+    qr_panel_body<RPT, NB, NT>(A, lda, n, jn, nbn, Vq, zw(Tn, zs), zw(tau, zs));
+  } else {
+    apply_wy_stripe<16>(sh, A, lda, n, jp, nbp, n, jn + nbn + (blockIdx.x - 1) * 16, Vq, lda, Tp, 1);
   }
 }
 
@@ -686,15 +719,40 @@ int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q) {
   if (n > 2048) return set_error(KDQMC_EUNSUPPORTED, "QR order above 2048");
   const size_t nn = (size_t)n * ld;
   hipLaunchKernelGGL(k_zero, dim3((nn + 255) / 256, 1, c->nch), dim3(256), 0, c->stream, c->Vq, nn, c->zs);
-  int npan = 0;
-  for (int j = 0; j < n; ++npan) {
-    const int nbp = std::min(panel_width(n - j), n - j);
-    double* Tp = c->Tq + (size_t)npan * kNBmax * kNBmax;
-    KDQMC_TRY(launch_panel(c, A, ld, n, j, nbp, Tp));
-    KDQMC_TRY(launch_apply(c, A, ld, n, j, nbp, j + nbp, n, Tp, true));
+  // the first panel alone; then per panel one step launch (the previous
+  // panel's update of the next panel's columns, that panel's factorization,
+  // and concurrently the previous panel's update of the columns beyond) while
+  // the next panel has at most 512 rows, else the update (split over the chip
+  // for taller panels, which is faster there than one workgroup per stripe)
+  // and the panel apart
+  int npan = 0, j = 0;
+  int nbp = std::min(panel_width(n), n);
+  KDQMC_TRY(launch_panel(c, A, ld, n, 0, nbp, c->Tq));
+  for (;;) {
     c->qr_panel_start[npan] = j;
     c->qr_panel_width[npan] = nbp;
-    j += nbp;
+    const int jn = j + nbp;
+    if (jn >= n) {
+      ++npan;
+      break;
+    }
+    const int nbn = std::min(panel_width(n - jn), n - jn);
+    double* Tp = c->Tq + (size_t)npan * kNBmax * kNBmax;
+    double* Tn = Tp + kNBmax * kNBmax;
+    const int mn = n - jn;
+    if (mn <= 512) {
+      const dim3 grid(1 + (n - jn - nbn + 15) / 16, 1, c->nch);
+      const int e0 = prof_mark(c);
+      hipLaunchKernelGGL((k_qr_step<2, 16, 256>), grid, dim3(512), 0, c->stream, A, ld, n, j, nbp, Tp, jn, nbn,
+                         c->Vq, Tn, c->tau, c->zs);
+      prof_pair(c, PH_QR_PANEL, e0, prof_mark(c));
+    } else {
+      KDQMC_TRY(launch_apply(c, A, ld, n, j, nbp, jn, n, Tp, true));
+      KDQMC_TRY(launch_panel(c, A, ld, n, jn, nbn, Tn));
+    }
+    ++npan;
+    j = jn;
+    nbp = nbn;
   }
   c->qr_npan = npan;
   if (Q) {
