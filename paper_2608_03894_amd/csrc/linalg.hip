@@ -116,20 +116,55 @@ int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, 
 constexpr int kNBmax = 32;
 constexpr int kPanelThreads = 256;
 
-// Lane exchange within a wave for a double: DPP quad permutations for xor 1
-// and xor 2 (no LDS traffic), ds_bpermute otherwise.
-__device__ __forceinline__ double xchg_xor(double v, int mask) {
-  if (mask == 1) {  // quad_perm [1,0,3,2]
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0xB1, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0xB1, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
+// Lane exchange within a wave (the value of lane ^ mask) without LDS
+// traffic: DPP quad permutations for masks 1 and 2; for 4 and 8 a shift
+// within the row of 16 lanes whose direction is the lane's bit (lane + mask
+// where the bit is clear, lane - mask where it is set); for 16 and 32 the
+// permlane swaps, which hand every lane both members of its pair.
+__device__ __forceinline__ int xchg_dword(int x, int mask, int lane) {
+  switch (mask) {
+    case 1:
+      return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+    case 2:
+      return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+    case 4: {
+      const int up = __builtin_amdgcn_mov_dpp(x, 0x104, 0xF, 0xF, true);  // row_shl:4
+      const int dn = __builtin_amdgcn_mov_dpp(x, 0x114, 0xF, 0xF, true);  // row_shr:4
+      return (lane & 4) ? dn : up;
+    }
+    case 8: {
+      const int up = __builtin_amdgcn_mov_dpp(x, 0x108, 0xF, 0xF, true);  // row_shl:8
+      const int dn = __builtin_amdgcn_mov_dpp(x, 0x118, 0xF, 0xF, true);  // row_shr:8
+      return (lane & 8) ? dn : up;
+    }
+    case 16: {  // element 0: even rows' values in every row; element 1: odd rows'
+      const auto sw = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+      return (lane & 16) ? (int)sw[0] : (int)sw[1];
+    }
+    default: {  // 32; element 0: lanes 0-31's values in both halves; element 1: lanes 32-63's
+      const auto sw = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+      return (lane & 32) ? (int)sw[0] : (int)sw[1];
+    }
   }
-  if (mask == 2) {  // quad_perm [2,3,0,1]
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x4E, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x4E, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-  }
-  return __shfl_xor(v, mask);
+}
+__device__ __forceinline__ double xchg_xor(double v, int mask, int lane) {
+  return __hiloint2double(xchg_dword(__double2hiint(v), mask, lane), xchg_dword(__double2loint(v), mask, lane));
+}
+
+// 1/sqrt(x) and 1/x for normal positive (resp. nonzero) x: the hardware
+// estimates refined by two Newton steps each (the estimates are good to about 2^-24
+// and the error squares per step).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) r = fma(r, fma(-x, r, 1.0), r);
+  return r;
 }
 
 // One panel of the Householder QR.  Column c (row jc = j + c) needs, over
@@ -144,9 +179,21 @@ __device__ __forceinline__ double xchg_xor(double v, int mask) {
 // reduction of NB sums and one barrier (the reduction buffers and the
 // published row are double-buffered).
 //
+// The same broadcast coefficients build T: with w_t = -tau_c (V^T V)[t][c]
+// for the earlier columns t, column c of T is T[0:c, 0:c] w (and tau_c on
+// the diagonal).  Workgroups of 256 threads keep row l of T in lane l's
+// registers and add one term per earlier column (no pass over T follows the
+// loop); larger ones, with less register room per thread, store V^T V and
+// build T after the loop with one wave.
+//
+// Workgroups of 256 threads also stage the panel through LDS on the way in
+// and out, so that global loads and stores run along rows (16 lanes per row
+// of 16 columns) rather than one row per lane, which touches 64 cache lines
+// per instruction.
+//
 // Register positions are static: the panel is processed in groups of U
-// columns, and after each group the per-thread register array is rotated by
-// U, so physical position p holds column g*U + p (mod NB) during group g.
+// columns, and after each group the per-thread register arrays are rotated
+// by U, so physical position p holds column g*U + p (mod NB) during group g.
 // The panel factorization by threads 0 .. NT-1 of a workgroup (pointers
 // already shifted to the chain).
 template <int RPT, int NB, int NT>
@@ -156,22 +203,45 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
   constexpr int NW = NT / 64;
   constexpr int U = 4;
   static_assert(NB % U == 0 && NB <= kNBmax && NT >= NB, "panel shape");
+  constexpr bool kRegT = NT <= 256;
   __shared__ double red[2][NW][NB];   // per-wave partial sums d_t
   __shared__ double rowv[2][NB];      // row jc of the panel
-  __shared__ double Sv[NB][NB + 1];   // V^T V, strict upper part
+  __shared__ double Sv[kRegT ? 1 : NB][NB + 1];  // V^T V, strict upper part
   __shared__ double Ts[NB][NB + 1];
+  __shared__ double Pst[kRegT ? RPT * NT : 1][NB + 1];  // the panel, staged
   __shared__ double betas[NB];
   __shared__ double taus[NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int pl = lane & (NB - 1);     // the sum this lane ends up holding
   double a[RPT][NB];
+  double tr[NB];  // row `lane` of T (lanes below NB), rotated with a
   int row[RPT];
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    row[q] = j + tid + q * NT;
+  for (int p = 0; p < NB; ++p) tr[p] = 0.0;
 #pragma unroll
-    for (int cc = 0; cc < NB; ++cc)
-      a[q][cc] = (row[q] < n && cc < nbp) ? A[(size_t)row[q] * lda + j + cc] : 0.0;
+  for (int q = 0; q < RPT; ++q) row[q] = j + tid + q * NT;
+  const int mrows = std::min(n - j, RPT * NT);  // rows of the panel
+  const int sc = lane & 15, sr = tid >> 4;      // staging: 16 lanes per row
+  if constexpr (kRegT) {
+    static_assert(NB == 16, "staging assumes 16 columns");
+    // rows past the panel and columns past nbp read a valid address and store 0
+#pragma unroll 8
+    for (int r = sr; r < mrows; r += NT / 16) {
+      const bool ok = sc < nbp;
+      const double v = A[(size_t)(j + r) * lda + j + (ok ? sc : 0)];
+      Pst[r][sc] = ok ? v : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc) a[q][cc] = (row[q] < n) ? Pst[tid + q * NT][cc] : 0.0;
+  } else {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc)
+        a[q][cc] = (row[q] < n && cc < nbp) ? A[(size_t)row[q] * lda + j + cc] : 0.0;
   }
 
   const int ngroups = (nbp + U - 1) / U;
@@ -211,13 +281,13 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
               if (h < cnt) {
                 const double keep = bit ? part[2 * h + 1] : part[2 * h];
                 const double send = bit ? part[2 * h] : part[2 * h + 1];
-                part[h] = keep + xchg_xor(send, 1 << b);
+                part[h] = keep + xchg_xor(send, 1 << b, lane);
               }
             }
           }
           double v = part[0];
 #pragma unroll
-          for (int o = NB; o < 64; o <<= 1) v += xchg_xor(v, o);
+          for (int o = NB; o < 64; o <<= 1) v += xchg_xor(v, o, lane);
           if (lane < NB) red[buf][wave][lane] = v;
         }
         __syncthreads();
@@ -233,16 +303,22 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
           beta = alpha;
           scale = 0.0;
         } else {
-          const double nrm = sqrt(ss);
+          // alpha - beta = alpha + sign(alpha) nrm (no cancellation) and
+          // tau = (beta - alpha) / beta = |alpha - beta| / nrm
+          const double y = rsqrt_nr(ss);
+          const double nrm = ss * y;
+          const double d = (alpha >= 0.0) ? alpha + nrm : alpha - nrm;
           beta = (alpha >= 0.0) ? -nrm : nrm;
-          tau_c = (beta - alpha) / beta;
-          scale = 1.0 / (alpha - beta);
+          tau_c = fabs(d) * y;
+          scale = rcp_nr(d);
         }
         const double wv = (tot - beta * rv) * scale;  // v_c^T a_t, t at position pl
         const double tw = -tau_c * wv;
-        if (wave == 0 && lane < NB) {
-          if (lane < i) Sv[g * U + lane][c] = wv;
-          else if (lane >= live) Sv[g * U + lane - NB][c] = wv;
+        if constexpr (!kRegT) {
+          if (wave == 0 && lane < NB) {
+            if (lane < i) Sv[g * U + lane][c] = wv;
+            else if (lane >= live) Sv[g * U + lane - NB][c] = wv;
+          }
         }
         if (tid == 0) {
           betas[c] = beta;
@@ -256,14 +332,21 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
           vq[q] = v;
           if (r >= jc) a[q][i] = v;
         }
+        // trailing positions (i, live) take the rank-1 update; the factored
+        // ones (below i, or from live on) add to row `lane` of T's column c
+        double tsum = 0.0;
 #pragma clang loop unroll(full)
-        for (int p = i + 1; p < NB; ++p) {
-          if (p < live) {
+        for (int p = 0; p < NB; ++p) {
+          if (p == i) continue;
+          if (p > i && p < live) {
             const double f = lane_value(tw, p);
 #pragma unroll
             for (int q = 0; q < RPT; ++q) a[q][p] = fma(f, vq[q], a[q][p]);
+          } else if constexpr (kRegT) {
+            tsum = fma(tr[p], lane_value(tw, p), tsum);
           }
         }
+        if constexpr (kRegT) tr[i] = (lane < c) ? tsum : (lane == c ? tau_c : 0.0);
       }
     }
 #pragma unroll
@@ -276,41 +359,72 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
 #pragma unroll
       for (int u = 0; u < U; ++u) a[q][NB - U + u] = keep[u];
     }
+    if constexpr (kRegT) {
+      double keep[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) keep[u] = tr[u];
+#pragma unroll
+      for (int p = 0; p + U < NB; ++p) tr[p] = tr[p + U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) tr[NB - U + u] = keep[u];
+    }
   }
-  __syncthreads();
-  // T of the block reflector from V^T V: T[cc][cc] = tau_cc,
-  // T[0:cc, cc] = -tau_cc T[0:cc, 0:cc] (V^T V)[0:cc, cc]  (one wave, no barriers)
-  if (wave == 0) {
-    for (int cc = 0; cc < nbp; ++cc) {
-      double tv = 0.0;
-      if (lane < cc) {
-        for (int t = lane; t < cc; ++t) tv += Ts[lane][t] * Sv[t][cc];
-        tv *= -taus[cc];
+  const int rot = (ngroups * U) % NB;  // position p now holds column (p + rot) % NB
+  if constexpr (kRegT) {
+    if (wave == 0 && lane < NB) {
+#pragma unroll
+      for (int p = 0; p < NB; ++p) Ts[lane][(p + rot < NB) ? p + rot : p + rot - NB] = tr[p];
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+      for (int p = 0; p < NB; ++p) Pst[tid + q * NT][(p + rot < NB) ? p + rot : p + rot - NB] = a[q][p];
+  } else {
+    __syncthreads();
+    // T[cc][cc] = tau_cc, T[0:cc, cc] = -tau_cc T[0:cc, 0:cc] (V^T V)[0:cc, cc]
+    // (one wave, no barriers)
+    if (wave == 0) {
+      for (int cc = 0; cc < nbp; ++cc) {
+        double tv = 0.0;
+        if (lane < cc) {
+          for (int t = lane; t < cc; ++t) tv += Ts[lane][t] * Sv[t][cc];
+          tv *= -taus[cc];
+        }
+        if (lane < cc) Ts[lane][cc] = tv;
+        if (lane == cc) Ts[cc][cc] = taus[cc];
+        if (lane > cc && lane < NB) Ts[lane][cc] = 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
       }
-      if (lane < cc) Ts[lane][cc] = tv;
-      if (lane == cc) Ts[cc][cc] = taus[cc];
-      if (lane > cc && lane < NB) Ts[lane][cc] = 0.0;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
     }
   }
   __syncthreads();
-  const int rot = (ngroups * U) % NB;  // position p now holds column (p + rot) % NB
+  if constexpr (kRegT) {
+    // R above the diagonal, beta on it, zeros below; V: zeros above, 1, v below
+    for (int r = sr; r < mrows; r += NT / 16) {
+      if (sc >= nbp) continue;
+      const int gr = j + r, jc = j + sc;
+      const double x = Pst[r][sc];
+      A[(size_t)gr * lda + jc] = (gr < jc) ? x : (gr == jc ? betas[sc] : 0.0);
+      Vq[(size_t)gr * lda + jc] = (gr < jc) ? 0.0 : (gr == jc ? 1.0 : x);
+    }
+  } else {
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int r = row[q];
-    if (r >= n) continue;
+    for (int q = 0; q < RPT; ++q) {
+      const int r = row[q];
+      if (r >= n) continue;
 #pragma unroll
-    for (int p = 0; p < NB; ++p) {
-      const int cc = (p + rot < NB) ? p + rot : p + rot - NB;
-      if (cc >= nbp) continue;
-      const int jc = j + cc;
-      double rvv, vv;
-      if (r < jc) { rvv = a[q][p]; vv = 0.0; }
-      else if (r == jc) { rvv = betas[cc]; vv = 1.0; }
-      else { rvv = 0.0; vv = a[q][p]; }
-      A[(size_t)r * lda + jc] = rvv;
-      Vq[(size_t)r * lda + jc] = vv;
+      for (int p = 0; p < NB; ++p) {
+        const int cc = (p + rot < NB) ? p + rot : p + rot - NB;
+        if (cc >= nbp) continue;
+        const int jc = j + cc;
+        double rvv, vv;
+        if (r < jc) { rvv = a[q][p]; vv = 0.0; }
+        else if (r == jc) { rvv = betas[cc]; vv = 1.0; }
+        else { rvv = 0.0; vv = a[q][p]; }
+        A[(size_t)r * lda + jc] = rvv;
+        Vq[(size_t)r * lda + jc] = vv;
+      }
     }
   }
   for (int idx = tid; idx < kNBmax * kNBmax; idx += NT) {
