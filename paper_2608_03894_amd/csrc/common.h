@@ -133,6 +133,15 @@ __device__ __forceinline__ T* zc_at(T* p, size_t zn, int z) {
   return p ? p + (size_t)z * zn : p;
 }
 
+// Wave-level ordering of LDS accesses (LDS writes and reads within one wave;
+// a wave's LDS operations complete in order, the fences keep the compiler
+// from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Lane `src` (wave-uniform) of a double held in a vector register; the value
 // is wave-uniform afterwards (scalar registers).
 __device__ __forceinline__ double lane_value(double v, int src) {

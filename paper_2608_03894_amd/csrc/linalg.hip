@@ -191,9 +191,11 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // of 16 columns) rather than one row per lane, which touches 64 cache lines
 // per instruction.
 //
-// Register positions are static: the panel is processed in groups of U
-// columns, and after each group the per-thread register arrays are rotated
-// by U, so physical position p holds column g*U + p (mod NB) during group g.
+// Register positions are static.  Workgroups of 256 threads unroll all NB
+// columns, so whether a position is trailing or factored is known at compile
+// time (no selects between the two updates).  The larger ones process groups
+// of U = 4 columns and rotate the register arrays by U after each group, so
+// physical position p holds column g*U + p (mod NB) during group g.
 // The panel factorization by threads 0 .. NT-1 of a workgroup (pointers
 // already shifted to the chain).
 template <int RPT, int NB, int NT>
@@ -201,9 +203,11 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
                                               double* __restrict__ Vq, double* __restrict__ Tq,
                                               double* __restrict__ tau_out) {
   constexpr int NW = NT / 64;
-  constexpr int U = 4;
-  static_assert(NB % U == 0 && NB <= kNBmax && NT >= NB, "panel shape");
   constexpr bool kRegT = NT <= 256;
+  // 256-thread workgroups unroll the whole panel as one group (every
+  // position's role static, no rotation); the others rotate by 4
+  constexpr int U = kRegT ? NB : 4;
+  static_assert(NB % U == 0 && NB <= kNBmax && NT >= NB, "panel shape");
   __shared__ double red[2][NW][NB];   // per-wave partial sums d_t
   __shared__ double rowv[2][NB];      // row jc of the panel
   __shared__ double Sv[kRegT ? 1 : NB][NB + 1];  // V^T V, strict upper part
@@ -224,12 +228,19 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
   const int sc = lane & 15, sr = tid >> 4;      // staging: 16 lanes per row
   if constexpr (kRegT) {
     static_assert(NB == 16, "staging assumes 16 columns");
-    // rows past the panel and columns past nbp read a valid address and store 0
-#pragma unroll 8
-    for (int r = sr; r < mrows; r += NT / 16) {
-      const bool ok = sc < nbp;
-      const double v = A[(size_t)(j + r) * lda + j + (ok ? sc : 0)];
-      Pst[r][sc] = ok ? v : 0.0;
+    // all loads issued before the first wait: rows past the panel and columns
+    // past nbp read a valid address and store 0
+    constexpr int kPass = RPT * NT / 16;
+    double v[kPass];
+#pragma unroll
+    for (int k = 0; k < kPass; ++k) {
+      const int r = sr + k * (NT / 16);
+      v[k] = A[(size_t)(j + std::min(r, mrows - 1)) * lda + j + (sc < nbp ? sc : 0)];
+    }
+#pragma unroll
+    for (int k = 0; k < kPass; ++k) {
+      const int r = sr + k * (NT / 16);
+      Pst[r][sc] = (r < mrows && sc < nbp) ? v[k] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -247,7 +258,7 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
   const int ngroups = (nbp + U - 1) / U;
 #pragma unroll 1
   for (int g = 0; g < ngroups; ++g) {
-    const int live = NB - g * U;  // positions below this hold columns not yet factored
+    const int live = kRegT ? NB : NB - g * U;  // positions below this hold columns not yet factored
 #pragma clang loop unroll(full)
     for (int i = 0; i < U; ++i) {
       const int c = g * U + i;
@@ -339,9 +350,9 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
         for (int p = 0; p < NB; ++p) {
           if (p == i) continue;
           if (p > i && p < live) {
-            const double f = lane_value(tw, p);
+            const double fp = lane_value(tw, p);
 #pragma unroll
-            for (int q = 0; q < RPT; ++q) a[q][p] = fma(f, vq[q], a[q][p]);
+            for (int q = 0; q < RPT; ++q) a[q][p] = fma(fp, vq[q], a[q][p]);
           } else if constexpr (kRegT) {
             tsum = fma(tr[p], lane_value(tw, p), tsum);
           }
@@ -401,12 +412,19 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
   __syncthreads();
   if constexpr (kRegT) {
     // R above the diagonal, beta on it, zeros below; V: zeros above, 1, v below
-    for (int r = sr; r < mrows; r += NT / 16) {
-      if (sc >= nbp) continue;
-      const int gr = j + r, jc = j + sc;
-      const double x = Pst[r][sc];
-      A[(size_t)gr * lda + jc] = (gr < jc) ? x : (gr == jc ? betas[sc] : 0.0);
-      Vq[(size_t)gr * lda + jc] = (gr < jc) ? 0.0 : (gr == jc ? 1.0 : x);
+    constexpr int kPass = RPT * NT / 16;
+    const double bsc = betas[sc];
+    double x[kPass];
+#pragma unroll
+    for (int k = 0; k < kPass; ++k) x[k] = Pst[sr + k * (NT / 16)][sc];
+#pragma unroll
+    for (int k = 0; k < kPass; ++k) {
+      const int r = sr + k * (NT / 16);
+      if (r < mrows && sc < nbp) {
+        const int gr = j + r, jc = j + sc;
+        A[(size_t)gr * lda + jc] = (r < sc) ? x[k] : (r == sc ? bsc : 0.0);
+        Vq[(size_t)gr * lda + jc] = (r < sc) ? 0.0 : (r == sc ? 1.0 : x[k]);
+      }
     }
   } else {
 #pragma unroll

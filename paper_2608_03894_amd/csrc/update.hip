@@ -296,15 +296,6 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
 //   Z'[n][q] = delta_nq - sum_{r<n} u_r[p] Z'[r][q],
 // with the same remote values w_r[p], u_r[p] as the sites use.
 // ---------------------------------------------------------------------------
-// Wave-level ordering of LDS accesses (one wave runs the decisions; its LDS
-// operations complete in order, the fence keeps the compiler from moving
-// them across).
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 // The decisions of one window whose submatrix G0 (tilde frame, zero outside
 // wn x wn) is in g0s, run by the calling wave alone.  sx, ux, fx: field,
 // uniform and forced flag of site `lane` (lanes < wn).  Writes the flipped
