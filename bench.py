@@ -80,8 +80,8 @@ CU_FP64_TFS = FP64_PEAK_TFS / 256   # one compute unit's share (4 SIMDs x 16 FP6
 
 
 def panel_width(m):
-    """The library's QR panel width for a panel of m rows."""
-    return 16 if m <= 512 else 32 if m <= 1024 else 16
+    """The library's QR panel width (16 columns for every panel height m)."""
+    return 16
 
 
 def qr_panel_flops(n):

@@ -103,9 +103,9 @@ int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, 
 // ---------------------------------------------------------------------------
 // Householder QR, blocked (compact WY form).
 //
-// Panels of width nbp (16 up to 512 rows, 32 up to 1024 rows, else 16) are
-// factored by one workgroup of NT = 256, 512 or 1024 threads holding the
-// panel in registers (thread t owns rows j+t and j+t+NT).  H_c = I - tau_c v_c v_c^T with
+// Panels of width nbp = 16 are factored by one workgroup of NT = 256 threads
+// (512 for panels of more than 1024 rows) holding the panel in registers
+// (thread t owns rows j+t, j+t+NT, ..., RPT = 2 or 4 of them).  H_c = I - tau_c v_c v_c^T with
 // v_c[jc] = 1 (LAPACK convention); H_0 ... H_{nbp-1} = I - V T V^T.
 // Outputs: R in A (zeros below the diagonal), explicit V in Vq (unit diagonal,
 // zeros above), T in Tq (row stride 32), tau.
@@ -186,16 +186,14 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // loop); larger ones, with less register room per thread, store V^T V and
 // build T after the loop with one wave.
 //
-// Workgroups of 256 threads also stage the panel through LDS on the way in
-// and out, so that global loads and stores run along rows (16 lanes per row
+// The panel passes through LDS on the way in and out (chunks of up to 1024
+// rows), so that global loads and stores run along rows (16 lanes per row
 // of 16 columns) rather than one row per lane, which touches 64 cache lines
 // per instruction.
 //
-// Register positions are static.  Workgroups of 256 threads unroll all NB
-// columns, so whether a position is trailing or factored is known at compile
-// time (no selects between the two updates).  The larger ones process groups
-// of U = 4 columns and rotate the register arrays by U after each group, so
-// physical position p holds column g*U + p (mod NB) during group g.
+// All NB columns are unrolled, so register indices and whether a column is
+// trailing or factored are compile-time constants (no selects between the
+// two updates).
 // The panel factorization by threads 0 .. NT-1 of a workgroup (pointers
 // already shifted to the chain).
 template <int RPT, int NB, int NT>
@@ -203,193 +201,160 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
                                               double* __restrict__ Vq, double* __restrict__ Tq,
                                               double* __restrict__ tau_out) {
   constexpr int NW = NT / 64;
-  constexpr bool kRegT = NT <= 256;
-  // 256-thread workgroups unroll the whole panel as one group (every
-  // position's role static, no rotation); the others rotate by 4
-  constexpr int U = kRegT ? NB : 4;
-  static_assert(NB % U == 0 && NB <= kNBmax && NT >= NB, "panel shape");
+  static_assert(NB == 16 && NT >= NB, "panel shape (staging assumes 16 columns)");
+  constexpr int kRows = RPT * NT;                         // rows the workgroup holds
+  constexpr int kChunk = kRows < 1024 ? kRows : 1024;     // rows staged at a time
+  constexpr int kQc = kChunk / NT;                        // row slots per thread and chunk
+  constexpr int kPass = kChunk / (NT / 16);               // staging rows per thread and chunk
+  static_assert(kRows % kChunk == 0 && kChunk % NT == 0, "staging chunks");
+  constexpr bool kRegT = NT <= 256;  // T in registers (else built from V^T V in LDS)
   __shared__ double red[2][NW][NB];   // per-wave partial sums d_t
   __shared__ double rowv[2][NB];      // row jc of the panel
-  __shared__ double Sv[kRegT ? 1 : NB][NB + 1];  // V^T V, strict upper part
   __shared__ double Ts[NB][NB + 1];
-  __shared__ double Pst[kRegT ? RPT * NT : 1][NB + 1];  // the panel, staged
+  __shared__ double Sv[kRegT ? 1 : NB][NB + 1];  // V^T V, strict upper part
+  __shared__ double Pst[kChunk][NB + 1];  // the panel, staged a chunk at a time
   __shared__ double betas[NB];
   __shared__ double taus[NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int pl = lane & (NB - 1);     // the sum this lane ends up holding
   double a[RPT][NB];
-  double tr[NB];  // row `lane` of T (lanes below NB), rotated with a
+  double tr[NB];  // row `lane` of T (lanes below NB)
   int row[RPT];
 #pragma unroll
   for (int p = 0; p < NB; ++p) tr[p] = 0.0;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) row[q] = j + tid + q * NT;
-  const int mrows = std::min(n - j, RPT * NT);  // rows of the panel
-  const int sc = lane & 15, sr = tid >> 4;      // staging: 16 lanes per row
-  if constexpr (kRegT) {
-    static_assert(NB == 16, "staging assumes 16 columns");
-    // all loads issued before the first wait: rows past the panel and columns
-    // past nbp read a valid address and store 0
-    constexpr int kPass = RPT * NT / 16;
+  const int mrows = std::min(n - j, kRows);  // rows of the panel
+  const int sc = lane & 15, sr = tid >> 4;   // staging: 16 lanes per row
+  // per chunk, all loads issued before the first wait (rows past the panel
+  // and columns past nbp read a valid address and store 0); thread t then
+  // takes its rows t + q NT of the chunk
+#pragma unroll
+  for (int h = 0; h < kRows / kChunk; ++h) {
     double v[kPass];
 #pragma unroll
     for (int k = 0; k < kPass; ++k) {
-      const int r = sr + k * (NT / 16);
+      const int r = h * kChunk + sr + k * (NT / 16);
       v[k] = A[(size_t)(j + std::min(r, mrows - 1)) * lda + j + (sc < nbp ? sc : 0)];
     }
+    if (h > 0) __syncthreads();  // the previous chunk has been read
 #pragma unroll
     for (int k = 0; k < kPass; ++k) {
-      const int r = sr + k * (NT / 16);
-      Pst[r][sc] = (r < mrows && sc < nbp) ? v[k] : 0.0;
+      const int r = h * kChunk + sr + k * (NT / 16);
+      Pst[sr + k * (NT / 16)][sc] = (r < mrows && sc < nbp) ? v[k] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < RPT; ++q)
+    for (int qq = 0; qq < kQc; ++qq) {
+      const int q = h * kQc + qq;
 #pragma unroll
-      for (int cc = 0; cc < NB; ++cc) a[q][cc] = (row[q] < n) ? Pst[tid + q * NT][cc] : 0.0;
-  } else {
-#pragma unroll
-    for (int q = 0; q < RPT; ++q)
-#pragma unroll
-      for (int cc = 0; cc < NB; ++cc)
-        a[q][cc] = (row[q] < n && cc < nbp) ? A[(size_t)row[q] * lda + j + cc] : 0.0;
+      for (int cc = 0; cc < NB; ++cc) a[q][cc] = (row[q] < n) ? Pst[tid + qq * NT][cc] : 0.0;
+    }
   }
 
-  const int ngroups = (nbp + U - 1) / U;
-#pragma unroll 1
-  for (int g = 0; g < ngroups; ++g) {
-    const int live = kRegT ? NB : NB - g * U;  // positions below this hold columns not yet factored
+  // every column unrolled: register indices and the roles of the positions
+  // (factored below c, trailing above) are compile-time constants
 #pragma clang loop unroll(full)
-    for (int i = 0; i < U; ++i) {
-      const int c = g * U + i;
-      if (c < nbp) {
-        const int jc = j + c;
-        const int buf = c & 1;
-        if (tid == c) {  // owner of row jc (its first row)
+  for (int c = 0; c < NB; ++c) {
+    if (c < nbp) {
+      const int jc = j + c;
+      const int buf = c & 1;
+      if (tid == c) {  // owner of row jc (its first row)
 #pragma unroll
-          for (int p = 0; p < NB; ++p) rowv[buf][p] = a[0][p];
-        }
-        double x[RPT];
+        for (int p = 0; p < NB; ++p) rowv[buf][p] = a[0][p];
+      }
+      double x[RPT];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) x[q] = (row[q] >= jc && row[q] < n) ? a[q][i] : 0.0;
-        double part[NB];
+      for (int q = 0; q < RPT; ++q) x[q] = (row[q] >= jc && row[q] < n) ? a[q][c] : 0.0;
+      double part[NB];
 #pragma unroll
-        for (int p = 0; p < NB; ++p) {
-          double sacc = 0.0;
+      for (int p = 0; p < NB; ++p) {
+        double sacc = 0.0;
 #pragma unroll
-          for (int q = 0; q < RPT; ++q) sacc = fma(x[q], a[q][p], sacc);
-          part[p] = sacc;
-        }
-        // reduce-scatter within the wave: lane l keeps sum number l % NB
-        {
-          int cnt = NB;
+        for (int q = 0; q < RPT; ++q) sacc = fma(x[q], a[q][p], sacc);
+        part[p] = sacc;
+      }
+      // reduce-scatter within the wave: lane l keeps sum number l % NB
+      {
+        int cnt = NB;
 #pragma unroll
-          for (int b = 0; (1 << b) < NB; ++b) {
-            const int bit = (lane >> b) & 1;
-            cnt >>= 1;
+        for (int b = 0; (1 << b) < NB; ++b) {
+          const int bit = (lane >> b) & 1;
+          cnt >>= 1;
 #pragma unroll
-            for (int h = 0; h < NB / 2; ++h) {
-              if (h < cnt) {
-                const double keep = bit ? part[2 * h + 1] : part[2 * h];
-                const double send = bit ? part[2 * h] : part[2 * h + 1];
-                part[h] = keep + xchg_xor(send, 1 << b, lane);
-              }
+          for (int h = 0; h < NB / 2; ++h) {
+            if (h < cnt) {
+              const double keep = bit ? part[2 * h + 1] : part[2 * h];
+              const double send = bit ? part[2 * h] : part[2 * h + 1];
+              part[h] = keep + xchg_xor(send, 1 << b, lane);
             }
           }
-          double v = part[0];
+        }
+        double v = part[0];
 #pragma unroll
-          for (int o = NB; o < 64; o <<= 1) v += xchg_xor(v, o, lane);
-          if (lane < NB) red[buf][wave][lane] = v;
-        }
-        __syncthreads();
-        double tot = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) tot += red[buf][w][pl];
-        const double rv = rowv[buf][pl];
-        const double ss = lane_value(tot, i);
-        const double alpha = lane_value(rv, i);
-        double tau_c, beta, scale;
-        if (!(ss - alpha * alpha > 0.0)) {  // nothing below the diagonal: H = I
-          tau_c = 0.0;
-          beta = alpha;
-          scale = 0.0;
-        } else {
-          // alpha - beta = alpha + sign(alpha) nrm (no cancellation) and
-          // tau = (beta - alpha) / beta = |alpha - beta| / nrm
-          const double y = rsqrt_nr(ss);
-          const double nrm = ss * y;
-          const double d = (alpha >= 0.0) ? alpha + nrm : alpha - nrm;
-          beta = (alpha >= 0.0) ? -nrm : nrm;
-          tau_c = fabs(d) * y;
-          scale = rcp_nr(d);
-        }
-        const double wv = (tot - beta * rv) * scale;  // v_c^T a_t, t at position pl
-        const double tw = -tau_c * wv;
-        if constexpr (!kRegT) {
-          if (wave == 0 && lane < NB) {
-            if (lane < i) Sv[g * U + lane][c] = wv;
-            else if (lane >= live) Sv[g * U + lane - NB][c] = wv;
-          }
-        }
-        if (tid == 0) {
-          betas[c] = beta;
-          taus[c] = tau_c;
-        }
-        double vq[RPT];
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          const int r = row[q];
-          const double v = (r < jc || r >= n) ? 0.0 : (r == jc ? 1.0 : a[q][i] * scale);
-          vq[q] = v;
-          if (r >= jc) a[q][i] = v;
-        }
-        // trailing positions (i, live) take the rank-1 update; the factored
-        // ones (below i, or from live on) add to row `lane` of T's column c
-        double tsum = 0.0;
-#pragma clang loop unroll(full)
-        for (int p = 0; p < NB; ++p) {
-          if (p == i) continue;
-          if (p > i && p < live) {
-            const double fp = lane_value(tw, p);
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) a[q][p] = fma(fp, vq[q], a[q][p]);
-          } else if constexpr (kRegT) {
-            tsum = fma(tr[p], lane_value(tw, p), tsum);
-          }
-        }
-        if constexpr (kRegT) tr[i] = (lane < c) ? tsum : (lane == c ? tau_c : 0.0);
+        for (int o = NB; o < 64; o <<= 1) v += xchg_xor(v, o, lane);
+        if (lane < NB) red[buf][wave][lane] = v;
       }
-    }
+      __syncthreads();
+      double tot = 0.0;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      double keep[U];
+      for (int w = 0; w < NW; ++w) tot += red[buf][w][pl];
+      const double rv = rowv[buf][pl];
+      const double ss = lane_value(tot, c);
+      const double alpha = lane_value(rv, c);
+      double tau_c, beta, scale;
+      if (!(ss - alpha * alpha > 0.0)) {  // nothing below the diagonal: H = I
+        tau_c = 0.0;
+        beta = alpha;
+        scale = 0.0;
+      } else {
+        // alpha - beta = alpha + sign(alpha) nrm (no cancellation) and
+        // tau = (beta - alpha) / beta = |alpha - beta| / nrm
+        const double y = rsqrt_nr(ss);
+        const double nrm = ss * y;
+        const double d = (alpha >= 0.0) ? alpha + nrm : alpha - nrm;
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau_c = fabs(d) * y;
+        scale = rcp_nr(d);
+      }
+      const double wv = (tot - beta * rv) * scale;  // v_c^T a_t for t = pl
+      const double tw = -tau_c * wv;
+      if constexpr (!kRegT) {
+        if (wave == 0 && lane < c) Sv[lane][c] = wv;
+      }
+      if (tid == 0) {
+        betas[c] = beta;
+        taus[c] = tau_c;
+      }
+      double vq[RPT];
 #pragma unroll
-      for (int u = 0; u < U; ++u) keep[u] = a[q][u];
+      for (int q = 0; q < RPT; ++q) {
+        const int r = row[q];
+        const double v = (r < jc || r >= n) ? 0.0 : (r == jc ? 1.0 : a[q][c] * scale);
+        vq[q] = v;
+        if (r >= jc) a[q][c] = v;
+      }
+      // trailing columns take the rank-1 update; the factored ones add to
+      // row `lane` of T's column c
+      double tsum = 0.0;
 #pragma unroll
-      for (int p = 0; p + U < NB; ++p) a[q][p] = a[q][p + U];
+      for (int p = 0; p < NB; ++p) {
+        if (p > c) {
+          const double fp = lane_value(tw, p);
 #pragma unroll
-      for (int u = 0; u < U; ++u) a[q][NB - U + u] = keep[u];
-    }
-    if constexpr (kRegT) {
-      double keep[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) keep[u] = tr[u];
-#pragma unroll
-      for (int p = 0; p + U < NB; ++p) tr[p] = tr[p + U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) tr[NB - U + u] = keep[u];
+          for (int q = 0; q < RPT; ++q) a[q][p] = fma(fp, vq[q], a[q][p]);
+        } else if (p < c) {
+          if constexpr (kRegT) tsum = fma(tr[p], lane_value(tw, p), tsum);
+        }
+      }
+      if constexpr (kRegT) tr[c] = (lane < c) ? tsum : (lane == c ? tau_c : 0.0);
     }
   }
-  const int rot = (ngroups * U) % NB;  // position p now holds column (p + rot) % NB
   if constexpr (kRegT) {
     if (wave == 0 && lane < NB) {
 #pragma unroll
-      for (int p = 0; p < NB; ++p) Ts[lane][(p + rot < NB) ? p + rot : p + rot - NB] = tr[p];
+      for (int p = 0; p < NB; ++p) Ts[lane][p] = tr[p];
     }
-#pragma unroll
-    for (int q = 0; q < RPT; ++q)
-#pragma unroll
-      for (int p = 0; p < NB; ++p) Pst[tid + q * NT][(p + rot < NB) ? p + rot : p + rot - NB] = a[q][p];
   } else {
     __syncthreads();
     // T[cc][cc] = tau_cc, T[0:cc, cc] = -tau_cc T[0:cc, 0:cc] (V^T V)[0:cc, cc]
@@ -409,39 +374,27 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
       }
     }
   }
-  __syncthreads();
-  if constexpr (kRegT) {
-    // R above the diagonal, beta on it, zeros below; V: zeros above, 1, v below
-    constexpr int kPass = RPT * NT / 16;
+  // out through LDS, a chunk at a time: R above the diagonal, beta on it,
+  // zeros below; V: zeros above, 1 on the diagonal, v below
+#pragma unroll
+  for (int h = 0; h < kRows / kChunk; ++h) {
+    if (h > 0) __syncthreads();  // the previous chunk has been stored
+#pragma unroll
+    for (int qq = 0; qq < kQc; ++qq)
+#pragma unroll
+      for (int p = 0; p < NB; ++p) Pst[tid + qq * NT][p] = a[h * kQc + qq][p];
+    __syncthreads();
     const double bsc = betas[sc];
     double x[kPass];
 #pragma unroll
     for (int k = 0; k < kPass; ++k) x[k] = Pst[sr + k * (NT / 16)][sc];
 #pragma unroll
     for (int k = 0; k < kPass; ++k) {
-      const int r = sr + k * (NT / 16);
+      const int r = h * kChunk + sr + k * (NT / 16);
       if (r < mrows && sc < nbp) {
         const int gr = j + r, jc = j + sc;
         A[(size_t)gr * lda + jc] = (r < sc) ? x[k] : (r == sc ? bsc : 0.0);
         Vq[(size_t)gr * lda + jc] = (r < sc) ? 0.0 : (r == sc ? 1.0 : x[k]);
-      }
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int r = row[q];
-      if (r >= n) continue;
-#pragma unroll
-      for (int p = 0; p < NB; ++p) {
-        const int cc = (p + rot < NB) ? p + rot : p + rot - NB;
-        if (cc >= nbp) continue;
-        const int jc = j + cc;
-        double rvv, vv;
-        if (r < jc) { rvv = a[q][p]; vv = 0.0; }
-        else if (r == jc) { rvv = betas[cc]; vv = 1.0; }
-        else { rvv = 0.0; vv = a[q][p]; }
-        A[(size_t)r * lda + jc] = rvv;
-        Vq[(size_t)r * lda + jc] = vv;
       }
     }
   }
@@ -783,7 +736,7 @@ namespace {
 // Width 16 at most 512 rows (the per-column reduction and update of a panel
 // scale with its width, and there the extra WY applies are cheap), 32 up to
 // 1024 rows, 16 beyond (registers).
-inline int panel_width(int rows) { return rows <= 512 ? 16 : rows <= 1024 ? 32 : 16; }
+inline int panel_width(int) { return 16; }
 
 int launch_panel(kdqmc_ctx* c, double* A, int ld, int n, int j, int nbp, double* Tp) {
   const int m = n - j;
@@ -791,10 +744,13 @@ int launch_panel(kdqmc_ctx* c, double* A, int ld, int n, int j, int nbp, double*
 #define PANEL(RPT, NB, NT)                                                                          \
   hipLaunchKernelGGL((k_qr_panel<RPT, NB, NT>), dim3(1, 1, c->nch), dim3(NT), 0, c->stream, A, ld, n, j, \
                      nbp, c->Vq, Tp, c->tau, c->zs)
-  // the panel's rows must fit in RPT * NT and its width in NB (panel_width)
+  // the panel's rows must fit in RPT * NT (lattices up to L = 24: N <= 1728)
+  // and its width in NB (panel_width); more rows per thread rather than more
+  // waves, whose per-wave reductions would compete for the same SIMDs
   if (m <= 512) PANEL(2, 16, 256);
-  else if (m <= 1024) PANEL(2, 32, 512);
-  else PANEL(2, 16, 1024);
+  else if (m <= 1024) PANEL(4, 16, 256);
+  else if (m <= 2048) PANEL(4, 16, 512);
+  else return set_error(KDQMC_EUNSUPPORTED, "QR panel of more than 2048 rows");
 #undef PANEL
   prof_pair(c, PH_QR_PANEL, e0, prof_mark(c));
   return KDQMC_OK;

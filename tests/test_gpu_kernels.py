@@ -58,7 +58,8 @@ def test_qr_f64(ch6, n):
 
 @pytest.mark.parametrize("L,n", [(12, 432), (12, 300), (24, 1728), (24, 1100)])
 def test_qr_f64_large(gpu_lib, L, n):
-    """Panels of 32 (<= 1024 rows) and 16 (more rows) columns, ragged tails."""
+    """16-column panels with 2 or 4 rows per thread (up to 512, 1024 and 2048
+    rows), ragged tails."""
     say("qr-large", L, n)
     ch = chain(L, 0.0, 1.0)
     N = ch.N
