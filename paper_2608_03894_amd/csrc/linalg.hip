@@ -11,71 +11,86 @@ namespace kdqmc {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
-// GEMM: C = alpha op(A) op(B) + beta C, row-major, 64 x 64 tile per
-// workgroup, K staged through LDS in steps of 16, v_mfma_f64_16x16x4.
+// GEMM: C = alpha op(A) op(B) + beta C, row-major, TS x TS tile per
+// workgroup of 4 waves (each a TS/2 x TS/2 quarter, v_mfma_f64_16x16x4),
+// K in slabs of 16 staged through LDS.  The next slab's global loads are in
+// flight while the current one is multiplied (clamped addresses, so every
+// load is issued unconditionally; out-of-range elements are zeroed after
+// the load).  TS = 32 where 64 x 64 tiles would leave most of the chip idle.
 // ---------------------------------------------------------------------------
-template <bool TA, bool TB>
+template <bool TA, bool TB, int TS>
 __global__ void __launch_bounds__(256)
 k_gemm_f64(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
            const double* __restrict__ B, int ldb, double beta, double* __restrict__ C, int ldc,
            size_t zs) {
-  __shared__ double As[16][64 + 2];
+  constexpr int LPT = TS / 16;  // elements of each slab per thread
+  constexpr int WB = TS / 32;   // 16 x 16 blocks per wave and dimension
+  __shared__ double As[16][TS + 2];
+  __shared__ double Bs[16][TS + 2];
   A = zw(A, zs);
   B = zw(B, zs);
   C = zw(C, zs);
-  __shared__ double Bs[16][64 + 2];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int m0 = blockIdx.y * TS, n0 = blockIdx.x * TS;
+  const int wr = (wave >> 1) * (TS / 2), wc = (wave & 1) * (TS / 2);
   const int lr = lane & 15, lk = lane >> 4;
-  v4d acc[2][2];
+  // this thread's slab elements: (i, k) of A's tile and (kk, j) of B's
+  int ai[LPT], ak[LPT], bk[LPT], bj[LPT];
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int q = 0; q < LPT; ++q) {
+    const int e = tid + 256 * q;
+    if (TA) { ai[q] = e % TS; ak[q] = e / TS; } else { ak[q] = e % 16; ai[q] = e / 16; }
+    if (TB) { bk[q] = e % 16; bj[q] = e / 16; } else { bj[q] = e % TS; bk[q] = e / TS; }
+  }
+  double ra[LPT], rb[LPT];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < LPT; ++q) {
+      const int gi = std::min(m0 + ai[q], M - 1), gk = std::min(k0 + ak[q], K - 1);
+      ra[q] = TA ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk];
+      const int gj = std::min(n0 + bj[q], N - 1), gkk = std::min(k0 + bk[q], K - 1);
+      rb[q] = TB ? B[(size_t)gj * ldb + gkk] : B[(size_t)gkk * ldb + gj];
+    }
+  };
+  v4d acc[WB][WB];
+#pragma unroll
+  for (int bi = 0; bi < WB; ++bi)
+#pragma unroll
+    for (int bjj = 0; bjj < WB; ++bjj) acc[bi][bjj] = v4d{0.0, 0.0, 0.0, 0.0};
+  if (K > 0) fetch(0);  // (K = 0: no slab, C = beta C)
   for (int k0 = 0; k0 < K; k0 += 16) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;  // 0..1023
-      int i, k;
-      if (TA) { i = e & 63; k = e >> 6; } else { k = e & 15; i = e >> 4; }
-      const int gi = m0 + i, gk = k0 + k;
-      double v = 0.0;
-      if (gi < M && gk < K) v = TA ? A[(size_t)gk * lda + gi] : A[(size_t)gi * lda + gk];
-      As[k][i] = v;
-      int j, kk;
-      if (TB) { kk = e & 15; j = e >> 4; } else { j = e & 63; kk = e >> 6; }
-      const int gj = n0 + j, gkk = k0 + kk;
-      double w = 0.0;
-      if (gj < N && gkk < K) w = TB ? B[(size_t)gj * ldb + gkk] : B[(size_t)gkk * ldb + gj];
-      Bs[kk][j] = w;
+    for (int q = 0; q < LPT; ++q) {
+      As[ak[q]][ai[q]] = (m0 + ai[q] < M && k0 + ak[q] < K) ? ra[q] : 0.0;
+      Bs[bk[q]][bj[q]] = (n0 + bj[q] < N && k0 + bk[q] < K) ? rb[q] : 0.0;
     }
     __syncthreads();
+    if (k0 + 16 < K) fetch(k0 + 16);
 #pragma unroll
     for (int k4 = 0; k4 < 16; k4 += 4) {
-      double a[2], b[2];
+      double a[WB], b[WB];
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi) {
+      for (int bi = 0; bi < WB; ++bi) {
         a[bi] = As[k4 + lk][wr + 16 * bi + lr];
         b[bi] = Bs[k4 + lk][wc + 16 * bi + lr];
       }
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+      for (int bi = 0; bi < WB; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+        for (int bjj = 0; bjj < WB; ++bjj)
+          acc[bi][bjj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bjj], acc[bi][bjj], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < WB; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bjj = 0; bjj < WB; ++bjj)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int r = m0 + wr + 16 * bi + lk + 4 * j, cc = n0 + wc + 16 * bj + lr;
+        const int r = m0 + wr + 16 * bi + lk + 4 * j, cc = n0 + wc + 16 * bjj + lr;
         if (r < M && cc < N) {
-          double v = alpha * acc[bi][bj][j];
+          double v = alpha * acc[bi][bjj][j];
           if (beta != 0.0) v += beta * C[(size_t)r * ldc + cc];
           C[(size_t)r * ldc + cc] = v;
         }
@@ -85,16 +100,24 @@ k_gemm_f64(int M, int N, int K, double alpha, const double* __restrict__ A, int 
 int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
              int lda, const double* B, int ldb, double beta, double* C, int ldc) {
   if (M <= 0 || N <= 0) return KDQMC_OK;
-  dim3 grid((N + 63) / 64, (M + 63) / 64, c->nch);
   const int e0 = prof_mark(c);
-  if (!ta && !tb)
-    hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, c->zs);
-  else if (ta && !tb)
-    hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, c->zs);
-  else if (!ta && tb)
-    hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, c->zs);
-  else
-    hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, dim3(256), 0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, c->zs);
+  // 64 x 64 tiles when they give at least one workgroup per CU, else 32 x 32
+  const bool big = (size_t)((N + 63) / 64) * ((M + 63) / 64) * c->nch >= 256;
+#define GEMM(TA, TB, TS)                                                                               \
+  hipLaunchKernelGGL((k_gemm_f64<TA, TB, TS>), dim3((N + TS - 1) / TS, (M + TS - 1) / TS, c->nch), dim3(256), \
+                     0, c->stream, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, c->zs)
+  if (big) {
+    if (!ta && !tb) GEMM(false, false, 64);
+    else if (ta && !tb) GEMM(true, false, 64);
+    else if (!ta && tb) GEMM(false, true, 64);
+    else GEMM(true, true, 64);
+  } else {
+    if (!ta && !tb) GEMM(false, false, 32);
+    else if (ta && !tb) GEMM(true, false, 32);
+    else if (!ta && tb) GEMM(false, true, 32);
+    else GEMM(true, true, 32);
+  }
+#undef GEMM
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;

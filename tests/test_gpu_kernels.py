@@ -33,6 +33,34 @@ def test_gemm_f64(ch6, ta, tb, M, N, K):
     assert np.abs(got - want).max() <= 1e-13 * max(1.0, np.abs(want).max()) * K
 
 
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("L,M,N,K", [(12, 432, 432, 432), (24, 1728, 1728, 1728), (24, 1100, 1700, 37)])
+def test_gemm_f64_large(gpu_lib, ta, tb, L, M, N, K):
+    """Both tile sizes (32 x 32 where 64 x 64 tiles would give under one
+    workgroup per CU), ragged edges, slabs of K in flight."""
+    say("gemm-large", L, M, N, K, ta, tb)
+    ch = chain(L, 0.0, 1.0)
+    rng = np.random.default_rng(M + N + K + 2 * ta + tb)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    B = rng.standard_normal((N, K) if tb else (K, N))
+    C = rng.standard_normal((M, N))
+    want = 0.5 * ((A.T if ta else A) @ (B.T if tb else B)) + 2.0 * C
+    a, b, c = dev(A), dev(B), dev(C)
+    ch.gemm_f64(ta, tb, M, N, K, 0.5, a, A.shape[1], b, B.shape[1], 2.0, c, N)
+    ch.sync()
+    got = c.cpu().numpy()
+    assert np.abs(got - want).max() <= 1e-13 * max(1.0, np.abs(want).max()) * K
+
+
+def test_gemm_f64_k0(ch6):
+    """K = 0: no slab is read and C = beta C."""
+    C = np.random.default_rng(5).standard_normal((20, 30))
+    a, b, c = dev(np.zeros((20, 1))), dev(np.zeros((1, 30))), dev(C)
+    ch6.gemm_f64(0, 0, 20, 30, 0, 1.0, a, 1, b, 30, -2.0, c, 30)
+    ch6.sync()
+    assert np.array_equal(c.cpu().numpy(), -2.0 * C)
+
+
 @pytest.mark.parametrize("n", [1, 17, 100, 108])
 def test_qr_f64(ch6, n):
     say("qr", n)
