@@ -112,7 +112,8 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   char* S[8];
   for (int i = 0; i < 8; ++i) S[i] = take(nn * 8);
   char* Vq = take(nn * 8);
-  char* Tq = take((N / nb + 2) * 32 * 32 * 8);
+  // per-panel factors, then those of the merged panel pairs
+  char* Tq = take((N / nb + 2 + N / (2 * nb) + 2) * 32 * 32 * 8);
   char* Wq = take((size_t)16 * 32 * N * 8);  // split WY apply: 16 row chunks of 32 x N partials
   char* tau = take(N * 8);
   char* nrm = take(2 * N * 8);
@@ -144,6 +145,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
     for (int i = 0; i < 8; ++i) c->S[i] = (double*)S[i];
     c->Vq = (double*)Vq;
     c->Tq = (double*)Tq;
+    c->Tm = c->Tq + (N / nb + 2) * 32 * 32;
     c->Wq = (double*)Wq;
     c->tau = (double*)tau;
     c->nrm = (double*)nrm;

@@ -240,6 +240,7 @@ struct kdqmc_ctx {
   double* S[8] = {nullptr};
   double* Vq = nullptr;        // N*N explicit Householder vectors
   double* Tq = nullptr;        // per-panel 32 x 32 block-reflector factors
+  double* Tm = nullptr;        // the same for consecutive panel pairs merged into one
   int qr_npan = 0;             // panels of the last QR (start column, width)
   int qr_panel_start[160] = {0};
   int qr_panel_width[160] = {0};

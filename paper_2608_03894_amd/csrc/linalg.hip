@@ -579,6 +579,53 @@ k_apply_wy_all(double* __restrict__ C, int ldc, int n, const double* __restrict_
   }
 }
 
+// Consecutive panels p, p+1 (columns j1.., width b1; j2 = j1 + b1.., width
+// b2) merged into one block reflector: H_p H_{p+1} = I - [V1 V2] T [V1 V2]^T
+// with T = [[T1, -T1 (V1^T V2) T2], [0, T2]].  The apply kernels cost the
+// same for widths up to 32, so applying the merged pairs halves the passes
+// over C.  One workgroup (256 threads) per pair; a lone last panel is copied.
+__global__ void __launch_bounds__(256)
+k_merge_t(const double* __restrict__ V, int ldv, int n, const double* __restrict__ Tq, PanelTable pt,
+          int npan, double* __restrict__ Tm, size_t zs) {
+  __shared__ double T1[16][17], T2[16][17], S[16][17], X[16][17];
+  V = zw(V, zs);
+  Tq = zw(Tq, zs);
+  Tm = zw(Tm, zs);
+  const int qp = blockIdx.x, p1 = 2 * qp, tid = threadIdx.x;
+  const int a = tid >> 4, b = tid & 15;
+  double* out = Tm + (size_t)qp * kNBmax * kNBmax;
+  const double* t1 = Tq + (size_t)p1 * kNBmax * kNBmax;
+  if (p1 + 1 >= npan) {
+    for (int e = tid; e < kNBmax * kNBmax; e += 256) out[e] = t1[e];
+    return;
+  }
+  const double* t2 = t1 + kNBmax * kNBmax;
+  const int j1 = pt.start[p1], b1 = pt.width[p1], j2 = pt.start[p1 + 1], b2 = pt.width[p1 + 1];
+  T1[a][b] = (a < b1 && b < b1) ? t1[a * kNBmax + b] : 0.0;
+  T2[a][b] = (a < b2 && b < b2) ? t2[a * kNBmax + b] : 0.0;
+  // (V1^T V2)[a][b] over the rows from j2 on (V2 is zero above)
+  double sacc = 0.0;
+  if (a < b1 && b < b2) {
+#pragma unroll 4
+    for (int r = j2; r < n; ++r) sacc = fma(V[(size_t)r * ldv + j1 + a], V[(size_t)r * ldv + j2 + b], sacc);
+  }
+  S[a][b] = sacc;
+  __syncthreads();
+  double x = 0.0;
+  for (int k = 0; k < 16; ++k) x = fma(S[a][k], T2[k][b], x);
+  X[a][b] = x;
+  __syncthreads();
+  double t12 = 0.0;
+  for (int k = 0; k < 16; ++k) t12 = fma(T1[a][k], X[k][b], t12);
+  for (int e = tid; e < kNBmax * kNBmax; e += 256) out[e] = 0.0;
+  __syncthreads();
+  out[a * kNBmax + b] = T1[a][b];
+  if (b < b2) {
+    out[a * kNBmax + b1 + b] = -t12;
+    if (a < b2) out[(b1 + a) * kNBmax + b1 + b] = T2[a][b];
+  }
+}
+
 // One step of the factorization with look-ahead: workgroup 0 applies panel
 // p's reflector (columns jp.., width nbp, factor Tp) to the next panel's
 // columns and then factors that panel (threads 0 .. NT-1); the other
@@ -808,17 +855,33 @@ int launch_apply(kdqmc_ctx* c, double* C, int ld, int n, int j, int nbp, int col
 
 // All panels of the last factorization applied to C, one launch: backward
 // (forming Q from the identity) or forward with H^T (applying Q^T).
+// The merged pairs' table and factors (k_merge_t, run at the end of every QR).
 int launch_apply_all(kdqmc_ctx* c, double* C, int ld, int n, bool backward) {
   static_assert(sizeof(PanelTable) <= 2048, "kernel argument size");
+  PanelTable pt;
+  const int nm = (c->qr_npan + 1) / 2;
+  for (int q = 0; q < nm; ++q) {
+    pt.start[q] = c->qr_panel_start[2 * q];
+    pt.width[q] = c->qr_panel_width[2 * q] + (2 * q + 1 < c->qr_npan ? c->qr_panel_width[2 * q + 1] : 0);
+  }
+  constexpr int SW = 16;
+  const int e0 = prof_mark(c);
+  hipLaunchKernelGGL(k_apply_wy_all<SW>, dim3((n + SW - 1) / SW, 1, c->nch), dim3(512), 0, c->stream, C, ld, n,
+                     c->Vq, ld, c->Tm, pt, nm, backward ? 1 : 0, c->zs);
+  prof_pair(c, PH_GEMM, e0, prof_mark(c));
+  return KDQMC_OK;
+}
+
+// Merges consecutive panel pairs of the last QR (k_merge_t).
+int launch_merge_t(kdqmc_ctx* c, int n) {
   PanelTable pt;
   for (int p = 0; p < c->qr_npan; ++p) {
     pt.start[p] = c->qr_panel_start[p];
     pt.width[p] = c->qr_panel_width[p];
   }
-  constexpr int SW = 16;
   const int e0 = prof_mark(c);
-  hipLaunchKernelGGL(k_apply_wy_all<SW>, dim3((n + SW - 1) / SW, 1, c->nch), dim3(512), 0, c->stream, C, ld, n,
-                     c->Vq, ld, c->Tq, pt, c->qr_npan, backward ? 1 : 0, c->zs);
+  hipLaunchKernelGGL(k_merge_t, dim3((c->qr_npan + 1) / 2, 1, c->nch), dim3(256), 0, c->stream, c->Vq, c->N, n,
+                     c->Tq, pt, c->qr_npan, c->Tm, c->zs);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   return KDQMC_OK;
 }
@@ -866,6 +929,7 @@ int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q) {
     nbp = nbn;
   }
   c->qr_npan = npan;
+  KDQMC_TRY(launch_merge_t(c, n));
   if (Q) {
     hipLaunchKernelGGL(k_set_identity, dim3((n * n + 255) / 256, 1, c->nch), dim3(256), 0, c->stream, Q, n,
                        ld, c->zs);
