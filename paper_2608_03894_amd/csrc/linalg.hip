@@ -583,33 +583,41 @@ k_apply_wy_all(double* __restrict__ C, int ldc, int n, const double* __restrict_
 // b2) merged into one block reflector: H_p H_{p+1} = I - [V1 V2] T [V1 V2]^T
 // with T = [[T1, -T1 (V1^T V2) T2], [0, T2]].  The apply kernels cost the
 // same for widths up to 32, so applying the merged pairs halves the passes
-// over C.  One workgroup (256 threads) per pair; a lone last panel is copied.
-__global__ void __launch_bounds__(256)
+// over C.  One workgroup (1024 threads: four row slices of the 16 x 16 sums
+// V1^T V2) per pair; a lone last panel is copied.
+__global__ void __launch_bounds__(1024)
 k_merge_t(const double* __restrict__ V, int ldv, int n, const double* __restrict__ Tq, PanelTable pt,
           int npan, double* __restrict__ Tm, size_t zs) {
-  __shared__ double T1[16][17], T2[16][17], S[16][17], X[16][17];
+  __shared__ double T1[16][17], T2[16][17], S[16][17], X[16][17], Sp[4][16][17];
   V = zw(V, zs);
   Tq = zw(Tq, zs);
   Tm = zw(Tm, zs);
   const int qp = blockIdx.x, p1 = 2 * qp, tid = threadIdx.x;
-  const int a = tid >> 4, b = tid & 15;
+  const int a = (tid >> 4) & 15, b = tid & 15, slice = tid >> 8;
   double* out = Tm + (size_t)qp * kNBmax * kNBmax;
   const double* t1 = Tq + (size_t)p1 * kNBmax * kNBmax;
   if (p1 + 1 >= npan) {
-    for (int e = tid; e < kNBmax * kNBmax; e += 256) out[e] = t1[e];
+    for (int e = tid; e < kNBmax * kNBmax; e += 1024) out[e] = t1[e];
     return;
   }
   const double* t2 = t1 + kNBmax * kNBmax;
   const int j1 = pt.start[p1], b1 = pt.width[p1], j2 = pt.start[p1 + 1], b2 = pt.width[p1 + 1];
-  T1[a][b] = (a < b1 && b < b1) ? t1[a * kNBmax + b] : 0.0;
-  T2[a][b] = (a < b2 && b < b2) ? t2[a * kNBmax + b] : 0.0;
-  // (V1^T V2)[a][b] over the rows from j2 on (V2 is zero above)
+  if (slice == 0) {
+    T1[a][b] = (a < b1 && b < b1) ? t1[a * kNBmax + b] : 0.0;
+    T2[a][b] = (a < b2 && b < b2) ? t2[a * kNBmax + b] : 0.0;
+  }
+  // (V1^T V2)[a][b] over the rows from j2 on (V2 is zero above), every
+  // fourth row per slice
   double sacc = 0.0;
   if (a < b1 && b < b2) {
 #pragma unroll 4
-    for (int r = j2; r < n; ++r) sacc = fma(V[(size_t)r * ldv + j1 + a], V[(size_t)r * ldv + j2 + b], sacc);
+    for (int r = j2 + slice; r < n; r += 4)
+      sacc = fma(V[(size_t)r * ldv + j1 + a], V[(size_t)r * ldv + j2 + b], sacc);
   }
-  S[a][b] = sacc;
+  Sp[slice][a][b] = sacc;
+  __syncthreads();
+  if (tid >= 256) return;  // the rest is one 16 x 16 product chain
+  S[a][b] = (Sp[0][a][b] + Sp[1][a][b]) + (Sp[2][a][b] + Sp[3][a][b]);
   __syncthreads();
   double x = 0.0;
   for (int k = 0; k < 16; ++k) x = fma(S[a][k], T2[k][b], x);
@@ -880,7 +888,7 @@ int launch_merge_t(kdqmc_ctx* c, int n) {
     pt.width[p] = c->qr_panel_width[p];
   }
   const int e0 = prof_mark(c);
-  hipLaunchKernelGGL(k_merge_t, dim3((c->qr_npan + 1) / 2, 1, c->nch), dim3(256), 0, c->stream, c->Vq, c->N, n,
+  hipLaunchKernelGGL(k_merge_t, dim3((c->qr_npan + 1) / 2, 1, c->nch), dim3(1024), 0, c->stream, c->Vq, c->N, n,
                      c->Tq, pt, c->qr_npan, c->Tm, c->zs);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   return KDQMC_OK;
