@@ -990,72 +990,69 @@ __global__ void k_trinv_blocks(const double* __restrict__ R, int n, int ld, doub
   }
 }
 
-// One workgroup per 32-column stripe of X; for each 32-row block row from the
-// bottom: acc = R[b, b1:] X[b1:, stripe] on the FP64 MFMA (4 waves split K,
-// partials summed in LDS), then X_b = Rinv_bb (X_b - acc).
-__global__ void __launch_bounds__(256)
+// One workgroup per 16-column stripe of X; for each 32-row block row from the
+// bottom: acc = R[b, b1:] X[b1:, stripe] on the FP64 MFMA (8 waves split K,
+// clamped unconditional loads, partials summed in LDS), then
+// X_b = Rinv_bb (X_b - acc).
+__global__ void __launch_bounds__(512)
 k_trsm_upper(const double* __restrict__ R, const double* __restrict__ Rinv, double* __restrict__ X,
              int n, int ld, size_t zs) {
-  __shared__ double Wp[4][32][33];
+  constexpr int NW = 8;
+  __shared__ double Wp[NW][32][17];
+  __shared__ double Rb[32][33];
   R = zw(R, zs);
   Rinv = zw(Rinv, zs);
   X = zw(X, zs);
-  __shared__ double Rb[32][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  const int s0 = blockIdx.x * 32;
+  const int s0 = blockIdx.x * 16;
   const int nblk = (n + kTB - 1) / kTB;
+  const int xc = std::min(s0 + lr, n - 1);  // this lane's column of X (clamped)
   for (int b = nblk - 1; b >= 0; --b) {
     const int b0 = b * kTB;
     const int b1 = min(n, b0 + kTB);
-    v4d acc[2][2];
+    v4d acc[2];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int bi = 0; bi < 2; ++bi) acc[bi] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-    for (int k0 = b1 + wave * 4; k0 < n; k0 += 16) {
+    for (int k0 = b1 + wave * 4; k0 < n; k0 += 4 * NW) {
       const int k = k0 + lk;
-      double av[2], bv[2];
+      const int kc = std::min(k, n - 1);
+      double av[2];
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) {
         const int r = b0 + bi * 16 + lr;
-        av[bi] = (r < n && k < n) ? R[(size_t)r * ld + k] : 0.0;
-        const int cc = s0 + bi * 16 + lr;
-        bv[bi] = (k < n && cc < n) ? X[(size_t)k * ld + cc] : 0.0;
+        const double v = R[(size_t)std::min(r, n - 1) * ld + kc];
+        av[bi] = (r < n && k < n) ? v : 0.0;
       }
+      const double xv = X[(size_t)kc * ld + xc];
+      const double bv = (k < n && s0 + lr < n) ? xv : 0.0;
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
+      for (int bi = 0; bi < 2; ++bi) acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv, acc[bi], 0, 0, 0);
     }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) Wp[wave][bi * 16 + lk + 4 * e][bj * 16 + lr] = acc[bi][bj][e];
-    for (int idx = tid; idx < 32 * 32; idx += 256) {
+      for (int e = 0; e < 4; ++e) Wp[wave][bi * 16 + lk + 4 * e][lr] = acc[bi][e];
+    for (int idx = tid; idx < 32 * 32; idx += 512) {
       const int r = idx >> 5, cc = idx & 31;
       Rb[r][cc] = Rinv[(size_t)b * kTB * kTB + r * kTB + cc];
     }
     __syncthreads();
-    for (int idx = tid; idx < 32 * 32; idx += 256) {
-      const int r = idx >> 5, cc = idx & 31;
-      const int gr = b0 + r, gc = s0 + cc;
+    const int r = tid >> 4, cc = tid & 15;  // 32 x 16: one element per thread
+    const int gr = b0 + r, gc = s0 + cc;
+    {
       const double xv = (gr < n && gc < n) ? X[(size_t)gr * ld + gc] : 0.0;
-      Wp[0][r][cc] = xv - (Wp[0][r][cc] + Wp[1][r][cc] + Wp[2][r][cc] + Wp[3][r][cc]);
+      double sacc = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) sacc += Wp[w][r][cc];
+      Wp[0][r][cc] = xv - sacc;  // (the element only this thread reads)
     }
     __syncthreads();
-    for (int idx = tid; idx < 32 * 32; idx += 256) {
-      const int r = idx >> 5, cc = idx & 31;
-      double y = 0.0;
+    double y = 0.0;
 #pragma unroll 8
-      for (int t = 0; t < 32; ++t) y += Rb[r][t] * Wp[0][t][cc];
-      const int gr = b0 + r, gc = s0 + cc;
-      if (gr < n && gc < n) X[(size_t)gr * ld + gc] = y;
-    }
+    for (int t = 0; t < 32; ++t) y += Rb[r][t] * Wp[0][t][cc];
+    if (gr < n && gc < n) X[(size_t)gr * ld + gc] = y;
     __syncthreads();
   }
 }
@@ -1066,7 +1063,7 @@ int trsm_upper_f64(kdqmc_ctx* c, int n, const double* R, double* X) {
   double* Rinv = c->Tq;  // nblk * 32 * 32 (the QR's T factors are no longer needed)
   const int e0 = prof_mark(c);
   hipLaunchKernelGGL(k_trinv_blocks, dim3(nblk, 1, c->nch), dim3(64), 0, c->stream, R, n, ld, Rinv, c->zs);
-  hipLaunchKernelGGL(k_trsm_upper, dim3((n + 31) / 32, 1, c->nch), dim3(256), 0, c->stream, R, Rinv, X, n, ld,
+  hipLaunchKernelGGL(k_trsm_upper, dim3((n + 15) / 16, 1, c->nch), dim3(512), 0, c->stream, R, Rinv, X, n, ld,
                      c->zs);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   KDQMC_HIP(hipGetLastError());
