@@ -133,6 +133,22 @@ __device__ __forceinline__ T* zc_at(T* p, size_t zn, int z) {
   return p ? p + (size_t)z * zn : p;
 }
 
+// 1/sqrt(x) and 1/x for normal positive (resp. nonzero) x: the hardware
+// estimates refined by two Newton steps each (the estimates are good to about 2^-24
+// and the error squares per step).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 // Wave-level ordering of LDS accesses (LDS writes and reads within one wave;
 // a wave's LDS operations complete in order, the fences keep the compiler
 // from moving them across).

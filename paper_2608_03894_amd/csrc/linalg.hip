@@ -174,22 +174,6 @@ __device__ __forceinline__ double xchg_xor(double v, int mask, int lane) {
   return __hiloint2double(xchg_dword(__double2hiint(v), mask, lane), xchg_dword(__double2loint(v), mask, lane));
 }
 
-// 1/sqrt(x) and 1/x for normal positive (resp. nonzero) x: the hardware
-// estimates refined by two Newton steps each (the estimates are good to about 2^-24
-// and the error squares per step).
-__device__ __forceinline__ double rsqrt_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int k = 0; k < 2; ++k) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
-  return y;
-}
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-#pragma unroll
-  for (int k = 0; k < 2; ++k) r = fma(r, fma(-x, r, 1.0), r);
-  return r;
-}
-
 // One panel of the Householder QR.  Column c (row jc = j + c) needs, over
 // the rows r >= jc, the dot products d_t = sum_r a_c[r] a_t[r] with every
 // column t of the panel, and the row jc itself.  With alpha = a_c[jc],
@@ -449,8 +433,9 @@ struct WyLds {
   double Tl[32][33];
 };
 
-// One panel applied to the stripe s0 of C (the body of k_apply_wy; 512 threads).
-template <int SW>
+// One panel applied to the stripe s0 of C (the body of k_apply_wy; 512 threads);
+// VB = 1 for reflectors of at most 16 columns (half the products of VB = 2).
+template <int SW, int VB = 2>
 __device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restrict__ C, int ldc, int n,
                                                 int j, int nbp, int ncols, int s0,
                                                 const double* __restrict__ V, int ldv,
@@ -468,17 +453,17 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restric
     Tl[r][cc] = (r < nbp && cc < nbp) ? T[r * kNBmax + cc] : 0.0;
   }
   // W = V^T C (32 x SW), rows split over waves in chunks of 4
-  v4d acc[2][BJ];
+  v4d acc[VB][BJ];
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < VB; ++bi)
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
   for (int kb = wave * 4; kb < m; kb += 4 * NW) {
     const int r = j + kb + lk;
-    double av[2], bv[BJ];
+    double av[VB], bv[BJ];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
+    for (int bi = 0; bi < VB; ++bi) {
       const int vc = bi * 16 + lr;
       av[bi] = (r < n && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
     }
@@ -488,19 +473,19 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restric
       bv[bj] = (r < n && cc < ncols) ? C[(size_t)r * ldc + cc] : 0.0;
     }
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < VB; ++bi)
 #pragma unroll
       for (int bj = 0; bj < BJ; ++bj)
         acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
   }
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < VB; ++bi)
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
       for (int e = 0; e < 4; ++e) Wp[wave][bi * 16 + lk + 4 * e][bj * 16 + lr] = acc[bi][bj][e];
   __syncthreads();
-  for (int idx = tid; idx < 32 * SW; idx += 512) {
+  for (int idx = tid; idx < 16 * VB * SW; idx += 512) {
     const int r = idx / SW, cc = idx % SW;
     double sacc = 0.0;
 #pragma unroll
@@ -509,10 +494,10 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restric
   }
   __syncthreads();
   // W2 = op(T) W
-  for (int idx = tid; idx < 32 * SW; idx += 512) {
+  for (int idx = tid; idx < 16 * VB * SW; idx += 512) {
     const int r = idx / SW, cc = idx % SW;
     double sacc = 0.0;
-    for (int t = 0; t < 32; ++t) sacc += (trans ? Tl[t][r] : Tl[r][t]) * Wp[0][t][cc];
+    for (int t = 0; t < 16 * VB; ++t) sacc += (trans ? Tl[t][r] : Tl[r][t]) * Wp[0][t][cc];
     W2[r][cc] = sacc;
   }
   __syncthreads();
@@ -523,7 +508,7 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restric
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj) d[bj] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kk = 0; kk < 32; kk += 4) {
+    for (int kk = 0; kk < 16 * VB; kk += 4) {
       const int r = j + rb + lr, vc = kk + lk;
       const double av = (r < n && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
 #pragma unroll
@@ -634,7 +619,8 @@ k_merge_t(const double* __restrict__ V, int ldv, int n, const double* __restrict
   }
 }
 
-// One step of the factorization with look-ahead: workgroup 0 applies panel
+// One step of the factorization with look-ahead (16-column panels of at
+// most 512 rows): workgroup 0 applies panel
 // p's reflector (columns jp.., width nbp, factor Tp) to the next panel's
 // columns and then factors that panel (threads 0 .. NT-1); the other
 // workgroups apply panel p's reflector to the 16-column stripes beyond the
@@ -652,13 +638,13 @@ k_qr_step(double* __restrict__ A, int lda, int n, int jp, int nbp, const double*
   Tp = zw(Tp, zs);
   if (blockIdx.x == 0) {
     for (int s0 = jn; s0 < jn + nbn; s0 += 16) {
-      apply_wy_stripe<16>(sh, A, lda, n, jp, nbp, n, s0, Vq, lda, Tp, 1);
+      apply_wy_stripe<16, 1>(sh, A, lda, n, jp, nbp, n, s0, Vq, lda, Tp, 1);
       __syncthreads();
     }
     if (threadIdx.x >= NT) return;  // waves past the panel's leave; barriers count the rest
     qr_panel_body<RPT, NB, NT>(A, lda, n, jn, nbn, Vq, zw(Tn, zs), zw(tau, zs));
   } else {
-    apply_wy_stripe<16>(sh, A, lda, n, jp, nbp, n, jn + nbn + (blockIdx.x - 1) * 16, Vq, lda, Tp, 1);
+    apply_wy_stripe<16, 1>(sh, A, lda, n, jp, nbp, n, jn + nbn + (blockIdx.x - 1) * 16, Vq, lda, Tp, 1);
   }
 }
 

@@ -331,7 +331,7 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
   int na = 0, p0 = 0;
   while (p0 < wn) {
     const double Rx = 1.0 + delta_x * (1.0 - diag);
-    double cx = delta_x / Rx;  // c of every candidate, off the ballot's path
+    double cx = delta_x * rcp_nr(Rx);  // c of every candidate, off the ballot's path
     const double ratio_x = e2as_x * Rx * Rx;
     const bool ax = use_forced ? fx : (ux < ratio_x);
     const unsigned long long hits = __ballot(xin && lane >= p0 && ax);
