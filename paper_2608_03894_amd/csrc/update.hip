@@ -191,7 +191,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     p0 = p + 1;
     const double R = lane_value(Rx, p);
     const double delta = lane_value(delta_x, p);
-    const double c = delta / R;
+    const double c = delta * rcp_nr(R);
     const int n = na;
     const int b = n & 1;
     const int ip = p / GR, pr = p % GR;
