@@ -448,17 +448,18 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restric
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int m = n - j;
-  for (int idx = tid; idx < 32 * 32; idx += 512) {
-    const int r = idx >> 5, cc = idx & 31;
-    Tl[r][cc] = (r < nbp && cc < nbp) ? T[r * kNBmax + cc] : 0.0;
-  }
+  // T's two elements per thread are loaded now and stored to LDS after the
+  // V^T C loop, so that the loop does not wait for them
+  double tv[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) tv[h] = T[tid + 512 * h];
   // W = V^T C (32 x SW), rows split over waves in chunks of 4
   v4d acc[VB][BJ];
 #pragma unroll
   for (int bi = 0; bi < VB; ++bi)
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
+#pragma unroll 8
   for (int kb = wave * 4; kb < m; kb += 4 * NW) {
     const int r = j + kb + lk;
     double av[VB], bv[BJ];
@@ -484,6 +485,11 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restric
     for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
       for (int e = 0; e < 4; ++e) Wp[wave][bi * 16 + lk + 4 * e][bj * 16 + lr] = acc[bi][bj][e];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int idx = tid + 512 * h, r = idx >> 5, cc = idx & 31;
+    Tl[r][cc] = (r < nbp && cc < nbp) ? tv[h] : 0.0;
+  }
   __syncthreads();
   for (int idx = tid; idx < 16 * VB * SW; idx += 512) {
     const int r = idx / SW, cc = idx % SW;
@@ -595,7 +601,7 @@ k_merge_t(const double* __restrict__ V, int ldv, int n, const double* __restrict
   // fourth row per slice
   double sacc = 0.0;
   if (a < b1 && b < b2) {
-#pragma unroll 4
+#pragma unroll 16
     for (int r = j2 + slice; r < n; r += 4)
       sacc = fma(V[(size_t)r * ldv + j1 + a], V[(size_t)r * ldv + j2 + b], sacc);
   }
