@@ -15,7 +15,8 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def gpu_lib():
-    """The loaded C-ABI library on a GPU machine; fails loudly when it is missing."""
+    """The loaded C-ABI library on a machine with a GPU; fails loudly when it is
+    missing."""
     from paper_2608_03894_amd import kdqmc
     lib = kdqmc.load()
     if not kdqmc.gpu_available():
