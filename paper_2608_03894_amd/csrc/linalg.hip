@@ -203,14 +203,24 @@ __device__ __forceinline__ double xchg_xor(double v, int mask, int lane) {
 // two updates).
 // The panel factorization by threads 0 .. NT-1 of a workgroup (pointers
 // already shifted to the chain).
-template <int RPT, int NB, int NT>
+// Rows of a panel staged through LDS at a time.
+template <int RPT, int NT>
+constexpr int panel_chunk() {
+  return RPT * NT < 1024 ? RPT * NT : 1024;
+}
+
+// Pst: the caller's staging buffer (panel_chunk x (NB + 1) doubles).  PRE: the
+// caller has already written the panel into it (rows j.., one chunk) and
+// synchronized, so the global load is skipped.
+template <int RPT, int NB, int NT, bool PRE = false>
 __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, int n, int j, int nbp,
                                               double* __restrict__ Vq, double* __restrict__ Tq,
-                                              double* __restrict__ tau_out) {
+                                              double* __restrict__ tau_out, double (*Pst)[NB + 1]) {
   constexpr int NW = NT / 64;
   static_assert(NB == 16 && NT >= NB, "panel shape (staging assumes 16 columns)");
   constexpr int kRows = RPT * NT;                         // rows the workgroup holds
-  constexpr int kChunk = kRows < 1024 ? kRows : 1024;     // rows staged at a time
+  constexpr int kChunk = panel_chunk<RPT, NT>();           // rows staged at a time
+  static_assert(!PRE || kRows == kChunk, "a pre-staged panel is one chunk");
   constexpr int kQc = kChunk / NT;                        // row slots per thread and chunk
   constexpr int kPass = kChunk / (NT / 16);               // staging rows per thread and chunk
   static_assert(kRows % kChunk == 0 && kChunk % NT == 0, "staging chunks");
@@ -219,7 +229,6 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
   __shared__ double rowv[2][NB];      // row jc of the panel
   __shared__ double Ts[NB][NB + 1];
   __shared__ double Sv[kRegT ? 1 : NB][NB + 1];  // V^T V, strict upper part
-  __shared__ double Pst[kChunk][NB + 1];  // the panel, staged a chunk at a time
   __shared__ double betas[NB];
   __shared__ double taus[NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -238,19 +247,21 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
   // takes its rows t + q NT of the chunk
 #pragma unroll
   for (int h = 0; h < kRows / kChunk; ++h) {
-    double v[kPass];
+    if constexpr (!PRE) {
+      double v[kPass];
 #pragma unroll
-    for (int k = 0; k < kPass; ++k) {
-      const int r = h * kChunk + sr + k * (NT / 16);
-      v[k] = A[(size_t)(j + std::min(r, mrows - 1)) * lda + j + (sc < nbp ? sc : 0)];
-    }
-    if (h > 0) __syncthreads();  // the previous chunk has been read
+      for (int k = 0; k < kPass; ++k) {
+        const int r = h * kChunk + sr + k * (NT / 16);
+        v[k] = A[(size_t)(j + std::min(r, mrows - 1)) * lda + j + (sc < nbp ? sc : 0)];
+      }
+      if (h > 0) __syncthreads();  // the previous chunk has been read
 #pragma unroll
-    for (int k = 0; k < kPass; ++k) {
-      const int r = h * kChunk + sr + k * (NT / 16);
-      Pst[sr + k * (NT / 16)][sc] = (r < mrows && sc < nbp) ? v[k] : 0.0;
+      for (int k = 0; k < kPass; ++k) {
+        const int r = h * kChunk + sr + k * (NT / 16);
+        Pst[sr + k * (NT / 16)][sc] = (r < mrows && sc < nbp) ? v[k] : 0.0;
+      }
+      __syncthreads();
     }
-    __syncthreads();
 #pragma unroll
     for (int qq = 0; qq < kQc; ++qq) {
       const int q = h * kQc + qq;
@@ -416,7 +427,8 @@ template <int RPT, int NB, int NT>
 __global__ void __launch_bounds__(NT)
 k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __restrict__ Vq,
            double* __restrict__ Tq, double* __restrict__ tau_out, size_t zs) {
-  qr_panel_body<RPT, NB, NT>(zw(A, zs), lda, n, j, nbp, zw(Vq, zs), zw(Tq, zs), zw(tau_out, zs));
+  __shared__ double Pst[panel_chunk<RPT, NT>()][NB + 1];  // the panel, staged a chunk at a time
+  qr_panel_body<RPT, NB, NT>(zw(A, zs), lda, n, j, nbp, zw(Vq, zs), zw(Tq, zs), zw(tau_out, zs), Pst);
 }
 
 // C[j:n, s0:s0+SW] -= V op(T) (V^T C[j:n, s0:s0+SW]) for the panel at column
@@ -439,7 +451,8 @@ template <int SW, int VB = 2>
 __device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restrict__ C, int ldc, int n,
                                                 int j, int nbp, int ncols, int s0,
                                                 const double* __restrict__ V, int ldv,
-                                                const double* __restrict__ T, int trans) {
+                                                const double* __restrict__ T, int trans,
+                                                double (*dst)[SW + 1] = nullptr, int dst_row0 = 0) {
   constexpr int NW = 8;
   constexpr int BJ = SW / 16;
   auto& Wp = sh.Wp;
@@ -526,7 +539,15 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restric
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = j + rb + lk + 4 * e, cc = s0 + bj * 16 + lr;
-        if (r < n && cc < ncols) C[(size_t)r * ldc + cc] -= d[bj][e];
+        if (dst != nullptr && r >= dst_row0) {  // into the caller's LDS rows (0 past ncols)
+          if (r < n) {
+            double x = 0.0;
+            if (cc < ncols) x = C[(size_t)r * ldc + cc] - d[bj][e];
+            dst[r - dst_row0][bj * 16 + lr] = x;
+          }
+        } else if (r < n && cc < ncols) {
+          C[(size_t)r * ldc + cc] -= d[bj][e];
+        }
       }
   }
 }
@@ -643,12 +664,14 @@ k_qr_step(double* __restrict__ A, int lda, int n, int jp, int nbp, const double*
   Vq = zw(Vq, zs);
   Tp = zw(Tp, zs);
   if (blockIdx.x == 0) {
-    for (int s0 = jn; s0 < jn + nbn; s0 += 16) {
-      apply_wy_stripe<16, 1>(sh, A, lda, n, jp, nbp, n, s0, Vq, lda, Tp, 1);
-      __syncthreads();
-    }
+    // the updated panel rows (from jn on) go straight into the panel's
+    // staging buffer; the rows above it (final entries of R) to A
+    __shared__ double Pst[panel_chunk<RPT, NT>()][NB + 1];
+    static_assert(NB == 16 && RPT * NT == panel_chunk<RPT, NT>(), "one 16-column stripe, one chunk");
+    apply_wy_stripe<16, 1>(sh, A, lda, n, jp, nbp, n, jn, Vq, lda, Tp, 1, Pst, jn);
+    __syncthreads();
     if (threadIdx.x >= NT) return;  // waves past the panel's leave; barriers count the rest
-    qr_panel_body<RPT, NB, NT>(A, lda, n, jn, nbn, Vq, zw(Tn, zs), zw(tau, zs));
+    qr_panel_body<RPT, NB, NT, true>(A, lda, n, jn, nbn, Vq, zw(Tn, zs), zw(tau, zs), Pst);
   } else {
     apply_wy_stripe<16, 1>(sh, A, lda, n, jp, nbp, n, jn + nbn + (blockIdx.x - 1) * 16, Vq, lda, Tp, 1);
   }
