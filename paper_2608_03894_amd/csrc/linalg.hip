@@ -486,6 +486,10 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restric
       const int cc = s0 + bj * 16 + lr;
       bv[bj] = (r < n && cc < ncols) ? C[(size_t)r * ldc + cc] : 0.0;
     }
+    if (dst != nullptr && r >= dst_row0 && r < n) {  // keep the LDS rows' old values
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj) dst[r - dst_row0][bj * 16 + lr] = bv[bj];
+    }
 #pragma unroll
     for (int bi = 0; bi < VB; ++bi)
 #pragma unroll
@@ -539,12 +543,8 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restric
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int r = j + rb + lk + 4 * e, cc = s0 + bj * 16 + lr;
-        if (dst != nullptr && r >= dst_row0) {  // into the caller's LDS rows (0 past ncols)
-          if (r < n) {
-            double x = 0.0;
-            if (cc < ncols) x = C[(size_t)r * ldc + cc] - d[bj][e];
-            dst[r - dst_row0][bj * 16 + lr] = x;
-          }
+        if (dst != nullptr && r >= dst_row0) {  // in the caller's LDS rows (0 past ncols)
+          if (r < n) dst[r - dst_row0][bj * 16 + lr] -= d[bj][e];
         } else if (r < n && cc < ncols) {
           C[(size_t)r * ldc + cc] -= d[bj][e];
         }
