@@ -63,3 +63,48 @@ def mp_log_weight(model: dqmc.Model, fields: np.ndarray, dps: int = 50, e=None):
             p = b * p
         det = mp.det(mp.eye(n) + p)
         return 2 * mp.log(abs(det)) - a * int(fields.sum())
+
+
+def _mp_b(e, a, s_row):
+    """B = E diag(exp(alpha s)) in multiprecision."""
+    n = e.rows
+    ev = [mp.exp(a * int(x)) for x in s_row]
+    b = e.copy()
+    for c in range(n):
+        for r in range(n):
+            b[r, c] *= ev[c]
+    return b
+
+
+def mp_pqmc_green(model: dqmc.Model, fields: np.ndarray, p: np.ndarray, l: int, dps: int = 40,
+                  e=None) -> np.ndarray:
+    """Projector G(l) = I - R (L R)^{-1} L, R = B_l ... B_1 P,
+    L = P^T B_{L_tau} ... B_{l+1}, plain products and inverse in
+    multiprecision (P given in FP64), returned as float64."""
+    with mp.workdps(dps):
+        if e is None:
+            e = mp_propagator(model, dps)
+        a = mp.mpf(model.alpha)
+        pm = _mp_matrix(p)
+        r = pm.copy()
+        for j in range(1, l + 1):
+            r = _mp_b(e, a, fields[j - 1]) * r
+        lm = pm.T
+        for j in range(fields.shape[0], l, -1):   # P^T B_{L_tau}, then B_{L_tau - 1}, ...
+            lm = lm * _mp_b(e, a, fields[j - 1])
+        g = mp.eye(model.N) - r * ((lm * r) ** -1) * lm
+        return np.array([[float(g[i, j]) for j in range(model.N)] for i in range(model.N)])
+
+
+def mp_pqmc_log_weight(model: dqmc.Model, fields: np.ndarray, p: np.ndarray, dps: int = 40, e=None):
+    """log of prod exp(-alpha s) det(P^T B_{L_tau} ... B_1 P)^2 in multiprecision."""
+    with mp.workdps(dps):
+        if e is None:
+            e = mp_propagator(model, dps)
+        a = mp.mpf(model.alpha)
+        pm = _mp_matrix(p)
+        x = pm.copy()
+        for j in range(1, fields.shape[0] + 1):
+            x = _mp_b(e, a, fields[j - 1]) * x
+        det = mp.det(pm.T * x)
+        return 2 * mp.log(abs(det)) - a * int(fields.sum())

@@ -85,11 +85,6 @@ def b_matrix(model: Model, s_l: np.ndarray) -> np.ndarray:
     return model.E * np.exp(model.alpha * s_l.astype(float))[None, :]
 
 
-def apply_kinetic(model: Model, m: np.ndarray) -> np.ndarray:
-    """exp(-dtau K) M, the product of Eq. (5) (dense)."""
-    return model.EK @ m
-
-
 def wrap(model: Model, g: np.ndarray, s_l: np.ndarray) -> np.ndarray:
     """G(l) = B_l G(l-1) B_l^{-1} with unchanged fields."""
     ev = np.exp(model.alpha * s_l.astype(float))
@@ -234,20 +229,24 @@ def update_slice(gt: np.ndarray, s: np.ndarray, alpha: float, u=None, forced=Non
 
 
 def sweep(model: Model, fields: np.ndarray, g0: np.ndarray, uniforms=None, forced=None,
-          k: int = 1, n_stab: int = 10, record: bool = True, l_stop=None):
+          k: int = 1, n_stab: int = 10, record: bool = True, l_stop=None, green=None):
     """One upward pass l = 1..L_tau over the slices.
 
     Per slice: G~ = exp(V_l) G exp(-V_l); sequential updates (delay k);
     G = exp(-dtau K) G~ exp(dtau K); every n_stab slices G is replaced by the
     QR-stabilized G(l) and max|G - G_fresh| is logged as the wrap error.
 
-    ``l_stop`` ends the pass after that slice (a partial sweep).
+    ``l_stop`` ends the pass after that slice (a partial sweep).  ``green``
+    (fields, l) -> G(l) gives the fresh G at the stabilizations (default: the
+    finite-temperature green_scratch; the projector passes its own).
 
     Returns a dict with the final fields, G after every slice (``G_slices``,
     index l-1, taken after the stabilization of that slice when there is one),
     the wrapped G before each stabilization (``G_prestab``), accept flags,
     ratios and wrap errors.
     """
+    if green is None:
+        green = lambda f, l: green_scratch(model, f, l)  # noqa: E731
     fields = fields.copy()
     L_tau, n = fields.shape
     acc = np.zeros((L_tau, n), dtype=bool)
@@ -266,7 +265,7 @@ def sweep(model: Model, fields: np.ndarray, g0: np.ndarray, uniforms=None, force
         g = model.EK @ gt @ model.EKinv
         if l % n_stab == 0:
             g_pre[l] = g.copy()
-            gf = green_scratch(model, fields, l)
+            gf = green(fields, l)
             wrap_err[l] = float(np.max(np.abs(g - gf)))
             g = gf
         if record:
@@ -276,7 +275,8 @@ def sweep(model: Model, fields: np.ndarray, g0: np.ndarray, uniforms=None, force
 
 
 def sweep_down(model: Model, fields: np.ndarray, g_top: np.ndarray, uniforms=None, forced=None,
-               k: int = 1, n_stab: int = 10, record: bool = True, l_stop=None, l_start=None):
+               k: int = 1, n_stab: int = 10, record: bool = True, l_stop=None, l_start=None,
+               green=None):
     """One downward pass l = L_tau..1 over the slices, starting from
     G(L_tau) = G(0).
 
@@ -288,10 +288,13 @@ def sweep_down(model: Model, fields: np.ndarray, g_top: np.ndarray, uniforms=Non
     G(l-1) and max|G - G_fresh| is logged.
 
     ``l_start`` begins at another slice (then ``g_top`` is G(l_start)) and
-    ``l_stop`` ends the pass after the slice of that index.  Returns the same
+    ``l_stop`` ends the pass after the slice of that index; ``green`` as in
+    ``sweep``.  Returns the same
     dict as ``sweep``; ``G_slices`` holds G(l-1) in visiting order (index
     L_tau - l), and ``G_prestab`` / ``wrap_err`` are keyed by l-1.
     """
+    if green is None:
+        green = lambda f, l: green_scratch(model, f, l)  # noqa: E731
     fields = fields.copy()
     L_tau, n = fields.shape
     acc = np.zeros((L_tau, n), dtype=bool)
@@ -311,7 +314,7 @@ def sweep_down(model: Model, fields: np.ndarray, g_top: np.ndarray, uniforms=Non
         g = gt / ev[:, None] * ev[None, :]
         if (l - 1) % n_stab == 0:
             g_pre[l - 1] = g.copy()
-            gf = green_scratch(model, fields, l - 1)
+            gf = green(fields, l - 1)
             wrap_err[l - 1] = float(np.max(np.abs(g - gf)))
             g = gf
         if record:
@@ -319,14 +322,3 @@ def sweep_down(model: Model, fields: np.ndarray, g_top: np.ndarray, uniforms=Non
     return dict(fields=fields, G=g, G_slices=g_slices, G_prestab=g_pre,
                 accepted=acc, ratios=ratios, wrap_err=wrap_err)
 
-
-def log_weight_det(model: Model, fields: np.ndarray) -> float:
-    """log of prod exp(-alpha s) * det(I + B_{L_tau} ... B_1)^2 (sign dropped).
-
-    Brute-force weight used to pin the single-flip ratio on tiny systems.
-    """
-    p = np.eye(model.N)
-    for j in range(1, fields.shape[0] + 1):
-        p = b_matrix(model, fields[j - 1]) @ p
-    sign, logdet = np.linalg.slogdet(np.eye(model.N) + p)
-    return 2.0 * logdet - model.alpha * float(fields.sum())

@@ -127,3 +127,49 @@ def test_down_pass_old_field_scaling_is_caught(monkeypatch):
     monkeypatch.setattr(dqmc, "sweep_down", bad)
     with pytest.raises(AssertionError):
         tdq.test_down_slice_update_equals_scratch(_c1())
+
+
+# ---- projector (PQMC) pieces -------------------------------------------------
+import test_oracle_pqmc as tpq  # noqa: E402
+from oracle import pqmc  # noqa: E402
+
+
+def _pq_small():
+    m = dqmc.Model(L=3, t=1.0, U=-4.0, beta=1.0, dtau=0.1, mu=-1.0)
+    f = si.ising_fields(3, m.L_tau, 33)
+    p, _ = pqmc.trial_orbitals(3, 9)
+    return m, f, p
+
+
+def test_pqmc_left_chain_untransposed_is_caught(monkeypatch):
+    """Left panel built from B instead of B^T."""
+    def bad(model, fields, p, l):
+        x = p.copy()
+        for j in range(fields.shape[0], l, -1):
+            x = pqmc._orth(dqmc.b_matrix(model, fields[j - 1]) @ x)
+        return x
+    monkeypatch.setattr(pqmc, "left_panel", bad)
+    with pytest.raises(AssertionError):
+        tpq.test_projector_green_vs_multiprecision(_pq_small())
+
+
+def test_pqmc_right_chain_short_is_caught(monkeypatch):
+    """Right panel missing the last B."""
+    def bad(model, fields, p, l):
+        r = p.copy()
+        for j in range(1, l):
+            r = pqmc._orth(dqmc.b_matrix(model, fields[j - 1]) @ r)
+        return r
+    monkeypatch.setattr(pqmc, "right_panel", bad)
+    with pytest.raises(AssertionError):
+        tpq.test_projector_wrap_relation(_pq_small())
+
+
+def test_pqmc_highest_orbitals_is_caught(monkeypatch):
+    """Trial orbitals taken from the top of the spectrum."""
+    def bad(L, n_occ, t=1.0, eps=pqmc.TRIAL_EPS):
+        w, v = np.linalg.eigh(pqmc.trial_K(L, t, eps))
+        return v[:, -n_occ:].copy(), w
+    monkeypatch.setattr(pqmc, "trial_orbitals", bad)
+    with pytest.raises(AssertionError):
+        tpq.test_free_projector_green_closed_form(3, 2.0, 7)
