@@ -52,7 +52,8 @@ enum {
   KDQMC_EUNSUPPORTED = -2, /* lattice size or precision not compiled in */
   KDQMC_ESTATE = -3,       /* call out of order (slice index, stabilize point) */
   KDQMC_EHIP = -4,         /* a HIP runtime call failed */
-  KDQMC_ENUMERIC = -5,     /* non-finite value detected */
+  KDQMC_ENUMERIC = -5,     /* a stabilization found G drifted beyond the wrap-error
+                              tolerance, or a non-finite value (see kdqmc_health) */
   KDQMC_ENOSPACE = -6      /* workspace smaller than kdqmc_workspace_bytes() */
 };
 
@@ -75,6 +76,10 @@ typedef struct {
   int window;     /* sites per decision window (at most 64), 0 = min(delay_k, 32) */
   int fft_tile;   /* complex vectors per wrap workgroup, 0 = automatic */
   int prec;       /* kdqmc_prec */
+  int n_occ;      /* 0: finite temperature (grand canonical, beta = 1/T);
+                     > 0: projector form of Sec. II with n_occ occupied trial
+                     orbitals per spin (filling rho = 2 n_occ / N) projected
+                     over beta (the projection length of Sec. III) */
 } kdqmc_params;
 
 typedef struct kdqmc_ctx kdqmc_ctx;
@@ -88,6 +93,30 @@ size_t kdqmc_workspace_bytes(const kdqmc_params* p);
 /* Bytes of device workspace for n_chains chains of one shape (1..65535):
  * n_chains per-chain blocks.  0 for invalid parameters. */
 size_t kdqmc_workspace_bytes_batch(const kdqmc_params* p, int n_chains);
+
+/* Projector form (Sec. II: the filling is set by a trial wave function that
+ * occupies the lowest N_occ eigenstates of K, rho = 2 N_occ / N).
+ * With params.n_occ > 0 the context computes
+ *   G(l) = I - R(l) (L(l) R(l))^{-1} L(l),  R(l) = B_l ... B_1 P,
+ *   L(l) = P^T B_{L_tau} ... B_{l+1},
+ * (P: N x n_occ trial orbitals); the update, the flip ratio and the wrap are
+ * those of the finite-temperature form, and the stabilization stacks hold
+ * orthonormal N x n_occ panels (no scale factors).  G(L_tau) differs from
+ * G(0): an upward pass runs from slice 0 to L_tau and ends there, a
+ * downward pass from L_tau to 0, so passes alternate (upward first). */
+
+/* Trial orbitals into P_host[N * n_occ] (host, row-major, site order above):
+ * the lowest n_occ eigenvectors of K + eps (n_A - n_C) (a sublattice
+ * potential on every cell; eps = 0.01 t splits the Dirac points of the
+ * kagome bands, where the lowest N/3 levels of K end inside a degenerate
+ * shell when 3 | L), as real orthonormal combinations of the Bloch states of
+ * Eq. (4).  KDQMC_EINVAL if level n_occ is degenerate with level n_occ + 1. */
+int kdqmc_trial_orbitals(int L, double t, int n_occ, double eps, double* P_host);
+
+/* Loads the trial orbitals P_dev[N * n_occ] (device, row-major; one record
+ * per chain for a batch) of a projector context.  Required before
+ * kdqmc_set_fields; KDQMC_EINVAL for a finite-temperature context. */
+int kdqmc_set_trial(kdqmc_ctx* c, const double* P_dev);
 
 /* Chemical potential at the Dirac energy of the kagome bands: the energy at
  * which the two dispersive bands of the 3x3 Bloch block (Eq. (4)) touch,
@@ -131,7 +160,8 @@ int kdqmc_get_fields(kdqmc_ctx* c, int8_t* s_dev);
  * it, else the first of the pass. */
 int kdqmc_set_G(kdqmc_ctx* c, const double* G_dev, int l);
 
-/* G(l) = B_l G(l-1) B_l^{-1} with unchanged fields: the column pass applies
+/* The propagator wrap of Sec. II, Eqs. (5)-(6) applied on both sides of G:
+ * G(l) = B_l G(l-1) B_l^{-1} with unchanged fields: the column pass applies
  * exp(V_l) then exp(-dtau K) to every column (batched 2D FFTs, 3x3 block
  * multiply, inverse FFTs), the row pass applies exp(+dtau K) to every row
  * (exp(dtau K) is symmetric).  Requires l == current slice + 1, and
@@ -139,7 +169,9 @@ int kdqmc_set_G(kdqmc_ctx* c, const double* G_dev, int l);
  * call has not been made (the same holds for kdqmc_sweep_slice). */
 int kdqmc_wrap_slice(kdqmc_ctx* c, int l);
 
-/* One slice of the Monte Carlo sweep (requires l == current slice + 1):
+/* One slice of the Monte Carlo sweep: the auxiliary-field update of the
+ * delay-update algorithm cited in Sec. II, then the wrap of Eqs. (5)-(6)
+ * (requires l == current slice + 1):
  * G~ = exp(V_l) G(l-1) exp(-V_l); sites i = 0..N-1 in order, in windows of
  * `window` sites; a flip of s_{l,i} is accepted iff u_dev[i] < ratio
  * (Metropolis) or, when forced_dev is not NULL, iff forced_dev[i] != 0;
@@ -166,8 +198,13 @@ int kdqmc_sweep_slice_down(kdqmc_ctx* c, int l, const double* u_dev, const uint8
 
 /* Recomputes G(l) in FP64 for the current slice l of a pass from the
  * QR-stabilized stacks (UDT form, pre-pivoted Householder QR, Loh-Gubernatis
- * scale separation), writes max |G_current - G_fresh| to wrap_err_dev[0]
- * (float64, optional) and replaces G.  l must be a multiple of n_stab
+ * scale separation; the paper applies its propagator product, Eq. (5), inside
+ * such chains but does not describe the stabilization itself), writes
+ * max |G_current - G_fresh| to wrap_err_dev[0] (float64, optional) and
+ * replaces G.  Synchronizes, then returns KDQMC_ENUMERIC when that wrap error
+ * (of any chain) is not finite or above the tolerance (kdqmc_set_wrap_tolerance)
+ * or a stabilization product had a non-finite column norm; G has been replaced
+ * by the fresh FP64 value either way.  l must be a multiple of n_stab
  * reached by the pass (upward: n_stab..L_tau, downward: L_tau - n_stab..0),
  * with every earlier one of the pass stabilized, else KDQMC_ESTATE.  An
  * upward pass extends the right stack (B_l ... B_1) by one entry, a downward
@@ -203,8 +240,29 @@ int kdqmc_sweep_down(kdqmc_ctx* c, const double* u_dev, const uint8_t* forced_de
  * directly (events inside a graph are not timed). */
 int kdqmc_use_graphs(kdqmc_ctx* c, int on);
 
-/* Copies G(current slice) to G_dev (FP64, N x N row-major, site order above). */
+/* The equal-time Green's function from which the measurements of Secs. IV-V
+ * are formed ("measurement" in the runtime breakdown of Sec. III): copies
+ * G(current slice) to G_dev (FP64, N x N row-major, site order above). */
 int kdqmc_measure_G(kdqmc_ctx* c, double* G_dev);
+
+/* Numeric health.  Every stabilization (direct or inside kdqmc_sweep /
+ * kdqmc_sweep_down) records its wrap error max |G_current - G_fresh| on the
+ * device; one that is not finite or exceeds the context's tolerance, or a
+ * non-finite column norm of a stabilization product, marks the chain.
+ * Default tolerance: 1e-5 (FP64; the largest FP64 wrap error of the
+ * workloads, U = -5 at 10-slice intervals, is about 1.4e-6), 1e-4 (mixed).  Sweeps do not
+ * synchronize, so their marks are read here. */
+
+/* Sets the largest accepted wrap error (tol > 0; INFINITY disables the check
+ * of the size but keeps that of finiteness).  Captured sweep graphs are
+ * dropped (they carry the old value). */
+int kdqmc_set_wrap_tolerance(kdqmc_ctx* c, double tol);
+
+/* Synchronizes; writes the largest wrap error of any chain since the last
+ * call (or kdqmc_set_fields / kdqmc_set_G) to *worst_wrap_err (host, may be
+ * NULL; NaN if one was not finite) and returns KDQMC_ENUMERIC if any chain was
+ * marked in that time, else KDQMC_OK.  Clears the records. */
+int kdqmc_health(kdqmc_ctx* c, double* worst_wrap_err);
 
 /* Current slice index (0..L_tau), or a negative error code. */
 int kdqmc_current_slice(const kdqmc_ctx* c);

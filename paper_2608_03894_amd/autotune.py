@@ -48,22 +48,29 @@ def lookup(L, U, beta, dtau=0.1, prec="fp64", n_stab=10, cache=DEFAULT_CACHE, an
 
 
 def _time_sweeps(params, fields, uni, sweeps, device):
+    """Seconds per pass, passes alternating upward and downward as the
+    benchmark runs them, replayed from the captured graphs: each pass's
+    uniforms are copied into one fixed buffer, so the pointers never change."""
     import torch
     ch = kdqmc.Chain(params, device=device)
     try:
+        ub = torch.empty_like(uni[0])
         ch.set_fields(fields)
-        ch.sweep(uni[0])           # capture + first replay (not timed)
+        for s in range(2):         # capture of both directions (not timed)
+            ub.copy_(uni[s])
+            (ch.sweep_down if s % 2 else ch.sweep)(ub)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(sweeps):
-            ch.sweep(uni[1 + s])
+            ub.copy_(uni[2 + s])
+            (ch.sweep_down if s % 2 else ch.sweep)(ub)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / sweeps
     finally:
         ch.close()
 
 
-def autotune(L, U, beta, dtau=0.1, prec="fp64", n_stab=10, seed=0, sweeps=2, device="cuda:0",
+def autotune(L, U, beta, dtau=0.1, prec="fp64", n_stab=10, seed=0, sweeps=4, device="cuda:0",
              cache=DEFAULT_CACHE, refresh=False, log=None):
     """Returns {"delay_k", "window", "fft_tile", "sec_per_sweep"} for the workload."""
     import torch
@@ -79,7 +86,7 @@ def autotune(L, U, beta, dtau=0.1, prec="fp64", n_stab=10, seed=0, sweeps=2, dev
         return table[key]
     L_tau = si.l_tau(beta, dtau)
     fields = torch.from_numpy(si.ising_fields(L, L_tau, seed)).to(device)
-    uni = torch.from_numpy(si.metropolis_uniforms(L, L_tau, seed, n_sweeps=1 + sweeps)).to(device)
+    uni = torch.from_numpy(si.metropolis_uniforms(L, L_tau, seed, n_sweeps=2 + sweeps)).to(device)
     best = None
     # stage 1: delay rank and window at the automatic tile
     for k, w in DELAY_CANDIDATES:
@@ -111,21 +118,164 @@ def autotune(L, U, beta, dtau=0.1, prec="fp64", n_stab=10, seed=0, sweeps=2, dev
     return best
 
 
+# ---------------------------------------------------------------------------
+# Stabilization interval of the mixed precisions
+# ---------------------------------------------------------------------------
+# FP32 rounding of G and of the wrap (about 6e-8 per slice) is amplified from
+# one slice to the next like FP64 rounding is (the wrap multiplies errors by
+# up to cond(B_l) per slice), so the error of a mixed-precision chain is set
+# by how many slices pass between two FP64 stabilizations.  The interval is
+# therefore tuned per lattice and coupling: the longest candidate whose G
+# and flip ratios stay within the target of the FP64 path over the first
+# 20 slices, with the FP64 path's own Metropolis decisions replayed.
+
+INTERVAL_CANDIDATES = (10, 5, 4, 2, 1)
+INTERVAL_SLICES = 20
+INTERVAL_TARGET = 1e-5
+
+
+INTERVAL_MARGIN = 2.0   # other fields and decisions than the tuning run's: half the target
+
+
+def select_interval(rows, target=INTERVAL_TARGET, margin=INTERVAL_MARGIN):
+    """The longest interval whose G and ratio errors are within target/margin."""
+    ok = [int(n) for n, r in rows.items() if r["max_dG"] <= target / margin and r["ratio_err"] <= target / margin]
+    return {"n_stab": max(ok) if ok else min(int(n) for n in rows), "target": target, "margin": margin,
+            "met_target": bool(ok)}
+
+
+def _ikey(L, U, beta, dtau, prec):
+    return f"interval_L{L}_U{U:g}_b{beta:g}_d{dtau:g}_{prec}"
+
+
+def lookup_interval(L, U, beta, dtau=0.1, prec="mixed_f16", cache=DEFAULT_CACHE):
+    """The tuned interval entry {"n_stab", "table", "target", ...} or None."""
+    if not (cache and os.path.exists(cache)):
+        return None
+    with open(cache) as fh:
+        table = json.load(fh)
+    return table.get(_ikey(L, U, beta, dtau, prec))
+
+
+def tune_interval(L, U, beta, dtau=0.1, prec="mixed_f16", seed=0, target=INTERVAL_TARGET,
+                  device="cuda:0", cache=DEFAULT_CACHE, refresh=False, log=None):
+    """Measures max |G_mixed - G_fp64| and the flips' ratio relative error per
+    candidate interval (decisions of an FP64 Metropolis run replayed) and
+    keeps the longest interval within the target."""
+    import torch
+
+    import seeded_inputs as si
+
+    key = _ikey(L, U, beta, dtau, prec)
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as fh:
+            table = json.load(fh)
+    if key in table and not refresh:
+        return table[key]
+    L_tau = si.l_tau(beta, dtau)
+    S = min(INTERVAL_SLICES, L_tau)
+    N = 3 * L * L
+    fields = torch.from_numpy(si.ising_fields(L, L_tau, seed)).to(device)
+    uni = torch.from_numpy(si.metropolis_uniforms(L, L_tau, seed)[0]).to(device)
+    # the FP64 reference: Metropolis decisions, G after every slice
+    ref_ns = 10 if L_tau % 10 == 0 else L_tau
+    ch = kdqmc.Chain(kdqmc.make_params(L, U, beta, dtau, n_stab=ref_ns, delay_k=32, prec="fp64"),
+                     device=device)
+    acc = torch.zeros((S, N), dtype=torch.uint8, device=device)
+    ratio = torch.zeros((S, N), dtype=torch.float64, device=device)
+    gref = torch.zeros((S, N, N), dtype=torch.float64, device=device)
+    ch.set_fields(fields)
+    for l in range(1, S + 1):
+        ch.sweep_slice(l, uni[l - 1], None, acc[l - 1], ratio[l - 1])
+        if l % ref_ns == 0:
+            ch.stabilize()
+        ch.measure_G(gref[l - 1])
+    ch.sync()
+    ch.close()
+    rmax = float(ratio.abs().max().item())
+    rows = {}
+    g = torch.zeros((N, N), dtype=torch.float64, device=device)
+    for ns in INTERVAL_CANDIDATES:
+        if L_tau % ns or S % ns:
+            continue
+        cm = kdqmc.Chain(kdqmc.make_params(L, U, beta, dtau, n_stab=ns, delay_k=32, prec=prec),
+                         device=device)
+        cm.set_wrap_tolerance(float("inf"))   # this measurement wants the drift, not an error
+        rm = torch.zeros((S, N), dtype=torch.float64, device=device)
+        cm.set_fields(fields)
+        worst = 0.0
+        for l in range(1, S + 1):
+            cm.sweep_slice(l, None, acc[l - 1], None, rm[l - 1])
+            if l % ns == 0:
+                try:
+                    cm.stabilize()
+                except kdqmc.KdqmcError:   # non-finite: the interval fails outright
+                    worst = float("inf")
+                    break
+            cm.measure_G(g)
+            d = float((g - gref[l - 1]).abs().max().item())
+            worst = d if not (d <= worst) else worst
+        rerr = float((rm - ratio).abs().max().item()) / rmax
+        cm.close()
+        rows[str(ns)] = {"max_dG": worst, "ratio_err": rerr}
+        if log:
+            log(f"interval {key}: n_stab={ns} max|dG|={worst:.3e} ratio rel err={rerr:.3e}")
+    best = select_interval(rows, target)
+    best.update({"table": rows, "slices": S,
+                 "measured_on": "FP64 GPU path (itself within 1e-10 of the oracle), decisions replayed"})
+    if cache:
+        table[key] = best
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return best
+
+
+def interval_workloads():
+    """(L, U, beta) of every mixed-precision workload: the L=12, 18 and 24
+    single chains and each distinct chain shape of the 64-chain batch."""
+    import seeded_inputs as si
+    out = [(si.C2.L, si.C2.U, si.C2.beta), (si.C3.L, si.C3.U, si.C3.beta), (si.C5.L, si.C5.U, si.C5.beta)]
+    for w in si.batched_chains(64, 64):
+        if (w.L, w.U, w.beta) not in out:
+            out.append((w.L, w.U, w.beta))
+    return out
+
+
 def main(argv=None):
     """python -m paper_2608_03894_amd.autotune --L 12 --U -4 --beta 8 [--prec fp64]"""
     import argparse
     import sys
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--L", type=int, required=True)
-    ap.add_argument("--U", type=float, required=True)
-    ap.add_argument("--beta", type=float, required=True)
+    ap.add_argument("--L", type=int, default=12)
+    ap.add_argument("--U", type=float, default=-4.0)
+    ap.add_argument("--beta", type=float, default=8.0)
+    ap.add_argument("--all-intervals", action="store_true",
+                    help="tune the mixed-precision interval of every workload (--prec, default mixed_f16)")
     ap.add_argument("--dtau", type=float, default=0.1)
     ap.add_argument("--prec", default="fp64")
     ap.add_argument("--n-stab", type=int, default=10)
-    ap.add_argument("--sweeps", type=int, default=2)
+    ap.add_argument("--sweeps", type=int, default=4)
     ap.add_argument("--refresh", action="store_true")
     ap.add_argument("--cache", default=DEFAULT_CACHE)
+    ap.add_argument("--interval", action="store_true",
+                    help="tune the stabilization interval of a mixed precision instead")
     a = ap.parse_args(argv)
+    if a.all_intervals:
+        prec = a.prec if a.prec != "fp64" else "mixed_f16"
+        for (L, U, beta) in interval_workloads():
+            best = tune_interval(L, U, beta, 0.1, prec, cache=a.cache, refresh=a.refresh,
+                                 log=lambda m: print(m, file=sys.stderr, flush=True))
+            print(json.dumps({"L": L, "U": U, "beta": beta, "n_stab": best["n_stab"],
+                              "met_target": best["met_target"]}), flush=True)
+        return
+    if a.interval:
+        best = tune_interval(a.L, a.U, a.beta, a.dtau, a.prec, cache=a.cache, refresh=a.refresh,
+                             log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(json.dumps(best))
+        return
     best = autotune(a.L, a.U, a.beta, a.dtau, a.prec, a.n_stab, sweeps=a.sweeps, cache=a.cache,
                     refresh=a.refresh, log=lambda m: print(m, file=sys.stderr, flush=True))
     print(json.dumps(best))

@@ -2,6 +2,7 @@
 // and the composition of the kernels into the calls declared in kdqmc.h.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -15,7 +16,7 @@ thread_local std::string g_last_error;
 
 struct Derived {
   int N = 0, Ltau = 0, nc = 0, w = 0, nw = 0, F = 0, kmax = 0, P = 0, P64 = 0;
-  bool fp64 = true;
+  bool fp64 = true, proj = false;
 };
 
 // Complex vectors per wrap workgroup: at least one workgroup per compute
@@ -62,6 +63,8 @@ int derive(const kdqmc_params* p, Derived* d, int nch = 1) {
   d->F = std::max(1, p->delay_k / d->w);
   d->kmax = d->F * d->w;
   d->fp64 = (p->prec == KDQMC_FP64);
+  if (p->n_occ < 0 || p->n_occ > d->N) return set_error(KDQMC_EINVAL, "n_occ must be in 0..N");
+  d->proj = p->n_occ > 0;
   const size_t es = d->fp64 ? 8 : 4;
   d->P = auto_tile(p->L, es, p->fft_tile, nch);
   d->P64 = d->fp64 ? d->P : auto_tile(p->L, 8, 0, nch);
@@ -103,12 +106,17 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   char* Gs = take((size_t)d.w * d.w * 8);
   char* flag = take(64);
   char* err = take(1024 * 8);
+  char* health = take(HL_COUNT * 8);
+  // stacks: U (and T, D) entries of N x N; the projector form keeps only the
+  // panels (N x n_occ, row stride N) in U
+  const size_t tmat = d.proj ? 0 : (d.nc + 1) * nn * 8;
   char* RU = take((d.nc + 1) * nn * 8);
-  char* RT = take((d.nc + 1) * nn * 8);
+  char* RT = take(tmat);
   char* RD = take((d.nc + 1) * N * 8);
   char* LU = take((d.nc + 1) * nn * 8);
-  char* LT = take((d.nc + 1) * nn * 8);
+  char* LT = take(tmat);
   char* LD = take((d.nc + 1) * N * 8);
+  char* Ptr = take(d.proj ? nn * 8 : 0);
   char* S[8];
   for (int i = 0; i < 8; ++i) S[i] = take(nn * 8);
   char* Vq = take(nn * 8);
@@ -117,7 +125,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   char* Wq = take((size_t)16 * 32 * N * 8);  // split WY apply: 16 row chunks of 32 x N partials
   char* tau = take(N * 8);
   char* nrm = take(2 * N * 8);
-  char* perm = take(N * 4);
+  char* perm = take(3 * N * 4);  // the pivot order, a second ranking and their composition
   char* sc = take(SC_COUNT * 8);
   if (c) {
     c->G = G;
@@ -140,8 +148,10 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
     c->Gs = (double*)Gs;
     c->flag = (int*)flag;
     c->err = (double*)err;
+    c->health = (double*)health;
     c->RU = (double*)RU; c->RT = (double*)RT; c->RD = (double*)RD;
     c->LU = (double*)LU; c->LT = (double*)LT; c->LD = (double*)LD;
+    c->Ptrial = d.proj ? (double*)Ptr : nullptr;
     for (int i = 0; i < 8; ++i) c->S[i] = (double*)S[i];
     c->Vq = (double*)Vq;
     c->Tq = (double*)Tq;
@@ -236,6 +246,28 @@ size_t kdqmc_workspace_bytes_batch(const kdqmc_params* p, int n_chains) {
 
 double kdqmc_dirac_mu(int L, double t) { return kdqmc::dirac_mu(L, t); }
 
+int kdqmc_trial_orbitals(int L, double t, int n_occ, double eps, double* P_host) {
+  if (!lattice_supported(L)) return set_error(KDQMC_EUNSUPPORTED, "L must be one of 3, 6, 9, 12, 15, 18, 24");
+  if (!P_host) return set_error(KDQMC_EINVAL, "P is NULL");
+  if (!(std::isfinite(t) && std::isfinite(eps))) return set_error(KDQMC_EINVAL, "t, eps must be finite");
+  return trial_orbitals(L, t, n_occ, eps, P_host);
+}
+
+int kdqmc_set_trial(kdqmc_ctx* c, const double* P_dev) {
+  KDQMC_TRY(check_ctx(c));
+  if (!c->proj) return set_error(KDQMC_EINVAL, "not a projector context (params.n_occ == 0)");
+  if (!P_dev) return set_error(KDQMC_EINVAL, "P is NULL");
+  // chain z's record at P_dev + z N n_occ, into its workspace copy (row stride N)
+  const size_t w = (size_t)c->nocc * sizeof(double);
+  for (int z = 0; z < c->nch; ++z)
+    KDQMC_HIP(hipMemcpy2DAsync(reinterpret_cast<char*>(c->Ptrial) + (size_t)z * c->zs, (size_t)c->N * sizeof(double),
+                               P_dev + (size_t)z * c->N * c->nocc, w, w, c->N, hipMemcpyDeviceToDevice, c->stream));
+  c->trial_set = true;
+  c->stacks_valid = false;
+  c->l_cur = -1;
+  return KDQMC_OK;
+}
+
 int kdqmc_init_lattice(kdqmc_ctx** out, const kdqmc_params* p, void* workspace_dev,
                        size_t workspace_bytes, void* hip_stream) {
   return kdqmc_init_batch(out, p, 1, nullptr, workspace_dev, workspace_bytes, hip_stream);
@@ -282,7 +314,10 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
   c->P64 = d.P64;
   c->nb = 16;
   c->fp64 = d.fp64;
+  c->proj = d.proj;
+  c->nocc = p->n_occ;
   c->alpha = std::acosh(std::exp(p->dtau * std::fabs(Uc[0]) / 2.0));
+  c->wrap_tol = d.fp64 ? 1e-5 : 1e-4;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->nch = n_chains;
   char* base = static_cast<char*>(workspace_dev);
@@ -322,6 +357,7 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
         (rc = upload(reinterpret_cast<char*>(c->sc) + o, scv, false)) != KDQMC_OK)
       break;
   }
+  if (rc == KDQMC_OK) rc = clear_health(c);
   if (rc != KDQMC_OK) {
     delete c;
     return rc;
@@ -336,6 +372,7 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
 int kdqmc_set_fields(kdqmc_ctx* c, const int8_t* s_dev) {
   KDQMC_TRY(check_ctx(c));
   if (!s_dev) return set_error(KDQMC_EINVAL, "fields pointer is NULL");
+  if (c->proj && !c->trial_set) return set_error(KDQMC_ESTATE, "projector context: call kdqmc_set_trial first");
   const size_t n = (size_t)c->Ltau * c->N;
   const size_t all = n * c->nch;  // chain z's fields at s_dev + z * n
   hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, c->stream, c->flag, 16);
@@ -346,6 +383,7 @@ int kdqmc_set_fields(kdqmc_ctx* c, const int8_t* s_dev) {
   KDQMC_HIP(hipStreamSynchronize(c->stream));
   if (bad) return set_error(KDQMC_EINVAL, "fields must be +1 or -1");
   KDQMC_HIP(hipMemcpy2DAsync(c->fields, c->zs, s_dev, n, n, c->nch, hipMemcpyDeviceToDevice, c->stream));
+  KDQMC_TRY(clear_health(c));
   KDQMC_TRY(stab_build_left(c));
   KDQMC_TRY(stab_identity(c, false, 0));
   KDQMC_TRY(stab_green(c, 0, c->G64));
@@ -372,6 +410,7 @@ int kdqmc_set_G(kdqmc_ctx* c, const double* G_dev, int l) {
   if (!G_dev) return set_error(KDQMC_EINVAL, "G pointer is NULL");
   if (l < 0 || l > c->Ltau) return set_error(KDQMC_EINVAL, "slice index out of range");
   KDQMC_TRY(copy_64_to_G(c, G_dev, (size_t)c->N * c->N));
+  KDQMC_TRY(clear_health(c));
   // positions an upward pass at slice l: right stack entries up to slice l
   // stay usable when this pass (or a complete earlier one) built them
   if (l == 0) {
@@ -402,6 +441,7 @@ static int check_stab_due_down(kdqmc_ctx* c, int l) {
 }
 
 static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev, size_t zn);
+static void drop_graphs(kdqmc_ctx* c);
 
 // Upward wrap G(l) = exp(-dtau K) [D G_store D^{-1}] exp(dtau K) (D = ev).
 static int wrap_pass(kdqmc_ctx* c) {
@@ -475,8 +515,11 @@ static int sweep_slice_down_impl(kdqmc_ctx* c, int l, const double* u_dev, const
   if (!c->stacks_valid) return set_error(KDQMC_ESTATE, "stacks not built (call set_fields)");
   if (c->dir > 0) return set_error(KDQMC_ESTATE, "an upward pass is in progress");
   if (c->dir == 0) {
-    if (c->l_cur != 0 || l != c->Ltau)
-      return set_error(KDQMC_ESTATE, "a downward pass starts at slice L_tau from slice 0");
+    // finite temperature: G(L_tau) = G(0); the projector form needs an upward
+    // pass to have ended at slice L_tau
+    if (c->l_cur != (c->proj ? c->Ltau : 0) || l != c->Ltau)
+      return set_error(KDQMC_ESTATE, c->proj ? "a projector downward pass starts where an upward pass ended (slice L_tau)"
+                                             : "a downward pass starts at slice L_tau from slice 0");
     c->dir = -1;
     c->l_cur = c->Ltau;  // G(L_tau) = G(0)
     c->stab_next = c->nc - 1;
@@ -505,15 +548,65 @@ static int stabilize_timed(kdqmc_ctx* c, double* wrap_err_dev, size_t zn) {
   return rc;
 }
 
-int kdqmc_stabilize(kdqmc_ctx* c, double* wrap_err_dev) {
-  KDQMC_TRY(check_ctx(c));
-  return stabilize_timed(c, wrap_err_dev, 1);
+// Reads every chain's health record (synchronizes).  latest: judge the
+// latest stabilization only; otherwise everything since the last clear.
+static int read_health(kdqmc_ctx* c, bool latest, double* worst_out) {
+  std::vector<double> h((size_t)c->nch * HL_COUNT);
+  KDQMC_HIP(hipMemcpy2DAsync(h.data(), HL_COUNT * sizeof(double), c->health, c->zs, HL_COUNT * sizeof(double),
+                             c->nch, hipMemcpyDeviceToHost, c->stream));
+  KDQMC_HIP(hipStreamSynchronize(c->stream));
+  double worst = 0.0;
+  int bad = -1;
+  for (int z = 0; z < c->nch; ++z) {
+    const double* r = &h[(size_t)z * HL_COUNT];
+    const double e = latest ? r[HL_LAST] : r[HL_WORST];
+    if (e != e || e > worst) worst = (worst != worst) ? worst : e;
+    const bool b = r[HL_NONFINITE] != 0.0 || (latest ? !(e <= c->wrap_tol) : r[HL_NVIOL] != 0.0);
+    if (b && bad < 0) bad = z;
+  }
+  if (worst_out) *worst_out = worst;
+  if (bad >= 0) {
+    const double* r = &h[(size_t)bad * HL_COUNT];
+    char msg[256];
+    std::snprintf(msg, sizeof msg,
+                  "chain %d: wrap error %.3e (tolerance %.3e)%s; G is not trusted (non-finite values or a "
+                  "drift beyond the tolerance)",
+                  bad, latest ? r[HL_LAST] : r[HL_WORST], c->wrap_tol,
+                  r[HL_NONFINITE] != 0.0 ? ", non-finite column norm in a stabilization product" : "");
+    return set_error(KDQMC_ENUMERIC, msg);
+  }
+  return KDQMC_OK;
 }
 
-// The state at the end of a whole pass: slice 0; an upward pass leaves the
-// right stack matching the new fields, a downward pass the left stack.
+int kdqmc_stabilize(kdqmc_ctx* c, double* wrap_err_dev) {
+  KDQMC_TRY(check_ctx(c));
+  KDQMC_TRY(stabilize_timed(c, wrap_err_dev, 1));
+  return read_health(c, true, nullptr);
+}
+
+int kdqmc_set_wrap_tolerance(kdqmc_ctx* c, double tol) {
+  KDQMC_TRY(check_ctx(c));
+  if (!(tol > 0.0)) return set_error(KDQMC_EINVAL, "tolerance must be > 0 (inf disables the check)");
+  if (tol != c->wrap_tol) {
+    drop_graphs(c);  // captured graphs carry the old value
+    c->wrap_tol = tol;
+  }
+  return KDQMC_OK;
+}
+
+int kdqmc_health(kdqmc_ctx* c, double* worst_host) {
+  KDQMC_TRY(check_ctx(c));
+  const int rc = read_health(c, false, worst_host);
+  KDQMC_TRY(clear_health(c));
+  return rc;
+}
+
+// The state at the end of a whole pass: slice 0 (the projector form: an
+// upward pass ends at slice L_tau, whose G differs from G(0)); an upward pass
+// leaves the right stack matching the new fields, a downward pass the left
+// stack.
 static void end_of_pass(kdqmc_ctx* c, int dir) {
-  c->l_cur = 0;
+  c->l_cur = (c->proj && dir > 0) ? c->Ltau : 0;
   c->dir = 0;
   c->stab_next = 1;
   c->left_valid = dir < 0;
@@ -545,7 +638,7 @@ static int stabilize_impl(kdqmc_ctx* c, double* wrap_err_dev, size_t zn) {
     KDQMC_TRY(stab_left_step(c, j));
   }
   KDQMC_TRY(stab_green(c, j, c->G64));
-  if (wrap_err_dev) KDQMC_TRY(max_abs_diff(c, c->G64, c->N, wrap_err_dev, zn));
+  KDQMC_TRY(max_abs_diff(c, c->G64, c->N, wrap_err_dev, zn));
   KDQMC_TRY(copy_64_to_G(c, c->G64));
   if (c->dir > 0) {
     c->stab_next = j + 1;
@@ -584,7 +677,10 @@ static int pass_range(kdqmc_ctx* c, int dir, int a, int b, const double* u_dev, 
   return KDQMC_OK;
 }
 
+// Graph execs may still be queued on the stream (the host runs ahead of the
+// device): they are destroyed only after the stream has drained.
 static void drop_graphs(kdqmc_ctx* c) {
+  if (!c->sweep_exec[0].empty() || !c->sweep_exec[1].empty()) (void)hipStreamSynchronize(c->stream);
   for (int g = 0; g < 2; ++g) {
     for (hipGraphExec_t e : c->sweep_exec[g]) (void)hipGraphExecDestroy(e);
     c->sweep_exec[g].clear();
@@ -601,7 +697,10 @@ static int graph_segment_slices(const kdqmc_ctx* c) {
 static int run_pass(kdqmc_ctx* c, int dir, const double* u_dev, const uint8_t* forced_dev,
                     uint8_t* accepted_dev, double* ratio_dev, double* wrap_err_dev) {
   KDQMC_TRY(check_ctx(c));
-  if (c->l_cur != 0 || c->dir != 0) return set_error(KDQMC_ESTATE, "a pass needs the current slice to be 0");
+  const int start = (dir < 0 && c->proj) ? c->Ltau : 0;
+  if (c->l_cur != start || c->dir != 0)
+    return set_error(KDQMC_ESTATE, c->proj ? "projector passes alternate: upward from slice 0, downward from L_tau"
+                                           : "a pass needs the current slice to be 0");
   if (!c->stacks_valid) return set_error(KDQMC_ESTATE, "stacks not built (call set_fields)");
   if (!u_dev && !forced_dev) return set_error(KDQMC_EINVAL, "need uniforms or forced decisions");
   const int first = dir > 0 ? 1 : c->Ltau, last = dir > 0 ? c->Ltau : 1;
@@ -618,6 +717,8 @@ static int run_pass(kdqmc_ctx* c, int dir, const double* u_dev, const uint8_t* f
   bool same = !c->sweep_exec[gi].empty();
   for (int i = 0; i < 7 && same; ++i) same = (key[i] == c->sweep_key[gi][i]);
   if (!same) {
+    // the execs being replaced may still be queued: wait for them first
+    if (!c->sweep_exec[gi].empty()) KDQMC_HIP(hipStreamSynchronize(c->stream));
     for (hipGraphExec_t e : c->sweep_exec[gi]) (void)hipGraphExecDestroy(e);
     c->sweep_exec[gi].clear();
     if (!c->cap_stream) KDQMC_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
@@ -776,7 +877,7 @@ int kdqmc_qr_f64(kdqmc_ctx* c, int n, double* A_dev, double* Q_dev) {
   if (c->nch != 1) return set_error(KDQMC_EINVAL, "building blocks need a single-chain context");
   if (n < 1 || n > c->N) return set_error(KDQMC_EINVAL, "QR order must be in 1..N");
   // the routine works with row stride N; callers pass N x N buffers
-  return qr_f64(c, n, A_dev, Q_dev);
+  return qr_f64(c, n, n, A_dev, Q_dev);
 }
 
 }  // extern "C"

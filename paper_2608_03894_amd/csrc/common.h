@@ -170,6 +170,13 @@ __device__ __forceinline__ double lane_value(double v, int src) {
 // between chains of a batch): exp(alpha), exp(-alpha), exp(-2 alpha), exp(2 alpha).
 enum { SC_EA = 0, SC_EAINV, SC_EM2A, SC_EP2A, SC_COUNT };
 
+// Per-chain numeric-health record (doubles in the workspace): the largest
+// wrap error since the record was cleared (NaN once any was not finite), the
+// number of stabilizations whose wrap error was not finite or above the
+// tolerance, 1 once a column norm of a stabilization product was not finite,
+// and the wrap error of the latest stabilization.
+enum { HL_WORST = 0, HL_NVIOL, HL_NONFINITE, HL_LAST, HL_COUNT };
+
 // ---------------------------------------------------------------------------
 // Context
 // ---------------------------------------------------------------------------
@@ -222,6 +229,11 @@ struct kdqmc_ctx {
   bool left_valid = false;  // left stack entries match the current fields
   bool right_valid = false; // right stack entries match the current fields
   bool fp64 = true;
+  // projector form: n_occ trial orbitals, stacks of N x nocc panels
+  bool proj = false;
+  int nocc = 0;
+  bool trial_set = false;
+  double* Ptrial = nullptr;    // N x nocc trial orbitals (row stride N)
 
   // device buffers (carved from the caller's workspace)
   void* G = nullptr;           // N*N, double (FP64) or float (mixed)
@@ -249,6 +261,9 @@ struct kdqmc_ctx {
   double* Gs = nullptr;        // w*w: G~cur[S,S] of the next window
   int* flag = nullptr;         // small device status words
   double* err = nullptr;       // reduction scratch
+  // numeric-health record (HL_* slots), cleared by set_fields / set_G / kdqmc_health
+  double* health = nullptr;
+  double wrap_tol = 1e-6;      // largest wrap error a stabilization accepts
   // stabilization stacks: entry j holds the UDT form of the chain up to checkpoint j
   double* RU = nullptr; double* RT = nullptr; double* RD = nullptr;
   double* LU = nullptr; double* LT = nullptr; double* LD = nullptr;
@@ -275,6 +290,8 @@ bool lattice_supported(int L);
 // Fills tab[L*L*9] complex (interleaved re, im) with exp(scale * (H(k) - shift)) / L^2.
 void bloch_table(int L, double t, double scale, double shift, double* tab);
 double dirac_mu(int L, double t);
+// Trial orbitals of the projector form into P[N * n_occ] (row-major, host).
+int trial_orbitals(int L, double t, int n_occ, double eps, double* P);
 
 // ---------------------------------------------------------------------------
 // Launchers (all enqueue on c->stream)
@@ -282,10 +299,11 @@ double dirac_mu(int L, double t);
 // Vector-batched kinetic operator: for every column (cols=true) or row of the
 // N x N matrix A (row stride lda): x <- post_e .* Op( pre_e .* x .* pre_v[v] ),
 // with Op the table operator.  Pointers pre_e/pre_v/post_e may be null.
+// nvec (> 0): only the first nvec columns (rows) are vectors.
 int launch_kinetic_f64(kdqmc_ctx* c, double* A, int lda, bool cols, const double* tab,
-                       const double* pre_e, const double* pre_v, const double* post_e);
+                       const double* pre_e, const double* pre_v, const double* post_e, int nvec = 0);
 int launch_kinetic_f32(kdqmc_ctx* c, float* A, int lda, bool cols, const float* tab,
-                       const double* pre_e, const double* pre_v, const double* post_e);
+                       const double* pre_e, const double* pre_v, const double* post_e, int nvec = 0);
 
 int prepare_kinetic(int L);
 int prepare_updates();
@@ -299,9 +317,13 @@ int run_slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* force
 
 int gemm_f64(kdqmc_ctx* c, bool ta, bool tb, int M, int N, int K, double alpha, const double* A,
              int lda, const double* B, int ldb, double beta, double* C, int ldc);
-int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q);
-int apply_qt_f64(kdqmc_ctx* c, int n, double* X);
-int trsm_upper_f64(kdqmc_ctx* c, int n, const double* R, double* X);
+// QR of the n x ncol matrix A (ncol <= n, row stride N); Q (n x ncol) formed
+// when non-null.
+int qr_f64(kdqmc_ctx* c, int n, int ncol, double* A, double* Q);
+// X (n rows x ncols, row stride N) <- Q^T X for the last qr_f64.
+int apply_qt_f64(kdqmc_ctx* c, int n, int ncols, double* X);
+// R Y = X for upper-triangular R (n x n) and X (n x ncols), in place on X.
+int trsm_upper_f64(kdqmc_ctx* c, int n, int ncols, const double* R, double* X);
 
 int stab_identity(kdqmc_ctx* c, bool left, int j);
 int stab_build_left(kdqmc_ctx* c);                  // all left entries from the current fields
@@ -313,8 +335,12 @@ int stab_right_step(kdqmc_ctx* c, int j);           // right stack entry j from 
 // or caller arrays (zn > 0: one N x N record per chain, zn elements apart).
 int copy_G_to64(kdqmc_ctx* c, double* out, size_t zn = 0);
 int copy_64_to_G(kdqmc_ctx* c, const double* in, size_t zn = 0);
-// max |G - a| (a in the workspace) into out[0] of each chain's record (zn apart).
+// max |G - a| (a in the workspace) into out[0] of each chain's record (zn
+// apart; out == nullptr: only into the health record), and the health record
+// updated with it against c->wrap_tol.
 int max_abs_diff(kdqmc_ctx* c, const double* a, int n, double* out, size_t zn);
+// Zeroes every chain's health record.
+int clear_health(kdqmc_ctx* c);
 
 // Device-to-device copy of n doubles as a kernel (graph-capture friendly).
 int copy_f64(kdqmc_ctx* c, double* dst, const double* src, size_t n);

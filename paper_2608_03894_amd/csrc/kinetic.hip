@@ -329,7 +329,7 @@ __device__ __forceinline__ void store_tile(T* __restrict__ A, int lda, int P, in
 
 template <typename T, int L, bool COLS>
 __global__ void __launch_bounds__(512)
-k_kinetic(T* __restrict__ A, int lda, int P, const T* __restrict__ tab,
+k_kinetic(T* __restrict__ A, int lda, int P, int nvec, const T* __restrict__ tab,
           const double* __restrict__ pre_e, const double* __restrict__ pre_v,
           const double* __restrict__ post_e, size_t zs) {
   constexpr int NS = 3 * L * L;
@@ -348,8 +348,8 @@ k_kinetic(T* __restrict__ A, int lda, int P, const T* __restrict__ tab,
   // segments of neighbouring tiles meet in the same L2.
   const int gx = gridDim.x, xk = blockIdx.x % 8, xq = gx / 8, xr = gx % 8;
   const int tile = xk * xq + min(xk, xr) + blockIdx.x / 8;
-  const int vbase = 2 * tile * P;            // first real vector of this workgroup
-  const int nreal = min(2 * P, NS - vbase);  // real vectors present (ragged tail)
+  const int vbase = 2 * tile * P;              // first real vector of this workgroup
+  const int nreal = min(2 * P, nvec - vbase);  // real vectors present (ragged tail)
 
   if (pre_e) {
     if (pre_v)
@@ -383,14 +383,15 @@ namespace {
 
 template <typename T, int L>
 int launch_L(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double* pre_e,
-             const double* pre_v, const double* post_e) {
+             const double* pre_v, const double* post_e, int nvec) {
   constexpr int NS = 3 * L * L;
+  if (nvec <= 0 || nvec > NS) nvec = NS;
   int P = (sizeof(T) == 8) ? c->P64 : c->P;
   if (P <= 0) P = 1;
   const size_t lds = size_t(2) * (NS + L) * P * sizeof(T);
   if (lds > 160 * 1024)
     return set_error(KDQMC_EINVAL, "fft_tile too large for LDS");
-  const int ncomplex = (NS + 1) / 2;
+  const int ncomplex = (nvec + 1) / 2;
   const int grid = (ncomplex + P - 1) / P;
   int threads = 3 * L * P;
   threads = ((threads + 63) / 64) * 64;
@@ -399,10 +400,10 @@ int launch_L(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double*
   const int e0 = prof_mark(c);
   if (cols)
     hipLaunchKernelGGL((k_kinetic<T, L, true>), dim3(grid, 1, c->nch), dim3(threads), lds, c->stream, A, lda, P,
-                       tab, pre_e, pre_v, post_e, c->zs);
+                       nvec, tab, pre_e, pre_v, post_e, c->zs);
   else
     hipLaunchKernelGGL((k_kinetic<T, L, false>), dim3(grid, 1, c->nch), dim3(threads), lds, c->stream, A, lda, P,
-                       tab, pre_e, pre_v, post_e, c->zs);
+                       nvec, tab, pre_e, pre_v, post_e, c->zs);
   prof_pair(c, (sizeof(T) == 8 && tab == (const T*)c->tab_mu64) ? PH_BMUL : (cols ? PH_WRAP_COLS : PH_WRAP_ROWS), e0, prof_mark(c));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
@@ -431,15 +432,15 @@ int prepare_any(int L) {
 
 template <typename T>
 int launch_any(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double* pre_e,
-               const double* pre_v, const double* post_e) {
+               const double* pre_v, const double* post_e, int nvec) {
   switch (c->L) {
-    case 3: return launch_L<T, 3>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
-    case 6: return launch_L<T, 6>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
-    case 9: return launch_L<T, 9>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
-    case 12: return launch_L<T, 12>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
-    case 15: return launch_L<T, 15>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
-    case 18: return launch_L<T, 18>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
-    case 24: return launch_L<T, 24>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+    case 3: return launch_L<T, 3>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
+    case 6: return launch_L<T, 6>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
+    case 9: return launch_L<T, 9>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
+    case 12: return launch_L<T, 12>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
+    case 15: return launch_L<T, 15>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
+    case 18: return launch_L<T, 18>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
+    case 24: return launch_L<T, 24>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
     default: return set_error(KDQMC_EUNSUPPORTED, "lattice size not compiled in");
   }
 }
@@ -454,13 +455,13 @@ int prepare_kinetic(int L) {
 }
 
 int launch_kinetic_f64(kdqmc_ctx* c, double* A, int lda, bool cols, const double* tab,
-                       const double* pre_e, const double* pre_v, const double* post_e) {
-  return launch_any<double>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+                       const double* pre_e, const double* pre_v, const double* post_e, int nvec) {
+  return launch_any<double>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
 }
 
 int launch_kinetic_f32(kdqmc_ctx* c, float* A, int lda, bool cols, const float* tab,
-                       const double* pre_e, const double* pre_v, const double* post_e) {
-  return launch_any<float>(c, A, lda, cols, tab, pre_e, pre_v, post_e);
+                       const double* pre_e, const double* pre_v, const double* post_e, int nvec) {
+  return launch_any<float>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
 }
 
 }  // namespace kdqmc

@@ -1,7 +1,9 @@
 // Host-side lattice algebra: the 3x3 Bloch blocks of the kagome kinetic
 // matrix (Eqs. (3)-(4)) and their exponentials, tabulated per momentum.
+#include <algorithm>
 #include <cmath>
 #include <complex>
+#include <vector>
 
 #include "common.h"
 
@@ -121,7 +123,141 @@ void eig3_hermitian(const cd h[3][3], double ev[3]) {
   ev[2] = e0;
 }
 
+// Eigen-decomposition of a 3x3 Hermitian matrix by cyclic complex Jacobi
+// rotations: h = V diag(w) V^+, w ascending, V unitary (columns = vectors).
+// Each rotation first turns h_pq real by a diagonal phase, then zeroes it by
+// a real plane rotation of angle 0.5 atan2(2 |h_pq|, h_qq - h_pp).
+void jacobi3(const cd h_in[3][3], double w[3], cd V[3][3]) {
+  cd a[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      a[i][j] = h_in[i][j];
+      V[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+  double scale = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) scale += std::norm(a[i][j]);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    const double off = std::norm(a[0][1]) + std::norm(a[0][2]) + std::norm(a[1][2]);
+    if (off <= 1e-34 * (scale + 1e-300)) break;
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      const double r = std::abs(a[p][q]);
+      if (r == 0.0) continue;
+      const cd ph = a[p][q] / r;  // exp(i phi)
+      const double th = 0.5 * std::atan2(2.0 * r, a[q][q].real() - a[p][p].real());
+      const double c = std::cos(th), sn = std::sin(th);
+      // G = identity except the (p, q) block diag(1, e^{-i phi}) [[c, s], [-s, c]]
+      cd G[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) G[i][j] = (i == j) ? 1.0 : 0.0;
+      const cd e = std::conj(ph);
+      G[p][p] = c;
+      G[p][q] = sn;
+      G[q][p] = -sn * e;
+      G[q][q] = c * e;
+      cd t1[3][3], Gh[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Gh[i][j] = std::conj(G[j][i]);
+      matmul3(a, G, t1);
+      matmul3(Gh, t1, a);
+      matmul3(V, G, t1);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) V[i][j] = t1[i][j];
+      a[q][p] = 0.0;
+      a[p][q] = 0.0;
+    }
+  }
+  int ord[3] = {0, 1, 2};
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (a[ord[j]][ord[j]].real() < a[ord[i]][ord[i]].real()) std::swap(ord[i], ord[j]);
+  cd Vs[3][3];
+  for (int k = 0; k < 3; ++k) {
+    w[k] = a[ord[k]][ord[k]].real();
+    for (int i = 0; i < 3; ++i) Vs[i][k] = V[i][ord[k]];
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) V[i][j] = Vs[i][j];
+}
+
 }  // namespace
+
+// The trial orbitals of the projector form: the lowest n_occ eigenvectors of
+// K_T = K + eps (n_A - n_C) (per cell), real and orthonormal, from the 3x3
+// Bloch blocks H(k) + diag(eps, 0, -eps) (the potential is translation
+// invariant).  A state of momentum k is psi(x, s) = e^{i k.x} v_s / L; the
+// pair k, -k (equal levels, H(-k) = H(k)*) gives sqrt(2) Re psi and
+// sqrt(2) Im psi, a self-conjugate k (2k on the grid's origin) the real psi.
+int trial_orbitals(int L, double t, int n_occ, double eps, double* P) {
+  const int N = 3 * L * L;
+  if (n_occ < 1 || n_occ > N) return set_error(KDQMC_EINVAL, "n_occ must be in 1..N");
+  struct Lev {
+    double e;
+    int m1, m2, b;
+  };
+  std::vector<Lev> lev;
+  std::vector<cd> vec((size_t)L * L * 9);
+  for (int m1 = 0; m1 < L; ++m1)
+    for (int m2 = 0; m2 < L; ++m2) {
+      cd h[3][3], V[3][3];
+      bloch_H(t, 2.0 * kPi * m1 / L, 2.0 * kPi * m2 / L, h);
+      h[0][0] += eps;
+      h[2][2] -= eps;
+      double w[3];
+      jacobi3(h, w, V);
+      for (int b = 0; b < 3; ++b) {
+        lev.push_back({w[b], m1, m2, b});
+        for (int sidx = 0; sidx < 3; ++sidx) vec[((size_t)(m1 * L + m2) * 3 + b) * 3 + sidx] = V[sidx][b];
+      }
+    }
+  std::stable_sort(lev.begin(), lev.end(), [](const Lev& x, const Lev& y) { return x.e < y.e; });
+  if (n_occ < N && lev[n_occ].e - lev[n_occ - 1].e < 1e-8)
+    return set_error(KDQMC_EINVAL, "open shell: trial levels n_occ and n_occ+1 are degenerate (choose eps or n_occ)");
+  std::vector<char> sel((size_t)L * L * 3, 0);
+  for (int i = 0; i < n_occ; ++i) sel[(size_t)(lev[i].m1 * L + lev[i].m2) * 3 + lev[i].b] = 1;
+  const double inv = 1.0 / L, r2 = std::sqrt(2.0) / L;
+  int col = 0;
+  for (int m1 = 0; m1 < L; ++m1)
+    for (int m2 = 0; m2 < L; ++m2)
+      for (int b = 0; b < 3; ++b) {
+        const size_t kb = (size_t)(m1 * L + m2) * 3 + b;
+        if (!sel[kb]) continue;
+        const int n1 = (L - m1) % L, n2 = (L - m2) % L;
+        const bool self = (n1 == m1 && n2 == m2);
+        if (!self && m1 * L + m2 > n1 * L + n2) continue;  // emitted with its partner
+        if (!self && !sel[(size_t)(n1 * L + n2) * 3 + b])
+          return set_error(KDQMC_EINVAL, "open shell: a level of k is selected without that of -k");
+        cd v[3];
+        for (int sidx = 0; sidx < 3; ++sidx) v[sidx] = vec[kb * 3 + sidx];
+        if (self) {  // a real vector up to a phase: make the largest component real
+          int im = 0;
+          for (int sidx = 1; sidx < 3; ++sidx)
+            if (std::abs(v[sidx]) > std::abs(v[im])) im = sidx;
+          const cd ph = std::conj(v[im]) / std::abs(v[im]);
+          for (int sidx = 0; sidx < 3; ++sidx) v[sidx] *= ph;
+        }
+        const int ncols = self ? 1 : 2;
+        if (col + ncols > n_occ) return set_error(KDQMC_EINVAL, "trial orbitals: inconsistent level count");
+        for (int x1 = 0; x1 < L; ++x1)
+          for (int x2 = 0; x2 < L; ++x2) {
+            const cd ex = std::polar(1.0, 2.0 * kPi * double(m1 * x1 + m2 * x2) / L);
+            for (int sidx = 0; sidx < 3; ++sidx) {
+              const cd psi = ex * v[sidx];
+              const size_t row = (size_t)((x1 * L + x2) * 3 + sidx);
+              if (self) {
+                P[row * n_occ + col] = psi.real() * inv;
+              } else {
+                P[row * n_occ + col] = psi.real() * r2;
+                P[row * n_occ + col + 1] = psi.imag() * r2;
+              }
+            }
+          }
+        col += ncols;
+      }
+  if (col != n_occ) return set_error(KDQMC_EINVAL, "trial orbitals: inconsistent level count");
+  return KDQMC_OK;
+}
 
 bool lattice_supported(int L) {
   switch (L) {

@@ -574,7 +574,7 @@ struct PanelTable {
 
 template <int SW>
 __global__ void __launch_bounds__(512)
-k_apply_wy_all(double* __restrict__ C, int ldc, int n, const double* __restrict__ V, int ldv,
+k_apply_wy_all(double* __restrict__ C, int ldc, int n, int ncols, const double* __restrict__ V, int ldv,
                const double* __restrict__ Tq, PanelTable pt, int npan, int backward, size_t zs) {
   __shared__ WyLds<SW> sh;
   C = zw(C, zs);
@@ -585,7 +585,7 @@ k_apply_wy_all(double* __restrict__ C, int ldc, int n, const double* __restrict_
     const int p = backward ? npan - 1 - i : i;
     const int j = pt.start[p];
     if (backward && j > s0) continue;  // columns left of the panel are untouched
-    apply_wy_stripe<SW>(sh, C, ldc, n, j, pt.width[p], n, s0, V, ldv, Tq + (size_t)p * kNBmax * kNBmax,
+    apply_wy_stripe<SW>(sh, C, ldc, n, j, pt.width[p], ncols, s0, V, ldv, Tq + (size_t)p * kNBmax * kNBmax,
                         backward ? 0 : 1);
     __syncthreads();  // this panel's update is read by the next one
   }
@@ -655,7 +655,7 @@ k_merge_t(const double* __restrict__ V, int ldv, int n, const double* __restrict
 // disjoint columns.
 template <int RPT, int NB, int NT>
 __global__ void __launch_bounds__(512)
-k_qr_step(double* __restrict__ A, int lda, int n, int jp, int nbp, const double* __restrict__ Tp,
+k_qr_step(double* __restrict__ A, int lda, int n, int ncols, int jp, int nbp, const double* __restrict__ Tp,
           int jn, int nbn, double* __restrict__ Vq, double* __restrict__ Tn, double* __restrict__ tau,
           size_t zs) {
   static_assert(NT <= 512, "the panel runs inside a 512-thread workgroup");
@@ -668,12 +668,12 @@ k_qr_step(double* __restrict__ A, int lda, int n, int jp, int nbp, const double*
     // staging buffer; the rows above it (final entries of R) to A
     __shared__ double Pst[panel_chunk<RPT, NT>()][NB + 1];
     static_assert(NB == 16 && RPT * NT == panel_chunk<RPT, NT>(), "one 16-column stripe, one chunk");
-    apply_wy_stripe<16, 1>(sh, A, lda, n, jp, nbp, n, jn, Vq, lda, Tp, 1, Pst, jn);
+    apply_wy_stripe<16, 1>(sh, A, lda, n, jp, nbp, ncols, jn, Vq, lda, Tp, 1, Pst, jn);
     __syncthreads();
     if (threadIdx.x >= NT) return;  // waves past the panel's leave; barriers count the rest
     qr_panel_body<RPT, NB, NT, true>(A, lda, n, jn, nbn, Vq, zw(Tn, zs), zw(tau, zs), Pst);
   } else {
-    apply_wy_stripe<16, 1>(sh, A, lda, n, jp, nbp, n, jn + nbn + (blockIdx.x - 1) * 16, Vq, lda, Tp, 1);
+    apply_wy_stripe<16, 1>(sh, A, lda, n, jp, nbp, ncols, jn + nbn + (blockIdx.x - 1) * 16, Vq, lda, Tp, 1);
   }
 }
 
@@ -806,10 +806,11 @@ k_wy_update(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
     }
 }
 
-__global__ void k_set_identity(double* __restrict__ Q, int n, int ld, size_t zs) {
+// Q[0:m, 0:n] = the first n columns of the m x m identity.
+__global__ void k_set_identity(double* __restrict__ Q, int m, int n, int ld, size_t zs) {
   Q = zw(Q, zs);
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < (size_t)n * n) {
+  if (idx < (size_t)m * n) {
     const int r = idx / n, cc = idx % n;
     Q[(size_t)r * ld + cc] = (r == cc) ? 1.0 : 0.0;
   }
@@ -877,7 +878,7 @@ int launch_apply(kdqmc_ctx* c, double* C, int ld, int n, int j, int nbp, int col
 // All panels of the last factorization applied to C, one launch: backward
 // (forming Q from the identity) or forward with H^T (applying Q^T).
 // The merged pairs' table and factors (k_merge_t, run at the end of every QR).
-int launch_apply_all(kdqmc_ctx* c, double* C, int ld, int n, bool backward) {
+int launch_apply_all(kdqmc_ctx* c, double* C, int ld, int n, int ncols, bool backward) {
   static_assert(sizeof(PanelTable) <= 2048, "kernel argument size");
   PanelTable pt;
   const int nm = (c->qr_npan + 1) / 2;
@@ -887,8 +888,8 @@ int launch_apply_all(kdqmc_ctx* c, double* C, int ld, int n, bool backward) {
   }
   constexpr int SW = 16;
   const int e0 = prof_mark(c);
-  hipLaunchKernelGGL(k_apply_wy_all<SW>, dim3((n + SW - 1) / SW, 1, c->nch), dim3(512), 0, c->stream, C, ld, n,
-                     c->Vq, ld, c->Tm, pt, nm, backward ? 1 : 0, c->zs);
+  hipLaunchKernelGGL(k_apply_wy_all<SW>, dim3((ncols + SW - 1) / SW, 1, c->nch), dim3(512), 0, c->stream, C, ld,
+                     n, ncols, c->Vq, ld, c->Tm, pt, nm, backward ? 1 : 0, c->zs);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   return KDQMC_OK;
 }
@@ -907,11 +908,13 @@ int launch_merge_t(kdqmc_ctx* c, int n) {
   return KDQMC_OK;
 }
 
-// A (n x n, leading dimension N) = Q R.  With Q != nullptr, Q is formed
-// explicitly; the panels' V and T stay in Vq / Tq for apply_qt_f64.
-int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q) {
+// A (n rows x ncol columns, ncol <= n, leading dimension N) = Q R.  With
+// Q != nullptr, the first ncol columns of Q are formed explicitly (n x ncol);
+// the panels' V and T stay in Vq / Tq for apply_qt_f64.
+int qr_f64(kdqmc_ctx* c, int n, int ncol, double* A, double* Q) {
   const int ld = c->N;
   if (n > 2048) return set_error(KDQMC_EUNSUPPORTED, "QR order above 2048");
+  if (ncol < 1 || ncol > n) return set_error(KDQMC_EINVAL, "QR: need 1 <= columns <= rows");
   const size_t nn = (size_t)n * ld;
   hipLaunchKernelGGL(k_zero, dim3((nn + 255) / 256, 1, c->nch), dim3(256), 0, c->stream, c->Vq, nn, c->zs);
   // the first panel alone; then per panel one step launch (the previous
@@ -921,28 +924,28 @@ int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q) {
   // for taller panels, which is faster there than one workgroup per stripe)
   // and the panel apart
   int npan = 0, j = 0;
-  int nbp = std::min(panel_width(n), n);
+  int nbp = std::min(panel_width(n), ncol);
   KDQMC_TRY(launch_panel(c, A, ld, n, 0, nbp, c->Tq));
   for (;;) {
     c->qr_panel_start[npan] = j;
     c->qr_panel_width[npan] = nbp;
     const int jn = j + nbp;
-    if (jn >= n) {
+    if (jn >= ncol) {
       ++npan;
       break;
     }
-    const int nbn = std::min(panel_width(n - jn), n - jn);
+    const int nbn = std::min(panel_width(n - jn), ncol - jn);
     double* Tp = c->Tq + (size_t)npan * kNBmax * kNBmax;
     double* Tn = Tp + kNBmax * kNBmax;
     const int mn = n - jn;
     if (mn <= 512) {
-      const dim3 grid(1 + (n - jn - nbn + 15) / 16, 1, c->nch);
+      const dim3 grid(1 + (ncol - jn - nbn + 15) / 16, 1, c->nch);
       const int e0 = prof_mark(c);
-      hipLaunchKernelGGL((k_qr_step<2, 16, 256>), grid, dim3(512), 0, c->stream, A, ld, n, j, nbp, Tp, jn, nbn,
-                         c->Vq, Tn, c->tau, c->zs);
+      hipLaunchKernelGGL((k_qr_step<2, 16, 256>), grid, dim3(512), 0, c->stream, A, ld, n, ncol, j, nbp, Tp, jn,
+                         nbn, c->Vq, Tn, c->tau, c->zs);
       prof_pair(c, PH_QR_PANEL, e0, prof_mark(c));
     } else {
-      KDQMC_TRY(launch_apply(c, A, ld, n, j, nbp, jn, n, Tp, true));
+      KDQMC_TRY(launch_apply(c, A, ld, n, j, nbp, jn, ncol, Tp, true));
       KDQMC_TRY(launch_panel(c, A, ld, n, jn, nbn, Tn));
     }
     ++npan;
@@ -952,17 +955,17 @@ int qr_f64(kdqmc_ctx* c, int n, double* A, double* Q) {
   c->qr_npan = npan;
   KDQMC_TRY(launch_merge_t(c, n));
   if (Q) {
-    hipLaunchKernelGGL(k_set_identity, dim3((n * n + 255) / 256, 1, c->nch), dim3(256), 0, c->stream, Q, n,
-                       ld, c->zs);
-    KDQMC_TRY(launch_apply_all(c, Q, ld, n, true));
+    hipLaunchKernelGGL(k_set_identity, dim3((n * ncol + 255) / 256, 1, c->nch), dim3(256), 0, c->stream, Q, n,
+                       ncol, ld, c->zs);
+    KDQMC_TRY(launch_apply_all(c, Q, ld, n, ncol, true));
   }
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
 
-// X <- Q^T X for the Q of the last qr_f64 call (n x n, ld = N).
-int apply_qt_f64(kdqmc_ctx* c, int n, double* X) {
-  KDQMC_TRY(launch_apply_all(c, X, c->N, n, false));
+// X <- Q^T X for the Q of the last qr_f64 call (X: n rows x ncols, ld = N).
+int apply_qt_f64(kdqmc_ctx* c, int n, int ncols, double* X) {
+  KDQMC_TRY(launch_apply_all(c, X, c->N, n, ncols, false));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
@@ -1009,7 +1012,7 @@ __global__ void k_trinv_blocks(const double* __restrict__ R, int n, int ld, doub
 // X_b = Rinv_bb (X_b - acc).
 __global__ void __launch_bounds__(512)
 k_trsm_upper(const double* __restrict__ R, const double* __restrict__ Rinv, double* __restrict__ X,
-             int n, int ld, size_t zs) {
+             int n, int ncols, int ld, size_t zs) {
   constexpr int NW = 8;
   __shared__ double Wp[NW][32][17];
   __shared__ double Rb[32][33];
@@ -1020,7 +1023,7 @@ k_trsm_upper(const double* __restrict__ R, const double* __restrict__ Rinv, doub
   const int lr = lane & 15, lk = lane >> 4;
   const int s0 = blockIdx.x * 16;
   const int nblk = (n + kTB - 1) / kTB;
-  const int xc = std::min(s0 + lr, n - 1);  // this lane's column of X (clamped)
+  const int xc = std::min(s0 + lr, ncols - 1);  // this lane's column of X (clamped)
   for (int b = nblk - 1; b >= 0; --b) {
     const int b0 = b * kTB;
     const int b1 = min(n, b0 + kTB);
@@ -1039,7 +1042,7 @@ k_trsm_upper(const double* __restrict__ R, const double* __restrict__ Rinv, doub
         av[bi] = (r < n && k < n) ? v : 0.0;
       }
       const double xv = X[(size_t)kc * ld + xc];
-      const double bv = (k < n && s0 + lr < n) ? xv : 0.0;
+      const double bv = (k < n && s0 + lr < ncols) ? xv : 0.0;
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi) acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv, acc[bi], 0, 0, 0);
     }
@@ -1055,7 +1058,7 @@ k_trsm_upper(const double* __restrict__ R, const double* __restrict__ Rinv, doub
     const int r = tid >> 4, cc = tid & 15;  // 32 x 16: one element per thread
     const int gr = b0 + r, gc = s0 + cc;
     {
-      const double xv = (gr < n && gc < n) ? X[(size_t)gr * ld + gc] : 0.0;
+      const double xv = (gr < n && gc < ncols) ? X[(size_t)gr * ld + gc] : 0.0;
       double sacc = 0.0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) sacc += Wp[w][r][cc];
@@ -1065,19 +1068,19 @@ k_trsm_upper(const double* __restrict__ R, const double* __restrict__ Rinv, doub
     double y = 0.0;
 #pragma unroll 8
     for (int t = 0; t < 32; ++t) y += Rb[r][t] * Wp[0][t][cc];
-    if (gr < n && gc < n) X[(size_t)gr * ld + gc] = y;
+    if (gr < n && gc < ncols) X[(size_t)gr * ld + gc] = y;
     __syncthreads();
   }
 }
 
-int trsm_upper_f64(kdqmc_ctx* c, int n, const double* R, double* X) {
+int trsm_upper_f64(kdqmc_ctx* c, int n, int ncols, const double* R, double* X) {
   const int ld = c->N;
   const int nblk = (n + kTB - 1) / kTB;
   double* Rinv = c->Tq;  // nblk * 32 * 32 (the QR's T factors are no longer needed)
   const int e0 = prof_mark(c);
   hipLaunchKernelGGL(k_trinv_blocks, dim3(nblk, 1, c->nch), dim3(64), 0, c->stream, R, n, ld, Rinv, c->zs);
-  hipLaunchKernelGGL(k_trsm_upper, dim3((n + 15) / 16, 1, c->nch), dim3(512), 0, c->stream, R, Rinv, X, n, ld,
-                     c->zs);
+  hipLaunchKernelGGL(k_trsm_upper, dim3((ncols + 15) / 16, 1, c->nch), dim3(512), 0, c->stream, R, Rinv, X, n,
+                     ncols, ld, c->zs);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;

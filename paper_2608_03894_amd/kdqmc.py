@@ -38,6 +38,7 @@ class Params(ctypes.Structure):
         ("window", ctypes.c_int),
         ("fft_tile", ctypes.c_int),
         ("prec", ctypes.c_int),
+        ("n_occ", ctypes.c_int),
     ]
 
 
@@ -76,6 +77,11 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_int)]),
     "kdqmc_phase_name": (ctypes.c_char_p, [ctypes.c_int]),
     "kdqmc_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "kdqmc_set_wrap_tolerance": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "kdqmc_trial_orbitals": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                            ctypes.POINTER(ctypes.c_double)]),
+    "kdqmc_set_trial": (ctypes.c_int, [_vp, _vp]),
+    "kdqmc_health": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
 }
 
 NPHASE = 11
@@ -117,13 +123,28 @@ def _check(rc):
 
 
 def make_params(L, U, beta, dtau=0.1, t=1.0, mu=None, n_stab=10, delay_k=32, window=0,
-                fft_tile=0, prec="fp64") -> Params:
+                fft_tile=0, prec="fp64", n_occ=0) -> Params:
+    """n_occ = 0: finite temperature; n_occ > 0: the projector form with n_occ
+    trial orbitals projected over beta."""
     if mu is None:
         mu = dirac_mu(L, t)
     if isinstance(prec, str):
         prec = PREC[prec]
     return Params(L=L, t=t, U=U, mu=mu, beta=beta, dtau=dtau, n_stab=n_stab, delay_k=delay_k,
-                  window=window, fft_tile=fft_tile, prec=prec)
+                  window=window, fft_tile=fft_tile, prec=prec, n_occ=n_occ)
+
+
+TRIAL_EPS = 0.01
+
+
+def trial_orbitals(L, n_occ, t=1.0, eps=TRIAL_EPS):
+    """The library's trial orbitals (host): numpy array N x n_occ."""
+    import numpy as np
+    N = 3 * L * L
+    out = np.zeros((N, n_occ), dtype=np.float64)
+    _check(load().kdqmc_trial_orbitals(L, t, n_occ, eps,
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
 
 
 def workspace_bytes(p: Params, n_chains: int = 1) -> int:
@@ -173,6 +194,9 @@ class Chain:
         self.ctx = ctx
 
     # -- the calls of the C ABI, same names ---------------------------------
+    def set_trial(self, P):
+        _check(self.lib.kdqmc_set_trial(self.ctx, _ptr(P)))
+
     def set_fields(self, s):
         _check(self.lib.kdqmc_set_fields(self.ctx, _ptr(s)))
 
@@ -222,6 +246,22 @@ class Chain:
 
     def qr_f64(self, n, A, Q):
         _check(self.lib.kdqmc_qr_f64(self.ctx, n, _ptr(A), _ptr(Q)))
+
+    def set_wrap_tolerance(self, tol):
+        _check(self.lib.kdqmc_set_wrap_tolerance(self.ctx, float(tol)))
+
+    def health(self, raise_on_error=True):
+        """Largest wrap error since the last call (synchronizes); raises
+        KdqmcError(ENUMERIC) when a chain drifted or went non-finite, unless
+        raise_on_error is False (then returns (worst, ok))."""
+        worst = ctypes.c_double(0.0)
+        rc = self.lib.kdqmc_health(self.ctx, ctypes.byref(worst))
+        if raise_on_error:
+            _check(rc)
+            return worst.value
+        if rc not in (OK, ENUMERIC):
+            _check(rc)
+        return worst.value, rc == OK
 
     def use_graphs(self, on=True):
         _check(self.lib.kdqmc_use_graphs(self.ctx, 1 if on else 0))
@@ -273,7 +313,8 @@ class Batch:
         self.params = list(params_list)
         groups = {}
         for i, p in enumerate(self.params):
-            key = (p.L, p.t, p.mu, p.beta, p.dtau, p.n_stab, p.delay_k, p.window, p.fft_tile, p.prec)
+            key = (p.L, p.t, p.mu, p.beta, p.dtau, p.n_stab, p.delay_k, p.window, p.fft_tile, p.prec,
+                   p.n_occ)
             groups.setdefault(key, []).append(i)
         self.groups = []
         for key, idx in groups.items():
@@ -292,6 +333,9 @@ class Batch:
             idx = g["idx"]
             g["fields"] = t.stack([fields[i] for i in idx]).contiguous()
             g["u"] = t.stack([uniforms[i] for i in idx], dim=1).contiguous()  # (sweeps, chains, L_tau, N)
+            # one fixed buffer per group: every sweep passes the same pointers,
+            # so its captured graphs are replayed rather than captured again
+            g["ub"] = t.empty_like(g["u"][0])
             ch = g["chain"]
             g["acc"] = t.zeros((len(idx), ch.L_tau, ch.N), dtype=t.uint8, device=self.device)
             g["err"] = t.zeros((len(idx), ch.L_tau // ch.p.n_stab), dtype=t.float64, device=self.device)
@@ -308,8 +352,10 @@ class Batch:
         cur = t.cuda.current_stream(self.device)
         for g in self.groups:
             g["stream"].wait_stream(cur)
+            with t.cuda.stream(g["stream"]):
+                g["ub"].copy_(g["u"][s])
             fn = g["chain"].sweep_down if down else g["chain"].sweep
-            fn(g["u"][s], None, g["acc"], None, g["err"])
+            fn(g["ub"], None, g["acc"], None, g["err"])
         for g in self.groups:
             cur.wait_stream(g["stream"])
 
@@ -318,6 +364,15 @@ class Batch:
 
     def max_wrap_err(self):
         return max(float(g["err"].max().item()) for g in self.groups)
+
+    def health(self):
+        """(largest wrap error of any chain since the last call, all healthy)."""
+        worst, ok = 0.0, True
+        for g in self.groups:
+            w, good = g["chain"].health(raise_on_error=False)
+            worst = w if (w != w or w > worst) else worst
+            ok = ok and good
+        return worst, ok
 
     def field_updates_per_sweep(self):
         return sum(3 * p.L * p.L * int(round(p.beta / p.dtau)) for p in self.params)

@@ -63,3 +63,24 @@ def test_invalid_params(kw, msg):
                           **{k: v for k, v in kw.items() if k not in ("L", "U", "beta")})
     assert kdqmc.workspace_bytes(p) == 0
     assert msg in kdqmc.last_error()
+
+
+@pytest.mark.parametrize("L,n_occ", [(3, 9), (6, 36), (6, 31), (6, 48), (12, 144)])
+def test_trial_orbitals_match_oracle(L, n_occ):
+    """The library's trial orbitals (Bloch states, host code) span the same
+    space as the oracle's dense eigenvectors of K + eps (n_A - n_C): equal
+    projectors P P^T; orthonormal and real."""
+    import numpy as np
+    from oracle import pqmc
+    from paper_2608_03894_amd import kdqmc
+    p = kdqmc.trial_orbitals(L, n_occ)
+    q, _ = pqmc.trial_orbitals(L, n_occ)
+    assert np.abs(p.T @ p - np.eye(n_occ)).max() < 1e-12
+    assert np.abs(p @ p.T - q @ q.T).max() < 1e-12
+
+
+def test_trial_orbitals_open_shell():
+    from paper_2608_03894_amd import kdqmc
+    with pytest.raises(kdqmc.KdqmcError) as e:
+        kdqmc.trial_orbitals(6, 36, eps=0.0)
+    assert e.value.code == kdqmc.EINVAL and "open shell" in str(e.value)

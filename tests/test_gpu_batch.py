@@ -185,3 +185,62 @@ def test_fused_window_launch_equals_three_kernel_schedule(gpu_lib):
         assert np.array_equal(a1.cpu().numpy(), a2[z].cpu().numpy())
         assert np.array_equal(r1.cpu().numpy(), r2[z].cpu().numpy())
         assert np.array_equal(G1, G2[z])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_f16"])
+def test_uneven_batch_against_oracle(gpu_lib, prec):
+    """Two chains of different lattices (L=3 and L=6) and couplings in one
+    uneven batch (two shape groups on two streams), an upward then a downward
+    Metropolis pass, each against the oracle's passes from the same uniforms:
+    the decisions must be identical and G within 1e-10 (FP64), or within the
+    mixed precision's 1e-5 target at a 2-slice interval (the flips are then
+    replayed from the oracle's decisions, so that a ratio within rounding of
+    its uniform cannot make the chains part)."""
+    from paper_2608_03894_amd import kdqmc
+    t = torch()
+    specs = [(3, -4.0, 2.0, 93), (6, -5.0, 2.0, 94), (6, -3.0, 2.0, 95)]
+    n_stab = 10 if prec == "fp64" else 2
+    params = [kdqmc.make_params(L, U, beta, 0.1, mu=-1.0, n_stab=n_stab, delay_k=8, prec=prec)
+              for (L, U, beta, _) in specs]
+    fs = [si.ising_fields(L, 20, s) for (L, U, beta, s) in specs]
+    us = [si.metropolis_uniforms(L, 20, s, n_sweeps=2) for (L, U, beta, s) in specs]
+    refs = []
+    for (L, U, beta, s), f, u in zip(specs, fs, us):
+        m = dqmc.Model(L=L, t=1.0, U=U, beta=beta, dtau=0.1, mu=-1.0)
+        r1 = dqmc.sweep(m, f, dqmc.green_scratch(m, f, 0), uniforms=u[0], k=1)
+        r2 = dqmc.sweep_down(m, r1["fields"], r1["G"], uniforms=u[1], k=1)
+        refs.append((r1, r2))
+    say("uneven batch vs oracle", prec)
+    b = kdqmc.Batch(params)
+    assert len(b.groups) == 2
+    if prec == "fp64":
+        b.set_inputs([dev(f) for f in fs], [dev(u) for u in us])
+        b.sweep(0)
+        b.sweep(1, down=True)
+    else:
+        # the oracle's decisions, through the same per-group buffers
+        b.set_inputs([dev(f) for f in fs], [dev(u) for u in us])
+        for g in b.groups:
+            g["forced"] = [dev(np.stack([refs[i][d]["accepted"].astype(np.uint8) for i in g["idx"]]))
+                           for d in range(2)]
+            ch = g["chain"]
+            with t.cuda.stream(g["stream"]):
+                ch.sweep(None, g["forced"][0], g["acc"], None, g["err"])
+                ch.sweep_down(None, g["forced"][1], None, None, None)
+    t.cuda.synchronize()
+    for g in b.groups:
+        G = g["chain"].G().cpu().numpy()
+        acc = g["acc"].cpu().numpy()
+        if G.ndim == 2:
+            G = G[None]
+        for k, i in enumerate(g["idx"]):
+            r1, r2 = refs[i]
+            d = float(np.abs(G[k] - r2["G"]).max())
+            say("chain", i, specs[i], "max|dG| vs oracle", d)
+            if prec == "fp64":
+                assert d < TOL64
+                # the group's accept buffer holds the last (downward) pass
+                assert np.array_equal(acc[k].astype(bool), r2["accepted"])
+            else:
+                assert d < 1e-5
+    b.close()
