@@ -405,6 +405,213 @@ def bench_wrap(Ls=(12, 18, 24), reps=50, fft_tile=0):
             "results": res}
 
 
+def batch_roofline(n_chains=256, L=12, beta=4.0, delay_k=128, window=32, steps=2, warmup=1):
+    """The batched form as the roofline case: n_chains chains of one shape
+    (L=12, U=-4, FP64) in one batched context, so every kernel launches once
+    for all of them (chains along the grid's z) and their G matrices
+    (n_chains x 1.5 MB) exceed the 256 MB Infinity Cache.  Delay rank 128 in
+    32-site windows: the pending factors are flushed every four windows, at a
+    rank near 80 (the FP64 ridge of 9.8 flop/B).  Rates from a timed run,
+    per-kernel rooflines from a profiled run (HIP events per launch)."""
+    import torch
+    from paper_2608_03894_amd import kdqmc
+    dev = torch.device("cuda:0")
+    p = kdqmc.make_params(L, -4.0, beta, 0.1, mu=-1.0, n_stab=10, delay_k=delay_k, window=window)
+    ch = kdqmc.Chain(p, device=dev, n_chains=n_chains)
+    N, Lt = ch.N, ch.L_tau
+    f = torch.from_numpy(np.stack([si.ising_fields(L, Lt, 9000 + z) for z in range(n_chains)])).to(dev)
+    u = torch.from_numpy(np.stack([si.metropolis_uniforms(L, Lt, 9000 + z, n_sweeps=warmup + 2 * steps)
+                                   for z in range(n_chains)], axis=1)).to(dev)   # (sweeps, chains, Lt, N)
+    ub = torch.empty_like(u[0])
+    acc = torch.zeros((n_chains, Lt, N), dtype=torch.uint8, device=dev)
+    ch.set_fields(f)
+
+    def one(s):
+        ub.copy_(u[s])
+        (ch.sweep_down if s % 2 else ch.sweep)(ub, None, acc, None, None)
+    for s in range(warmup):
+        one(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        one(warmup + s)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    worst, ok = ch.health(raise_on_error=False)
+    accepts = float(acc.sum().item())
+    ch.set_fields(f)
+    ch.profile_enable(True)
+    for s in range(steps):
+        one(warmup + steps + s)
+    prof = ch.profile_read()
+    ch.profile_enable(False)
+    ch.close()
+    n_fl = prof["flush"][1] // steps
+    k_avg = accepts / n_chains / max(1, n_fl)           # rank of one chain's flush
+    kern = {}
+    for name in ("wrap_cols", "wrap_rows", "flush", "decide", "extend", "prep", "bmul"):
+        ms, n = prof[name]
+        if not n:
+            continue
+        t = ms / n / 1000.0
+        r = {"avg_us": round(1e6 * t, 2), "launches": n}
+        if name in ("wrap_cols", "wrap_rows", "bmul"):
+            byt = 2.0 * N * N * 8 * n_chains
+            r.update(bound="hbm", achieved=byt / t / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                     frac=byt / t / 1e9 / HBM_PEAK_GBS)
+        elif name == "flush":
+            fl = 2.0 * N * N * k_avg * n_chains
+            byt = (2.0 * N * N * 8 + 2.0 * N * k_avg * 8) * n_chains
+            r.update(bound="mfma", achieved=fl / t / 1e12, peak=FP64_PEAK_TFS, unit="TFLOP/s",
+                     frac=fl / t / 1e12 / FP64_PEAK_TFS, rank=k_avg, hbm_gbs=byt / t / 1e9,
+                     hbm_frac=byt / t / 1e9 / HBM_PEAK_GBS)
+        kern[name] = r
+    res = {"workload": f"kagome-batch-{n_chains}x-L{L}-U-4-beta{beta:g}-fp64-k{delay_k}",
+           "chains": n_chains, "N": N, "L_tau": Lt, "G_bytes_total": N * N * 8 * n_chains,
+           "value": n_chains * steps / el if ok else None, "unit": "chain-sweeps/s", "steps": steps,
+           "warmup": warmup, "ms_per_step": 1000.0 * el / steps, "healthy": ok, "max_wrap_err": worst,
+           "field_updates_per_s": n_chains * N * Lt * steps / el if ok else None,
+           "phases_ms_per_sweep": {k: round(v[0] / steps, 3) for k, v in prof.items() if v[1]},
+           "kernels": kern}
+    log("batch roofline", json.dumps(res))
+    return res
+
+
+def _loglog_slope(xs, ys):
+    x, y = np.log(np.asarray(xs, float)), np.log(np.asarray(ys, float))
+    return float(np.polyfit(x, y, 1)[0])
+
+
+def fig1_multiply(Ls=(3, 6, 9, 12, 15, 18, 24), reps=20):
+    """The paper's Fig. 1 on this GPU: time of one propagator product
+    e^{-dtau K} M (N x N, FP64) by the FFT path of Eqs. (5)-(6)
+    (kdqmc_expK_f64: per column 2D FFTs, 3x3 Bloch blocks, inverse FFTs)
+    against a dense multiply by the N x N matrix e^{-dtau K}: this library's
+    FP64 MFMA GEMM and the vendor DGEMM (torch.matmul, FP64).  Log-log slopes
+    of time against L as the paper's linear fits."""
+    import torch
+    from paper_2608_03894_amd import kdqmc
+    dev = torch.device("cuda:0")
+    rows = []
+    for L in Ls:
+        p = kdqmc.make_params(L, -4.0, 1.0, 0.1, mu=-1.0, n_stab=10, delay_k=1 if L == 3 else 32)
+        ch = kdqmc.Chain(p, device=dev)
+        N = ch.N
+        g = torch.Generator(device="cpu").manual_seed(L)
+        M = torch.rand((N, N), dtype=torch.float64, generator=g).to(dev)
+        A = M.clone()
+        E = torch.eye(N, dtype=torch.float64, device=dev)
+        ch.expK_f64(E)                         # the dense e^{-dtau K}, built by the FFT path
+        C = torch.empty_like(M)
+        ch.expK_f64(A)
+        ref = E @ M
+        err = float(((A - ref).abs().max() / ref.abs().max()).item())
+        timing = {}
+        for name, fn in (("fft", lambda: ch.expK_f64(A)),
+                         ("gemm_mfma", lambda: ch.gemm_f64(False, False, N, N, N, 1.0, E, N, M, N, 0.0, C, N)),
+                         ("gemm_vendor", lambda: torch.matmul(E, M, out=C))):
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            timing[name] = e0.elapsed_time(e1) * 1000.0 / reps   # us per product
+        row = {"L": L, "N": N, "fft_us": round(timing["fft"], 2), "gemm_mfma_us": round(timing["gemm_mfma"], 2),
+               "gemm_vendor_us": round(timing["gemm_vendor"], 2),
+               "speedup_vs_vendor": round(timing["gemm_vendor"] / timing["fft"], 2),
+               "fft_vs_dense_rel_err": err}
+        log("fig1", json.dumps(row))
+        rows.append(row)
+        ch.close()
+    big = [r for r in rows if r["L"] >= 9]
+    fits = {k: _loglog_slope([r["L"] for r in big], [r[k] for r in big])
+            for k in ("fft_us", "gemm_mfma_us", "gemm_vendor_us")}
+    return {"what": "time per product e^{-dtau K} M (N x N, FP64): FFT path vs dense GEMM",
+            "rows": rows, "loglog_slope_vs_L_for_L_ge_9": fits,
+            "expected_slopes": "FFT N^2 log N ~ L^4 (x log); dense N^3 ~ L^6"}
+
+
+def fig2_runtime(Ls=(6, 9, 12, 15, 18, 24), U=-5.0, beta=10.0, passes=2, window=5):
+    """The paper's Fig. 2 on this GPU: the projector workload of Sec. III
+    (U = -5, rho = 2/3: n_occ = L^2 trial orbitals, projection length
+    beta = 10, delay k = 32, stabilization every 10 slices).  One step = an
+    upward and a downward pass (a sweep), with the estimators measured after
+    every slice within `window` slices of the middle of the projection.
+    Time per sweep (wall clock, synchronized), the share of the GPU time per
+    process from HIP events around every launch (FFT multiplication: wrap and
+    stack products; delay update: decisions, factors and flushes;
+    measurement; the rest of the stabilization: QR, GEMM, solves), and the
+    fitted exponent of time against L over 12 <= L <= 24."""
+    import torch
+    from paper_2608_03894_amd import kdqmc
+    dev = torch.device("cuda:0")
+    rows = []
+    for L in Ls:
+        n_occ = L * L
+        p = kdqmc.make_params(L, U, beta, 0.1, mu=-1.0, n_stab=10, delay_k=32, n_occ=n_occ)
+        ch = kdqmc.Chain(p, device=dev)
+        N, Lt = ch.N, ch.L_tau
+        ch.set_trial(torch.from_numpy(kdqmc.trial_orbitals(L, n_occ)).to(dev))
+        f = torch.from_numpy(si.ising_fields(L, Lt, 7000 + L)).to(dev)
+        u = torch.from_numpy(si.metropolis_uniforms(L, Lt, 7000 + L, n_sweeps=2 + 2 * passes)).to(dev)
+        obs = torch.zeros(8, dtype=torch.float64, device=dev)
+        ch.set_fields(f)
+        ub = torch.empty_like(u[0])
+        for s in range(2):                      # warm-up: one sweep from captured graphs
+            ub.copy_(u[s])
+            (ch.sweep_down if s % 2 else ch.sweep)(ub)
+        mid = Lt // 2
+
+        def one_sweep(s0):
+            for l in range(1, Lt + 1):
+                ch.sweep_slice(l, u[s0][l - 1])
+                if l % 10 == 0:
+                    ch.stabilize()
+                if abs(l - mid) <= window:
+                    ch.measure(obs)
+            for l in range(Lt, 0, -1):
+                ch.sweep_slice_down(l, u[s0 + 1][l - 1])
+                if (l - 1) % 10 == 0:
+                    ch.stabilize()
+                if abs(l - 1 - mid) <= window:
+                    ch.measure(obs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(passes // 2 or 1):
+            one_sweep(2 + 2 * k)
+        torch.cuda.synchronize()
+        sweeps = passes // 2 or 1
+        t_sweep = (time.perf_counter() - t0) / sweeps
+        ch.set_fields(f)
+        ch.profile_enable(True)
+        for k in range(sweeps):
+            one_sweep(2 + 2 * k)
+        prof = ch.profile_read()
+        ch.profile_enable(False)
+        ms = {k: v[0] / sweeps for k, v in prof.items()}
+        fft = ms["wrap_cols"] + ms["wrap_rows"] + ms["bmul"]
+        delay = ms["decide"] + ms["extend"] + ms["prep"] + ms["flush"] + ms["flush_decide"]
+        meas = ms["measure"]
+        stab_rest = ms["stabilize"] - ms["bmul"]
+        tot = fft + delay + meas + stab_rest
+        row = {"L": L, "N": N, "L_tau": Lt, "n_occ": n_occ, "s_per_sweep": round(t_sweep, 5),
+               "gpu_ms_per_sweep": round(tot, 3),
+               "share": {"fft_multiply": round(fft / tot, 4), "delay_update": round(delay / tot, 4),
+                         "measurement": round(meas / tot, 4), "stabilization_qr_gemm": round(stab_rest / tot, 4)}}
+        log("fig2", json.dumps(row))
+        rows.append(row)
+        ch.close()
+    big = [r for r in rows if r["L"] >= 12]
+    a = _loglog_slope([r["L"] for r in big], [r["s_per_sweep"] for r in big])
+    return {"what": "projector workload of Sec. III (U=-5, rho=2/3, beta=10): time per sweep and GPU-time "
+                    "shares per process vs L", "rows": rows,
+            "fit_12_le_L_le_24": {"time_vs_L_exponent": a, "time_vs_N_exponent": a / 2.0},
+            "paper_context": "Time ~ L^4.98 ~ N^2.49 over 12 <= L <= 27 on 20-30 Xeon E5-2678 v3 cores"}
+
+
 def workload_record(w, prec, n_stab, k, window, tile, res, tuned, table=None):
     rec = {"metric": "HS-field sweeps/sec", "value": res["value"], "unit": "sweeps/s",
            "steps": res["steps"], "warmup": res["warmup"], "ms_per_step": res["ms_per_step"],
@@ -464,6 +671,12 @@ def extras(args):
         out["wrap"] = bench_wrap()
     except Exception as e:
         out["wrap"] = {"error": str(e)}
+    for key, fn in (("batch_roofline", batch_roofline), ("fig1_multiply", fig1_multiply),
+                    ("fig2_runtime", fig2_runtime)):
+        try:
+            out[key] = fn()
+        except Exception as e:
+            out[key] = {"error": str(e)}
     return out
 
 
@@ -490,6 +703,10 @@ def main():
     ap.add_argument("--extra-steps-batch", type=int, default=4)
     ap.add_argument("--wrap-only", action="store_true",
                     help="only time the FFT wrap passes at L = 12, 18, 24 and exit")
+    ap.add_argument("--fig", choices=["1", "2"], default=None,
+                    help="only run the paper's Fig. 1 (multiply) or Fig. 2 (runtime) experiment and exit")
+    ap.add_argument("--batch-roofline", action="store_true",
+                    help="only run the 256-chain batched roofline case and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -502,6 +719,12 @@ def main():
 
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batch_roofline:
+        print(json.dumps(batch_roofline(steps=args.steps, warmup=args.warmup)), flush=True)
+        return
+    if args.fig:
+        print(json.dumps(fig1_multiply() if args.fig == "1" else fig2_runtime()), flush=True)
         return
     if args.wrap_only:
         print(json.dumps(bench_wrap(fft_tile=args.fft_tile)), flush=True)

@@ -64,6 +64,12 @@ typedef enum {
   KDQMC_MIXED_BF16 = 2  /* as MIXED_F16 with split BF16 products */
 } kdqmc_prec;
 
+typedef enum {
+  KDQMC_KAGOME = 0,      /* 3 sites per cell, K of Eq. (3) */
+  KDQMC_TRIANGULAR = 1,  /* 1 site per cell, K of App. A1 */
+  KDQMC_HONEYCOMB = 2    /* 2 sites per cell, K of App. A2 */
+} kdqmc_lattice;
+
 typedef struct {
   int L;          /* cells per side; supported: 3, 6, 9, 12, 15, 18, 24 */
   double t;       /* hopping, K_ij = -t on nearest neighbours (Eq. (1)) */
@@ -80,6 +86,9 @@ typedef struct {
                      > 0: projector form of Sec. II with n_occ occupied trial
                      orbitals per spin (filling rho = 2 n_occ / N) projected
                      over beta (the projection length of Sec. III) */
+  int lattice;    /* a kdqmc_lattice value, 0 = kagome: N = S L^2 sites with S = 3, 1, 2
+                     sites per cell, ordered i = (x1 L + x2) S + s; the
+                     measurements and kdqmc_trial_orbitals are kagome only */
 } kdqmc_params;
 
 typedef struct kdqmc_ctx kdqmc_ctx;
@@ -245,6 +254,37 @@ int kdqmc_use_graphs(kdqmc_ctx* c, int on);
  * G(current slice) to G_dev (FP64, N x N row-major, site order above). */
 int kdqmc_measure_G(kdqmc_ctx* c, double* G_dev);
 
+/* ---- equal-time measurements (Secs. IV-V) ----
+ * Per-configuration estimators from the current G by Wick's theorem with
+ * G_ab = <c_a c_b^+> for either spin (the charge decoupling keeps both spins
+ * equal).  Real parts; the Monte-Carlo averages, the correlation ratio
+ * R_Pair = 1 - S(Gamma + dk) / S(Gamma) and the order parameter
+ * P = sqrt(S(Gamma) / N) of Sec. IV are formed from averages by the caller.
+ *   SPAIR_*: S_Pair(Q) = (1/N) sum_ij e^{iQ.(r_i - r_j)}
+ *            <c+_{i up} c+_{i dn} c_{j dn} c_{j up} + c_{j dn} c_{j up} c+_{i up} c+_{i dn}>
+ *            (the symmetric form of Sec. IV) at Gamma and at the two
+ *            smallest momenta Gamma + dk, dk = 2 pi b_1 / L and 2 pi b_2 / L;
+ *   CDW2_*:  D(Q)^2 = <phi^+(Q) phi(Q)>, phi(Q) = (1/N) sum_cells e^{iQ.R}
+ *            (n_A + e^{2 pi i/3} n_B + e^{4 pi i/3} n_C) (Sec. V), at Gamma and
+ *            at the Dirac point K;
+ *   DENSITY: particles per site, both spins.
+ * Sites sit at x1 a1 + x2 a2 plus (0, 0), -a2/2, -a1/2 for A, B, C, with a1,
+ * a2 at 60 degrees (every bond of Eq. (3) then has the same length). */
+enum {
+  KDQMC_OBS_SPAIR_GAMMA = 0,
+  KDQMC_OBS_SPAIR_DK1 = 1,
+  KDQMC_OBS_SPAIR_DK2 = 2,
+  KDQMC_OBS_CDW2_GAMMA = 3,
+  KDQMC_OBS_CDW2_K = 4,
+  KDQMC_OBS_DENSITY = 5,
+  KDQMC_NOBS = 6
+};
+
+/* Writes the KDQMC_NOBS estimators of G(current slice) to obs_dev[KDQMC_NOBS]
+ * (device, float64; one record per chain for a batch).  Asynchronous; one
+ * pass over G. */
+int kdqmc_measure(kdqmc_ctx* c, double* obs_dev);
+
 /* Numeric health.  Every stabilization (direct or inside kdqmc_sweep /
  * kdqmc_sweep_down) records its wrap error max |G_current - G_fresh| on the
  * device; one that is not finite or exceeds the context's tolerance, or a
@@ -278,14 +318,15 @@ const char* kdqmc_last_error(void);
 
 /* ---- profiling: HIP events around every kernel launch of the context ---- */
 
-#define KDQMC_NPHASE 11
+#define KDQMC_NPHASE 12
 /* Phases: 0 wrap_cols, 1 wrap_rows (the two FFT passes of the wrap),
  * 2 decide, 3 extend, 4 prep (window decisions and delayed factors),
  * 5 flush (rank-k MFMA update), 6 bmul (B-chain products of the stacks),
  * 7 qr_panel, 8 gemm (stabilization linear algebra), 9 stabilize (whole
  * kdqmc_stabilize calls, which contain phases 6-8), 10 flush_decide (FP64
  * with a flush after every window: one launch per window that forms the
- * window's factors, flushes them and runs the next window's decisions). */
+ * window's factors, flushes them and runs the next window's decisions),
+ * 11 measure (kdqmc_measure). */
 
 /* on != 0 starts recording (clearing earlier records); 0 stops. */
 int kdqmc_profile_enable(kdqmc_ctx* c, int on);
@@ -308,6 +349,12 @@ const char* kdqmc_phase_name(int phase);
 int kdqmc_gemm_f64(kdqmc_ctx* c, int trans_a, int trans_b, int M, int N, int K, double alpha,
                    const double* A_dev, int lda, const double* B_dev, int ldb, double beta,
                    double* C_dev, int ldc);
+
+/* The propagator product of Eq. (5) alone, by the three steps of Eq. (6):
+ * A <- exp(sign dtau K) A for the first ncols columns of the N x N row-major
+ * A_dev (row stride lda), sign = -1 or +1.  Needs a single-chain FP64
+ * context (its tables).  The FFT side of the paper's Fig. 1 comparison. */
+int kdqmc_expK_f64(kdqmc_ctx* c, double* A_dev, int lda, int ncols, int sign);
 
 /* Householder QR of the n x n row-major A_dev (FP64) in place: on return
  * Q_dev holds Q (n x n), A_dev holds R in its upper triangle (zeros below).

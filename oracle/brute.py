@@ -108,3 +108,34 @@ def mp_pqmc_log_weight(model: dqmc.Model, fields: np.ndarray, p: np.ndarray, dps
             x = _mp_b(e, a, fields[j - 1]) * x
         det = mp.det(pm.T * x)
         return 2 * mp.log(abs(det)) - a * int(fields.sum())
+
+
+# ---------------------------------------------------------------------------
+# Fock-space brute force (tiny systems): expectation values under a Gaussian
+# weight operator, computed from the many-body matrices themselves.
+# ---------------------------------------------------------------------------
+
+def fock_annihilators(modes: int):
+    """Jordan-Wigner annihilation matrices c_k (2^modes x 2^modes), mode 0 first."""
+    a = np.array([[0.0, 1.0], [0.0, 0.0]])   # |1> -> |0>
+    z = np.diag([1.0, -1.0])
+    eye = np.eye(2)
+    ops = []
+    for k in range(modes):
+        m = np.array([[1.0]])
+        for j in range(modes):
+            m = np.kron(m, z if j < k else (a if j == k else eye))
+        ops.append(m)
+    return ops
+
+
+def fock_quadratic(cs, a: np.ndarray, spins: int = 2) -> np.ndarray:
+    """sum over spins and sites of c^+_{s,i} A_ij c_{s,j} (mode = s * n + i)."""
+    n = a.shape[0]
+    out = np.zeros_like(cs[0])
+    for s in range(spins):
+        for i in range(n):
+            for j in range(n):
+                if a[i, j] != 0.0:
+                    out += a[i, j] * cs[s * n + i].T @ cs[s * n + j]
+    return out

@@ -53,11 +53,12 @@ class Model:
     beta: float
     dtau: float
     mu: float
+    lattice: str = "kagome"   # or "triangular", "honeycomb" (App. A)
 
     def __post_init__(self):
-        self.N = 3 * self.L * self.L
+        self.K = lattice.lattice_K(self.lattice, self.L, self.t)
+        self.N = self.K.shape[0]
         self.L_tau = int(round(self.beta / self.dtau))
-        self.K = lattice.kagome_K(self.L, self.t)
         km = self.K - self.mu * np.eye(self.N)
         # Dense propagators: the plain definition of the product of Eq. (5).
         self.E = scipy.linalg.expm(-self.dtau * km)

@@ -53,6 +53,58 @@ def kagome_K(L: int, t: float = 1.0) -> np.ndarray:
     return -t * (m + m.T.conj())
 
 
+def triangular_K(L: int, t: float = 1.0) -> np.ndarray:
+    """Dense L^2 x L^2 kinetic matrix of the triangular lattice (App. A1):
+    the Kronecker sum I (x) K_s + K_s (x) I + K_s (x) K_s plus its Hermitian
+    conjugate, scaled by -t (Eq. (1)).  One site per cell, i = x1 L + x2."""
+    eye = np.eye(L)
+    ks = shift_matrix(L)
+    m = np.kron(eye, ks) + np.kron(ks, eye) + np.kron(ks, ks)
+    return -t * (m + m.T.conj())
+
+
+def honeycomb_K(L: int, t: float = 1.0) -> np.ndarray:
+    """Dense 2L^2 x 2L^2 kinetic matrix of the honeycomb lattice (App. A2):
+    (I (x) I + I (x) K_s + K_s (x) I) (x) delta plus its Hermitian conjugate,
+    delta the 2 x 2 matrix with one unit entry at (2, 1) (1-based); scaled by
+    -t.  Site i = (x1 L + x2) 2 + s, s = 0, 1 for the two sublattices."""
+    eye = np.eye(L)
+    ks = shift_matrix(L)
+    d = np.zeros((2, 2))
+    d[1, 0] = 1.0
+    m = np.kron(np.kron(eye, eye) + np.kron(eye, ks) + np.kron(ks, eye), d)
+    return -t * (m + m.T.conj())
+
+
+LATTICES = {"kagome": (3, kagome_K), "triangular": (1, triangular_K), "honeycomb": (2, honeycomb_K)}
+
+
+def lattice_K(name: str, L: int, t: float = 1.0) -> np.ndarray:
+    """K of a lattice by name (kagome, triangular, honeycomb)."""
+    return LATTICES[name][1](L, t)
+
+
+def triangular_band_energies(L: int, t: float = 1.0) -> np.ndarray:
+    """Closed form: -2t (cos k1 + cos k2 + cos(k1 + k2)) on the L x L grid (sorted)."""
+    e = []
+    for m1 in range(L):
+        for m2 in range(L):
+            k1, k2 = 2 * np.pi * m1 / L, 2 * np.pi * m2 / L
+            e.append(-2 * t * (np.cos(k1) + np.cos(k2) + np.cos(k1 + k2)))
+    return np.sort(np.array(e))
+
+
+def honeycomb_band_energies(L: int, t: float = 1.0) -> np.ndarray:
+    """Closed form: +-t |1 + e^{i k1} + e^{i k2}| on the L x L grid (sorted)."""
+    e = []
+    for m1 in range(L):
+        for m2 in range(L):
+            k1, k2 = 2 * np.pi * m1 / L, 2 * np.pi * m2 / L
+            r = abs(1 + np.exp(1j * k1) + np.exp(1j * k2))
+            e.extend([t * r, -t * r])
+    return np.sort(np.array(e))
+
+
 def dft_matrix(L: int) -> np.ndarray:
     """Unitary one-dimensional DFT matrix F, F[m, x] = exp(-2 pi i m x / L) / sqrt(L).
 

@@ -15,7 +15,7 @@ namespace {
 thread_local std::string g_last_error;
 
 struct Derived {
-  int N = 0, Ltau = 0, nc = 0, w = 0, nw = 0, F = 0, kmax = 0, P = 0, P64 = 0;
+  int N = 0, S = 3, Ltau = 0, nc = 0, w = 0, nw = 0, F = 0, kmax = 0, P = 0, P64 = 0;
   bool fp64 = true, proj = false;
 };
 
@@ -23,12 +23,12 @@ struct Derived {
 // unit (256) over all chains of the context where the matrices allow, at most
 // 4 (wider tiles coalesce the column pass but leave fewer workgroups), within
 // 64 KB of LDS and 512 threads.
-int auto_tile(int L, size_t elem, int requested, int nch) {
+int auto_tile(int L, int S, size_t elem, int requested, int nch) {
   if (requested > 0) return requested;
-  const int N = 3 * L * L;
+  const int N = S * L * L;
   const int ncomplex = (N + 1) / 2;
   int P = std::max(1, std::min(4, (int)((size_t)nch * ncomplex / 256)));
-  while (P > 1 && (2 * (size_t)(N + L) * P * elem > 64 * 1024 || 3 * L * P > 512)) --P;
+  while (P > 1 && (2 * (size_t)(N + L) * P * elem > 64 * 1024 || S * L * P > 512)) --P;
   return P;
 }
 
@@ -36,6 +36,8 @@ int derive(const kdqmc_params* p, Derived* d, int nch = 1) {
   if (!p) return set_error(KDQMC_EINVAL, "params is NULL");
   if (!lattice_supported(p->L))
     return set_error(KDQMC_EUNSUPPORTED, "L must be one of 3, 6, 9, 12, 15, 18, 24");
+  if (p->lattice < KDQMC_KAGOME || p->lattice > KDQMC_HONEYCOMB)
+    return set_error(KDQMC_EINVAL, "lattice must be KDQMC_KAGOME, KDQMC_TRIANGULAR or KDQMC_HONEYCOMB");
   if (!(std::isfinite(p->t) && std::isfinite(p->U) && std::isfinite(p->mu)))
     return set_error(KDQMC_EINVAL, "t, U, mu must be finite");
   if (p->U > 0.0)
@@ -55,7 +57,8 @@ int derive(const kdqmc_params* p, Derived* d, int nch = 1) {
   int w = p->window > 0 ? p->window : std::min(p->delay_k, 32);
   if (w > 64) return set_error(KDQMC_EINVAL, "window above 64");
   if (w > p->delay_k) return set_error(KDQMC_EINVAL, "window larger than delay_k");
-  d->N = 3 * p->L * p->L;
+  d->S = lattice_nsub(p->lattice);
+  d->N = d->S * p->L * p->L;
   d->Ltau = Ltau;
   d->nc = Ltau / p->n_stab;
   d->w = std::min(w, d->N);
@@ -66,9 +69,9 @@ int derive(const kdqmc_params* p, Derived* d, int nch = 1) {
   if (p->n_occ < 0 || p->n_occ > d->N) return set_error(KDQMC_EINVAL, "n_occ must be in 0..N");
   d->proj = p->n_occ > 0;
   const size_t es = d->fp64 ? 8 : 4;
-  d->P = auto_tile(p->L, es, p->fft_tile, nch);
-  d->P64 = d->fp64 ? d->P : auto_tile(p->L, 8, 0, nch);
-  if (2 * (size_t)(d->N + p->L) * d->P * es > 160 * 1024 || 3 * p->L * d->P > 512)
+  d->P = auto_tile(p->L, d->S, es, p->fft_tile, nch);
+  d->P64 = d->fp64 ? d->P : auto_tile(p->L, d->S, 8, 0, nch);
+  if (2 * (size_t)(d->N + p->L) * d->P * es > 160 * 1024 || d->S * p->L * d->P > 512)
     return set_error(KDQMC_EINVAL, "fft_tile exceeds LDS or thread limits");
   return KDQMC_OK;
 }
@@ -117,6 +120,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   char* LT = take(tmat);
   char* LD = take((d.nc + 1) * N * 8);
   char* Ptr = take(d.proj ? nn * 8 : 0);
+  char* obs = take(N * 8 * 8);
   char* S[8];
   for (int i = 0; i < 8; ++i) S[i] = take(nn * 8);
   char* Vq = take(nn * 8);
@@ -152,6 +156,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
     c->RU = (double*)RU; c->RT = (double*)RT; c->RD = (double*)RD;
     c->LU = (double*)LU; c->LT = (double*)LT; c->LD = (double*)LD;
     c->Ptrial = d.proj ? (double*)Ptr : nullptr;
+    c->obs_tab = (double*)obs;
     for (int i = 0; i < 8; ++i) c->S[i] = (double*)S[i];
     c->Vq = (double*)Vq;
     c->Tq = (double*)Tq;
@@ -294,12 +299,14 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
   const size_t need = batch_bytes(p, d, n_chains);
   if (workspace_bytes < need)
     return set_error(KDQMC_ENOSPACE, "workspace smaller than kdqmc_workspace_bytes_batch()");
-  KDQMC_TRY(prepare_kinetic(p->L));
+  KDQMC_TRY(prepare_kinetic(p->L, d.S));
   KDQMC_TRY(prepare_updates());
   kdqmc_ctx* c = new kdqmc_ctx();
   c->p = *p;
   c->N = d.N;
   c->L = p->L;
+  c->lattice = p->lattice;
+  c->nsub = d.S;
   c->Ltau = d.Ltau;
   c->nc = d.nc;
   c->w = d.w;
@@ -326,10 +333,11 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
   // Bloch tables: exp(-dtau H(k)) and exp(+dtau H(k)) for the wrap (mu cancels),
   // exp(-dtau (H(k) - mu)) for the B-chains; 1/L^2 folded in.
   const size_t L2 = (size_t)p->L * p->L;
-  std::vector<double> tm(L2 * 18), tp(L2 * 18), tmu(L2 * 18);
-  bloch_table(p->L, p->t, -p->dtau, 0.0, tm.data());
-  bloch_table(p->L, p->t, +p->dtau, 0.0, tp.data());
-  bloch_table(p->L, p->t, -p->dtau, p->mu, tmu.data());
+  std::vector<double> tm(L2 * 18), tp(L2 * 18), tmu(L2 * 18), otab((size_t)d.N * 8);
+  if (p->lattice == KDQMC_KAGOME) measure_table(p->L, otab.data());  // (kagome estimators only)
+  bloch_table(p->lattice, p->L, p->t, -p->dtau, 0.0, tm.data());
+  bloch_table(p->lattice, p->L, p->t, +p->dtau, 0.0, tp.data());
+  bloch_table(p->lattice, p->L, p->t, -p->dtau, p->mu, tmu.data());
   int rc = KDQMC_OK;
   auto upload = [&](void* dst, const std::vector<double>& src, bool as_float) -> int {
     if (as_float) {
@@ -354,7 +362,8 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
     if ((rc = upload(static_cast<char*>(c->tab_m) + o, tm, !c->fp64)) != KDQMC_OK ||
         (rc = upload(static_cast<char*>(c->tab_p) + o, tp, !c->fp64)) != KDQMC_OK ||
         (rc = upload(reinterpret_cast<char*>(c->tab_mu64) + o, tmu, false)) != KDQMC_OK ||
-        (rc = upload(reinterpret_cast<char*>(c->sc) + o, scv, false)) != KDQMC_OK)
+        (rc = upload(reinterpret_cast<char*>(c->sc) + o, scv, false)) != KDQMC_OK ||
+        (rc = upload(reinterpret_cast<char*>(c->obs_tab) + o, otab, false)) != KDQMC_OK)
       break;
   }
   if (rc == KDQMC_OK) rc = clear_health(c);
@@ -797,6 +806,14 @@ int kdqmc_measure_G(kdqmc_ctx* c, double* G_dev) {
   return copy_G_to64(c, G_dev, (size_t)c->N * c->N);
 }
 
+int kdqmc_measure(kdqmc_ctx* c, double* obs_dev) {
+  KDQMC_TRY(check_ctx(c));
+  if (!obs_dev) return set_error(KDQMC_EINVAL, "obs pointer is NULL");
+  if (c->l_cur < 0) return set_error(KDQMC_ESTATE, "no G loaded");
+  if (c->lattice != KDQMC_KAGOME) return set_error(KDQMC_EUNSUPPORTED, "the estimators are defined for the kagome lattice");
+  return launch_measure(c, obs_dev, KDQMC_NOBS);
+}
+
 int kdqmc_current_slice(const kdqmc_ctx* c) {
   if (!c) return set_error(KDQMC_EINVAL, "context is NULL");
   return c->l_cur;
@@ -852,7 +869,7 @@ int kdqmc_profile_read(kdqmc_ctx* c, double* ms, int* launches) {
 const char* kdqmc_phase_name(int phase) {
   static const char* names[KDQMC_NPHASE] = {"wrap_cols", "wrap_rows", "decide",  "extend",
                                             "prep",      "flush",     "bmul",    "qr_panel",
-                                            "gemm",      "stabilize", "flush_decide"};
+                                            "gemm",      "stabilize", "flush_decide", "measure"};
   return (phase >= 0 && phase < KDQMC_NPHASE) ? names[phase] : "";
 }
 
@@ -869,6 +886,16 @@ int kdqmc_gemm_f64(kdqmc_ctx* c, int trans_a, int trans_b, int M, int N, int K, 
   if (lda < std::max(1, acols) || ldb < std::max(1, bcols) || ldc < std::max(1, N))
     return set_error(KDQMC_EINVAL, "leading dimension too small");
   return gemm_f64(c, trans_a != 0, trans_b != 0, M, N, K, alpha, A_dev, lda, B_dev, ldb, beta, C_dev, ldc);
+}
+
+int kdqmc_expK_f64(kdqmc_ctx* c, double* A_dev, int lda, int ncols, int sign) {
+  KDQMC_TRY(check_ctx(c));
+  if (!A_dev) return set_error(KDQMC_EINVAL, "NULL matrix");
+  if (c->nch != 1 || !c->fp64) return set_error(KDQMC_EINVAL, "needs a single-chain FP64 context");
+  if (sign != 1 && sign != -1) return set_error(KDQMC_EINVAL, "sign must be +1 or -1");
+  if (ncols < 1 || ncols > c->N || lda < c->N) return set_error(KDQMC_EINVAL, "bad ncols or lda");
+  return launch_kinetic_f64(c, A_dev, lda, true, (const double*)(sign < 0 ? c->tab_m : c->tab_p), nullptr,
+                            nullptr, nullptr, ncols);
 }
 
 int kdqmc_qr_f64(kdqmc_ctx* c, int n, double* A_dev, double* Q_dev) {

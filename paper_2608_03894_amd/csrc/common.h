@@ -188,7 +188,7 @@ namespace kdqmc {
 // Phases timed by the optional HIP-event profiler (kdqmc_profile_*).
 enum Phase {
   PH_WRAP_COLS = 0, PH_WRAP_ROWS, PH_DECIDE, PH_EXTEND, PH_PREP, PH_FLUSH, PH_BMUL, PH_QR_PANEL,
-  PH_GEMM, PH_STABILIZE, PH_FLUSH_DECIDE, PH_COUNT
+  PH_GEMM, PH_STABILIZE, PH_FLUSH_DECIDE, PH_MEASURE, PH_COUNT
 };
 }  // namespace kdqmc
 
@@ -212,6 +212,7 @@ struct kdqmc_ctx {
   double prof_acc_ms[16] = {0};
   int prof_acc_n[16] = {0};
   int N = 0, L = 0, Ltau = 0, nc = 0;     // sites, cells/side, slices, stack checkpoints
+  int lattice = 0, nsub = 3;              // kdqmc_lattice, sublattices per cell
   int w = 0, nw = 0, F = 0;               // window size, windows per slice, windows per flush
   int P = 0;                              // complex vectors per wrap workgroup (storage type)
   int P64 = 0;                            // same for the FP64 stack products
@@ -234,6 +235,7 @@ struct kdqmc_ctx {
   int nocc = 0;
   bool trial_set = false;
   double* Ptrial = nullptr;    // N x nocc trial orbitals (row stride N)
+  double* obs_tab = nullptr;   // N x 8: phases of the measurement estimators
 
   // device buffers (carved from the caller's workspace)
   void* G = nullptr;           // N*N, double (FP64) or float (mixed)
@@ -287,9 +289,15 @@ namespace kdqmc {
 // Host helpers implemented in lattice.hip
 // ---------------------------------------------------------------------------
 bool lattice_supported(int L);
-// Fills tab[L*L*9] complex (interleaved re, im) with exp(scale * (H(k) - shift)) / L^2.
-void bloch_table(int L, double t, double scale, double shift, double* tab);
+// Sublattices per cell: 3 (kagome), 1 (triangular), 2 (honeycomb).
+int lattice_nsub(int lattice);
+// Fills tab[L*L*S*S] complex (interleaved re, im) with exp(scale * (H(k) - shift)) / L^2.
+void bloch_table(int lattice, int L, double t, double scale, double shift, double* tab);
 double dirac_mu(int L, double t);
+// Per-site phase table of the measurement estimators (host, tab[N * 8]).
+void measure_table(int L, double* tab);
+// The KDQMC_NOBS estimators of the current G into out (records zn doubles apart).
+int launch_measure(kdqmc_ctx* c, double* out, size_t zn);
 // Trial orbitals of the projector form into P[N * n_occ] (row-major, host).
 int trial_orbitals(int L, double t, int n_occ, double eps, double* P);
 
@@ -305,7 +313,7 @@ int launch_kinetic_f64(kdqmc_ctx* c, double* A, int lda, bool cols, const double
 int launch_kinetic_f32(kdqmc_ctx* c, float* A, int lda, bool cols, const float* tab,
                        const double* pre_e, const double* pre_v, const double* post_e, int nvec = 0);
 
-int prepare_kinetic(int L);
+int prepare_kinetic(int L, int nsub);
 int prepare_updates();
 int launch_frame_scale(kdqmc_ctx* c, int l);
 // Downward pass: after the flips of slice l, G <- F G F^{-1} with

@@ -1,14 +1,16 @@
 // Kinetic propagator applied to every column (or row) of a dense N x N
 // matrix through the momentum-space block form (Eq. (6)): per vector, a 2D
-// L x L FFT of each sublattice component, a 3x3 complex block multiply per
-// momentum, and the inverse 2D FFT.  Two real vectors travel as one complex
-// vector (the operator is real, so the real and imaginary parts do not mix).
+// L x L FFT of each sublattice component, an n x n complex block multiply per
+// momentum (n = S sublattices: 3 kagome, 1 triangular, 2 honeycomb; Eq. (4)
+// and App. A), and the inverse 2D FFT.  Two real vectors travel as one
+// complex vector (the operator is real, so the real and imaginary parts do
+// not mix).
 //
 // One workgroup owns P complex vectors (2P real columns or rows), staged in
 // LDS as separate real/imaginary planes [slot][vector]; the FFT lines are
-// processed in registers, one line per thread.  Element e = (x1 L + x2) 3 + s
-// sits in slot e + x1: every x1 row of 3L elements is padded by one slot, so
-// that the lanes of an x2-direction stage (one x1 row each, 3L + 1 slots
+// processed in registers, one line per thread.  Element e = (x1 L + x2) S + s
+// sits in slot e + x1: every x1 row of S L elements is padded by one slot, so
+// that the lanes of an x2-direction stage (one x1 row each, S L + 1 slots
 // apart) spread over the LDS banks instead of sharing one.
 #include "common.h"
 
@@ -145,26 +147,26 @@ struct FFT {
   }
 };
 
-// LDS slot of element e (row x1 = e / 3L padded by one slot).
-template <int L>
+// LDS slot of element e (row x1 = e / (S L) padded by one slot).
+template <int L, int S>
 __device__ __forceinline__ int slot_of(int e) {
-  return e + e / (3 * L);
+  return e + e / (S * L);
 }
 
 // One FFT stage over all lines of the tile: line (a, s, c) for a in [0, L),
-// s in [0, 3), c in [0, P): slots base(a, s) + m * stride, m in [0, L).
-// AXIS == 2: lines along x2 (a = x1, stride 3); AXIS == 1: along x1 (a = x2,
-// stride 3L + 1, the padded row).
-template <typename T, int L, int AXIS, int SIGN>
+// s in [0, S), c in [0, P): slots base(a, s) + m * stride, m in [0, L).
+// AXIS == 2: lines along x2 (a = x1, stride S); AXIS == 1: along x1 (a = x2,
+// stride S L + 1, the padded row).
+template <typename T, int L, int S, int AXIS, int SIGN>
 __device__ __forceinline__ void fft_stage(T* sre, T* sim, int P) {
-  const int nlines = 3 * L * P;
+  const int nlines = S * L * P;
   for (int idx = threadIdx.x; idx < nlines; idx += blockDim.x) {
     const int c = idx % P;
-    const int q = idx / P;  // q = a*3 + s
-    const int s = q % 3;
-    const int a = q / 3;
-    const int base = (AXIS == 2) ? (a * (3 * L + 1) + s) : (a * 3 + s);
-    constexpr int stride = (AXIS == 2) ? 3 : 3 * L + 1;
+    const int q = idx / P;  // q = a*S + s
+    const int s = q % S;
+    const int a = q / S;
+    const int base = (AXIS == 2) ? (a * (S * L + 1) + s) : (a * S + s);
+    constexpr int stride = (AXIS == 2) ? S : S * L + 1;
     T re[L], im[L];
 #pragma unroll
     for (int m = 0; m < L; ++m) {
@@ -180,27 +182,27 @@ __device__ __forceinline__ void fft_stage(T* sre, T* sim, int P) {
   }
 }
 
-// Per momentum k and vector c: (x_A, x_B, x_C) <- T(k) (x_A, x_B, x_C).
-template <typename T, int L>
+// Per momentum k and vector c: (x_0 .. x_{S-1}) <- T(k) (x_0 .. x_{S-1}).
+template <typename T, int L, int S>
 __device__ __forceinline__ void mix_stage(T* sre, T* sim, int P, const T* __restrict__ tab) {
   const int nitems = L * L * P;
   for (int idx = threadIdx.x; idx < nitems; idx += blockDim.x) {
     const int c = idx % P;
     const int k = idx / P;
-    const T* tk = tab + 18 * k;
-    const int b = (k / L) * (3 * L + 1) + 3 * (k % L);  // slot of (k, s = 0)
-    T xr[3], xi[3];
+    const T* tk = tab + 2 * S * S * k;
+    const int b = (k / L) * (S * L + 1) + S * (k % L);  // slot of (k, s = 0)
+    T xr[S], xi[S];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < S; ++s) {
       xr[s] = sre[(b + s) * P + c];
       xi[s] = sim[(b + s) * P + c];
     }
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
+    for (int s = 0; s < S; ++s) {
       T yr = T(0), yi = T(0);
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        const T ar = tk[2 * (3 * s + t)], ai = tk[2 * (3 * s + t) + 1];
+      for (int t = 0; t < S; ++t) {
+        const T ar = tk[2 * (S * s + t)], ai = tk[2 * (S * s + t) + 1];
         yr += ar * xr[t] - ai * xi[t];
         yi += ar * xi[t] + ai * xr[t];
       }
@@ -217,11 +219,11 @@ __device__ __forceinline__ void mix_stage(T* sre, T* sim, int P, const T* __rest
 // and pre_v[v] (vector) on the way in.
 constexpr int kWrapBatch = 16;
 
-template <typename T, int L, bool COLS, bool HE, bool HV>
+template <typename T, int L, int S, bool COLS, bool HE, bool HV>
 __device__ __forceinline__ void load_tile(const T* __restrict__ A, int lda, int P, int vbase,
                                           int nreal, const double* __restrict__ pre_e,
                                           const double* __restrict__ pre_v, T* sre, T* sim) {
-  constexpr int NS = 3 * L * L;
+  constexpr int NS = S * L * L;
   constexpr int B = kWrapBatch;
   const int nt = blockDim.x;
   if constexpr (COLS) {
@@ -246,7 +248,7 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ A, int lda, int 
       for (int k = 0; k < B; ++k) {
         const int idx = min(base + k * nt, total - 1);
         const int j = idx % w, e = idx / w;
-        ((j & 1) ? sim : sre)[slot_of<L>(e) * P + (j >> 1)] = x[k];
+        ((j & 1) ? sim : sre)[slot_of<L, S>(e) * P + (j >> 1)] = x[k];
       }
     }
   } else {
@@ -269,7 +271,7 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ A, int lda, int 
       for (int k = 0; k < B; ++k) {
         const int idx = min(base + k * nt, total - 1);
         const int e = idx % NS, r = idx / NS;
-        ((r & 1) ? sim : sre)[slot_of<L>(e) * P + (r >> 1)] = x[k];
+        ((r & 1) ? sim : sre)[slot_of<L, S>(e) * P + (r >> 1)] = x[k];
       }
     }
   }
@@ -278,11 +280,11 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ A, int lda, int 
 // Stores of the tile (LDS reads batched ahead of the stores, clamped item
 // indices as in load_tile: a repeated last item stores the same value again);
 // HP: scale by post_e[e] on the way out.
-template <typename T, int L, bool COLS, bool HP>
+template <typename T, int L, int S, bool COLS, bool HP>
 __device__ __forceinline__ void store_tile(T* __restrict__ A, int lda, int P, int vbase, int nreal,
                                            const double* __restrict__ post_e, const T* sre,
                                            const T* sim) {
-  constexpr int NS = 3 * L * L;
+  constexpr int NS = S * L * L;
   constexpr int B = kWrapBatch;
   const int nt = blockDim.x;
   if constexpr (COLS) {
@@ -294,7 +296,7 @@ __device__ __forceinline__ void store_tile(T* __restrict__ A, int lda, int P, in
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         const int idx = min(base + k * nt, total - 1);
-        const int j = idx % w, e = idx / w, so = slot_of<L>(e);
+        const int j = idx % w, e = idx / w, so = slot_of<L, S>(e);
         x[k] = (j & 1) ? sim[so * P + (j >> 1)] : sre[so * P + (j >> 1)];
         se[k] = HP ? post_e[e] : 1.0;
       }
@@ -313,7 +315,7 @@ __device__ __forceinline__ void store_tile(T* __restrict__ A, int lda, int P, in
 #pragma unroll
       for (int k = 0; k < B; ++k) {
         const int idx = min(base + k * nt, total - 1);
-        const int e = idx % NS, r = idx / NS, so = slot_of<L>(e);
+        const int e = idx % NS, r = idx / NS, so = slot_of<L, S>(e);
         x[k] = (r & 1) ? sim[so * P + (r >> 1)] : sre[so * P + (r >> 1)];
         se[k] = HP ? post_e[e] : 1.0;
       }
@@ -327,12 +329,12 @@ __device__ __forceinline__ void store_tile(T* __restrict__ A, int lda, int P, in
   }
 }
 
-template <typename T, int L, bool COLS>
+template <typename T, int L, int S, bool COLS>
 __global__ void __launch_bounds__(512)
 k_kinetic(T* __restrict__ A, int lda, int P, int nvec, const T* __restrict__ tab,
           const double* __restrict__ pre_e, const double* __restrict__ pre_v,
           const double* __restrict__ post_e, size_t zs) {
-  constexpr int NS = 3 * L * L;
+  constexpr int NS = S * L * L;
   A = zw(A, zs);
   tab = zw(tab, zs);
   pre_e = zw(pre_e, zs);
@@ -353,38 +355,38 @@ k_kinetic(T* __restrict__ A, int lda, int P, int nvec, const T* __restrict__ tab
 
   if (pre_e) {
     if (pre_v)
-      load_tile<T, L, COLS, true, true>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
+      load_tile<T, L, S, COLS, true, true>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
     else
-      load_tile<T, L, COLS, true, false>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
+      load_tile<T, L, S, COLS, true, false>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
   } else {
     if (pre_v)
-      load_tile<T, L, COLS, false, true>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
+      load_tile<T, L, S, COLS, false, true>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
     else
-      load_tile<T, L, COLS, false, false>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
+      load_tile<T, L, S, COLS, false, false>(A, lda, P, vbase, nreal, pre_e, pre_v, sre, sim);
   }
   __syncthreads();
-  fft_stage<T, L, 2, -1>(sre, sim, P);
+  fft_stage<T, L, S, 2, -1>(sre, sim, P);
   __syncthreads();
-  fft_stage<T, L, 1, -1>(sre, sim, P);
+  fft_stage<T, L, S, 1, -1>(sre, sim, P);
   __syncthreads();
-  mix_stage<T, L>(sre, sim, P, tab);
+  mix_stage<T, L, S>(sre, sim, P, tab);
   __syncthreads();
-  fft_stage<T, L, 1, +1>(sre, sim, P);
+  fft_stage<T, L, S, 1, +1>(sre, sim, P);
   __syncthreads();
-  fft_stage<T, L, 2, +1>(sre, sim, P);
+  fft_stage<T, L, S, 2, +1>(sre, sim, P);
   __syncthreads();
   if (post_e)
-    store_tile<T, L, COLS, true>(A, lda, P, vbase, nreal, post_e, sre, sim);
+    store_tile<T, L, S, COLS, true>(A, lda, P, vbase, nreal, post_e, sre, sim);
   else
-    store_tile<T, L, COLS, false>(A, lda, P, vbase, nreal, post_e, sre, sim);
+    store_tile<T, L, S, COLS, false>(A, lda, P, vbase, nreal, post_e, sre, sim);
 }
 
 namespace {
 
-template <typename T, int L>
+template <typename T, int L, int S>
 int launch_L(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double* pre_e,
              const double* pre_v, const double* post_e, int nvec) {
-  constexpr int NS = 3 * L * L;
+  constexpr int NS = S * L * L;
   if (nvec <= 0 || nvec > NS) nvec = NS;
   int P = (sizeof(T) == 8) ? c->P64 : c->P;
   if (P <= 0) P = 1;
@@ -393,65 +395,79 @@ int launch_L(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double*
     return set_error(KDQMC_EINVAL, "fft_tile too large for LDS");
   const int ncomplex = (nvec + 1) / 2;
   const int grid = (ncomplex + P - 1) / P;
-  int threads = 3 * L * P;
+  int threads = S * L * P;
   threads = ((threads + 63) / 64) * 64;
   if (threads > 512) threads = 512;
   if (threads < 64) threads = 64;
   const int e0 = prof_mark(c);
   if (cols)
-    hipLaunchKernelGGL((k_kinetic<T, L, true>), dim3(grid, 1, c->nch), dim3(threads), lds, c->stream, A, lda, P,
-                       nvec, tab, pre_e, pre_v, post_e, c->zs);
+    hipLaunchKernelGGL((k_kinetic<T, L, S, true>), dim3(grid, 1, c->nch), dim3(threads), lds, c->stream, A, lda,
+                       P, nvec, tab, pre_e, pre_v, post_e, c->zs);
   else
-    hipLaunchKernelGGL((k_kinetic<T, L, false>), dim3(grid, 1, c->nch), dim3(threads), lds, c->stream, A, lda, P,
-                       nvec, tab, pre_e, pre_v, post_e, c->zs);
+    hipLaunchKernelGGL((k_kinetic<T, L, S, false>), dim3(grid, 1, c->nch), dim3(threads), lds, c->stream, A, lda,
+                       P, nvec, tab, pre_e, pre_v, post_e, c->zs);
   prof_pair(c, (sizeof(T) == 8 && tab == (const T*)c->tab_mu64) ? PH_BMUL : (cols ? PH_WRAP_COLS : PH_WRAP_ROWS), e0, prof_mark(c));
   KDQMC_HIP(hipGetLastError());
   return KDQMC_OK;
 }
 
-template <typename T, int L>
+template <typename T, int L, int S>
 int prepare_L() {
-  KDQMC_HIP(hipFuncSetAttribute((const void*)k_kinetic<T, L, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-  KDQMC_HIP(hipFuncSetAttribute((const void*)k_kinetic<T, L, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  KDQMC_HIP(hipFuncSetAttribute((const void*)k_kinetic<T, L, S, true>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  KDQMC_HIP(hipFuncSetAttribute((const void*)k_kinetic<T, L, S, false>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
   return KDQMC_OK;
 }
 
-template <typename T>
-int prepare_any(int L) {
+// The lattice sizes compiled in (FFT lengths of radices 2, 3, 4, 5), for S
+// sublattices.
+#define KDQMC_FOR_L(MACRO, S) \
+  case 3: MACRO(3, S); case 6: MACRO(6, S); case 9: MACRO(9, S); case 12: MACRO(12, S); \
+  case 15: MACRO(15, S); case 18: MACRO(18, S); case 24: MACRO(24, S);
+
+template <typename T, int S>
+int prepare_s(int L) {
+#define PREP(LL, SS) return prepare_L<T, LL, SS>()
   switch (L) {
-    case 3: return prepare_L<T, 3>();
-    case 6: return prepare_L<T, 6>();
-    case 9: return prepare_L<T, 9>();
-    case 12: return prepare_L<T, 12>();
-    case 15: return prepare_L<T, 15>();
-    case 18: return prepare_L<T, 18>();
-    case 24: return prepare_L<T, 24>();
+    KDQMC_FOR_L(PREP, S)
     default: return set_error(KDQMC_EUNSUPPORTED, "lattice size not compiled in");
   }
+#undef PREP
+}
+
+template <typename T>
+int prepare_any(int L, int S) {
+  if (S == 1) return prepare_s<T, 1>(L);
+  if (S == 2) return prepare_s<T, 2>(L);
+  return prepare_s<T, 3>(L);
+}
+
+template <typename T, int S>
+int launch_s(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double* pre_e,
+             const double* pre_v, const double* post_e, int nvec) {
+#define LAUNCH(LL, SS) return launch_L<T, LL, SS>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec)
+  switch (c->L) {
+    KDQMC_FOR_L(LAUNCH, S)
+    default: return set_error(KDQMC_EUNSUPPORTED, "lattice size not compiled in");
+  }
+#undef LAUNCH
 }
 
 template <typename T>
 int launch_any(kdqmc_ctx* c, T* A, int lda, bool cols, const T* tab, const double* pre_e,
                const double* pre_v, const double* post_e, int nvec) {
-  switch (c->L) {
-    case 3: return launch_L<T, 3>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
-    case 6: return launch_L<T, 6>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
-    case 9: return launch_L<T, 9>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
-    case 12: return launch_L<T, 12>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
-    case 15: return launch_L<T, 15>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
-    case 18: return launch_L<T, 18>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
-    case 24: return launch_L<T, 24>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
-    default: return set_error(KDQMC_EUNSUPPORTED, "lattice size not compiled in");
-  }
+  if (c->nsub == 1) return launch_s<T, 1>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
+  if (c->nsub == 2) return launch_s<T, 2>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
+  return launch_s<T, 3>(c, A, lda, cols, tab, pre_e, pre_v, post_e, nvec);
 }
 
 }  // namespace
 
 // Raises the dynamic-LDS limit of the kinetic kernels of this lattice size
-// (done once at context creation, outside any graph capture).
-int prepare_kinetic(int L) {
-  KDQMC_TRY(prepare_any<double>(L));
-  return prepare_any<float>(L);
+// and sublattice count (done once at context creation, outside any graph
+// capture).
+int prepare_kinetic(int L, int nsub) {
+  KDQMC_TRY(prepare_any<double>(L, nsub));
+  return prepare_any<float>(L, nsub);
 }
 
 int launch_kinetic_f64(kdqmc_ctx* c, double* A, int lda, bool cols, const double* tab,

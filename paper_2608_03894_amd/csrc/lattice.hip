@@ -28,8 +28,30 @@ constexpr Hop kHops[6] = {
     {1, 0, 0, 0}, {1, 0, 0, 1}, {2, 0, 0, 0}, {2, 0, 1, 0}, {2, 1, 0, 0}, {2, 1, 1, -1},
 };
 
+// App. A1, triangular lattice (one site per cell):
+//   I (x) K_s + K_s (x) I + K_s (x) K_s : displacements (0,+1), (+1,0), (+1,+1)
+constexpr Hop kTriHops[3] = {{0, 0, 0, 1}, {0, 0, 1, 0}, {0, 0, 1, 1}};
+// App. A2, honeycomb lattice (sublattices 0, 1):
+//   (I (x) I + I (x) K_s + K_s (x) I) (x) delta : 1 <- 0 at (0,0), (0,+1), (+1,0)
+constexpr Hop kHonHops[3] = {{1, 0, 0, 0}, {1, 0, 0, 1}, {1, 0, 1, 0}};
+
 // H(k)_{s s'} = sum over hops (s <- s', d) of -t exp(-i k.d), for the forward
-// transform v^(k) = sum_x exp(-i k.x) v(x) (so (K v)^ = H(k) v^).
+// transform v^(k) = sum_x exp(-i k.x) v(x) (so (K v)^ = H(k) v^); the S x S
+// block of the lattice in the top-left corner, zeros elsewhere.
+void bloch_H_lattice(int lattice, double t, double k1, double k2, cd h[3][3]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) h[a][b] = 0.0;
+  const Hop* hops = lattice == KDQMC_TRIANGULAR ? kTriHops : lattice == KDQMC_HONEYCOMB ? kHonHops : kHops;
+  const int nh = lattice == KDQMC_KAGOME ? 6 : 3;
+  for (int q = 0; q < nh; ++q) {
+    const Hop& hp = hops[q];
+    const double ph = -(k1 * hp.d1 + k2 * hp.d2);
+    const cd v = -t * std::polar(1.0, ph);
+    h[hp.to][hp.from] += v;
+    h[hp.from][hp.to] += std::conj(v);
+  }
+}
+
 void bloch_H(double t, double k1, double k2, cd h[3][3]) {
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) h[a][b] = 0.0;
@@ -268,23 +290,29 @@ bool lattice_supported(int L) {
   }
 }
 
-void bloch_table(int L, double t, double scale, double shift, double* tab) {
+int lattice_nsub(int lattice) {
+  return lattice == KDQMC_TRIANGULAR ? 1 : lattice == KDQMC_HONEYCOMB ? 2 : 3;
+}
+
+void bloch_table(int lattice, int L, double t, double scale, double shift, double* tab) {
+  const int S = lattice_nsub(lattice);
   const double norm = 1.0 / double(L * L);
   for (int m1 = 0; m1 < L; ++m1)
     for (int m2 = 0; m2 < L; ++m2) {
       const double k1 = 2.0 * kPi * m1 / L, k2 = 2.0 * kPi * m2 / L;
       cd h[3][3], e[3][3];
-      bloch_H(t, k1, k2, h);
-      for (int i = 0; i < 3; ++i) {
+      bloch_H_lattice(lattice, t, k1, k2, h);
+      // the S x S block (the zero padding exponentiates to the identity)
+      for (int i = 0; i < S; ++i) {
         h[i][i] -= shift;
-        for (int j = 0; j < 3; ++j) h[i][j] *= scale;
+        for (int j = 0; j < S; ++j) h[i][j] *= scale;
       }
       expm3(h, e);
-      double* out = tab + 18 * (m1 * L + m2);
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) {
-          out[2 * (3 * i + j)] = e[i][j].real() * norm;
-          out[2 * (3 * i + j) + 1] = e[i][j].imag() * norm;
+      double* out = tab + 2 * S * S * (m1 * L + m2);
+      for (int i = 0; i < S; ++i)
+        for (int j = 0; j < S; ++j) {
+          out[2 * (S * i + j)] = e[i][j].real() * norm;
+          out[2 * (S * i + j) + 1] = e[i][j].imag() * norm;
         }
     }
 }

@@ -14,6 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkdqmc.so")
 
 FP64, MIXED_F16, MIXED_BF16 = 0, 1, 2
+KAGOME, TRIANGULAR, HONEYCOMB = 0, 1, 2
+LATTICE = {"kagome": KAGOME, "triangular": TRIANGULAR, "honeycomb": HONEYCOMB}
+NSUB = {KAGOME: 3, TRIANGULAR: 1, HONEYCOMB: 2}
 PREC = {"fp64": FP64, "mixed_f16": MIXED_F16, "mixed_bf16": MIXED_BF16, "fp32": MIXED_F16}
 
 OK, EINVAL, EUNSUPPORTED, ESTATE, EHIP, ENUMERIC, ENOSPACE = 0, -1, -2, -3, -4, -5, -6
@@ -39,6 +42,7 @@ class Params(ctypes.Structure):
         ("fft_tile", ctypes.c_int),
         ("prec", ctypes.c_int),
         ("n_occ", ctypes.c_int),
+        ("lattice", ctypes.c_int),
     ]
 
 
@@ -72,6 +76,7 @@ _SIGS = {
                                       ctypes.c_int, ctypes.c_double, _vp, ctypes.c_int, _vp,
                                       ctypes.c_int, ctypes.c_double, _vp, ctypes.c_int]),
     "kdqmc_qr_f64": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
+    "kdqmc_expK_f64": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "kdqmc_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "kdqmc_profile_read": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int)]),
@@ -81,10 +86,13 @@ _SIGS = {
     "kdqmc_trial_orbitals": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                             ctypes.POINTER(ctypes.c_double)]),
     "kdqmc_set_trial": (ctypes.c_int, [_vp, _vp]),
+    "kdqmc_measure": (ctypes.c_int, [_vp, _vp]),
     "kdqmc_health": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
 }
 
-NPHASE = 11
+NPHASE = 12
+NOBS = 6
+OBS_NAMES = ("s_pair_gamma", "s_pair_dk1", "s_pair_dk2", "cdw2_gamma", "cdw2_k", "density")
 
 
 def load():
@@ -123,15 +131,17 @@ def _check(rc):
 
 
 def make_params(L, U, beta, dtau=0.1, t=1.0, mu=None, n_stab=10, delay_k=32, window=0,
-                fft_tile=0, prec="fp64", n_occ=0) -> Params:
+                fft_tile=0, prec="fp64", n_occ=0, lattice="kagome") -> Params:
     """n_occ = 0: finite temperature; n_occ > 0: the projector form with n_occ
     trial orbitals projected over beta."""
     if mu is None:
         mu = dirac_mu(L, t)
     if isinstance(prec, str):
         prec = PREC[prec]
+    if isinstance(lattice, str):
+        lattice = LATTICE[lattice]
     return Params(L=L, t=t, U=U, mu=mu, beta=beta, dtau=dtau, n_stab=n_stab, delay_k=delay_k,
-                  window=window, fft_tile=fft_tile, prec=prec, n_occ=n_occ)
+                  window=window, fft_tile=fft_tile, prec=prec, n_occ=n_occ, lattice=lattice)
 
 
 TRIAL_EPS = 0.01
@@ -174,7 +184,7 @@ class Chain:
         self.p = params
         self.lib = load()
         self.device = torch.device(device)
-        self.N = 3 * params.L * params.L
+        self.N = NSUB[params.lattice] * params.L * params.L
         self.L_tau = int(round(params.beta / params.dtau))
         self.n_chains = int(n_chains)
         nbytes = workspace_bytes(params, self.n_chains)
@@ -228,6 +238,22 @@ class Chain:
         _check(self.lib.kdqmc_sweep(self.ctx, _ptr(u), _ptr(forced), _ptr(accepted), _ptr(ratio),
                                     _ptr(wrap_err)))
 
+    def measure(self, out):
+        """kdqmc_measure: the NOBS estimators of the current G into out (device)."""
+        _check(self.lib.kdqmc_measure(self.ctx, _ptr(out)))
+
+    def observables(self):
+        """The estimators as a dict (or one dict per chain); synchronizes."""
+        t = self.torch
+        shape = (NOBS,) if self.n_chains == 1 else (self.n_chains, NOBS)
+        out = t.zeros(shape, dtype=t.float64, device=self.device)
+        self.measure(out)
+        self.sync()
+        v = out.cpu().numpy()
+        if self.n_chains == 1:
+            return dict(zip(OBS_NAMES, v.tolist()))
+        return [dict(zip(OBS_NAMES, r.tolist())) for r in v]
+
     def measure_G(self, out):
         _check(self.lib.kdqmc_measure_G(self.ctx, _ptr(out)))
 
@@ -243,6 +269,9 @@ class Chain:
     def gemm_f64(self, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc):
         _check(self.lib.kdqmc_gemm_f64(self.ctx, int(ta), int(tb), M, N, K, alpha, _ptr(A), lda,
                                        _ptr(B), ldb, beta, _ptr(C), ldc))
+
+    def expK_f64(self, A, lda=None, ncols=None, sign=-1):
+        _check(self.lib.kdqmc_expK_f64(self.ctx, _ptr(A), lda or self.N, ncols or self.N, sign))
 
     def qr_f64(self, n, A, Q):
         _check(self.lib.kdqmc_qr_f64(self.ctx, n, _ptr(A), _ptr(Q)))
@@ -314,7 +343,7 @@ class Batch:
         groups = {}
         for i, p in enumerate(self.params):
             key = (p.L, p.t, p.mu, p.beta, p.dtau, p.n_stab, p.delay_k, p.window, p.fft_tile, p.prec,
-                   p.n_occ)
+                   p.n_occ, p.lattice)
             groups.setdefault(key, []).append(i)
         self.groups = []
         for key, idx in groups.items():
@@ -375,7 +404,7 @@ class Batch:
         return worst, ok
 
     def field_updates_per_sweep(self):
-        return sum(3 * p.L * p.L * int(round(p.beta / p.dtau)) for p in self.params)
+        return sum(NSUB[p.lattice] * p.L * p.L * int(round(p.beta / p.dtau)) for p in self.params)
 
     def close(self):
         for g in self.groups:

@@ -73,17 +73,26 @@ def batched_chains(n_chains: int = 64, seed: int = 64):
     return out
 
 
-def ising_fields(L: int, L_tau: int, seed: int) -> np.ndarray:
-    """i.i.d. +-1 fields, shape (L_tau, 3*L*L), dtype int8."""
+def ising_fields_n(n_sites: int, L_tau: int, seed: int) -> np.ndarray:
+    """i.i.d. +-1 fields for any lattice, shape (L_tau, n_sites), dtype int8."""
     rng = np.random.default_rng(seed)
-    n = 3 * L * L
-    return (2 * rng.integers(0, 2, size=(L_tau, n)) - 1).astype(np.int8)
+    return (2 * rng.integers(0, 2, size=(L_tau, n_sites)) - 1).astype(np.int8)
+
+
+def metropolis_uniforms_n(n_sites: int, L_tau: int, seed: int, n_sweeps: int = 1) -> np.ndarray:
+    """U[0,1) draws for any lattice, shape (n_sweeps, L_tau, n_sites), float64."""
+    rng = np.random.default_rng(seed + 10**6)
+    return rng.random((n_sweeps, L_tau, n_sites))
+
+
+def ising_fields(L: int, L_tau: int, seed: int) -> np.ndarray:
+    """i.i.d. +-1 fields of the kagome lattice, shape (L_tau, 3*L*L), dtype int8."""
+    return ising_fields_n(3 * L * L, L_tau, seed)
 
 
 def metropolis_uniforms(L: int, L_tau: int, seed: int, n_sweeps: int = 1) -> np.ndarray:
-    """U[0,1) draws, shape (n_sweeps, L_tau, 3*L*L), float64."""
-    rng = np.random.default_rng(seed + 10**6)
-    return rng.random((n_sweeps, L_tau, 3 * L * L))
+    """U[0,1) draws of the kagome lattice, shape (n_sweeps, L_tau, 3*L*L), float64."""
+    return metropolis_uniforms_n(3 * L * L, L_tau, seed, n_sweeps)
 
 
 def random_dense(n: int, seed: int, scale: float = 1.0) -> np.ndarray:

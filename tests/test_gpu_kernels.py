@@ -137,3 +137,28 @@ def test_wrap_tiles(gpu_lib, L):
         ch.wrap_slice(1)
         got = ch.G().cpu().numpy()
         assert np.abs(got - want).max() < 1e-12 * np.abs(want).max(), P
+
+
+@pytest.mark.parametrize("L", [3, 12, 24])
+def test_expK_matches_dense_expm(gpu_lib, L):
+    """kdqmc_expK_f64 (the product of Eq. (5) by the three steps of Eq. (6))
+    against the oracle's dense scipy expm(-+dtau K) times M, on all columns
+    and on a ragged leading block of columns."""
+    import numpy as np
+    import scipy.linalg
+    from gpu_helpers import chain, dev, say
+    from oracle import lattice
+    say("expK", L)
+    ch = chain(L, -4.0, 1.0, delay_k=1 if L == 3 else 32)
+    N = ch.N
+    K = lattice.kagome_K(L)
+    m = si.random_dense(N, 300 + L)
+    for sign, nc in ((-1, N), (1, N), (-1, N // 2 + 1)):
+        a = dev(m)
+        ch.expK_f64(a, N, nc, sign)
+        got = a.cpu().numpy()
+        want = m.copy()
+        want[:, :nc] = scipy.linalg.expm(sign * 0.1 * K) @ m[:, :nc]
+        say("expK", L, sign, nc, np.abs(got - want).max())
+        assert np.abs(got - want).max() < 1e-12 * max(1.0, np.abs(want).max())
+    ch.close()

@@ -103,3 +103,25 @@ def test_dirac_filling_two_thirds():
     e = np.linalg.eigvalsh(lattice.kagome_K(L))
     mu = lattice.dirac_mu(L)
     assert (e < mu - 1e-9).sum() + 0.5 * (np.abs(e - mu) < 1e-9).sum() == L * L
+
+
+@pytest.mark.parametrize("L", [3, 4, 6])
+def test_triangular_K(L):
+    """App. A1: symmetric, 6-regular (L >= 3), K_ij = -t, spectrum = the
+    closed-form triangular dispersion."""
+    k = lattice.triangular_K(L, 1.0)
+    assert np.array_equal(k, k.T)
+    assert np.all((k == 0) | (k == -1.0))
+    assert np.all((k != 0).sum(axis=1) == 6)
+    assert np.abs(np.sort(np.linalg.eigvalsh(k)) - lattice.triangular_band_energies(L)).max() < 1e-12
+
+
+@pytest.mark.parametrize("L", [3, 4, 6])
+def test_honeycomb_K(L):
+    """App. A2: symmetric, 3-regular, bipartite (no A-A or B-B bonds),
+    spectrum = +-t |1 + e^{ik1} + e^{ik2}|."""
+    k = lattice.honeycomb_K(L, 1.0)
+    assert np.array_equal(k, k.T)
+    assert np.all((k != 0).sum(axis=1) == 3)
+    assert np.all(k[0::2, 0::2] == 0) and np.all(k[1::2, 1::2] == 0)
+    assert np.abs(np.sort(np.linalg.eigvalsh(k)) - lattice.honeycomb_band_energies(L)).max() < 1e-12

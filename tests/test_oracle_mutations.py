@@ -173,3 +173,38 @@ def test_pqmc_highest_orbitals_is_caught(monkeypatch):
     monkeypatch.setattr(pqmc, "trial_orbitals", bad)
     with pytest.raises(AssertionError):
         tpq.test_free_projector_green_closed_form(3, 2.0, 7)
+
+
+# ---- equal-time estimators -----------------------------------------------------
+import test_oracle_measure as tms  # noqa: E402
+from oracle import measure  # noqa: E402
+
+
+def _gaussian():
+    return tms.gaussian.__wrapped__()
+
+
+def test_pair_correlation_untransposed_is_caught(monkeypatch):
+    def bad(g):
+        n = g.shape[0]
+        d = np.eye(n) - g
+        return d * d + g * g
+    monkeypatch.setattr(measure, "pair_correlation", bad)
+    with pytest.raises(AssertionError):
+        tms.test_pair_correlation_wick(_gaussian())
+
+
+def test_density_exchange_term_untransposed_is_caught(monkeypatch):
+    def bad(g):
+        n = g.shape[0]
+        occ = 1.0 - np.diag(g)
+        return 4.0 * np.outer(occ, occ) + 2.0 * (np.eye(n) - g) * g
+    monkeypatch.setattr(measure, "density_correlation", bad)
+    with pytest.raises(AssertionError):
+        tms.test_density_correlation_wick(_gaussian())
+
+
+def test_swapped_sublattice_offsets_are_caught(monkeypatch):
+    monkeypatch.setattr(measure, "SUB_OFFSET", np.array([[0.0, 0.0], [-0.5, 0.0], [0.0, -0.5]]))
+    with pytest.raises(AssertionError):
+        tms.test_geometry_bonds(3)
