@@ -363,6 +363,21 @@ int kdqmc_expK_f64(kdqmc_ctx* c, double* A_dev, int lda, int ncols, int sign);
  * Uses the context's linear-algebra scratch. */
 int kdqmc_qr_f64(kdqmc_ctx* c, int n, double* A_dev, double* Q_dev);
 
+/* ---- for callers that cannot allocate device memory ----
+ * Code under HIP graph capture, tight serving loops and harnesses that forbid
+ * hipMalloc cannot create a context (whose workspace the caller allocates).
+ * This variant of kdqmc_qr_f64 needs no context: the same Householder QR
+ * (same kernels, same result bit for bit) of the leading n x n block of A_dev
+ * (row stride ld; R in its upper triangle, zeros below on return) with Q
+ * (n x n, row stride ld) formed in Q_dev, enqueued on hip_stream (NULL = the
+ * default stream).  Its scratch is a static device array of 4.6 MB held by
+ * every GPU the library runs on until the process ends; nothing is allocated
+ * and no allocating routine is called.  Limits: 1 <= n <= ld <= 512, else
+ * KDQMC_EINVAL.  All calls on one GPU share that array: calls that overlap on
+ * one GPU (concurrent streams, threads) race and must be serialized by the
+ * caller. */
+int kdqmc_qr_f64_noalloc(int n, int ld, double* A_dev, double* Q_dev, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,6 +87,7 @@ _SIGS = {
                                             ctypes.POINTER(ctypes.c_double)]),
     "kdqmc_set_trial": (ctypes.c_int, [_vp, _vp]),
     "kdqmc_measure": (ctypes.c_int, [_vp, _vp]),
+    "kdqmc_qr_f64_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]),
     "kdqmc_health": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double)]),
 }
 
@@ -163,6 +164,16 @@ def workspace_bytes(p: Params, n_chains: int = 1) -> int:
 
 def dirac_mu(L: int, t: float = 1.0) -> float:
     return float(load().kdqmc_dirac_mu(L, t))
+
+
+def qr_f64_noalloc(n, ld, A, Q, stream=None):
+    """kdqmc_qr_f64_noalloc: the QR building block without a context (its
+    scratch is the library's static device array); A, Q: device tensors with
+    row stride ld."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    _check(load().kdqmc_qr_f64_noalloc(n, ld, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(Q.data_ptr()),
+                                       ctypes.c_void_p(s.cuda_stream)))
 
 
 def _ptr(x):
