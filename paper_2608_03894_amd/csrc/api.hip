@@ -15,7 +15,7 @@ namespace {
 thread_local std::string g_last_error;
 
 struct Derived {
-  int N = 0, S = 3, Ltau = 0, nc = 0, w = 0, nw = 0, F = 0, kmax = 0, P = 0, P64 = 0;
+  int N = 0, S = 3, Ltau = 0, nc = 0, w = 0, wm = 0, nw = 0, F = 0, kmax = 0, P = 0, P64 = 0;
   bool fp64 = true, proj = false;
 };
 
@@ -62,6 +62,7 @@ int derive(const kdqmc_params* p, Derived* d, int nch = 1) {
   d->Ltau = Ltau;
   d->nc = Ltau / p->n_stab;
   d->w = std::min(w, d->N);
+  d->wm = window_pad(d->w);
   d->nw = (d->N + d->w - 1) / d->w;
   d->F = std::max(1, p->delay_k / d->w);
   d->kmax = d->F * d->w;
@@ -101,10 +102,10 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   char* Wp = take((size_t)d.kmax * N * es);
   char* win_a = take((size_t)d.nw * 4);
   char* win_p = take((size_t)d.nw * d.w * 4);
-  char* Zg = take(2 * (size_t)d.w * d.w * 8);
-  char* Zpg = take(2 * (size_t)d.w * d.w * 8);
-  char* snapc = take(2 * N * d.w * 8);
-  char* snapr = take(2 * N * d.w * 8);
+  char* Zg = take(2 * (size_t)d.wm * d.wm * 8);
+  char* Zpg = take(2 * (size_t)d.wm * d.wm * 8);
+  char* snapc = take(2 * N * d.wm * 8);
+  char* snapr = take(2 * N * d.wm * 8);
   char* snapb = take(2 * (size_t)d.w * d.w * 8);
   char* Gs = take((size_t)d.w * d.w * 8);
   char* flag = take(64);
@@ -310,6 +311,7 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
   c->Ltau = d.Ltau;
   c->nc = d.nc;
   c->w = d.w;
+  c->wm = d.wm;
   c->nw = d.nw;
   c->F = d.F;
   // the fused window launch for one chain; batched chains (whose shape groups
@@ -367,6 +369,15 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
       break;
   }
   if (rc == KDQMC_OK) rc = clear_health(c);
+  if (rc == KDQMC_OK) {
+    // the window snapshots are read whole (padding included) and multiplied
+    // by exact zeros there, so they must never hold non-finite bit patterns
+    const size_t sb = 2 * (size_t)d.N * d.wm * 8;
+    if (hipMemset2DAsync(c->snapc, c->zs, 0, sb, n_chains, c->stream) != hipSuccess ||
+        hipMemset2DAsync(c->snapr, c->zs, 0, sb, n_chains, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      rc = set_error(KDQMC_EHIP, "clearing the window snapshots failed");
+  }
   if (rc != KDQMC_OK) {
     delete c;
     return rc;

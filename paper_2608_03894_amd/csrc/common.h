@@ -60,6 +60,10 @@ constexpr double taylor_cos(double x) {
 // returns {cos, sin} of 2 pi e / n as a pair via two functions
 constexpr long mod_pos(long a, long n) { return ((a % n) + n) % n; }
 
+// The padded window size of the decision kernels (16, 32 or 64): Z, Z' and the
+// window snapshots are stored with this stride, zero past the window.
+constexpr int window_pad(int w) { return w <= 16 ? 16 : (w <= 32 ? 32 : 64); }
+
 constexpr double cos2pi(long e, long n) {
   const long ee = mod_pos(e, n);
   const long q = (4 * ee + n / 2) / n;  // nearest quarter turn
@@ -214,6 +218,7 @@ struct kdqmc_ctx {
   int N = 0, L = 0, Ltau = 0, nc = 0;     // sites, cells/side, slices, stack checkpoints
   int lattice = 0, nsub = 3;              // kdqmc_lattice, sublattices per cell
   int w = 0, nw = 0, F = 0;               // window size, windows per slice, windows per flush
+  int wm = 0;                             // window_pad(w): the padded size of Z, Z' and the snapshots
   int P = 0;                              // complex vectors per wrap workgroup (storage type)
   int P64 = 0;                            // same for the FP64 stack products
   int kmax = 0;                           // columns of the pending factors (F * w)
@@ -254,10 +259,10 @@ struct kdqmc_ctx {
   int* win_a = nullptr;        // nw: accepted count per window
   int* win_p = nullptr;        // nw*w: window-local positions of the accepts
   double* win_c = nullptr;     // nw*w: Delta/R of the accepts
-  double* Xw = nullptr;        // 2*w*w: Z of a window (two buffers by window parity)
-  double* Yw = nullptr;        // 2*w*w: Z' of a window
-  double* snapc = nullptr;     // 2*N*w: G[:, S] of a window (fused schedule, by parity)
-  double* snapr = nullptr;     // 2*w*N: G[S, :] of a window
+  double* Xw = nullptr;        // 2*wm*wm: Z of a window by position, n-major (two buffers by parity)
+  double* Yw = nullptr;        // 2*wm*wm: Z' of a window by position, n-major
+  double* snapc = nullptr;     // 2*N*wm: G[:, S] of a window, row stride wm (fused schedule, by parity)
+  double* snapr = nullptr;     // 2*N*wm: G[S, :] of a window stored transposed, G[s][c] at c*wm + s
   double* snapb = nullptr;     // 2*w*w: G[S, S] of the window after next
   bool fused = false;          // FP64, one window per flush, windows inside 64 x 64 tiles
   double* Gs = nullptr;        // w*w: G~cur[S,S] of the next window

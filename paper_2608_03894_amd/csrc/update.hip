@@ -121,7 +121,7 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
   __shared__ double rowp[2][WM], colp[2][WM], cfp[2][WM], crp[2][WM], diagB[2][WM];
   __shared__ double ul[WM], rl[WM];
   __shared__ double Zs[WM][WM + 1], Zps[WM][WM + 1];
-  __shared__ int pl[WM];
+  __shared__ int pl[WM], posq[WM];
   __shared__ int8_t sl[WM];
   __shared__ uint8_t fl[WM], al[WM];
   const int tid = threadIdx.x;
@@ -271,10 +271,20 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
     if (ratio_out) ratio_out[w0 + p] = rl[p];
     if (acc_out) acc_out[w0 + p] = al[p];
   }
-  for (int idx = tid; idx < na * na; idx += NT) {
-    const int q = idx / na, n = idx % na;
-    if (q <= n) Zg[q * W + n] = Zs[q][n];
-    if (n <= q) Zpg[q * W + n] = Zps[q][n];
+  // Z and Z' by window position, n-major with stride WM and the frame scales
+  // folded in (as written by decide_window):
+  //   Zh[n][p] = evinv[w0+p] Z[q_p][n],  Zph[n][p] = ev[w0+p] Z'[n][q_p]
+  for (int p = tid; p < WM; p += NT) posq[p] = -1;
+  __syncthreads();
+  for (int n = tid; n < na; n += NT) posq[pl[n]] = n;
+  __syncthreads();
+  for (int idx = tid; idx < WM * WM; idx += NT) {
+    const int n = idx / WM, p = idx % WM;
+    const int q = posq[p];
+    const bool live = q >= 0 && q <= n && n < na;
+    const int pc = w0 + min(p, wn - 1);
+    Zg[idx] = live ? Zs[q][n] * evinv[pc] : 0.0;
+    Zpg[idx] = live ? Zps[n][q] * ev[pc] : 0.0;
   }
 }
 
@@ -308,7 +318,8 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
                                               int8_t* __restrict__ s_l, uint8_t* __restrict__ acc_out,
                                               double* __restrict__ ratio_out, int* __restrict__ win_a,
                                               int* __restrict__ win_p, double* __restrict__ Zg,
-                                              double* __restrict__ Zpg) {
+                                              double* __restrict__ Zpg, const double* __restrict__ ev,
+                                              const double* __restrict__ evinv) {
   static_assert(WM <= 32, "one wave holds the sites in lanes 0..31 and Z in lanes 32..63");
   static_assert(WM % 8 == 0, "history rows are read in blocks of 8");
   const bool site = lane < WM;
@@ -329,6 +340,11 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
   bool my_acc = false;
   int my_pos = 0;
   int na = 0, p0 = 0;
+  // per-lane constants of the loop: the loop body is branch-free apart from
+  // its exit and the uniform skips of history blocks (divergent updates are
+  // selects, the window entries of the coefficient lanes are weighted by 0)
+  const double sitef = site ? 1.0 : 0.0;
+  const int lx = lane & (WM - 1);
   while (p0 < wn) {
     const double Rx = 1.0 + delta_x * (1.0 - diag);
     double cx = delta_x * rcp_nr(Rx);  // c of every candidate, off the ballot's path
@@ -337,44 +353,49 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
     const unsigned long long hits = __ballot(xin && lane >= p0 && ax);
     asm volatile("" : "+v"(cx));  // (the division is issued before the branch below)
     const int p = hits ? __builtin_ctzll(hits) : wn;
-    if (lane >= p0 && lane <= p) {
-      my_ratio = ratio_x;
-      my_acc = lane == p;
-    }
+    const bool upd = lane >= p0 && lane <= p;
+    my_ratio = upd ? ratio_x : my_ratio;
+    my_acc = upd ? (lane == p) : my_acc;
     if (p >= wn) break;
     p0 = p + 1;
     const double c = lane_value(cx, p);
     const int n = na;
-    if (lane == n) my_pos = p;
-    double A, B;
-    if (site) {
-      A = g0s[lane][p];
-      B = g0s[p][lane];
-    } else {  // coefficient lanes; lanes WM..31 (16-site windows) compute unused values
-      A = (q == n) ? 1.0 : 0.0;
-      B = 0.0;
-    }
-    // blocks of 8 history rows read at once (rows n.. of the last block are zero)
-    for (int r0 = 0; r0 < n; r0 += 8) {
-      double2 own[8], rem[8];
+    my_pos = (lane == n) ? p : my_pos;
+    // window entries G0[x][p], G0[p][x] (the coefficient lanes, and lanes
+    // WM..31 of 16-site windows, read a row they weight by zero)
+    // (added after the history sums, so that their reads overlap these)
+    const double gA = g0s[lx][p], gB = g0s[p][lx];
+    double A0 = 0.0, B0 = 0.0, A1 = 0.0, B1 = 0.0;
+    // blocks of 8 history rows read at once (rows n.. of the last block are
+    // zero); even and odd rows summed apart to halve the dependent chains
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        own[j] = hist[r0 + j][lane];
-        rem[j] = hist[r0 + j][p];  // (u_r[p], w_r[p]), the same for every lane
-      }
+    for (int r0 = 0; r0 < WM; r0 += 8) {
+      if (r0 < n) {
+        double2 own[8], rem[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        A = fma(own[j].x, rem[j].y, A);
-        B = fma(rem[j].x, own[j].y, B);
+        for (int j = 0; j < 8; ++j) {
+          own[j] = hist[r0 + j][lane];
+          rem[j] = hist[r0 + j][p];  // (u_r[p], w_r[p]), the same for every lane
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          A0 = fma(own[j].x, rem[j].y, A0);
+          B0 = fma(rem[j].x, own[j].y, B0);
+          A1 = fma(own[j + 1].x, rem[j + 1].y, A1);
+          B1 = fma(rem[j + 1].x, own[j + 1].y, B1);
+        }
       }
     }
+    const double A = fma(gA, sitef, (!site && q == n) ? 1.0 : 0.0) + (A0 + A1);
+    const double B = fma(gB, sitef, B0 + B1);
     const double Xn = -c * A;
     const double Yn = ((site ? lane == p : q == n) ? 1.0 : 0.0) - B;
     hist[n][lane] = make_double2(Xn, Yn);
-    if (site) diag = fma(Xn, Yn, diag);
+    diag = fma(Xn * sitef, Yn, diag);
     ++na;
   }
   wave_sync();
+  const unsigned long long accm = __ballot(xin && my_acc);
   if (lane == 0) win_a[win] = na;
   if (lane < na) win_p[win * W + lane] = my_pos;
   if (xin) {
@@ -382,11 +403,29 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
     if (ratio_out) ratio_out[w0 + lane] = my_ratio;
     if (acc_out) acc_out[w0 + lane] = my_acc ? 1 : 0;
   }
-  if (zlane && q < na) {
-    for (int n = q; n < na; ++n) {
-      const double2 h = hist[n][lane];
-      Zg[q * W + n] = h.x;   // Z[q][n], q <= n
-      Zpg[n * W + q] = h.y;  // Z'[n][q], q <= n
+  // Z and Z' by window position, n-major with stride WM and the frame scales
+  // folded in, so that the factors in the store frame of G are
+  // U = G[:, S] Zh^T and W = Zph (E_S - G[S, :]):
+  //   Zh[n][p] = evinv[w0+p] Z[q_p][n],  Zph[n][p] = ev[w0+p] Z'[n][q_p]
+  // with q_p the accept at position p (q_p <= n < na), zero elsewhere
+  // (also past the window up to WM).  Lanes 0..31 write Zh, lanes 32..63
+  // Zph, the lane's position p = lane % 32.
+  {
+    const int p = lane & 31;
+    if (p < WM) {
+      const bool acc_p = (accm >> p) & 1ull;
+      const int qp = __popcll(accm & ((1ull << p) - 1ull));
+      const int pc = w0 + min(p, wn - 1);
+      const double f = zlane ? ev[pc] : evinv[pc];
+      double* __restrict__ dst = zlane ? Zpg : Zg;
+      for (int n = 0; n < WM; ++n) {
+        double v = 0.0;
+        if (acc_p && n >= qp && n < na) {
+          const double2 h = hist[n][32 + qp];
+          v = (zlane ? h.y : h.x) * f;
+        }
+        dst[n * WM + p] = v;
+      }
     }
   }
 }
@@ -474,7 +513,7 @@ decide_wave_body(const T* __restrict__ G, int N, const double* __restrict__ ev,
   }
   wave_sync();
   decide_window<WM>(lane, wn, w0, W, win, g0s, hist, sx, ux, fx, forced != nullptr, em2a, ep2a, s_l,
-                    acc_out, ratio_out, win_a, win_p, Zg, Zpg);
+                    acc_out, ratio_out, win_a, win_p, Zg, Zpg, ev, evinv);
 }
 
 template <typename T, int WM>
@@ -527,9 +566,10 @@ k_window_start(const double* __restrict__ G, int N, const double* __restrict__ e
   csn = zw(csn, zs);
   rsn = zw(rsn, zs);
   bk1 = zw(bk1, zs);
-  // column snapshot csn[r][y] = G[r][y], row snapshot rsn[x][c] = G[x][c]
-  // (x, y < wn), and window 1's diagonal block bk1[x][y] = G[W + x][W + y]
-  // (x, y < wn1): 8 elements per thread, loads before stores
+  // column snapshot csn[r][y] = G[r][y] (row stride WM), row snapshot stored
+  // transposed, rsn[c][x] = G[x][c] (stride WM), for x, y < wn, and window
+  // 1's diagonal block bk1[x][y] = G[W + x][W + y] (x, y < wn1): 8 elements
+  // per thread, loads before stores
   constexpr int B = 8;
   const int wn1 = max(min(W, N - W), 0);
   const int nc = N * wn, total = 2 * nc + wn1 * wn1;
@@ -551,13 +591,54 @@ k_window_start(const double* __restrict__ G, int N, const double* __restrict__ e
   for (int k = 0; k < B; ++k) {
     const int e = base + 64 * k;
     if (e < nc)
-      csn[(size_t)(e / wn) * W + e % wn] = v[k];
+      csn[(size_t)(e / wn) * WM + e % wn] = v[k];
     else if (e < 2 * nc)
-      rsn[(size_t)((e - nc) / N) * N + (e - nc) % N] = v[k];
+      rsn[(size_t)((e - nc) % N) * WM + (e - nc) / N] = v[k];
     else if (e < total)
       bk1[(size_t)((e - 2 * nc) / wn1) * W + (e - 2 * nc) % wn1] = v[k];
   }
 }
+
+// PS consecutive doubles from a 16-byte aligned address, two per load.
+template <int PS>
+__device__ __forceinline__ void load_run(double (&v)[PS], const double* __restrict__ src) {
+  static_assert(PS % 2 == 0, "runs of pairs");
+  const double2* s2 = reinterpret_cast<const double2*>(src);
+#pragma unroll
+  for (int i = 0; i < PS / 2; ++i) {
+    const double2 t = s2[i];
+    v[2 * i] = t.x;
+    v[2 * i + 1] = t.y;
+  }
+}
+
+// The window's factor products on the FP64 MFMA (16x16x4; lane l holds
+// A[l%16][l/16] and B[l/16][l%16], and element j of the result is
+// D[l/16 + 4j][l%16]).  In the store frame of G the window's factors are
+//   U[r][n] = sum_p G~cur[r, w0+p] Zh[n][p],
+//   W[n][c] = sum_p Zph[n][p] (delta(c, w0+p) - G~cur[w0+p, c])
+// (Zh, Zph n-major with the frame scales folded in, zero past the accepts).
+// U is formed transposed: block (nb, rows) of U^T holds in its element j
+// exactly the A operand of k-step 16 nb + 4 j of the flush G += U W, and
+// block (nb, cols) of W the B operand of the same step, so neither goes
+// through LDS.  p-step s takes position p = PS (l/16) + s, so that every
+// lane reads PS consecutive positions (two per load); steps s >= wn are
+// skipped (all their positions lie past the window).
+template <int WM>
+struct WinOps {
+  static constexpr int PS = WM / 4;   // p-steps
+  static constexpr int NB = WM / 16;  // n blocks
+  double za[NB][PS], zpa[NB][PS];     // A operands: Zh, Zph
+
+  __device__ __forceinline__ void load_z(const double* __restrict__ Zh, const double* __restrict__ Zph,
+                                         int lr, int lk) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      load_run<PS>(za[nb], Zh + (16 * nb + lr) * WM + PS * lk);
+      load_run<PS>(zpa[nb], Zph + (16 * nb + lr) * WM + PS * lk);
+    }
+  }
+};
 
 template <int WM>
 __global__ void __launch_bounds__(256)
@@ -570,6 +651,8 @@ k_flush_decide(double* __restrict__ G, int N, int gxt, const double* __restrict_
                double* __restrict__ Zn, double* __restrict__ Zpn, const double* __restrict__ csc,
                const double* __restrict__ rsc, double* __restrict__ csn, double* __restrict__ rsn,
                const double* __restrict__ bkc, double* __restrict__ bkn, size_t zs, size_t zn) {
+  typedef WinOps<WM> Ops;
+  constexpr int PS = Ops::PS, NB = Ops::NB;
   // Roles: with a next window, workgroup z < nch (the first dispatched)
   // decides chain z's next window; the others take the gxt x gxt tiles.
   const int w1 = (win + 1) * W, w2 = (win + 2) * W;
@@ -608,193 +691,96 @@ k_flush_decide(double* __restrict__ G, int N, int gxt, const double* __restrict_
   bkc = zw_at(bkc, zs, z);
   bkn = zw_at(bkn, zs, z);
   sc = zw_at(sc, zs, z);
-  // LDS: Zs, Zps (WM x (WM+1) each); R2 = gl [64][WM+1], later Ul [WM][64];
-  // R3 = hl [WM][65], later Wl [WM][64].  The decisions reuse Zs (window
-  // block) and R2..R3 (history).
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* lds = reinterpret_cast<double*>(smem_raw);
-  double(*Zs)[WM + 1] = reinterpret_cast<double(*)[WM + 1]>(lds);
-  double(*Zps)[WM + 1] = reinterpret_cast<double(*)[WM + 1]>(lds + WM * (WM + 1));
-  double* R2 = lds + 2 * WM * (WM + 1);
-  double* R3 = R2 + 64 * (WM + 1);
-  __shared__ int il[WM];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
   const int w0 = win * W;
+  const int wn = min(W, N - w0);
   const int a = win_a[win];
+  const int nbl = (a + 15) >> 4;  // n blocks holding factors
   const int wn1 = has_next ? min(W, N - w1) : 0;
   const int wn2 = win + 2 < nw ? min(W, N - w2) : 0;
-  const int R0 = by * 64, C0 = bx * 64;
-  const int row0 = R0 + (wave >> 1) * 32, col0 = C0 + (wave & 1) * 32;
-  const int lr = lane & 15, lk = lane >> 4;
+  Ops ops;
   if (decider) {
-    // The decider: the next window's block only.  Every input is requested
-    // at once (Z, Z' whole, the block's rows of window k's columns and window
-    // k's rows at the block's columns, the scales, the block before this
-    // window's flush); the accepts are picked in LDS.  Per element the
-    // arithmetic is the tile's (same sums in the same order, same 16 x 16
-    // MFMA blocks), so the block equals the one written to G bit for bit.
-    const int Q0 = w1 & ~31;  // the 32 x 32 quadrant holding the block
-    constexpr int PZ = (WM * WM + 255) / 256;
-    double zv[PZ], zpv[PZ];
+    // The decider: the next window's block only, on four waves (wave (bi,
+    // bj) the 16 x 16 block (bi, bj) of the 32 x 32 quadrant holding it) in
+    // the arithmetic of the tiles (the same operands, the same MFMA steps in
+    // the same order), so the block equals the one written to G bit for bit;
+    // then wave 0 runs the window's decisions on it.
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double(*Zs)[WM + 1] = reinterpret_cast<double(*)[WM + 1]>(smem_raw);
+    double2(*hist)[64] = reinterpret_cast<double2(*)[64]>(smem_raw + sizeof(double) * WM * (WM + 1));
+    const int Q0 = w1 & ~31;
+    const int bi = wave >> 1, bj = wave & 1;
+    const int rq = Q0 + 16 * bi, cq = Q0 + 16 * bj;
+    // (entries outside the window block are computed but never used); the
+    // frame scales of the block's rows and column are read up front
+    v4d blk;
+    double evr[4];
+    const double evic = evinv[min(cq + lr, N - 1)];
 #pragma unroll
-    for (int j = 0; j < PZ; ++j) {
-      const int idx = tid + 256 * j;
-      const int q = min(idx / WM, W - 1), n = min(idx % WM, W - 1);
-      zv[j] = Zc[q * W + n];
-      zpv[j] = Zpc[q * W + n];
+    for (int j = 0; j < 4; ++j) {
+      const int r = rq + lk + 4 * j, cc = cq + lr;
+      blk[j] = bkc[(size_t)min(max(r - w1, 0), W - 1) * W + min(max(cc - w1, 0), W - 1)];
+      evr[j] = ev[min(r, N - 1)];
     }
-    // quadrant rows x (32) by window-k column y (WM): g source; window-k row y
-    // by quadrant column x: h source (4 + 4 per thread at WM = 32)
-    constexpr int PG = 32 * WM / 256;
-    double gsv[PG], hsv[PG];
-#pragma unroll
-    for (int j = 0; j < PG; ++j) {
-      const int idx = tid + 256 * j;
-      const int x = idx / WM, y = min(idx % WM, W - 1);
-      gsv[j] = csc[(size_t)min(Q0 + x, N - 1) * W + y];
-      hsv[j] = rsc[(size_t)y * N + min(Q0 + x, N - 1)];
-    }
-    const int pv = win_p[win * W + min(tid, W - 1)];
-    const int qs = min(Q0 + (tid & 31), N - 1);  // quadrant site
-    const double evq = ev[qs], evinvq = evinv[qs];
-    const int ks = min(w0 + (tid & (WM - 1)), N - 1);  // window-k site
-    const double evk = ev[ks], evinvk = evinv[ks];
-    v4d bacc[2][2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = Q0 + 16 * bi + lk + 4 * j, cc = Q0 + 16 * bj + lr;
-          const bool in = r >= w1 && r < w1 + wn1 && cc >= w1 && cc < w1 + wn1;
-          const double v = bkc[(size_t)min(max(r - w1, 0), W - 1) * W + min(max(cc - w1, 0), W - 1)];
-          bacc[bi][bj][j] = in ? v : 0.0;
-        }
     int sx;
     double ux;
     bool fx;
     site_inputs(lane, min(w1, N - 1), max(wn1, 1), s_l, u, forced, ev, sx, ux, fx);
-    __shared__ double evs[32], evinvs[32], evks[WM], evinvks[WM];
-    double(*gs)[WM + 1] = reinterpret_cast<double(*)[WM + 1]>(R2);  // [32][WM+1]
-    double(*hs)[33] = reinterpret_cast<double(*)[33]>(R3);          // [WM][33]
     if (a > 0) {
+      // operands: Zh, Zph rows, the snapshot row rq + l%16 (g) and the
+      // transposed row snapshot at column cq + l%16 (h), PS positions each
+      double gb[PS], hb[PS];
+      ops.load_z(Zc, Zpc, lr, lk);
+      load_run<PS>(gb, csc + (size_t)min(rq + lr, N - 1) * WM + PS * lk);
+      const int ch = min(cq + lr, N - 1);
+      load_run<PS>(hb, rsc + (size_t)ch * WM + PS * lk);
 #pragma unroll
-      for (int j = 0; j < PZ; ++j) {
-        const int idx = tid + 256 * j;
-        if (idx < WM * WM) {
-          const int q = idx / WM, n = idx % WM;
-          const bool in = q < a && n < a;
-          Zs[q][n] = (in && q <= n) ? zv[j] : 0.0;
-          Zps[q][n] = (in && n <= q) ? zpv[j] : 0.0;
-        }
-      }
+      for (int s = 0; s < PS; ++s) hb[s] = ((ch == w0 + PS * lk + s) ? 1.0 : 0.0) - hb[s];
+      v4d ut[NB], wt[NB];
 #pragma unroll
-      for (int j = 0; j < PG; ++j) {
-        const int idx = tid + 256 * j;
-        gs[idx / WM][idx % WM] = gsv[j];
-        hs[idx % WM][idx / WM] = hsv[j];
-      }
-      if (tid < WM) il[tid] = tid < a ? pv : 0;  // window-local accept positions
-      if (tid < 32) {
-        evs[tid] = evq;
-        evinvs[tid] = evinvq;
-      }
-      if (tid < WM) {
-        evks[tid] = evk;
-        evinvks[tid] = evinvk;
-      }
-      __syncthreads();
-      // thread (lane < 32, wave): quadrant row / column lane, factors n = wave + 4 k2
-      constexpr int PERU = WM / 4;
-      double uvals[PERU], wvals[PERU];
-      const int x = lane & 31;
-      const int r = Q0 + x;
-      {
-        double gr[WM];
+      for (int nb = 0; nb < NB; ++nb) ut[nb] = wt[nb] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < WM; ++q) {
-          const int pq = il[q];
-          gr[q] = (r < N && q < a) ? gs[x][pq] * evs[x] * evinvks[pq] : 0.0;
+      for (int s = 0; s < PS; ++s)
+        if (s < wn) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            if (nb < nbl) {
+              ut[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.za[nb][s], gb[s], ut[nb], 0, 0, 0);
+              wt[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.zpa[nb][s], hb[s], wt[nb], 0, 0, 0);
+            }
         }
 #pragma unroll
-        for (int k2 = 0; k2 < PERU; ++k2) {
-          const int n = wave + 4 * k2;
-          double uv = 0.0;
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-          for (int q = 0; q < WM; ++q) uv += gr[q] * Zs[q][n];
-          uvals[k2] = r < N ? uv * evinvs[x] : 0.0;
-        }
-      }
-      {
-        double hr[WM];
-#pragma unroll
-        for (int q = 0; q < WM; ++q) {
-          const int pq = il[q];
-          hr[q] = (r < N && q < a) ? ((r == w0 + pq) ? 1.0 : 0.0) - hs[pq][x] * evks[pq] * evinvs[x] : 0.0;
-        }
-#pragma unroll
-        for (int k2 = 0; k2 < PERU; ++k2) {
-          const int n = wave + 4 * k2;
-          double wv = 0.0;
-#pragma unroll
-          for (int q = 0; q < WM; ++q) wv += Zps[n][q] * hr[q];
-          wvals[k2] = r < N ? wv * evs[x] : 0.0;
-        }
-      }
-      __syncthreads();
-      double(*Ul)[32] = reinterpret_cast<double(*)[32]>(R2);
-      double(*Wl)[32] = reinterpret_cast<double(*)[32]>(R3);
-      if (lane < 32) {
-#pragma unroll
-        for (int k2 = 0; k2 < PERU; ++k2) {
-          const int n = wave + 4 * k2;
-          if (n < a) {
-            Ul[n][x] = uvals[k2];
-            Wl[n][x] = wvals[k2];
-          }
-        }
-      }
-      __syncthreads();
-      if (wave == 0) {
-        for (int k0 = 0; k0 < a; k0 += 4) {
-          const int k = k0 + lk;
-          double av[2], bv[2];
-#pragma unroll
-          for (int bi = 0; bi < 2; ++bi) {
-            av[bi] = k < a ? Ul[k < a ? k : 0][16 * bi + lr] : 0.0;
-            bv[bi] = k < a ? Wl[k < a ? k : 0][16 * bi + lr] : 0.0;
-          }
-#pragma unroll
-          for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-              bacc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], bacc[bi][bj], 0, 0, 0);
-        }
-      }
-      __syncthreads();  // the factor buffers are free again
+        for (int j = 0; j < 4; ++j)
+          if (16 * nb + 4 * j < a)
+            blk = __builtin_amdgcn_mfma_f64_16x16x4f64(ut[nb][j], wt[nb][j], blk, 0, 0, 0);
     }
+    // the window block (tilde frame) into LDS, zero outside wn1 x wn1
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = rq + lk + 4 * j, cc = cq + lr;
+      const double v = blk[j] * evr[j] * evic;
+      if (r >= w1 && r < w1 + wn1 && cc >= w1 && cc < w1 + wn1) Zs[r - w1][cc - w1] = v;
+    }
+    // (the decisions read rows and columns below WM only: nothing to clear
+    // for a full window)
+    if (wave == 0 && wn1 < WM)
+      for (int idx = lane; idx < WM * WM; idx += 64) {
+        const int x = idx / WM, y = idx % WM;
+        if (x >= wn1 || y >= wn1) Zs[x][y] = 0.0;
+      }
+    __syncthreads();
     if (wave != 0) return;
-    // the window block (tilde frame), zero outside wn1 x wn1
-    for (int idx = lane; idx < WM * (WM + 1); idx += 64) lds[idx] = 0.0;
-    wave_sync();
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = Q0 + 16 * bi + lk + 4 * j, cc = Q0 + 16 * bj + lr;
-          if (r >= w1 && r < w1 + wn1 && cc >= w1 && cc < w1 + wn1)
-            Zs[r - w1][cc - w1] = bacc[bi][bj][j] * ev[r] * evinv[cc];
-        }
-    wave_sync();
     const double em2a = sc[SC_EM2A], ep2a = sc[SC_EP2A];
-    decide_window<WM>(lane, wn1, w1, W, win + 1, Zs, reinterpret_cast<double2(*)[64]>(R2), sx, ux, fx,
-                      forced != nullptr, em2a, ep2a, s_l, acc_out, ratio_out, win_a, win_p, Zn, Zpn);
+    decide_window<WM>(lane, wn1, w1, W, win + 1, Zs, hist, sx, ux, fx, forced != nullptr, em2a, ep2a,
+                      s_l, acc_out, ratio_out, win_a, win_p, Zn, Zpn, ev, evinv);
     return;
   }
-  // a tile: the G tile (clamped loads, in flight during the factor work)
+  // a tile: wave (wave >> 1, wave & 1) takes the 32 x 32 quarter at (row0, col0)
+  const int R0 = by * 64, C0 = bx * 64;
+  const int row0 = R0 + (wave >> 1) * 32, col0 = C0 + (wave & 1) * 32;
   v4d acc[2][2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -806,88 +792,49 @@ k_flush_decide(double* __restrict__ G, int N, int gxt, const double* __restrict_
         acc[bi][bj][j] = G[(size_t)min(r, N - 1) * N + min(cc, N - 1)];
       }
   if (a > 0) {
-    // Z (upper) and Z' (lower) triangles of the a accepts, zeros elsewhere in
-    // WM x WM, and g, h zero past the a accepts: the sums below then run over
-    // all WM terms without tests (the extra terms are exact zeros)
-    for (int idx = tid; idx < WM * WM; idx += 256) {
-      const int q = idx / WM, n = idx % WM;
-      const bool in = q < a && n < a;
-      Zs[q][n] = (in && q <= n) ? Zc[q * W + n] : 0.0;
-      Zps[q][n] = (in && n <= q) ? Zpc[q * W + n] : 0.0;
-    }
-    for (int n = tid; n < a; n += 256) il[n] = w0 + win_p[win * W + n];
-    __syncthreads();
-    double(*gl)[WM + 1] = reinterpret_cast<double(*)[WM + 1]>(R2);
-    double(*hl)[65] = reinterpret_cast<double(*)[65]>(R3);
-    for (int idx = tid; idx < 64 * WM; idx += 256) {
-      const int rr = idx / WM, q = idx % WM;
-      const int r = R0 + rr, i = il[q < a ? q : 0];
-      gl[rr][q] = (r < N && q < a) ? csc[(size_t)r * W + (i - w0)] * ev[r] * evinv[i] : 0.0;
-    }
-    for (int idx = tid; idx < WM * 64; idx += 256) {
-      const int q = idx / 64, cc = idx % 64;
-      const int cg = C0 + cc, i = il[q < a ? q : 0];
-      hl[q][cc] = (cg < N && q < a)
-                      ? ((cg == i) ? 1.0 : 0.0) - rsc[(size_t)(i - w0) * N + cg] * ev[i] * evinv[cg]
-                      : 0.0;
-    }
-    __syncthreads();
-    // thread (lane, wave): row / column lane of the tile, factors n = wave + 4 k2;
-    // its row of gl and column of hl are read once into registers
-    constexpr int PERU = WM / 4;
-    double uvals[PERU], wvals[PERU];
-    {
-      double gr[WM];
+    double gb[2][PS], hb[2][PS];
+    ops.load_z(Zc, Zpc, lr, lk);
 #pragma unroll
-      for (int q = 0; q < WM; ++q) gr[q] = gl[lane][q];
+    for (int b = 0; b < 2; ++b) {
+      load_run<PS>(gb[b], csc + (size_t)min(row0 + 16 * b + lr, N - 1) * WM + PS * lk);
+      load_run<PS>(hb[b], rsc + (size_t)min(col0 + 16 * b + lr, N - 1) * WM + PS * lk);
+    }
 #pragma unroll
-      for (int k2 = 0; k2 < PERU; ++k2) {
-        const int n = wave + 4 * k2;
-        double uv = 0.0;
+    for (int b = 0; b < 2; ++b) {
+      const int ch = min(col0 + 16 * b + lr, N - 1);
 #pragma unroll
-        for (int q = 0; q < WM; ++q) uv += gr[q] * Zs[q][n];
-        uvals[k2] = R0 + lane < N ? uv * evinv[R0 + lane] : 0.0;
+      for (int s = 0; s < PS; ++s) hb[b][s] = ((ch == w0 + PS * lk + s) ? 1.0 : 0.0) - hb[b][s];
+    }
+    v4d ut[NB][2], wt[NB][2];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) ut[nb][b] = wt[nb][b] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < PS; ++s)
+      if (s < wn) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          if (nb < nbl) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              ut[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.za[nb][s], gb[b][s], ut[nb][b], 0, 0, 0);
+              wt[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.zpa[nb][s], hb[b][s], wt[nb][b], 0, 0, 0);
+            }
+          }
       }
-    }
-    {
-      double hr[WM];
+    // G += U W, k-steps 16 nb + 4 j in increasing order (the order of k_flush_f64)
 #pragma unroll
-      for (int q = 0; q < WM; ++q) hr[q] = hl[q][lane];
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int k2 = 0; k2 < PERU; ++k2) {
-        const int n = wave + 4 * k2;
-        double wv = 0.0;
+      for (int j = 0; j < 4; ++j)
+        if (16 * nb + 4 * j < a) {
 #pragma unroll
-        for (int q = 0; q < WM; ++q) wv += Zps[n][q] * hr[q];
-        wvals[k2] = C0 + lane < N ? wv * ev[C0 + lane] : 0.0;
-      }
-    }
-    __syncthreads();
-    double(*Ul)[64] = reinterpret_cast<double(*)[64]>(R2);
-    double(*Wl)[64] = reinterpret_cast<double(*)[64]>(R3);
+          for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int k2 = 0; k2 < PERU; ++k2) {
-      const int n = wave + 4 * k2;
-      if (n < a) {
-        Ul[n][lane] = uvals[k2];
-        Wl[n][lane] = wvals[k2];
-      }
-    }
-    __syncthreads();
-    for (int k0 = 0; k0 < a; k0 += 4) {
-      const int k = k0 + lk;
-      double av[2], bv[2];
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi) {
-        av[bi] = k < a ? Ul[k < a ? k : 0][row0 - R0 + 16 * bi + lr] : 0.0;
-        bv[bi] = k < a ? Wl[k < a ? k : 0][col0 - C0 + 16 * bi + lr] : 0.0;
-      }
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
-    }
+            for (int bj = 0; bj < 2; ++bj)
+              acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ut[nb][bi][j], wt[nb][bj][j], acc[bi][bj], 0, 0, 0);
+        }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -909,8 +856,8 @@ k_flush_decide(double* __restrict__ G, int N, int gxt, const double* __restrict_
         for (int j = 0; j < 4; ++j) {
           const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
           if (r < N && cc < N) {
-            if (cc >= w1 && cc < w1 + wn1) csn[(size_t)r * W + (cc - w1)] = acc[bi][bj][j];
-            if (r >= w1 && r < w1 + wn1) rsn[(size_t)(r - w1) * N + cc] = acc[bi][bj][j];
+            if (cc >= w1 && cc < w1 + wn1) csn[(size_t)r * WM + (cc - w1)] = acc[bi][bj][j];
+            if (r >= w1 && r < w1 + wn1) rsn[(size_t)cc * WM + (r - w1)] = acc[bi][bj][j];
             if (r >= w2 && r < w2 + wn2 && cc >= w2 && cc < w2 + wn2)
               bkn[(size_t)(r - w2) * W + (cc - w2)] = acc[bi][bj][j];
           }
@@ -918,91 +865,112 @@ k_flush_decide(double* __restrict__ G, int N, int gxt, const double* __restrict_
   }
 }
 
+// the decider's LDS: the window block and the decision history
 template <int WM>
 constexpr size_t flush_decide_lds() {
-  return size_t(2 * WM * (WM + 1) + 64 * (WM + 1) + WM * 65) * 8;
+  return size_t(WM * (WM + 1)) * 8 + size_t(WM) * 64 * 16;
 }
 
 // ---------------------------------------------------------------------------
-// New pending columns of the window: with g[r][n] = G~cur[r, i_n] and
-// h[n][r] = delta(r, i_n) - G~cur[i_n, r] (G~cur includes the m pending
-// columns of this flush group),
-//   U[:, m+n] = sum_{q<=n} g[:, q] Z[q][n],   W[m+n, :] = sum_{q<=n} Z'[n][q] h[q, :].
-// One workgroup per block of RB rows r; Z, Z' staged in LDS.
+// New pending factors of the window (store frame), with G~cur = G + U_pend
+// W_pend (the m pending factors of this flush group):
+//   U[:, m+n] = sum_p G~cur[:, w0+p] Zh[n][p],
+//   W[m+n, :] = sum_p Zph[n][p] (e_{w0+p} - G~cur[w0+p, :]).
+// One wave per 16 rows r (which are also the columns of W): the columns
+// G~cur[r, S] and rows G~cur[S, r] start from G and take the pending products
+// on the MFMA, laid out so that element j of block pb is the operand of p-step
+// 4 pb + j; then U^T and W on the MFMA with the operands and steps of the
+// fused window launch (both schedules produce the same factors bit for bit).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int WM>
 __global__ void __launch_bounds__(256)
-k_extend(const T* __restrict__ G, int N, const double* __restrict__ ev,
-         const double* __restrict__ evinv, T* __restrict__ Up, T* __restrict__ Wp,
-         const int* __restrict__ win_a, int win, int grp0, const int* __restrict__ win_p,
-         const double* __restrict__ Zg, const double* __restrict__ Zpg, int W, int w0, int RB,
-         size_t zs) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+k_extend(const T* __restrict__ G, int N, T* __restrict__ Up, T* __restrict__ Wp,
+         const int* __restrict__ win_a, int win, int grp0, const double* __restrict__ Zg,
+         const double* __restrict__ Zpg, int W, int w0, size_t zs) {
+  typedef WinOps<WM> Ops;
+  constexpr int PS = Ops::PS, NB = Ops::NB, PB = PS / 4;
   G = zw(G, zs);
-  ev = zw(ev, zs);
-  evinv = zw(evinv, zs);
   Up = zw(Up, zs);
   Wp = zw(Wp, zs);
   win_a = zw(win_a, zs);
-  win_p = zw(win_p, zs);
   Zg = zw(Zg, zs);
   Zpg = zw(Zpg, zs);
   const int a = win_a[win];
   if (a == 0) return;
   int m = 0;
   for (int j = grp0; j < win; ++j) m += win_a[j];
-  double* Z = reinterpret_cast<double*>(smem_raw);  // a*a
-  double* Zp = Z + a * a;                            // a*a
-  double* gl = Zp + a * a;                           // RB*a : gl[rr*a + n]
-  double* hl = gl + RB * a;                          // a*RB : hl[n*RB + rr]
-  int* il = reinterpret_cast<int*>(hl + a * RB);     // a
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int r0 = blockIdx.x * RB;
-  for (int idx = tid; idx < a * a; idx += nth) {
-    const int q = idx / a, n = idx % a;
-    Z[idx] = Zg[q * W + n];
-    Zp[idx] = Zpg[q * W + n];
-  }
-  for (int n = tid; n < a; n += nth) il[n] = w0 + win_p[win * W + n];
-  __syncthreads();
-  // phase 1: g and h for the RB rows of this block
-  for (int idx = tid; idx < RB * a; idx += nth) {
-    const int n = idx % a, rr = idx / a;
-    const int r = r0 + rr;
-    if (r >= N) continue;
-    const int i = il[n];
-    double gv = double(G[(size_t)r * N + i]);
-    double hv = double(G[(size_t)i * N + r]);
-    for (int j = 0; j < m; ++j) {
-      gv += double(Up[(size_t)j * N + r]) * double(Wp[(size_t)j * N + i]);
-      hv += double(Up[(size_t)j * N + i]) * double(Wp[(size_t)j * N + r]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int r0 = blockIdx.x * 64 + 16 * wave;
+  if (r0 >= N) return;  // (no barriers below)
+  const int wn = min(W, N - w0);
+  const int nbl = (a + 15) >> 4;
+  const int r = r0 + lr, rc = min(r, N - 1);
+  Ops ops;
+  ops.load_z(Zg, Zpg, lr, lk);
+  // element j of block pb: position PS (l/16) + 4 pb + j; the A operands of
+  // the pending products take row i = l%16 at position PS (i%4) + 4 pb + i/4
+  v4d gT[PB], hT[PB];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = min(w0 + PS * lk + 4 * pb + j, N - 1);
+      gT[pb][j] = double(G[(size_t)rc * N + col]);
+      hT[pb][j] = double(G[(size_t)col * N + rc]);
     }
-    gl[rr * a + n] = gv * ev[r] * evinv[i];
-    hl[n * RB + rr] = ((r == i) ? 1.0 : 0.0) - hv * ev[i] * evinv[r];
-  }
-  __syncthreads();
-  // phase 2: triangular combinations, stored in the store frame
-  for (int idx = tid; idx < RB * a; idx += nth) {
-    const int rr = idx % RB, n = idx / RB;
-    const int r = r0 + rr;
-    if (r >= N) continue;
-    double uv = 0.0, wv = 0.0;
-    for (int q = 0; q <= n; ++q) {
-      uv += gl[rr * a + q] * Z[q * a + n];
-      wv += Zp[n * a + q] * hl[q * RB + rr];
+  for (int j0 = 0; j0 < m; j0 += 4) {
+    const int jj = min(j0 + lk, m - 1);
+    const bool jin = j0 + lk < m;
+    const double ub = jin ? double(Up[(size_t)jj * N + rc]) : 0.0;
+    const double wb = jin ? double(Wp[(size_t)jj * N + rc]) : 0.0;
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      const int col = min(w0 + PS * (lr & 3) + 4 * pb + (lr >> 2), N - 1);
+      const double wa = jin ? double(Wp[(size_t)jj * N + col]) : 0.0;
+      const double ua = jin ? double(Up[(size_t)jj * N + col]) : 0.0;
+      gT[pb] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa, ub, gT[pb], 0, 0, 0);
+      hT[pb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua, wb, hT[pb], 0, 0, 0);
     }
-    Up[(size_t)(m + n) * N + r] = T(uv * evinv[r]);
-    Wp[(size_t)(m + n) * N + r] = T(wv * ev[r]);
   }
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) hT[pb][j] = ((rc == w0 + PS * lk + 4 * pb + j) ? 1.0 : 0.0) - hT[pb][j];
+  v4d ut[NB], wt[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) ut[nb] = wt[nb] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < PS; ++s)
+    if (s < wn) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        if (nb < nbl) {
+          ut[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.za[nb][s], gT[s >> 2][s & 3], ut[nb], 0, 0, 0);
+          wt[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.zpa[nb][s], hT[s >> 2][s & 3], wt[nb], 0, 0, 0);
+        }
+    }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = 16 * nb + lk + 4 * j;
+      if (n < a && r < N) {
+        Up[(size_t)(m + n) * N + r] = T(ut[nb][j]);
+        Wp[(size_t)(m + n) * N + r] = T(wt[nb][j]);
+      }
+    }
 }
 
 // Window submatrix of the next window from G and the pending factors:
-// Gs[x][y] = ev_x evinv_y (G[x,y] + sum_{j<m} U[j][x] W[j][y]).
+// Gs[x][y] = ev_x evinv_y (G[x,y] + sum_{j<m} U[j][x] W[j][y]), the sum on the
+// MFMA; one wave per 16 x 16 block of the (at most 64 x 64) window.
 template <typename T>
-__global__ void k_prep(const T* __restrict__ G, int N, const double* __restrict__ ev,
-                       const double* __restrict__ evinv, const T* __restrict__ Up,
-                       const T* __restrict__ Wp, const int* __restrict__ win_a, int grp0,
-                       int upto, int w0, int wn, int W, double* __restrict__ Gs, size_t zs) {
+__global__ void __launch_bounds__(256)
+k_prep(const T* __restrict__ G, int N, const double* __restrict__ ev,
+       const double* __restrict__ evinv, const T* __restrict__ Up, const T* __restrict__ Wp,
+       const int* __restrict__ win_a, int grp0, int upto, int w0, int wn, int W,
+       double* __restrict__ Gs, size_t zs) {
   G = zw(G, zs);
   ev = zw(ev, zs);
   evinv = zw(evinv, zs);
@@ -1012,12 +980,30 @@ __global__ void k_prep(const T* __restrict__ G, int N, const double* __restrict_
   Gs = zw(Gs, zs);
   int m = 0;
   for (int j = grp0; j <= upto; ++j) m += win_a[j];
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= wn * wn) return;
-  const int x = w0 + idx / wn, y = w0 + idx % wn;
-  double g = double(G[(size_t)x * N + y]);
-  for (int j = 0; j < m; ++j) g += double(Up[(size_t)j * N + x]) * double(Wp[(size_t)j * N + y]);
-  Gs[(idx / wn) * W + (idx % wn)] = g * ev[x] * evinv[y];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nbk = (wn + 15) >> 4;
+  for (int blk = wave; blk < nbk * nbk; blk += 4) {
+    const int x0 = (blk / nbk) * 16, y0 = (blk % nbk) * 16;
+    v4d d;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = min(x0 + lk + 4 * j, wn - 1), y = min(y0 + lr, wn - 1);
+      d[j] = double(G[(size_t)(w0 + x) * N + w0 + y]);
+    }
+    for (int j0 = 0; j0 < m; j0 += 4) {
+      const int jj = min(j0 + lk, m - 1);
+      const bool jin = j0 + lk < m;
+      const double ua = jin ? double(Up[(size_t)jj * N + w0 + min(x0 + lr, wn - 1)]) : 0.0;
+      const double wb = jin ? double(Wp[(size_t)jj * N + w0 + min(y0 + lr, wn - 1)]) : 0.0;
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(ua, wb, d, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int x = x0 + lk + 4 * j, y = y0 + lr;
+      if (x < wn && y < wn) Gs[x * W + y] = d[j] * ev[w0 + x] * evinv[w0 + y];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1177,11 +1163,6 @@ k_flush_split(float* __restrict__ G, int N, const float* __restrict__ Up,
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename T>
-int set_lds_limits() {
-  KDQMC_HIP(hipFuncSetAttribute((const void*)k_extend<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-  return KDQMC_OK;
-}
 
 // The fused schedule of one slice (see k_flush_decide): 1 + nw launches.
 template <int WM>
@@ -1192,7 +1173,9 @@ int fused_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
   int8_t* s_l = c->fields + (size_t)(l - 1) * N;
   const unsigned Z = (unsigned)c->nch;
   const size_t zs = c->zs;
-  const size_t ww = (size_t)W * W, nwv = (size_t)N * W;
+  // Z, Z' and the snapshots have the padded stride WM (= c->wm), the block
+  // copies the window's own W
+  const size_t zz = (size_t)WM * WM, nwv = (size_t)N * WM, ww = (size_t)W * W;
   const int wn0 = std::min(W, N), wn1 = std::max(std::min(W, N - W), 0);
   const int nsnap = (2 * N * wn0 + wn1 * wn1 + 64 * 8 - 1) / (64 * 8);
   const int e0 = prof_mark(c);
@@ -1208,7 +1191,7 @@ int fused_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
     const dim3 grid(gxt * gxt + (win + 1 < c->nw ? 1 : 0), 1, Z);
     hipLaunchKernelGGL((k_flush_decide<WM>), grid, dim3(256), flush_decide_lds<WM>(), c->stream, G, N,
                        gxt, c->ev, c->evinv, s_l, u, forced, acc, ratio, c->sc, win, W, c->nw, c->win_a,
-                       c->win_p, c->Xw + cur * ww, c->Yw + cur * ww, c->Xw + nxt * ww, c->Yw + nxt * ww,
+                       c->win_p, c->Xw + cur * zz, c->Yw + cur * zz, c->Xw + nxt * zz, c->Yw + nxt * zz,
                        c->snapc + cur * nwv, c->snapr + cur * nwv, c->snapc + nxt * nwv,
                        c->snapr + nxt * nwv, c->snapb + nxt * ww, c->snapb + cur * ww, zs, zn);
     const int e2 = prof_mark(c);
@@ -1232,7 +1215,6 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
   T* Up = static_cast<T*>(c->Upend);
   T* Wp = static_cast<T*>(c->Wpend);
   int8_t* s_l = c->fields + (size_t)(l - 1) * N;
-  const int RB = 32;
   const unsigned Z = (unsigned)c->nch;
   const size_t zs = c->zs;
   for (int win = 0; win < c->nw; ++win) {
@@ -1242,12 +1224,14 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
     const bool first_in_group = (win == grp0);
     // decide
     const int e_d = prof_mark(c);
-    if (wn <= 16)
+    // (the template's window size is the padded size of Z and Z': chosen by
+    // the window size W, not by this window's own wn)
+    if (c->wm == 16)
       hipLaunchKernelGGL((k_decide_wave<T, 16>), dim3(1, 1, Z), dim3(64), 0, c->stream, G, N, c->ev,
                          c->evinv, s_l, u, forced, acc, ratio, w0, wn, W,
                          first_in_group ? nullptr : c->Gs, c->sc, win, c->win_a, c->win_p, c->Xw,
                          c->Yw, zs, zn);
-    else if (wn <= 32)
+    else if (c->wm == 32)
       hipLaunchKernelGGL((k_decide_wave<T, 32>), dim3(1, 1, Z), dim3(64), 0, c->stream, G, N, c->ev,
                          c->evinv, s_l, u, forced, acc, ratio, w0, wn, W,
                          first_in_group ? nullptr : c->Gs, c->sc, win, c->win_a, c->win_p, c->Xw,
@@ -1260,10 +1244,16 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
     const int e_e = prof_mark(c);
     prof_pair(c, PH_DECIDE, e_d, e_e);
     // extend
-    const size_t lds_e = 2 * size_t(W) * W * 8 + 2 * size_t(RB) * W * 8 + size_t(W) * 4 + 16;
-    hipLaunchKernelGGL(k_extend<T>, dim3((N + RB - 1) / RB, 1, Z), dim3(256), lds_e, c->stream, G, N,
-                       c->ev, c->evinv, Up, Wp, c->win_a, win, grp0, c->win_p, c->Xw, c->Yw, W,
-                       w0, RB, zs);
+    const dim3 ge((N + 63) / 64, 1, Z);
+    if (W <= 16)
+      hipLaunchKernelGGL((k_extend<T, 16>), ge, dim3(256), 0, c->stream, G, N, Up, Wp, c->win_a, win,
+                         grp0, c->Xw, c->Yw, W, w0, zs);
+    else if (W <= 32)
+      hipLaunchKernelGGL((k_extend<T, 32>), ge, dim3(256), 0, c->stream, G, N, Up, Wp, c->win_a, win,
+                         grp0, c->Xw, c->Yw, W, w0, zs);
+    else
+      hipLaunchKernelGGL((k_extend<T, 64>), ge, dim3(256), 0, c->stream, G, N, Up, Wp, c->win_a, win,
+                         grp0, c->Xw, c->Yw, W, w0, zs);
     const int e_x = prof_mark(c);
     prof_pair(c, PH_EXTEND, e_e, e_x);
     const bool last_in_group = (win - grp0 == c->F - 1) || (win == c->nw - 1);
@@ -1285,8 +1275,8 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
       const int nx = win + 1;
       const int nw0 = nx * W;
       const int nwn = std::min(W, N - nw0);
-      hipLaunchKernelGGL(k_prep<T>, dim3((nwn * nwn + 255) / 256, 1, Z), dim3(256), 0, c->stream, G,
-                         N, c->ev, c->evinv, Up, Wp, c->win_a, grp0, win, nw0, nwn, W, c->Gs, zs);
+      hipLaunchKernelGGL(k_prep<T>, dim3(1, 1, Z), dim3(256), 0, c->stream, G, N, c->ev, c->evinv,
+                         Up, Wp, c->win_a, grp0, win, nw0, nwn, W, c->Gs, zs);
       prof_pair(c, PH_PREP, e_x, prof_mark(c));
     }
   }
@@ -1296,10 +1286,7 @@ int slice_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
 
 }  // namespace
 
-int prepare_updates() {
-  KDQMC_TRY(set_lds_limits<double>());
-  return set_lds_limits<float>();
-}
+int prepare_updates() { return KDQMC_OK; }
 
 int launch_frame_scale(kdqmc_ctx* c, int l) {
   hipLaunchKernelGGL(k_frame_scale, dim3((c->N + 255) / 256, 1, (unsigned)c->nch), dim3(256), 0,
