@@ -646,6 +646,105 @@ k_merge_t(const double* __restrict__ V, int ldv, int n, const double* __restrict
   }
 }
 
+// The same apply for one 16-column reflector on a 16-column stripe in the
+// look-ahead step (at most 512 rows below the next panel, so at most 528
+// from the reflector's first row), with every global load of both products
+// issued before the first is used: rows of V and C for W = V^T C (wave w
+// takes rows w*4 + 32 i, i < 17) and rows of V for C -= V W2 (16-row blocks
+// w*16 + 128 k, k < 5).  512 threads.
+__device__ __forceinline__ void apply_wy_short(WyLds<16>& sh, double* __restrict__ C, int ldc, int n,
+                                               int j, int nbp, int ncols, int s0,
+                                               const double* __restrict__ V, int ldv,
+                                               const double* __restrict__ T,
+                                               double (*dst)[17] = nullptr, int dst_row0 = 0) {
+  constexpr int NW = 8, KI = 17, KB = 5;  // 32 KI >= 528 and 128 KB >= 528
+  auto& Wp = sh.Wp;
+  auto& W2 = sh.W2;
+  auto& Tl = sh.Tl;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int m = n - j;
+  const bool vin = lr < nbp, cin = s0 + lr < ncols;
+  const int vcol = j + (vin ? lr : 0), ccol = cin ? s0 + lr : 0;
+  double tv[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) tv[h] = T[tid + 512 * h];
+  double av[KI], bv[KI], vq[KB][4];
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int r = j + min(wave * 4 + 32 * i + lk, m - 1);
+    av[i] = V[(size_t)r * ldv + vcol];
+    bv[i] = C[(size_t)r * ldc + ccol];
+  }
+#pragma unroll
+  for (int k = 0; k < KB; ++k)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int r = j + min(wave * 16 + 128 * k + lr, m - 1);
+      vq[k][kk] = V[(size_t)r * ldv + j + min(4 * kk + lk, nbp - 1)];
+    }
+  // W = V^T C over the rows (rows past the panel and columns past the
+  // reflector / the stripe weigh 0)
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < KI; ++i) {
+    const int rr = wave * 4 + 32 * i + lk;
+    const bool in = rr < m;
+    const double a = (in && vin) ? av[i] : 0.0;
+    const double b = (in && cin) ? bv[i] : 0.0;
+    if (dst != nullptr && in && j + rr >= dst_row0) dst[j + rr - dst_row0][lr] = b;
+    if (wave * 4 + 32 * i < m) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) Wp[wave][lk + 4 * e][lr] = acc[e];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int idx = tid + 512 * h, r = idx >> 5, cc = idx & 31;
+    Tl[r][cc] = (r < nbp && cc < nbp) ? tv[h] : 0.0;
+  }
+  __syncthreads();
+  if (tid < 256) {
+    const int r = tid >> 4, cc = tid & 15;
+    double sacc = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sacc += Wp[w][r][cc];
+    Wp[0][r][cc] = sacc;
+  }
+  __syncthreads();
+  // W2 = T^T W
+  if (tid < 256) {
+    const int r = tid >> 4, cc = tid & 15;
+    double sacc = 0.0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) sacc += Tl[t][r] * Wp[0][t][cc];
+    W2[r][cc] = sacc;
+  }
+  __syncthreads();
+  // C -= V W2
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int rb = wave * 16 + 128 * k;
+    if (rb < m) {
+      v4d d = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int vc = 4 * kk + lk;
+        const double a = (j + rb + lr < n && vc < nbp) ? vq[k][kk] : 0.0;
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, W2[vc][lr], d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = j + rb + lk + 4 * e, cc = s0 + lr;
+        if (dst != nullptr && r >= dst_row0) {  // in the caller's LDS rows (0 past ncols)
+          if (r < n) dst[r - dst_row0][lr] -= d[e];
+        } else if (r < n && cc < ncols) {
+          C[(size_t)r * ldc + cc] -= d[e];
+        }
+      }
+    }
+  }
+}
+
 // One step of the factorization with look-ahead (16-column panels of at
 // most 512 rows): workgroup 0 applies panel
 // p's reflector (columns jp.., width nbp, factor Tp) to the next panel's
@@ -668,12 +767,12 @@ k_qr_step(double* __restrict__ A, int lda, int n, int ncols, int jp, int nbp, co
     // staging buffer; the rows above it (final entries of R) to A
     __shared__ double Pst[panel_chunk<RPT, NT>()][NB + 1];
     static_assert(NB == 16 && RPT * NT == panel_chunk<RPT, NT>(), "one 16-column stripe, one chunk");
-    apply_wy_stripe<16, 1>(sh, A, lda, n, jp, nbp, ncols, jn, Vq, lda, Tp, 1, Pst, jn);
+    apply_wy_short(sh, A, lda, n, jp, nbp, ncols, jn, Vq, lda, Tp, Pst, jn);
     __syncthreads();
     if (threadIdx.x >= NT) return;  // waves past the panel's leave; barriers count the rest
     qr_panel_body<RPT, NB, NT, true>(A, lda, n, jn, nbn, Vq, zw(Tn, zs), zw(tau, zs), Pst);
   } else {
-    apply_wy_stripe<16, 1>(sh, A, lda, n, jp, nbp, ncols, jn + nbn + (blockIdx.x - 1) * 16, Vq, lda, Tp, 1);
+    apply_wy_short(sh, A, lda, n, jp, nbp, ncols, jn + nbn + (blockIdx.x - 1) * 16, Vq, lda, Tp);
   }
 }
 
@@ -938,7 +1037,7 @@ int qr_f64(kdqmc_ctx* c, int n, int ncol, double* A, double* Q) {
     double* Tp = c->Tq + (size_t)npan * kNBmax * kNBmax;
     double* Tn = Tp + kNBmax * kNBmax;
     const int mn = n - jn;
-    if (mn <= 512) {
+    if (mn <= 512) {  // (the apply inside covers at most mn + 16 <= 528 rows)
       const dim3 grid(1 + (ncol - jn - nbn + 15) / 16, 1, c->nch);
       const int e0 = prof_mark(c);
       hipLaunchKernelGGL((k_qr_step<2, 16, 256>), grid, dim3(512), 0, c->stream, A, ld, n, ncol, j, nbp, Tp, jn,

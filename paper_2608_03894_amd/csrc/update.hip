@@ -294,8 +294,8 @@ k_decide(const T* __restrict__ G, int N, const double* __restrict__ ev,
 //   u_n = -c G~cur[:, p] = -c (G0[:, p] + sum_{r<n} u_r w_r[p]),
 //   w_n = e_p - G~cur[p, :] = e_p - G0[p, :] - sum_{r<n} u_r[p] w_r,
 // so lane x (site x of the window) rebuilds column and row p from G0 (LDS)
-// and the factors of the earlier accepts (a lane-private history in LDS),
-// and keeps only its own diagonal entry current.  Rejections leave G~cur
+// and the factors of the earlier accepts (its own in registers, lane p's
+// read back from LDS), and keeps only its own diagonal entry current.  Rejections leave G~cur
 // unchanged: all sites past the latest accept are tested at once against
 // that state and a ballot names the next accept (the sites before it are
 // rejections with the ratios a one-by-one scan computes).  Lanes 32 + q run
@@ -321,7 +321,6 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
                                               double* __restrict__ Zpg, const double* __restrict__ ev,
                                               const double* __restrict__ evinv) {
   static_assert(WM <= 32, "one wave holds the sites in lanes 0..31 and Z in lanes 32..63");
-  static_assert(WM % 8 == 0, "history rows are read in blocks of 8");
   const bool site = lane < WM;
   const bool xin = lane < wn;
   const bool zlane = lane >= 32;  // coefficient lanes (q = lane - 32)
@@ -329,23 +328,25 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
   const double delta_x = (sx > 0 ? em2a : ep2a) - 1.0;
   const double e2as_x = sx > 0 ? ep2a : em2a;
   double diag = xin ? g0s[lane][lane] : 0.0;
-  // history rows not yet written hold zeros, so the dot products below run
-  // over whole blocks of 8 rows without tests (a zero row adds exactly 0)
-#pragma unroll
-  for (int r = 0; r < WM; ++r) hist[r][lane] = make_double2(0.0, 0.0);
-  wave_sync();
   // the ratio and decision of site `lane` and the position of accept number
-  // `lane` stay in registers until the end (no LDS traffic but the history)
+  // `lane` stay in registers until the end
   double my_ratio = 0.0;
   bool my_acc = false;
   int my_pos = 0;
   int na = 0, p0 = 0;
-  // per-lane constants of the loop: the loop body is branch-free apart from
-  // its exit and the uniform skips of history blocks (divergent updates are
-  // selects, the window entries of the coefficient lanes are weighted by 0)
+  // per-lane constants: the accept step is branch-free apart from the exit
+  // (divergent updates are selects, the window entries read by the
+  // coefficient lanes are weighted by 0)
   const double sitef = site ? 1.0 : 0.0;
   const int lx = lane & (WM - 1);
-  while (p0 < wn) {
+  // The accept loop is unrolled, so that the accept index n is a
+  // compile-time constant: the lane's own factor history (u_r[x], w_r[x])
+  // lives in registers hu[r], hw[r]; the rows also go to LDS (hist[r][lane]),
+  // from where every lane reads the accepted site's row r < n (one broadcast
+  // read per row, all issued together).
+  double hu[WM], hw[WM];
+#pragma unroll
+  for (int n = 0; n < WM; ++n) {
     const double Rx = 1.0 + delta_x * (1.0 - diag);
     double cx = delta_x * rcp_nr(Rx);  // c of every candidate, off the ballot's path
     const double ratio_x = e2as_x * Rx * Rx;
@@ -359,40 +360,28 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
     if (p >= wn) break;
     p0 = p + 1;
     const double c = lane_value(cx, p);
-    const int n = na;
     my_pos = (lane == n) ? p : my_pos;
-    // window entries G0[x][p], G0[p][x] (the coefficient lanes, and lanes
-    // WM..31 of 16-site windows, read a row they weight by zero)
-    // (added after the history sums, so that their reads overlap these)
+    // window entries G0[x][p], G0[p][x], and row r < n of lane p's history
+    // (u_r[p], w_r[p]); four partial sums per product
     const double gA = g0s[lx][p], gB = g0s[p][lx];
-    double A0 = 0.0, B0 = 0.0, A1 = 0.0, B1 = 0.0;
-    // blocks of 8 history rows read at once (rows n.. of the last block are
-    // zero); even and odd rows summed apart to halve the dependent chains
+    double2 rem[WM > 1 ? WM - 1 : 1];
 #pragma unroll
-    for (int r0 = 0; r0 < WM; r0 += 8) {
-      if (r0 < n) {
-        double2 own[8], rem[8];
+    for (int r = 0; r < n; ++r) rem[r] = hist[r][p];
+    double A[4] = {0.0, 0.0, 0.0, 0.0}, B[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          own[j] = hist[r0 + j][lane];
-          rem[j] = hist[r0 + j][p];  // (u_r[p], w_r[p]), the same for every lane
-        }
-#pragma unroll
-        for (int j = 0; j < 8; j += 2) {
-          A0 = fma(own[j].x, rem[j].y, A0);
-          B0 = fma(rem[j].x, own[j].y, B0);
-          A1 = fma(own[j + 1].x, rem[j + 1].y, A1);
-          B1 = fma(rem[j + 1].x, own[j + 1].y, B1);
-        }
-      }
+    for (int r = 0; r < n; ++r) {
+      A[r & 3] = fma(hu[r], rem[r].y, A[r & 3]);
+      B[r & 3] = fma(rem[r].x, hw[r], B[r & 3]);
     }
-    const double A = fma(gA, sitef, (!site && q == n) ? 1.0 : 0.0) + (A0 + A1);
-    const double B = fma(gB, sitef, B0 + B1);
-    const double Xn = -c * A;
-    const double Yn = ((site ? lane == p : q == n) ? 1.0 : 0.0) - B;
+    const double As = fma(gA, sitef, (!site && q == n) ? 1.0 : 0.0) + ((A[0] + A[1]) + (A[2] + A[3]));
+    const double Bs = fma(gB, sitef, (B[0] + B[1]) + (B[2] + B[3]));
+    const double Xn = -c * As;
+    const double Yn = ((site ? lane == p : q == n) ? 1.0 : 0.0) - Bs;
+    hu[n] = Xn;
+    hw[n] = Yn;
     hist[n][lane] = make_double2(Xn, Yn);
     diag = fma(Xn * sitef, Yn, diag);
-    ++na;
+    na = n + 1;
   }
   wave_sync();
   const unsigned long long accm = __ballot(xin && my_acc);
