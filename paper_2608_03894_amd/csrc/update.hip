@@ -328,17 +328,20 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
   const double delta_x = (sx > 0 ? em2a : ep2a) - 1.0;
   const double e2as_x = sx > 0 ? ep2a : em2a;
   double diag = xin ? g0s[lane][lane] : 0.0;
-  // the ratio and decision of site `lane` and the position of accept number
-  // `lane` stay in registers until the end
+  // the ratio of site `lane` stays in a register until the end; the accepted
+  // positions are a wave-uniform bit mask
   double my_ratio = 0.0;
-  bool my_acc = false;
-  int my_pos = 0;
+  unsigned long long accm = 0;
   int na = 0, p0 = 0;
   // per-lane constants: the accept step is branch-free apart from the exit
   // (divergent updates are selects, the window entries read by the
-  // coefficient lanes are weighted by 0)
+  // coefficient lanes are weighted by 0).  With replayed decisions a forced
+  // accept compares -1 < ratio (always true, the ratio being positive) and a
+  // forced reject +inf < ratio (always false).
   const double sitef = site ? 1.0 : 0.0;
   const int lx = lane & (WM - 1);
+  const double ucmp = use_forced ? (fx ? -1.0 : __builtin_inf()) : ux;
+  const unsigned long long live = __ballot(xin);
   // The accept loop is unrolled, so that the accept index n is a
   // compile-time constant: the lane's own factor history (u_r[x], w_r[x])
   // lives in registers hu[r], hw[r]; the rows also go to LDS (hist[r][lane]),
@@ -350,17 +353,15 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
     const double Rx = 1.0 + delta_x * (1.0 - diag);
     double cx = delta_x * rcp_nr(Rx);  // c of every candidate, off the ballot's path
     const double ratio_x = e2as_x * Rx * Rx;
-    const bool ax = use_forced ? fx : (ux < ratio_x);
-    const unsigned long long hits = __ballot(xin && lane >= p0 && ax);
+    const unsigned long long hits = __ballot(ucmp < ratio_x) & live & ~((1ull << p0) - 1ull);
     asm volatile("" : "+v"(cx));  // (the division is issued before the branch below)
     const int p = hits ? __builtin_ctzll(hits) : wn;
-    const bool upd = lane >= p0 && lane <= p;
-    my_ratio = upd ? ratio_x : my_ratio;
-    my_acc = upd ? (lane == p) : my_acc;
+    // (a site's last update is at its own decision: p0 passes it afterwards)
+    my_ratio = (lane >= p0) ? ratio_x : my_ratio;
     if (p >= wn) break;
     p0 = p + 1;
+    accm |= 1ull << p;
     const double c = lane_value(cx, p);
-    my_pos = (lane == n) ? p : my_pos;
     // window entries G0[x][p], G0[p][x], and row r < n of lane p's history
     // (u_r[p], w_r[p]); four partial sums per product
     const double gA = g0s[lx][p], gB = g0s[p][lx];
@@ -384,9 +385,9 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
     na = n + 1;
   }
   wave_sync();
-  const unsigned long long accm = __ballot(xin && my_acc);
+  const bool my_acc = xin && ((accm >> lane) & 1ull);
   if (lane == 0) win_a[win] = na;
-  if (lane < na) win_p[win * W + lane] = my_pos;
+  if (my_acc) win_p[win * W + __popcll(accm & ((1ull << lane) - 1ull))] = lane;
   if (xin) {
     s_l[w0 + lane] = my_acc ? int8_t(-sx) : int8_t(sx);
     if (ratio_out) ratio_out[w0 + lane] = my_ratio;
