@@ -298,6 +298,20 @@ int kdqmc_measure(kdqmc_ctx* c, double* obs_dev);
  * dropped (they carry the old value). */
 int kdqmc_set_wrap_tolerance(kdqmc_ctx* c, double tol);
 
+/* Slice schedule of a single FP64 chain that uses the fused window launch
+ * (the delayed update of the delay-update algorithm cited in Sec. II, one
+ * flush per window): persistent != 0 runs each slice's window steps as one
+ * resident launch (one workgroup per 64 x 64 tile of G, holding it in
+ * registers for the slice, and one deciding workgroup, handing over through
+ * counters in the workspace; possible when 1 + ceil(N/64)^2 workgroups fit on
+ * the device at once, and the default then), 0 one launch per window.  Both
+ * compute the same G, decisions and ratios bit for bit.  A wait that cannot
+ * complete (the device shared with other resident work) is abandoned after a
+ * bounded spin and leaves NaN in G, which the next stabilization reports as
+ * KDQMC_ENUMERIC.  Returns 1 if the persistent launch is in use afterwards,
+ * 0 if not, or a negative error code.  Captured sweep graphs are dropped. */
+int kdqmc_set_slice_launch(kdqmc_ctx* c, int persistent);
+
 /* Synchronizes; writes the largest wrap error of any chain since the last
  * call (or kdqmc_set_fields / kdqmc_set_G) to *worst_wrap_err (host, may be
  * NULL; NaN if one was not finite) and returns KDQMC_ENUMERIC if any chain was

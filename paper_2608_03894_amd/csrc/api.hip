@@ -108,6 +108,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   char* snapr = take(2 * N * d.wm * 8);
   char* snapb = take(2 * (size_t)d.w * d.w * 8);
   char* Gs = take((size_t)d.w * d.w * 8);
+  char* ctl = take((size_t)(d.nw + 3) * 4);
   char* flag = take(64);
   char* err = take(1024 * 8);
   char* health = take(HL_COUNT * 8);
@@ -151,6 +152,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
     c->snapr = (double*)snapr;
     c->snapb = (double*)snapb;
     c->Gs = (double*)Gs;
+    c->ctl = (int*)ctl;
     c->flag = (int*)flag;
     c->err = (double*)err;
     c->health = (double*)health;
@@ -318,6 +320,17 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
   // run on concurrent streams, hiding launch gaps) take the three-kernel
   // schedule, which forms each window's factors once instead of per tile
   c->fused = d.fp64 && d.F == 1 && d.w <= 32 && (64 % d.w == 0 || d.nw == 1) && n_chains == 1;
+  // the persistent slice launch needs every workgroup resident: one per
+  // 64 x 64 tile plus the decider, at most one per compute unit
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
+      const int gxt = (d.N + 63) / 64;
+      c->persist_ok = c->fused && 1 + gxt * gxt <= cus;
+    }
+    c->persist = c->persist_ok;
+  }
   c->kmax = d.kmax;
   c->P = d.P;
   c->P64 = d.P64;
@@ -612,6 +625,17 @@ int kdqmc_set_wrap_tolerance(kdqmc_ctx* c, double tol) {
     c->wrap_tol = tol;
   }
   return KDQMC_OK;
+}
+
+int kdqmc_set_slice_launch(kdqmc_ctx* c, int persistent) {
+  KDQMC_TRY(check_ctx(c));
+  const bool want = persistent != 0 && c->persist_ok;
+  if (want != c->persist) {
+    drop_graphs(c);  // captured graphs carry the old schedule
+    c->persist = want;
+  }
+  clear_error();
+  return c->persist ? 1 : 0;
 }
 
 int kdqmc_health(kdqmc_ctx* c, double* worst_host) {

@@ -630,6 +630,198 @@ struct WinOps {
   }
 };
 
+// The pieces of the fused window step, shared by the per-window launch
+// (k_flush_decide) and the persistent slice launch (k_slice_persist), which
+// therefore compute the same values bit for bit.
+//
+// decider_block: the next window's block (window w1, wn1 sites) on the four
+// waves of the calling workgroup, wave (bi, bj) the 16 x 16 block (bi, bj) of
+// the 32 x 32 quadrant holding it, in the arithmetic of the tiles (the same
+// operands and MFMA steps in the same order, so the block equals the one the
+// tiles write to G bit for bit), written in the tilde frame to Zs (zero
+// outside wn1 x wn1).  Inputs: the window's accepts a and Z, Z' (Zc, Zpc),
+// the snapshots of its columns and rows (csc, rsc) and the copy of the next
+// window's block before this window's flush (bkc).  The caller synchronizes
+// the workgroup before Zs is read.
+template <int WM>
+__device__ __forceinline__ void decider_block(int tid, int N, int W, int w0, int wn, int a, int w1, int wn1,
+                                              const double* __restrict__ ev, const double* __restrict__ evinv,
+                                              const double* __restrict__ Zc, const double* __restrict__ Zpc,
+                                              const double* __restrict__ csc, const double* __restrict__ rsc,
+                                              const double* __restrict__ bkc, double (*Zs)[WM + 1]) {
+  typedef WinOps<WM> Ops;
+  constexpr int PS = Ops::PS, NB = Ops::NB;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nbl = (a + 15) >> 4;
+  const int Q0 = w1 & ~31;
+  const int bi = wave >> 1, bj = wave & 1;
+  const int rq = Q0 + 16 * bi, cq = Q0 + 16 * bj;
+  // (entries outside the window block are computed but never used); the
+  // frame scales of the block's rows and column are read up front
+  v4d blk;
+  double evr[4];
+  const double evic = evinv[min(cq + lr, N - 1)];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = rq + lk + 4 * j, cc = cq + lr;
+    blk[j] = bkc[(size_t)min(max(r - w1, 0), W - 1) * W + min(max(cc - w1, 0), W - 1)];
+    evr[j] = ev[min(r, N - 1)];
+  }
+  if (a > 0) {
+    // operands: Zh, Zph rows, the snapshot row rq + l%16 (g) and the
+    // transposed row snapshot at column cq + l%16 (h), PS positions each
+    Ops ops;
+    double gb[PS], hb[PS];
+    ops.load_z(Zc, Zpc, lr, lk);
+    load_run<PS>(gb, csc + (size_t)min(rq + lr, N - 1) * WM + PS * lk);
+    const int ch = min(cq + lr, N - 1);
+    load_run<PS>(hb, rsc + (size_t)ch * WM + PS * lk);
+#pragma unroll
+    for (int s = 0; s < PS; ++s) hb[s] = ((ch == w0 + PS * lk + s) ? 1.0 : 0.0) - hb[s];
+    v4d ut[NB], wt[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) ut[nb] = wt[nb] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < PS; ++s)
+      if (s < wn) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          if (nb < nbl) {
+            ut[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.za[nb][s], gb[s], ut[nb], 0, 0, 0);
+            wt[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.zpa[nb][s], hb[s], wt[nb], 0, 0, 0);
+          }
+      }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (16 * nb + 4 * j < a) blk = __builtin_amdgcn_mfma_f64_16x16x4f64(ut[nb][j], wt[nb][j], blk, 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = rq + lk + 4 * j, cc = cq + lr;
+    const double v = blk[j] * evr[j] * evic;
+    if (r >= w1 && r < w1 + wn1 && cc >= w1 && cc < w1 + wn1) Zs[r - w1][cc - w1] = v;
+  }
+  // (the decisions read rows and columns below WM only: nothing to clear
+  // for a full window)
+  if (wave == 0 && wn1 < WM)
+    for (int idx = lane; idx < WM * WM; idx += 64) {
+      const int x = idx / WM, y = idx % WM;
+      if (x >= wn1 || y >= wn1) Zs[x][y] = 0.0;
+    }
+}
+
+// tile_flush: a 64 x 64 tile's quarter (wave (wave >> 1, wave & 1), rows
+// row0.., columns col0..) in registers takes the window's rank-a update
+// G += U W, U^T and W formed from Z, Z' and the snapshots on the MFMA.
+template <int WM>
+__device__ __forceinline__ void tile_flush(v4d (&acc)[2][2], int lane, int N, int w0, int wn, int a, int row0,
+                                           int col0, const double* __restrict__ Zc,
+                                           const double* __restrict__ Zpc, const double* __restrict__ csc,
+                                           const double* __restrict__ rsc) {
+  typedef WinOps<WM> Ops;
+  constexpr int PS = Ops::PS, NB = Ops::NB;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nbl = (a + 15) >> 4;
+  Ops ops;
+  double gb[2][PS], hb[2][PS];
+  ops.load_z(Zc, Zpc, lr, lk);
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    load_run<PS>(gb[b], csc + (size_t)min(row0 + 16 * b + lr, N - 1) * WM + PS * lk);
+    load_run<PS>(hb[b], rsc + (size_t)min(col0 + 16 * b + lr, N - 1) * WM + PS * lk);
+  }
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int ch = min(col0 + 16 * b + lr, N - 1);
+#pragma unroll
+    for (int s = 0; s < PS; ++s) hb[b][s] = ((ch == w0 + PS * lk + s) ? 1.0 : 0.0) - hb[b][s];
+  }
+  v4d ut[NB][2], wt[NB][2];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) ut[nb][b] = wt[nb][b] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < PS; ++s)
+    if (s < wn) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        if (nb < nbl) {
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            ut[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.za[nb][s], gb[b][s], ut[nb][b], 0, 0, 0);
+            wt[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.zpa[nb][s], hb[b][s], wt[nb][b], 0, 0, 0);
+          }
+        }
+    }
+  // G += U W, k-steps 16 nb + 4 j in increasing order (the order of k_flush_f64)
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (16 * nb + 4 * j < a) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+            acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ut[nb][bi][j], wt[nb][bj][j], acc[bi][bj], 0, 0, 0);
+      }
+}
+
+// tile_snapshots: the tile quarter's part of the next window's columns and
+// rows (csn, rsn) and of the diagonal block of the window after next (bkn).
+__device__ __forceinline__ void tile_snapshots(const v4d (&acc)[2][2], int lane, int N, int W, int WMs, int row0,
+                                               int col0, int w1, int wn1, int w2, int wn2,
+                                               double* __restrict__ csn, double* __restrict__ rsn,
+                                               double* __restrict__ bkn) {
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
+        if (r < N && cc < N) {
+          if (cc >= w1 && cc < w1 + wn1) csn[(size_t)r * WMs + (cc - w1)] = acc[bi][bj][j];
+          if (r >= w1 && r < w1 + wn1) rsn[(size_t)cc * WMs + (r - w1)] = acc[bi][bj][j];
+          if (r >= w2 && r < w2 + wn2 && cc >= w2 && cc < w2 + wn2)
+            bkn[(size_t)(r - w2) * W + (cc - w2)] = acc[bi][bj][j];
+        }
+      }
+}
+
+__device__ __forceinline__ void tile_load(v4d (&acc)[2][2], const double* __restrict__ G, int N, int lane,
+                                          int row0, int col0) {
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
+        acc[bi][bj][j] = G[(size_t)min(r, N - 1) * N + min(cc, N - 1)];
+      }
+}
+
+__device__ __forceinline__ void tile_store(const v4d (&acc)[2][2], double* __restrict__ G, int N, int lane,
+                                           int row0, int col0) {
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
+        if (r < N && cc < N) G[(size_t)r * N + cc] = acc[bi][bj][j];
+      }
+}
+
 template <int WM>
 __global__ void __launch_bounds__(256)
 k_flush_decide(double* __restrict__ G, int N, int gxt, const double* __restrict__ ev,
@@ -641,8 +833,6 @@ k_flush_decide(double* __restrict__ G, int N, int gxt, const double* __restrict_
                double* __restrict__ Zn, double* __restrict__ Zpn, const double* __restrict__ csc,
                const double* __restrict__ rsc, double* __restrict__ csn, double* __restrict__ rsn,
                const double* __restrict__ bkc, double* __restrict__ bkn, size_t zs, size_t zn) {
-  typedef WinOps<WM> Ops;
-  constexpr int PS = Ops::PS, NB = Ops::NB;
   // Roles: with a next window, workgroup z < nch (the first dispatched)
   // decides chain z's next window; the others take the gxt x gxt tiles.
   const int w1 = (win + 1) * W, w2 = (win + 2) * W;
@@ -653,7 +843,7 @@ k_flush_decide(double* __restrict__ G, int N, int gxt, const double* __restrict_
   int z, t;
   if (decider) {
     z = lin;
-    t = (w1 >> 6) * gxt + (w1 >> 6);  // the tile holding the next window's block
+    t = 0;
   } else {
     const int j = lin - (has_next ? nz : 0);
     z = j / T;
@@ -682,85 +872,20 @@ k_flush_decide(double* __restrict__ G, int N, int gxt, const double* __restrict_
   bkn = zw_at(bkn, zs, z);
   sc = zw_at(sc, zs, z);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
   const int w0 = win * W;
   const int wn = min(W, N - w0);
   const int a = win_a[win];
-  const int nbl = (a + 15) >> 4;  // n blocks holding factors
   const int wn1 = has_next ? min(W, N - w1) : 0;
   const int wn2 = win + 2 < nw ? min(W, N - w2) : 0;
-  Ops ops;
   if (decider) {
-    // The decider: the next window's block only, on four waves (wave (bi,
-    // bj) the 16 x 16 block (bi, bj) of the 32 x 32 quadrant holding it) in
-    // the arithmetic of the tiles (the same operands, the same MFMA steps in
-    // the same order), so the block equals the one written to G bit for bit;
-    // then wave 0 runs the window's decisions on it.
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double(*Zs)[WM + 1] = reinterpret_cast<double(*)[WM + 1]>(smem_raw);
     double2(*hist)[64] = reinterpret_cast<double2(*)[64]>(smem_raw + sizeof(double) * WM * (WM + 1));
-    const int Q0 = w1 & ~31;
-    const int bi = wave >> 1, bj = wave & 1;
-    const int rq = Q0 + 16 * bi, cq = Q0 + 16 * bj;
-    // (entries outside the window block are computed but never used); the
-    // frame scales of the block's rows and column are read up front
-    v4d blk;
-    double evr[4];
-    const double evic = evinv[min(cq + lr, N - 1)];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = rq + lk + 4 * j, cc = cq + lr;
-      blk[j] = bkc[(size_t)min(max(r - w1, 0), W - 1) * W + min(max(cc - w1, 0), W - 1)];
-      evr[j] = ev[min(r, N - 1)];
-    }
     int sx;
     double ux;
     bool fx;
     site_inputs(lane, min(w1, N - 1), max(wn1, 1), s_l, u, forced, ev, sx, ux, fx);
-    if (a > 0) {
-      // operands: Zh, Zph rows, the snapshot row rq + l%16 (g) and the
-      // transposed row snapshot at column cq + l%16 (h), PS positions each
-      double gb[PS], hb[PS];
-      ops.load_z(Zc, Zpc, lr, lk);
-      load_run<PS>(gb, csc + (size_t)min(rq + lr, N - 1) * WM + PS * lk);
-      const int ch = min(cq + lr, N - 1);
-      load_run<PS>(hb, rsc + (size_t)ch * WM + PS * lk);
-#pragma unroll
-      for (int s = 0; s < PS; ++s) hb[s] = ((ch == w0 + PS * lk + s) ? 1.0 : 0.0) - hb[s];
-      v4d ut[NB], wt[NB];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) ut[nb] = wt[nb] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < PS; ++s)
-        if (s < wn) {
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            if (nb < nbl) {
-              ut[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.za[nb][s], gb[s], ut[nb], 0, 0, 0);
-              wt[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.zpa[nb][s], hb[s], wt[nb], 0, 0, 0);
-            }
-        }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (16 * nb + 4 * j < a)
-            blk = __builtin_amdgcn_mfma_f64_16x16x4f64(ut[nb][j], wt[nb][j], blk, 0, 0, 0);
-    }
-    // the window block (tilde frame) into LDS, zero outside wn1 x wn1
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = rq + lk + 4 * j, cc = cq + lr;
-      const double v = blk[j] * evr[j] * evic;
-      if (r >= w1 && r < w1 + wn1 && cc >= w1 && cc < w1 + wn1) Zs[r - w1][cc - w1] = v;
-    }
-    // (the decisions read rows and columns below WM only: nothing to clear
-    // for a full window)
-    if (wave == 0 && wn1 < WM)
-      for (int idx = lane; idx < WM * WM; idx += 64) {
-        const int x = idx / WM, y = idx % WM;
-        if (x >= wn1 || y >= wn1) Zs[x][y] = 0.0;
-      }
+    decider_block<WM>(tid, N, W, w0, wn, a, w1, wn1, ev, evinv, Zc, Zpc, csc, rsc, bkc, Zs);
     __syncthreads();
     if (wave != 0) return;
     const double em2a = sc[SC_EM2A], ep2a = sc[SC_EP2A];
@@ -769,96 +894,200 @@ k_flush_decide(double* __restrict__ G, int N, int gxt, const double* __restrict_
     return;
   }
   // a tile: wave (wave >> 1, wave & 1) takes the 32 x 32 quarter at (row0, col0)
-  const int R0 = by * 64, C0 = bx * 64;
-  const int row0 = R0 + (wave >> 1) * 32, col0 = C0 + (wave & 1) * 32;
+  const int row0 = by * 64 + (wave >> 1) * 32, col0 = bx * 64 + (wave & 1) * 32;
   v4d acc[2][2];
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
-        acc[bi][bj][j] = G[(size_t)min(r, N - 1) * N + min(cc, N - 1)];
-      }
+  tile_load(acc, G, N, lane, row0, col0);
   if (a > 0) {
-    double gb[2][PS], hb[2][PS];
-    ops.load_z(Zc, Zpc, lr, lk);
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      load_run<PS>(gb[b], csc + (size_t)min(row0 + 16 * b + lr, N - 1) * WM + PS * lk);
-      load_run<PS>(hb[b], rsc + (size_t)min(col0 + 16 * b + lr, N - 1) * WM + PS * lk);
-    }
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int ch = min(col0 + 16 * b + lr, N - 1);
-#pragma unroll
-      for (int s = 0; s < PS; ++s) hb[b][s] = ((ch == w0 + PS * lk + s) ? 1.0 : 0.0) - hb[b][s];
-    }
-    v4d ut[NB][2], wt[NB][2];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) ut[nb][b] = wt[nb][b] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s = 0; s < PS; ++s)
-      if (s < wn) {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          if (nb < nbl) {
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-              ut[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.za[nb][s], gb[b][s], ut[nb][b], 0, 0, 0);
-              wt[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.zpa[nb][s], hb[b][s], wt[nb][b], 0, 0, 0);
-            }
-          }
-      }
-    // G += U W, k-steps 16 nb + 4 j in increasing order (the order of k_flush_f64)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (16 * nb + 4 * j < a) {
-#pragma unroll
-          for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-              acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ut[nb][bi][j], wt[nb][bj][j], acc[bi][bj], 0, 0, 0);
-        }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
-          if (r < N && cc < N) G[(size_t)r * N + cc] = acc[bi][bj][j];
-        }
+    tile_flush<WM>(acc, lane, N, w0, wn, a, row0, col0, Zc, Zpc, csc, rsc);
+    tile_store(acc, G, N, lane, row0, col0);
   }
-  {
-    // copies for the next launches: the next window's columns and rows, and
-    // the diagonal block of the window after next
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int r = row0 + 16 * bi + lk + 4 * j, cc = col0 + 16 * bj + lr;
-          if (r < N && cc < N) {
-            if (cc >= w1 && cc < w1 + wn1) csn[(size_t)r * WM + (cc - w1)] = acc[bi][bj][j];
-            if (r >= w1 && r < w1 + wn1) rsn[(size_t)cc * WM + (r - w1)] = acc[bi][bj][j];
-            if (r >= w2 && r < w2 + wn2 && cc >= w2 && cc < w2 + wn2)
-              bkn[(size_t)(r - w2) * W + (cc - w2)] = acc[bi][bj][j];
-          }
-        }
-  }
+  // copies for the next launches: the next window's columns and rows, and
+  // the diagonal block of the window after next
+  tile_snapshots(acc, lane, N, W, WM, row0, col0, w1, wn1, w2, wn2, csn, rsn, bkn);
 }
 
 // the decider's LDS: the window block and the decision history
 template <int WM>
 constexpr size_t flush_decide_lds() {
   return size_t(WM * (WM + 1)) * 8 + size_t(WM) * 64 * 16;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent slice launch (one chain, FP64, every workgroup resident): the
+// window steps of the per-window launches in one launch per slice.
+// Workgroup 0 decides the windows in turn; workgroups 1..T own one 64 x 64
+// tile of G each, held in registers for the whole slice.  They hand over
+// through counters in the chain's workspace: ctl[1 + k] counts the tiles done
+// with the snapshots of window k (the flush of window k - 1, or for k = 0 the
+// initial copies); ctl[0] = k + 1 is window k's go, set by the decider once
+// window k's Z, Z' are written and ctl[1 + k] = T; ctl[2 + nw] is set by a
+// workgroup whose wait ran out.  Producer: its stores, a device-scope release,
+// then the counter; consumer: a bounded spin on the counter, then a
+// device-scope acquire before its loads.  A wait that runs out (a workgroup
+// not resident, or a fault) sets the abort flag, after which every wait
+// returns at once and the tiles write NaN into G, which the next
+// stabilization reports (KDQMC_ENUMERIC); nothing spins without bound.
+// Order of the data (buffers by window parity): window k's Z, Z' are written
+// by the decider before go k and read by flush k; the decider rewrites their
+// buffer with window k + 2 after go k + 1, i.e. after every tile is done with
+// flush k.  Window k's snapshots are written during flush k - 1 (complete at
+// go k) and read by flush k and the decider's block of window k + 1; flush
+// k + 1 rewrites them after go k + 1, which the decider gives after that
+// block.  Window k's block copy is written during flush k - 2 and read for
+// the block of window k (before go k), and rewritten during flush k.
+// ---------------------------------------------------------------------------
+constexpr int kSpinLimit = 1 << 22;
+
+// One thread spins and takes the device-scope acquire (the cache
+// invalidations act for the whole compute unit); the workgroup barrier then
+// orders the other waves' loads after it.
+__device__ __forceinline__ bool wait_count(int* __restrict__ ctr, int target, int* __restrict__ abort_flag) {
+  int good = 1;
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    for (;;) {
+      if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          ++spins > kSpinLimit) {
+        good = 0;
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  return __syncthreads_and(good) != 0;
+}
+
+// Every wave's stores complete (workgroup-scope release), the barrier, then
+// one thread's device-scope release (the write-back acts for the whole
+// cache) and the counter.
+__device__ __forceinline__ void signal_count(int* __restrict__ ctr) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int WM>
+__global__ void __launch_bounds__(256)
+k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict__ ev,
+                const double* __restrict__ evinv, int8_t* __restrict__ s_l,
+                const double* __restrict__ u, const uint8_t* __restrict__ forced,
+                uint8_t* __restrict__ acc_out, double* __restrict__ ratio_out,
+                const double* __restrict__ sc, int W, int nw, int* __restrict__ win_a,
+                int* __restrict__ win_p, double* __restrict__ Zb, double* __restrict__ Zpb,
+                double* __restrict__ csb, double* __restrict__ rsb, double* __restrict__ bkb,
+                int* __restrict__ ctl) {
+  const int T = gxt * gxt;
+  const size_t zz = (size_t)WM * WM, nwv = (size_t)N * WM, ww = (size_t)W * W;
+  int* zflag = ctl;
+  int* cnt = ctl + 1;          // cnt[k], k = 0 .. nw
+  int* abort_flag = ctl + 2 + nw;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double Zs[WM][WM + 1];
+  __shared__ double2 hist[WM][64];
+  if (blockIdx.x == 0) {
+    // ---- the decider
+    const double em2a = sc[SC_EM2A], ep2a = sc[SC_EP2A];
+    if (wave == 0) {
+      // window 0 straight from G (nothing flushed yet)
+      const int wn0 = min(W, N);
+      int sx;
+      double ux;
+      bool fx;
+      site_inputs(lane, 0, wn0, s_l, u, forced, ev, sx, ux, fx);
+      constexpr int PER = (WM * WM + 63) / 64;
+      double gv[PER];
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int idx = lane + 64 * j;
+        const int gx = min(idx / WM, wn0 - 1), gy = min(idx % WM, wn0 - 1);
+        gv[j] = G[(size_t)gx * N + gy] * ev[gx] * evinv[gy];
+      }
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int idx = lane + 64 * j;
+        const bool ok = idx / WM < wn0 && idx % WM < wn0;
+        if (idx < WM * WM) Zs[idx / WM][idx % WM] = ok ? gv[j] : 0.0;
+      }
+      wave_sync();
+      decide_window<WM>(lane, wn0, 0, W, 0, Zs, hist, sx, ux, fx, forced != nullptr, em2a, ep2a, s_l, acc_out,
+                        ratio_out, win_a, win_p, Zb, Zpb, ev, evinv);
+    }
+    // window 0's Z is out and the tiles' initial copies are complete: go
+    bool ok = wait_count(cnt + 0, T, abort_flag);
+    signal_count(zflag);
+    for (int k = 0; k + 1 < nw; ++k) {
+      const int w0 = k * W, wn = min(W, N - w0);
+      const int w1 = w0 + W, wn1 = min(W, N - w1);
+      int sx = 1;
+      double ux = 0.0;
+      bool fx = false;
+      if (wave == 0) site_inputs(lane, w1, wn1, s_l, u, forced, ev, sx, ux, fx);
+      // (window k's snapshots and window k + 1's block copy are complete:
+      // the wait before window k's go)
+      if (ok) {
+        const int a = win_a[k];
+        decider_block<WM>(tid, N, W, w0, wn, a, w1, wn1, ev, evinv, Zb + (k & 1) * zz, Zpb + (k & 1) * zz,
+                          csb + (k & 1) * nwv, rsb + (k & 1) * nwv, bkb + ((k + 1) & 1) * ww, Zs);
+      }
+      __syncthreads();
+      if (ok && wave == 0)
+        decide_window<WM>(lane, wn1, w1, W, k + 1, Zs, hist, sx, ux, fx, forced != nullptr, em2a, ep2a, s_l,
+                          acc_out, ratio_out, win_a, win_p, Zb + ((k + 1) & 1) * zz, Zpb + ((k + 1) & 1) * zz,
+                          ev, evinv);
+      // window k + 1's go once every tile is done with flush k (whose
+      // snapshots window k + 1's flush and the next block read)
+      ok = ok && wait_count(cnt + k + 1, T, abort_flag);
+      signal_count(zflag);
+    }
+    return;
+  }
+  // ---- a tile, held in registers for the whole slice
+  const int t = blockIdx.x - 1;
+  const int bx = t % gxt, by = t / gxt;
+  const int row0 = by * 64 + (wave >> 1) * 32, col0 = bx * 64 + (wave & 1) * 32;
+  v4d acc[2][2];
+  tile_load(acc, G, N, lane, row0, col0);
+  {
+    // window 0's columns and rows, window 1's block
+    const int wn0 = min(W, N), w1 = W, wn1 = nw > 1 ? min(W, N - W) : 0;
+    tile_snapshots(acc, lane, N, W, WM, row0, col0, 0, wn0, w1, wn1, csb, rsb, bkb + ww);
+  }
+  signal_count(cnt + 0);
+  bool ok = true;
+  for (int k = 0; k < nw; ++k) {
+    const int w0 = k * W, wn = min(W, N - w0);
+    const int w1 = w0 + W, wn1 = k + 1 < nw ? min(W, N - w1) : 0;
+    const int w2 = w1 + W, wn2 = k + 2 < nw ? min(W, N - w2) : 0;
+    // window k's go: its Z is published and every tile is done with the
+    // snapshots it reads
+    ok = ok && wait_count(zflag, k + 1, abort_flag);
+    if (ok) {
+      const int a = win_a[k];
+      if (a > 0)
+        tile_flush<WM>(acc, lane, N, w0, wn, a, row0, col0, Zb + (k & 1) * zz, Zpb + (k & 1) * zz,
+                       csb + (k & 1) * nwv, rsb + (k & 1) * nwv);
+      tile_snapshots(acc, lane, N, W, WM, row0, col0, w1, wn1, w2, wn2, csb + ((k + 1) & 1) * nwv,
+                     rsb + ((k + 1) & 1) * nwv, bkb + (k & 1) * ww);
+    }
+    signal_count(cnt + k + 1);
+  }
+  if (!ok) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{__builtin_nan(""), __builtin_nan(""), __builtin_nan(""), __builtin_nan("")};
+  }
+  tile_store(acc, G, N, lane, row0, col0);
+}
+
+__global__ void k_zero_ints(int* __restrict__ x, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1168,13 +1397,24 @@ int fused_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
   const size_t zz = (size_t)WM * WM, nwv = (size_t)N * WM, ww = (size_t)W * W;
   const int wn0 = std::min(W, N), wn1 = std::max(std::min(W, N - W), 0);
   const int nsnap = (2 * N * wn0 + wn1 * wn1 + 64 * 8 - 1) / (64 * 8);
+  const int gxt = (N + 63) / 64;
+  if (c->persist) {
+    // one resident launch for the slice (the caller checked 1 + gxt^2 <= CUs)
+    const int e0 = prof_mark(c);
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, c->stream, c->ctl, c->nw + 3);
+    hipLaunchKernelGGL((k_slice_persist<WM>), dim3(1 + gxt * gxt), dim3(256), 0, c->stream, G, N, gxt, c->ev,
+                       c->evinv, s_l, u, forced, acc, ratio, c->sc, W, c->nw, c->win_a, c->win_p, c->Xw, c->Yw,
+                       c->snapc, c->snapr, c->snapb, c->ctl);
+    prof_pair(c, PH_FLUSH_DECIDE, e0, prof_mark(c));
+    KDQMC_HIP(hipGetLastError());
+    return KDQMC_OK;
+  }
   const int e0 = prof_mark(c);
   hipLaunchKernelGGL((k_window_start<WM>), dim3(1 + nsnap, 1, Z), dim3(64), 0, c->stream, G, N, c->ev,
                      c->evinv, s_l, u, forced, acc, ratio, wn0, W, c->sc, c->win_a, c->win_p, c->Xw,
                      c->Yw, c->snapc, c->snapr, c->snapb + ww, zs, zn);
   int e1 = prof_mark(c);
   prof_pair(c, PH_DECIDE, e0, e1);
-  const int gxt = (N + 63) / 64;
   for (int win = 0; win < c->nw; ++win) {
     const size_t cur = win & 1, nxt = cur ^ 1;
     // the tiles, and with a next window one deciding workgroup per chain

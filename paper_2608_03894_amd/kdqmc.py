@@ -83,6 +83,7 @@ _SIGS = {
     "kdqmc_phase_name": (ctypes.c_char_p, [ctypes.c_int]),
     "kdqmc_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "kdqmc_set_wrap_tolerance": (ctypes.c_int, [_vp, ctypes.c_double]),
+    "kdqmc_set_slice_launch": (ctypes.c_int, [_vp, ctypes.c_int]),
     "kdqmc_trial_orbitals": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                             ctypes.POINTER(ctypes.c_double)]),
     "kdqmc_set_trial": (ctypes.c_int, [_vp, _vp]),
@@ -289,6 +290,15 @@ class Chain:
 
     def set_wrap_tolerance(self, tol):
         _check(self.lib.kdqmc_set_wrap_tolerance(self.ctx, float(tol)))
+
+    def set_slice_launch(self, persistent):
+        """True: one resident launch per slice where the shape allows it;
+        False: one launch per window.  Returns whether the persistent launch
+        is in use."""
+        rc = self.lib.kdqmc_set_slice_launch(self.ctx, 1 if persistent else 0)
+        if rc < 0:
+            _check(rc)
+        return rc == 1
 
     def health(self, raise_on_error=True):
         """Largest wrap error since the last call (synchronizes); raises
