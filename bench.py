@@ -115,7 +115,7 @@ def qr_panels(n, b=16):
     return (n + b - 1) // b
 
 
-def kernel_rooflines(prof, N, prec, k_avg, a_avg):
+def kernel_rooflines(prof, N, prec, k_avg, a_avg, windows_per_launch=1):
     """{phase: roofline dict} from the profiled (HIP-event) per-phase totals.
 
     achieved = algorithmic bytes or flops per launch / average launch time:
@@ -131,6 +131,10 @@ def kernel_rooflines(prof, N, prec, k_avg, a_avg):
           decisions, whose latency per accepted flip is reported separately;
       qr_panel: Householder panel flops; one workgroup per panel, so it is
           rated against one compute unit's FP64 rate (78.6 TFLOP/s / 256).
+    With the persistent slice launch (windows_per_launch = the slice's
+    windows) one flush_decide launch carries all of a slice's windows: its
+    algorithmic work is that many window flushes (the tiles keep G in
+    registers across them, so the measured HBM traffic is far lower).
     """
     out = {}
     es = 8 if prec == "fp64" else 4
@@ -147,8 +151,9 @@ def kernel_rooflines(prof, N, prec, k_avg, a_avg):
                      algorithmic_per_launch=byt)
         elif name in ("flush", "flush_decide"):
             rank = k_avg if name == "flush" else a_avg
-            fl = 2.0 * N * N * rank
-            byt = 2.0 * N * N * es + 2.0 * N * rank * es
+            nwin = windows_per_launch if name == "flush_decide" else 1
+            fl = 2.0 * N * N * rank * nwin
+            byt = (2.0 * N * N * es + 2.0 * N * rank * es) * nwin
             pk = FP64_PEAK_TFS if prec == "fp64" else F16_PEAK_TFS
             ach = byt / t / 1e9
             r.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
@@ -156,10 +161,20 @@ def kernel_rooflines(prof, N, prec, k_avg, a_avg):
                      mfma_tflops=fl / t / 1e12, mfma_peak=pk, mfma_frac=fl / t / 1e12 / pk,
                      flops_per_launch=fl)
             if name == "flush_decide":
-                r["us_per_accept"] = round(1e6 * t / max(rank, 1e-9), 4)
-                r["note"] = ("one launch per window: the window's factors and its rank-a flush on every "
-                             "64x64 tile, and the next window's sequential decisions on one workgroup; "
-                             "us_per_accept = launch time / accepted flips of the window")
+                r["us_per_accept"] = round(1e6 * t / max(rank * nwin, 1e-9), 4)
+                r["windows_per_launch"] = nwin
+                if nwin > 1:
+                    r["kernel_name"] = "k_slice_persist"
+                    r["note"] = ("one resident launch per slice: every 64x64 tile of G in registers for the "
+                                 "slice takes each window's factors and rank-a flush, one workgroup decides "
+                                 "the windows in turn; the algorithmic bytes count a G read and write per "
+                                 "window (the method's flush), the tiles touch G once per slice; "
+                                 "us_per_accept = launch time / accepted flips of the slice")
+                else:
+                    r["kernel_name"] = "k_flush_decide"
+                    r["note"] = ("one launch per window: the window's factors and its rank-a flush on every "
+                                 "64x64 tile, and the next window's sequential decisions on one workgroup; "
+                                 "us_per_accept = launch time / accepted flips of the window")
         elif name == "qr_panel":
             fl = qr_panel_flops(N) * (n / qr_panels(N)) / n
             ach = fl / t / 1e12
@@ -235,7 +250,11 @@ def run_chain(w, prec, n_stab, k, window, tile, steps, warmup, passes="alternate
     ub = torch.empty_like(uni[0])          # the one buffer every pass reads
     acc = torch.zeros((Lt, N), dtype=torch.uint8, device=dev)
     errs = torch.zeros(Lt // n_stab, dtype=torch.float64, device=dev)
-    log(f"{label or w.name}: prec={prec} k={k} window={window} n_stab={n_stab} N={N} L_tau={Lt}")
+    # the library's default: one resident launch per slice where the shape allows it
+    persistent = ch.set_slice_launch(True)
+    wps = -(-N // min(window or min(k, 32), N))
+    log(f"{label or w.name}: prec={prec} k={k} window={window} n_stab={n_stab} N={N} L_tau={Lt} "
+        f"persistent={persistent}")
     ch.set_fields(fields)
     alt = passes == "alternate"
 
@@ -260,7 +279,8 @@ def run_chain(w, prec, n_stab, k, window, tile, steps, warmup, passes="alternate
     res = {"steps": steps, "warmup": warmup, "ms_per_step": 1000.0 * elapsed / steps,
            "value": steps / elapsed, "unit": "sweeps/s", "healthy": ok, "max_wrap_err": worst,
            "wrap_tolerance": 1e-5 if prec == "fp64" else 1e-4, "acceptance": accepts / (N * Lt),
-           "accepts_last_sweep": accepts, "N": N, "L_tau": Lt}
+           "accepts_last_sweep": accepts, "N": N, "L_tau": Lt, "persistent": persistent,
+           "windows_per_slice": wps}
     log(f"  timed {steps} sweeps in {elapsed:.3f} s -> {res['value']:.4f} sweeps/s "
         f"(max wrap error {worst:.3e}, healthy={ok})")
     if not ok:
@@ -766,9 +786,10 @@ def main():
         # window's accepts)
         n_fl = prof["flush"][1] // steps
         n_fd = prof.get("flush_decide", (0, 0))[1] // steps
+        nwin = res["windows_per_slice"] if res.get("persistent") else 1
         k_avg = accepts / n_fl if n_fl else 0.0
-        a_avg = accepts / n_fd if n_fd else 0.0
-        kernels = kernel_rooflines(prof, N, prec, k_avg, a_avg)
+        a_avg = accepts / (n_fd * nwin) if n_fd else 0.0
+        kernels = kernel_rooflines(prof, N, prec, k_avg, a_avg, nwin)
         cand = {n: v for n, v in prof.items() if n != "stabilize" and v[1] > 0}
         dom = max(cand, key=lambda n: cand[n][0])
         roof = dict(kernels.get(dom, {"bound": None, "achieved": None, "peak": None, "unit": None,

@@ -438,17 +438,17 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
 // give more workgroups for the few-hundred-column matrices here).
 // W = V^T C: the waves split the rows and their partial 32 x SW products are
 // summed in LDS; then C -= V W2 with the waves splitting the rows.
-template <int SW>
+template <int SW, int VB = 2>
 struct WyLds {
-  double Wp[8][32][SW + 1];
-  double W2[32][SW + 1];
+  double Wp[8][16 * VB][SW + 1];
+  double W2[16 * VB][SW + 1];
   double Tl[32][33];
 };
 
 // One panel applied to the stripe s0 of C (the body of k_apply_wy; 512 threads);
 // VB = 1 for reflectors of at most 16 columns (half the products of VB = 2).
 template <int SW, int VB = 2>
-__device__ __forceinline__ void apply_wy_stripe(WyLds<SW>& sh, double* __restrict__ C, int ldc, int n,
+__device__ __forceinline__ void apply_wy_stripe(WyLds<SW, VB>& sh, double* __restrict__ C, int ldc, int n,
                                                 int j, int nbp, int ncols, int s0,
                                                 const double* __restrict__ V, int ldv,
                                                 const double* __restrict__ T, int trans,
@@ -572,6 +572,39 @@ struct PanelTable {
   int width[160];
 };
 
+// The whole Householder QR of one chain's n x ncol matrix in one workgroup
+// (512 threads): panel by panel (the panels of the per-panel launches), each
+// panel's reflector then applied to every trailing column in 64-column
+// stripes.  For batches of many chains, where one workgroup per chain fills
+// the device and the per-panel launches would spread every step of every
+// chain over the chip; V, T and tau are those of the per-panel launches.
+// The panel staging buffer and the apply's buffers share the LDS (never in
+// use at the same time).
+template <int RPT>
+__global__ void __launch_bounds__(512)
+k_qr_chain(double* __restrict__ A, int lda, int n, int ncol, double* __restrict__ Vq,
+           double* __restrict__ Tq, double* __restrict__ tau, PanelTable pt, int npan, size_t zs) {
+  constexpr size_t kPst = sizeof(double) * panel_chunk<RPT, 512>() * 17;
+  constexpr size_t kWy = sizeof(WyLds<64, 1>);
+  __shared__ __align__(16) unsigned char smem[kPst > kWy ? kPst : kWy];
+  A = zw(A, zs);
+  Vq = zw(Vq, zs);
+  Tq = zw(Tq, zs);
+  tau = zw(tau, zs);
+  double(*Pst)[17] = reinterpret_cast<double(*)[17]>(smem);
+  WyLds<64, 1>& sh = *reinterpret_cast<WyLds<64, 1>*>(smem);
+  for (int p = 0; p < npan; ++p) {
+    const int j = pt.start[p], nbp = pt.width[p];
+    double* Tp = Tq + (size_t)p * kNBmax * kNBmax;
+    qr_panel_body<RPT, 16, 512>(A, lda, n, j, nbp, Vq, Tp, tau, Pst);
+    __syncthreads();
+    for (int s0 = j + nbp; s0 < ncol; s0 += 64) {
+      apply_wy_stripe<64, 1>(sh, A, lda, n, j, nbp, ncol, s0, Vq, lda, Tp, 1);
+      __syncthreads();
+    }
+  }
+}
+
 template <int SW>
 __global__ void __launch_bounds__(512)
 k_apply_wy_all(double* __restrict__ C, int ldc, int n, int ncols, const double* __restrict__ V, int ldv,
@@ -652,7 +685,7 @@ k_merge_t(const double* __restrict__ V, int ldv, int n, const double* __restrict
 // issued before the first is used: rows of V and C for W = V^T C (wave w
 // takes rows w*4 + 32 i, i < 17) and rows of V for C -= V W2 (16-row blocks
 // w*16 + 128 k, k < 5).  512 threads.
-__device__ __forceinline__ void apply_wy_short(WyLds<16>& sh, double* __restrict__ C, int ldc, int n,
+__device__ __forceinline__ void apply_wy_short(WyLds<16, 1>& sh, double* __restrict__ C, int ldc, int n,
                                                int j, int nbp, int ncols, int s0,
                                                const double* __restrict__ V, int ldv,
                                                const double* __restrict__ T,
@@ -758,7 +791,7 @@ k_qr_step(double* __restrict__ A, int lda, int n, int ncols, int jp, int nbp, co
           int jn, int nbn, double* __restrict__ Vq, double* __restrict__ Tn, double* __restrict__ tau,
           size_t zs) {
   static_assert(NT <= 512, "the panel runs inside a 512-thread workgroup");
-  __shared__ WyLds<16> sh;
+  __shared__ WyLds<16, 1> sh;
   A = zw(A, zs);
   Vq = zw(Vq, zs);
   Tp = zw(Tp, zs);
@@ -929,6 +962,9 @@ namespace {
 // thread).
 inline int panel_width(int) { return 16; }
 
+// batches of at least this many chains factor each chain in one workgroup
+constexpr int kQrChainMin = 128;
+
 int launch_panel(kdqmc_ctx* c, double* A, int ld, int n, int j, int nbp, double* Tp) {
   const int m = n - j;
   const int e0 = prof_mark(c);
@@ -1022,6 +1058,37 @@ int qr_f64(kdqmc_ctx* c, int n, int ncol, double* A, double* Q) {
   // the next panel has at most 512 rows, else the update (split over the chip
   // for taller panels, which is faster there than one workgroup per stripe)
   // and the panel apart
+  if (c->nch >= kQrChainMin && n <= 2048) {
+    // one workgroup per chain for the whole factorization
+    PanelTable pt;
+    int npan = 0;
+    for (int j = 0; j < ncol; ++npan) {
+      const int nbp = std::min(panel_width(n - j), ncol - j);
+      pt.start[npan] = c->qr_panel_start[npan] = j;
+      pt.width[npan] = c->qr_panel_width[npan] = nbp;
+      j += nbp;
+    }
+    c->qr_npan = npan;
+    const int e0 = prof_mark(c);
+    if (n <= 512)
+      hipLaunchKernelGGL((k_qr_chain<1>), dim3(1, 1, c->nch), dim3(512), 0, c->stream, A, ld, n, ncol, c->Vq,
+                         c->Tq, c->tau, pt, npan, c->zs);
+    else if (n <= 1024)
+      hipLaunchKernelGGL((k_qr_chain<2>), dim3(1, 1, c->nch), dim3(512), 0, c->stream, A, ld, n, ncol, c->Vq,
+                         c->Tq, c->tau, pt, npan, c->zs);
+    else
+      hipLaunchKernelGGL((k_qr_chain<4>), dim3(1, 1, c->nch), dim3(512), 0, c->stream, A, ld, n, ncol, c->Vq,
+                         c->Tq, c->tau, pt, npan, c->zs);
+    prof_pair(c, PH_QR_PANEL, e0, prof_mark(c));
+    KDQMC_TRY(launch_merge_t(c, n));
+    if (Q) {
+      hipLaunchKernelGGL(k_set_identity, dim3((n * ncol + 255) / 256, 1, c->nch), dim3(256), 0, c->stream, Q, n,
+                         ncol, ld, c->zs);
+      KDQMC_TRY(launch_apply_all(c, Q, ld, n, ncol, true));
+    }
+    KDQMC_HIP(hipGetLastError());
+    return KDQMC_OK;
+  }
   int npan = 0, j = 0;
   int nbp = std::min(panel_width(n), ncol);
   KDQMC_TRY(launch_panel(c, A, ld, n, 0, nbp, c->Tq));
