@@ -232,7 +232,7 @@ def copy_calibration(mib=1024, reps=5):
 
 
 def run_chain(w, prec, n_stab, k, window, tile, steps, warmup, passes="alternate", profile=False,
-              label=None):
+              label=None, slice_launch="persistent"):
     """Times `steps` sweeps of one chain after `warmup` sweeps (graphs
     captured in the warm-up, replayed in the timed region).  Returns a dict;
     with profile=True the same sweeps are run again with a HIP event around
@@ -251,7 +251,7 @@ def run_chain(w, prec, n_stab, k, window, tile, steps, warmup, passes="alternate
     acc = torch.zeros((Lt, N), dtype=torch.uint8, device=dev)
     errs = torch.zeros(Lt // n_stab, dtype=torch.float64, device=dev)
     # the library's default: one resident launch per slice where the shape allows it
-    persistent = ch.set_slice_launch(True)
+    persistent = ch.set_slice_launch(slice_launch == "persistent")
     wps = -(-N // min(window or min(k, 32), N))
     log(f"{label or w.name}: prec={prec} k={k} window={window} n_stab={n_stab} N={N} L_tau={Lt} "
         f"persistent={persistent}")
@@ -713,6 +713,9 @@ def main():
     ap.add_argument("--n-stab", type=int, default=None, help="slices between stabilizations")
     ap.add_argument("--passes", default="alternate", choices=["alternate", "up"],
                     help="sweep directions: alternating upward/downward passes, or upward only")
+    ap.add_argument("--slice-launch", default="persistent", choices=["persistent", "per-window"],
+                    help="FP64 site updates: one resident launch per slice (where it fits) "
+                         "or one launch per window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slices", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
@@ -772,7 +775,7 @@ def main():
     k, window, tile, tuned = schedule(args.delay_k, args.window, args.fft_tile, w, prec, n_stab,
                                       args.config in AUTOTUNED)
     res = run_chain(w, prec, n_stab, k, window, tile, args.steps, args.warmup, args.passes,
-                    profile=not args.no_profile)
+                    profile=not args.no_profile, slice_launch=args.slice_launch)
     N, Lt = res["N"], res["L_tau"]
     win = min(window or min(k, 32), N)   # the library's default window: min(delay_k, 32)
 

@@ -301,10 +301,11 @@ int kdqmc_set_wrap_tolerance(kdqmc_ctx* c, double tol);
 /* Slice schedule of a single FP64 chain that uses the fused window launch
  * (the delayed update of the delay-update algorithm cited in Sec. II, one
  * flush per window): persistent != 0 runs each slice's window steps as one
- * resident launch (one workgroup per 64 x 64 tile of G, holding it in
+ * resident launch (workgroups holding one to three 64 x 64 tiles of G in
  * registers for the slice, and one deciding workgroup, handing over through
- * counters in the workspace; possible when 1 + ceil(N/64)^2 workgroups fit on
- * the device at once, and the default then), 0 one launch per window.  Both
+ * counters in the workspace; possible when 1 + ceil(ceil(N/64)^2 / 3)
+ * workgroups fit on the device at once, i.e. N <= 1728 on 256 compute
+ * units, and the default then), 0 one launch per window.  Both
  * compute the same G, decisions and ratios bit for bit.  A wait that cannot
  * complete (the device shared with other resident work) is abandoned after a
  * bounded spin and leaves NaN in G, which the next stabilization reports as

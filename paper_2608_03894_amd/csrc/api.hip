@@ -320,14 +320,18 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
   // run on concurrent streams, hiding launch gaps) take the three-kernel
   // schedule, which forms each window's factors once instead of per tile
   c->fused = d.fp64 && d.F == 1 && d.w <= 32 && (64 % d.w == 0 || d.nw == 1) && n_chains == 1;
-  // the persistent slice launch needs every workgroup resident: one per
-  // 64 x 64 tile plus the decider, at most one per compute unit
+  // the persistent slice launch needs every workgroup resident, at most one
+  // per compute unit: the decider and the tile workgroups
   {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) {
-      const int gxt = (d.N + 63) / 64;
-      c->persist_ok = c->fused && 1 + gxt * gxt <= cus;
+      // one 64 x 64 tile per workgroup where they fit, else two or three
+      const int T = ((d.N + 63) / 64) * ((d.N + 63) / 64);
+      int tpw = 1;
+      while (tpw < 3 && 1 + (T + tpw - 1) / tpw > cus) ++tpw;
+      c->persist_tpw = tpw;
+      c->persist_ok = c->fused && 1 + (T + tpw - 1) / tpw <= cus;
     }
     c->persist = c->persist_ok;
   }

@@ -266,7 +266,8 @@ struct kdqmc_ctx {
   double* snapb = nullptr;     // 2*w*w: G[S, S] of the window after next
   int* ctl = nullptr;          // nw + 3 counters of the persistent slice launch
   bool persist = false;        // one resident launch per slice (single FP64 chain, small N)
-  bool persist_ok = false;     // the shape allows it (1 + tiles <= compute units)
+  bool persist_ok = false;     // the shape allows it (1 + ceil(tiles / persist_tpw) <= compute units)
+  int persist_tpw = 1;         // tiles per workgroup of the persistent launch (1..3)
   bool fused = false;          // FP64, one window per flush, windows inside 64 x 64 tiles
   double* Gs = nullptr;        // w*w: G~cur[S,S] of the next window
   int* flag = nullptr;         // small device status words

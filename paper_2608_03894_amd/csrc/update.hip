@@ -713,31 +713,41 @@ __device__ __forceinline__ void decider_block(int tid, int N, int W, int w0, int
     }
 }
 
-// tile_flush: a 64 x 64 tile's quarter (wave (wave >> 1, wave & 1), rows
-// row0.., columns col0..) in registers takes the window's rank-a update
-// G += U W, U^T and W formed from Z, Z' and the snapshots on the MFMA.
+// The tile quarter's operands of the factor products: G~cur[rows, w0..]
+// (from the column snapshot) and G~cur[w0.., cols] (from the row snapshot).
+template <int PS>
+struct TileEdges {
+  double gb[2][PS], hb[2][PS];
+};
+
 template <int WM>
-__device__ __forceinline__ void tile_flush(v4d (&acc)[2][2], int lane, int N, int w0, int wn, int a, int row0,
-                                           int col0, const double* __restrict__ Zc,
-                                           const double* __restrict__ Zpc, const double* __restrict__ csc,
-                                           const double* __restrict__ rsc) {
+__device__ __forceinline__ void tile_edges(TileEdges<WM / 4>& e, int lane, int N, int row0, int col0,
+                                           const double* __restrict__ csc, const double* __restrict__ rsc) {
+  constexpr int PS = WM / 4;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    load_run<PS>(e.gb[b], csc + (size_t)min(row0 + 16 * b + lr, N - 1) * WM + PS * lk);
+    load_run<PS>(e.hb[b], rsc + (size_t)min(col0 + 16 * b + lr, N - 1) * WM + PS * lk);
+  }
+}
+
+// tile_apply: a 64 x 64 tile's quarter (wave (wave >> 1, wave & 1), rows
+// row0.., columns col0..) in registers takes the window's rank-a update
+// G += U W, U^T and W formed from Z, Z' (ops) and the tile's edges on the
+// MFMA.
+template <int WM>
+__device__ __forceinline__ void tile_apply(v4d (&acc)[2][2], const WinOps<WM>& ops, TileEdges<WM / 4>& e,
+                                           int lane, int N, int w0, int wn, int a, int col0) {
   typedef WinOps<WM> Ops;
   constexpr int PS = Ops::PS, NB = Ops::NB;
   const int lr = lane & 15, lk = lane >> 4;
   const int nbl = (a + 15) >> 4;
-  Ops ops;
-  double gb[2][PS], hb[2][PS];
-  ops.load_z(Zc, Zpc, lr, lk);
-#pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    load_run<PS>(gb[b], csc + (size_t)min(row0 + 16 * b + lr, N - 1) * WM + PS * lk);
-    load_run<PS>(hb[b], rsc + (size_t)min(col0 + 16 * b + lr, N - 1) * WM + PS * lk);
-  }
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const int ch = min(col0 + 16 * b + lr, N - 1);
 #pragma unroll
-    for (int s = 0; s < PS; ++s) hb[b][s] = ((ch == w0 + PS * lk + s) ? 1.0 : 0.0) - hb[b][s];
+    for (int s = 0; s < PS; ++s) e.hb[b][s] = ((ch == w0 + PS * lk + s) ? 1.0 : 0.0) - e.hb[b][s];
   }
   v4d ut[NB][2], wt[NB][2];
 #pragma unroll
@@ -752,8 +762,8 @@ __device__ __forceinline__ void tile_flush(v4d (&acc)[2][2], int lane, int N, in
         if (nb < nbl) {
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
-            ut[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.za[nb][s], gb[b][s], ut[nb][b], 0, 0, 0);
-            wt[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.zpa[nb][s], hb[b][s], wt[nb][b], 0, 0, 0);
+            ut[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.za[nb][s], e.gb[b][s], ut[nb][b], 0, 0, 0);
+            wt[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.zpa[nb][s], e.hb[b][s], wt[nb][b], 0, 0, 0);
           }
         }
     }
@@ -769,6 +779,20 @@ __device__ __forceinline__ void tile_flush(v4d (&acc)[2][2], int lane, int N, in
           for (int bj = 0; bj < 2; ++bj)
             acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ut[nb][bi][j], wt[nb][bj][j], acc[bi][bj], 0, 0, 0);
       }
+}
+
+// tile_flush: the window's update of one tile quarter, Z and the edges
+// loaded here.
+template <int WM>
+__device__ __forceinline__ void tile_flush(v4d (&acc)[2][2], int lane, int N, int w0, int wn, int a, int row0,
+                                           int col0, const double* __restrict__ Zc,
+                                           const double* __restrict__ Zpc, const double* __restrict__ csc,
+                                           const double* __restrict__ rsc) {
+  WinOps<WM> ops;
+  ops.load_z(Zc, Zpc, lane & 15, lane >> 4);
+  TileEdges<WM / 4> e;
+  tile_edges<WM>(e, lane, N, row0, col0, csc, rsc);
+  tile_apply<WM>(acc, ops, e, lane, N, w0, wn, a, col0);
 }
 
 // tile_snapshots: the tile quarter's part of the next window's columns and
@@ -972,7 +996,7 @@ __device__ __forceinline__ void signal_count(int* __restrict__ ctr) {
   }
 }
 
-template <int WM>
+template <int WM, int TPW>
 __global__ void __launch_bounds__(256)
 k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict__ ev,
                 const double* __restrict__ evinv, int8_t* __restrict__ s_l,
@@ -983,6 +1007,7 @@ k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict
                 double* __restrict__ csb, double* __restrict__ rsb, double* __restrict__ bkb,
                 int* __restrict__ ctl) {
   const int T = gxt * gxt;
+  const int nwg = gridDim.x - 1;  // tile workgroups, TPW tiles each at most
   const size_t zz = (size_t)WM * WM, nwv = (size_t)N * WM, ww = (size_t)W * W;
   int* zflag = ctl;
   int* cnt = ctl + 1;          // cnt[k], k = 0 .. nw
@@ -1019,7 +1044,7 @@ k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict
                         ratio_out, win_a, win_p, Zb, Zpb, ev, evinv);
     }
     // window 0's Z is out and the tiles' initial copies are complete: go
-    bool ok = wait_count(cnt + 0, T, abort_flag);
+    bool ok = wait_count(cnt + 0, nwg, abort_flag);
     signal_count(zflag);
     for (int k = 0; k + 1 < nw; ++k) {
       const int w0 = k * W, wn = min(W, N - w0);
@@ -1042,21 +1067,30 @@ k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict
                           ev, evinv);
       // window k + 1's go once every tile is done with flush k (whose
       // snapshots window k + 1's flush and the next block read)
-      ok = ok && wait_count(cnt + k + 1, T, abort_flag);
+      ok = ok && wait_count(cnt + k + 1, nwg, abort_flag);
       signal_count(zflag);
     }
     return;
   }
-  // ---- a tile, held in registers for the whole slice
-  const int t = blockIdx.x - 1;
-  const int bx = t % gxt, by = t / gxt;
-  const int row0 = by * 64 + (wave >> 1) * 32, col0 = bx * 64 + (wave & 1) * 32;
-  v4d acc[2][2];
-  tile_load(acc, G, N, lane, row0, col0);
+  // ---- TPW tiles (t = blockIdx.x - 1 + i nwg), held in registers for the whole slice
+  v4d acc[TPW][2][2];
+  int row0[TPW], col0[TPW];
+  bool live[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int t = blockIdx.x - 1 + i * nwg;
+    live[i] = t < T;
+    const int tc = live[i] ? t : 0;
+    row0[i] = (tc / gxt) * 64 + (wave >> 1) * 32;
+    col0[i] = (tc % gxt) * 64 + (wave & 1) * 32;
+    tile_load(acc[i], G, N, lane, row0[i], col0[i]);
+  }
   {
     // window 0's columns and rows, window 1's block
     const int wn0 = min(W, N), w1 = W, wn1 = nw > 1 ? min(W, N - W) : 0;
-    tile_snapshots(acc, lane, N, W, WM, row0, col0, 0, wn0, w1, wn1, csb, rsb, bkb + ww);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i)
+      if (live[i]) tile_snapshots(acc[i], lane, N, W, WM, row0[i], col0[i], 0, wn0, w1, wn1, csb, rsb, bkb + ww);
   }
   signal_count(cnt + 0);
   bool ok = true;
@@ -1069,21 +1103,45 @@ k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict
     ok = ok && wait_count(zflag, k + 1, abort_flag);
     if (ok) {
       const int a = win_a[k];
-      if (a > 0)
-        tile_flush<WM>(acc, lane, N, w0, wn, a, row0, col0, Zb + (k & 1) * zz, Zpb + (k & 1) * zz,
-                       csb + (k & 1) * nwv, rsb + (k & 1) * nwv);
-      tile_snapshots(acc, lane, N, W, WM, row0, col0, w1, wn1, w2, wn2, csb + ((k + 1) & 1) * nwv,
-                     rsb + ((k + 1) & 1) * nwv, bkb + (k & 1) * ww);
+      const double* csc = csb + (k & 1) * nwv;
+      const double* rsc = rsb + (k & 1) * nwv;
+      if (a > 0) {
+        // Z once for the window; the next tile's edges in flight while the
+        // current tile is on the MFMA (up to two tiles: with three, the
+        // second set of edges would not fit in the registers)
+        constexpr bool PF = TPW <= 2;
+        WinOps<WM> ops;
+        ops.load_z(Zb + (k & 1) * zz, Zpb + (k & 1) * zz, lane & 15, lane >> 4);
+        TileEdges<WM / 4> e[PF ? 2 : 1];
+        if (PF) tile_edges<WM>(e[0], lane, N, row0[0], col0[0], csc, rsc);
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+          TileEdges<WM / 4>& ei = e[PF ? (i & 1) : 0];
+          if (PF && i + 1 < TPW) tile_edges<WM>(e[(i + 1) & 1], lane, N, row0[i + 1], col0[i + 1], csc, rsc);
+          if (!PF) tile_edges<WM>(ei, lane, N, row0[i], col0[i], csc, rsc);
+          if (live[i]) tile_apply<WM>(acc[i], ops, ei, lane, N, w0, wn, a, col0[i]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < TPW; ++i)
+        if (live[i])
+          tile_snapshots(acc[i], lane, N, W, WM, row0[i], col0[i], w1, wn1, w2, wn2, csb + ((k + 1) & 1) * nwv,
+                         rsb + ((k + 1) & 1) * nwv, bkb + (k & 1) * ww);
     }
     signal_count(cnt + k + 1);
   }
-  if (!ok) {
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+  for (int i = 0; i < TPW; ++i) {
+    if (!live[i]) continue;
+    if (!ok) {
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{__builtin_nan(""), __builtin_nan(""), __builtin_nan(""), __builtin_nan("")};
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+          acc[i][bi][bj] = v4d{__builtin_nan(""), __builtin_nan(""), __builtin_nan(""), __builtin_nan("")};
+    }
+    tile_store(acc[i], G, N, lane, row0[i], col0[i]);
   }
-  tile_store(acc, G, N, lane, row0, col0);
 }
 
 __global__ void k_zero_ints(int* __restrict__ x, int n) {
@@ -1399,12 +1457,19 @@ int fused_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
   const int nsnap = (2 * N * wn0 + wn1 * wn1 + 64 * 8 - 1) / (64 * 8);
   const int gxt = (N + 63) / 64;
   if (c->persist) {
-    // one resident launch for the slice (the caller checked 1 + gxt^2 <= CUs)
+    // one resident launch for the slice (the context checked that the
+    // decider and ceil(gxt^2 / tpw) tile workgroups fit on the device)
     const int e0 = prof_mark(c);
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, c->stream, c->ctl, c->nw + 3);
-    hipLaunchKernelGGL((k_slice_persist<WM>), dim3(1 + gxt * gxt), dim3(256), 0, c->stream, G, N, gxt, c->ev,
-                       c->evinv, s_l, u, forced, acc, ratio, c->sc, W, c->nw, c->win_a, c->win_p, c->Xw, c->Yw,
-                       c->snapc, c->snapr, c->snapb, c->ctl);
+    const int T = gxt * gxt, tpw = c->persist_tpw, nwg = (T + tpw - 1) / tpw;
+#define PERSIST(TPW)                                                                                    \
+  hipLaunchKernelGGL((k_slice_persist<WM, TPW>), dim3(1 + nwg), dim3(256), 0, c->stream, G, N, gxt, c->ev,   \
+                     c->evinv, s_l, u, forced, acc, ratio, c->sc, W, c->nw, c->win_a, c->win_p, c->Xw, c->Yw, \
+                     c->snapc, c->snapr, c->snapb, c->ctl)
+    if (tpw == 1) PERSIST(1);
+    else if (tpw == 2) PERSIST(2);
+    else PERSIST(3);
+#undef PERSIST
     prof_pair(c, PH_FLUSH_DECIDE, e0, prof_mark(c));
     KDQMC_HIP(hipGetLastError());
     return KDQMC_OK;

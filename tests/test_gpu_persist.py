@@ -3,8 +3,9 @@ held in registers, workgroups handing over through counters) against the
 per-window launches it replaces: the same G, decisions and ratios bit for bit
 over an upward and a downward Metropolis pass, at shapes with one tile
 (L = 3), ragged 16- and 32-site windows (L = 6, 9), the headline lattice
-(L = 12) and the largest resident shape (L = 15, 121 tiles); and against the
-oracle at L = 6 with its decisions replayed."""
+(L = 12), one tile per workgroup up to L = 15 (121 tiles) and two or three
+per workgroup at L = 18 and 24; and against the oracle at L = 6 with its
+decisions replayed."""
 import numpy as np
 import pytest
 
@@ -36,10 +37,12 @@ def _run(L, U, beta, k, persistent, seed):
     return used, G, (a1, r1, a2, r2), ok
 
 
-@pytest.mark.parametrize("L,k", [(3, 8), (6, 16), (9, 32), (12, 32), (15, 32)])
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("L,k", [(3, 8), (6, 16), (9, 32), (12, 32), (15, 32), (18, 32), (24, 32)])
 def test_persistent_equals_per_window(gpu_lib, L, k):
+    """(L = 18 and 24: 256 and 729 tiles, two and three per workgroup.)"""
     say("persistent vs per-window", L, k)
-    U, beta, seed = -4.0, 2.0, 500 + L
+    U, beta, seed = -4.0, (2.0 if L <= 15 else 1.0), 500 + L
     used_p, Gp, dp, okp = _run(L, U, beta, k, True, seed)
     used_w, Gw, dw, okw = _run(L, U, beta, k, False, seed)
     say("  persistent used", used_p, "per-window used", used_w)
