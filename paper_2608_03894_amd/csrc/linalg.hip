@@ -174,6 +174,31 @@ __device__ __forceinline__ double xchg_xor(double v, int mask, int lane) {
   return __hiloint2double(xchg_dword(__double2hiint(v), mask, lane), xchg_dword(__double2loint(v), mask, lane));
 }
 
+// a + (a of lane l ^ M) in the lanes whose bit M is clear, b + (b of lane
+// l ^ M) in the others (M = 32: v_permlane32_swap, 16: v_permlane16_swap,
+// which exchange a's upper half / odd rows with b's lower half / even rows).
+template <int M>
+__device__ __forceinline__ double swap_sum(double a, double b) {
+  static_assert(M == 16 || M == 32, "permlane swap width");
+  const int ah = __double2hiint(a), al = __double2loint(a), bh = __double2hiint(b), bl = __double2loint(b);
+  if constexpr (M == 32) {
+    const auto h = __builtin_amdgcn_permlane32_swap(ah, bh, false, false);
+    const auto l = __builtin_amdgcn_permlane32_swap(al, bl, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+  } else {
+    const auto h = __builtin_amdgcn_permlane16_swap(ah, bh, false, false);
+    const auto l = __builtin_amdgcn_permlane16_swap(al, bl, false, false);
+    return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+  }
+}
+
+// a double moved by one DPP control (both halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true),
+                          __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true));
+}
+
 // One panel of the Householder QR.  Column c (row jc = j + c) needs, over
 // the rows r >= jc, the dot products d_t = sum_r a_c[r] a_t[r] with every
 // column t of the panel, and the row jc itself.  With alpha = a_c[jc],
@@ -292,26 +317,31 @@ __device__ __forceinline__ void qr_panel_body(double* __restrict__ A, int lda, i
         for (int q = 0; q < RPT; ++q) sacc = fma(x[q], a[q][p], sacc);
         part[p] = sacc;
       }
-      // reduce-scatter within the wave: lane l keeps sum number l % NB
+      // reduce-scatter within the wave: halving the sums a lane holds on
+      // lane bits 5 and 4 (permlane swaps, which move a pair of sums
+      // without selects), then 1 and 0 (quad DPP), and the full sum over
+      // bits 2 and 3 (row rotations); lane l then holds sum number
+      // 8 b0 + 4 b1 + 2 b4 + b5 (bK = bit K of l)
       {
-        int cnt = NB;
 #pragma unroll
-        for (int b = 0; (1 << b) < NB; ++b) {
+        for (int h = 0; h < NB / 2; ++h) part[h] = swap_sum<32>(part[2 * h], part[2 * h + 1]);
+#pragma unroll
+        for (int h = 0; h < NB / 4; ++h) part[h] = swap_sum<16>(part[2 * h], part[2 * h + 1]);
+#pragma unroll
+        for (int b = 1; b >= 0; --b) {
           const int bit = (lane >> b) & 1;
-          cnt >>= 1;
 #pragma unroll
-          for (int h = 0; h < NB / 2; ++h) {
-            if (h < cnt) {
-              const double keep = bit ? part[2 * h + 1] : part[2 * h];
-              const double send = bit ? part[2 * h] : part[2 * h + 1];
-              part[h] = keep + xchg_xor(send, 1 << b, lane);
-            }
+          for (int h = 0; h < (1 << b); ++h) {
+            const double keep = bit ? part[2 * h + 1] : part[2 * h];
+            const double send = bit ? part[2 * h] : part[2 * h + 1];
+            part[h] = keep + xchg_xor(send, 1 << b, lane);
           }
         }
         double v = part[0];
-#pragma unroll
-        for (int o = NB; o < 64; o <<= 1) v += xchg_xor(v, o, lane);
-        if (lane < NB) red[buf][wave][lane] = v;
+        v += dpp_f64<0x124>(v);  // row_ror:4
+        v += dpp_f64<0x128>(v);  // row_ror:8
+        if ((lane & 12) == 0)
+          red[buf][wave][8 * (lane & 1) + 2 * (lane & 2) + 2 * ((lane >> 4) & 1) + (lane >> 5)] = v;
       }
       __syncthreads();
       double tot = 0.0;
