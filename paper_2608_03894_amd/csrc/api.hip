@@ -108,7 +108,7 @@ size_t carve(const kdqmc_params* p, const Derived& d, kdqmc_ctx* c, char* base) 
   char* snapr = take(2 * N * d.wm * 8);
   char* snapb = take(2 * (size_t)d.w * d.w * 8);
   char* Gs = take((size_t)d.w * d.w * 8);
-  char* ctl = take((size_t)(d.nw + 3) * 4);
+  char* ctl = take((size_t)(d.nw + 4) * 4);
   char* flag = take(64);
   char* err = take(1024 * 8);
   char* health = take(HL_COUNT * 8);
@@ -392,8 +392,9 @@ int kdqmc_init_batch(kdqmc_ctx** out, const kdqmc_params* p, int n_chains, const
     const size_t sb = 2 * (size_t)d.N * d.wm * 8;
     if (hipMemset2DAsync(c->snapc, c->zs, 0, sb, n_chains, c->stream) != hipSuccess ||
         hipMemset2DAsync(c->snapr, c->zs, 0, sb, n_chains, c->stream) != hipSuccess ||
+        hipMemset2DAsync(c->ctl, c->zs, 0, (size_t)(d.nw + 4) * 4, n_chains, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
-      rc = set_error(KDQMC_EHIP, "clearing the window snapshots failed");
+      rc = set_error(KDQMC_EHIP, "clearing the window snapshots and counters failed");
   }
   if (rc != KDQMC_OK) {
     delete c;

@@ -264,7 +264,7 @@ struct kdqmc_ctx {
   double* snapc = nullptr;     // 2*N*wm: G[:, S] of a window, row stride wm (fused schedule, by parity)
   double* snapr = nullptr;     // 2*N*wm: G[S, :] of a window stored transposed, G[s][c] at c*wm + s
   double* snapb = nullptr;     // 2*w*w: G[S, S] of the window after next
-  int* ctl = nullptr;          // nw + 3 counters of the persistent slice launch
+  int* ctl = nullptr;          // nw + 4 counters of the persistent slice launch
   bool persist = false;        // one resident launch per slice (single FP64 chain, small N)
   bool persist_ok = false;     // the shape allows it (1 + ceil(tiles / persist_tpw) <= compute units)
   int persist_tpw = 1;         // tiles per workgroup of the persistent launch (1..3)

@@ -996,6 +996,19 @@ __device__ __forceinline__ void signal_count(int* __restrict__ ctr) {
   }
 }
 
+// The end of a workgroup of the slice launch: the last of the grid to get
+// here clears every counter (ctl[0 .. n), the exit count at ctl[n - 1]
+// included) for the next launch on the stream; the others have made their
+// last counter update before their own increment.
+__device__ __forceinline__ void slice_exit(int* __restrict__ ctl, int n) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int prev = __hip_atomic_fetch_add(ctl + n - 1, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == (int)gridDim.x - 1)
+      for (int i = 0; i < n; ++i) __hip_atomic_store(ctl + i, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 template <int WM, int TPW>
 __global__ void __launch_bounds__(256)
 k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict__ ev,
@@ -1012,6 +1025,7 @@ k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict
   int* zflag = ctl;
   int* cnt = ctl + 1;          // cnt[k], k = 0 .. nw
   int* abort_flag = ctl + 2 + nw;
+  const int nctl = nw + 4;     // (and the exit count)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ double Zs[WM][WM + 1];
   __shared__ double2 hist[WM][64];
@@ -1070,6 +1084,7 @@ k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict
       ok = ok && wait_count(cnt + k + 1, nwg, abort_flag);
       signal_count(zflag);
     }
+    slice_exit(ctl, nctl);
     return;
   }
   // ---- TPW tiles (t = blockIdx.x - 1 + i nwg), held in registers for the whole slice
@@ -1142,10 +1157,7 @@ k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict
     }
     tile_store(acc[i], G, N, lane, row0[i], col0[i]);
   }
-}
-
-__global__ void k_zero_ints(int* __restrict__ x, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0;
+  slice_exit(ctl, nctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1460,7 +1472,8 @@ int fused_updates(kdqmc_ctx* c, int l, const double* u, const uint8_t* forced, u
     // one resident launch for the slice (the context checked that the
     // decider and ceil(gxt^2 / tpw) tile workgroups fit on the device)
     const int e0 = prof_mark(c);
-    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, c->stream, c->ctl, c->nw + 3);
+    // (the counters start at zero: cleared when the context is made and
+    // by the last workgroup of every launch)
     const int T = gxt * gxt, tpw = c->persist_tpw, nwg = (T + tpw - 1) / tpw;
 #define PERSIST(TPW)                                                                                    \
   hipLaunchKernelGGL((k_slice_persist<WM, TPW>), dim3(1 + nwg), dim3(256), 0, c->stream, G, N, gxt, c->ev,   \
