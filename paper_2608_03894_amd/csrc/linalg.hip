@@ -654,137 +654,6 @@ k_apply_wy_all(double* __restrict__ C, int ldc, int n, int ncols, const double* 
   }
 }
 
-// The same, with the stripe held in registers from the first reflector to
-// the last (C is read and written once instead of once per reflector).
-// Every wave owns the 16-row blocks w, w + 8, ... (MB of them at most); in
-// both products a lane holds C[16 b + lk + 4 e][lr] of block b (lk = l / 16,
-// lr = l % 16), the B operand of k-step e of W = V^T C and element e of the
-// result of C -= V W2, so the stripe never moves between the two.  V is read
-// once per reflector, as the A operand of W = V^T C (lane: four rows of one
-// column; a load instruction touches four rows' 128-byte segments); the
-// update's A operand (lane: one row, four columns) is the same 16 x 32 block
-// transposed through a tile of the wave's own in LDS, not a second read of V
-// with 16 rows per instruction.  Blocks above the reflector's first row are
-// skipped (V is zero there).  Per reflector (merged pairs, up to 32
-// columns): partial W per wave, their sum in LDS, W2 = op(T) W, the update.
-template <int MB>
-__global__ void __launch_bounds__(512)
-k_apply_wy_res(double* __restrict__ C, int ldc, int n, int ncols, const double* __restrict__ V, int ldv,
-               const double* __restrict__ Tq, PanelTable pt, int npan, int backward, size_t zs) {
-  // (C and one reflector's V for all of a wave's blocks fill the registers:
-  // more than four blocks per wave spill)
-  static_assert(MB <= 4, "C and one reflector's V in the registers");
-  __shared__ double Wp[8][32][17];
-  __shared__ double Ws[32][17];
-  __shared__ double W2[32][17];
-  __shared__ double Tl[32][33];
-  __shared__ double Vx[8][16][33];  // each wave's transposition tile
-  C = zw(C, zs);
-  V = zw(V, zs);
-  Tq = zw(Tq, zs);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int lr = lane & 15, lk = lane >> 4;
-  const int s0 = blockIdx.x * 16;
-  const int cc = s0 + lr;
-  const bool colok = cc < ncols;
-  double c[MB][4];
-#pragma unroll
-  for (int i = 0; i < MB; ++i)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = 16 * (wave + 8 * i) + lk + 4 * e;
-      c[i][e] = (r < n && colok) ? C[(size_t)r * ldc + cc] : 0.0;
-    }
-  for (int it = 0; it < npan; ++it) {
-    const int p = backward ? npan - 1 - it : it;
-    const int j = pt.start[p], nbp = pt.width[p];
-    if (backward && j > s0) continue;  // columns left of the panel are untouched
-    const double* T = Tq + (size_t)p * kNBmax * kNBmax;
-    const double tv0 = T[tid], tv1 = T[tid + 512];
-    // V[16 b + 4 e + lk][j + 16 bi + lr] of every block, rows past n and
-    // columns past the reflector zeroed (addresses clamped)
-    double va[MB][4][2];
-#pragma unroll
-    for (int i = 0; i < MB; ++i)
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi) {
-          const int r = 16 * (wave + 8 * i) + 4 * e + lk;
-          const int vc = 16 * bi + lr;
-          const double v = V[(size_t)min(r, n - 1) * ldv + j + min(vc, nbp - 1)];
-          va[i][e][bi] = (r < n && vc < nbp) ? v : 0.0;
-        }
-    // W = V^T C
-    v4d acc[2] = {v4d{0.0, 0.0, 0.0, 0.0}, v4d{0.0, 0.0, 0.0, 0.0}};
-#pragma unroll
-    for (int i = 0; i < MB; ++i) {
-      const int rb = 16 * (wave + 8 * i);
-      if (rb < n && rb + 16 > j) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int bi = 0; bi < 2; ++bi)
-            acc[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(va[i][e][bi], c[i][e], acc[bi], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) Wp[wave][16 * bi + lk + 4 * e][lr] = acc[bi][e];
-    {
-      const int r0 = tid >> 5, c0 = tid & 31;
-      Tl[r0][c0] = (r0 < nbp && c0 < nbp) ? tv0 : 0.0;
-      Tl[r0 + 16][c0] = (r0 + 16 < nbp && c0 < nbp) ? tv1 : 0.0;
-    }
-    __syncthreads();
-    {
-      const int r = tid >> 4, q = tid & 15;
-      double sacc = 0.0;
-#pragma unroll
-      for (int w = 0; w < 8; ++w) sacc += Wp[w][r][q];
-      Ws[r][q] = sacc;
-    }
-    __syncthreads();
-    {
-      // W2 = op(T) W, four partial sums
-      const int r = tid >> 4, q = tid & 15;
-      double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-      for (int t = 0; t < 32; ++t) s4[t & 3] = fma(backward ? Tl[r][t] : Tl[t][r], Ws[t][q], s4[t & 3]);
-      W2[r][q] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-    }
-    __syncthreads();
-    // C -= V W2: each block's V through the wave's tile, element (4 e + lk,
-    // 16 bi + lr) in, (lr, 4 q + lk) out
-#pragma unroll
-    for (int i = 0; i < MB; ++i) {
-      const int rb = 16 * (wave + 8 * i);
-      if (rb < n && rb + 16 > j) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int bi = 0; bi < 2; ++bi) Vx[wave][4 * e + lk][16 * bi + lr] = va[i][e][bi];
-        wave_sync();
-        v4d d = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          d = __builtin_amdgcn_mfma_f64_16x16x4f64(Vx[wave][lr][4 * q + lk], W2[4 * q + lk][lr], d, 0, 0, 0);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) c[i][e] -= d[e];
-        wave_sync();  // (the tile is rewritten for the next block)
-      }
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < MB; ++i)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int r = 16 * (wave + 8 * i) + lk + 4 * e;
-      if (r < n && colok) C[(size_t)r * ldc + cc] = c[i][e];
-    }
-}
-
 // Consecutive panels p, p+1 (columns j1.., width b1; j2 = j1 + b1.., width
 // b2) merged into one block reflector: H_p H_{p+1} = I - [V1 V2] T [V1 V2]^T
 // with T = [[T1, -T1 (V1^T V2) T2], [0, T2]].  The apply kernels cost the
@@ -1182,17 +1051,10 @@ int launch_apply_all(kdqmc_ctx* c, double* C, int ld, int n, int ncols, bool bac
     pt.start[q] = c->qr_panel_start[2 * q];
     pt.width[q] = c->qr_panel_width[2 * q] + (2 * q + 1 < c->qr_npan ? c->qr_panel_width[2 * q + 1] : 0);
   }
+  constexpr int SW = 16;
   const int e0 = prof_mark(c);
-  const dim3 grid((ncols + 15) / 16, 1, c->nch);
-  // the stripe in registers up to 512 rows (four 16-row blocks per wave);
-  // taller stripes do not fit beside the loads in flight: C through memory
-  // per reflector
-  if (n <= 512)
-    hipLaunchKernelGGL(k_apply_wy_res<4>, grid, dim3(512), 0, c->stream, C, ld, n, ncols, c->Vq, ld, c->Tm, pt,
-                       nm, backward ? 1 : 0, c->zs);
-  else
-    hipLaunchKernelGGL(k_apply_wy_all<16>, grid, dim3(512), 0, c->stream, C, ld, n, ncols, c->Vq, ld, c->Tm, pt,
-                       nm, backward ? 1 : 0, c->zs);
+  hipLaunchKernelGGL(k_apply_wy_all<SW>, dim3((ncols + SW - 1) / SW, 1, c->nch), dim3(512), 0, c->stream, C, ld,
+                     n, ncols, c->Vq, ld, c->Tm, pt, nm, backward ? 1 : 0, c->zs);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   return KDQMC_OK;
 }
