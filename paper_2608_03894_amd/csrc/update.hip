@@ -399,7 +399,10 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
   //   Zh[n][p] = evinv[w0+p] Z[q_p][n],  Zph[n][p] = ev[w0+p] Z'[n][q_p]
   // with q_p the accept at position p (q_p <= n < na), zero elsewhere
   // (also past the window up to WM).  Lanes 0..31 write Zh, lanes 32..63
-  // Zph, the lane's position p = lane % 32.
+  // Zph, the lane's position p = lane % 32.  Every history row is read
+  // (qp < 32 always indexes a coefficient lane) and the unused ones are
+  // selected away, so the reads and the stores each go out together rather
+  // than one branch and round trip per row.
   {
     const int p = lane & 31;
     if (p < WM) {
@@ -408,14 +411,13 @@ __device__ __forceinline__ void decide_window(int lane, int wn, int w0, int W, i
       const int pc = w0 + min(p, wn - 1);
       const double f = zlane ? ev[pc] : evinv[pc];
       double* __restrict__ dst = zlane ? Zpg : Zg;
-      for (int n = 0; n < WM; ++n) {
-        double v = 0.0;
-        if (acc_p && n >= qp && n < na) {
-          const double2 h = hist[n][32 + qp];
-          v = (zlane ? h.y : h.x) * f;
-        }
-        dst[n * WM + p] = v;
-      }
+      double2 h[WM];
+#pragma unroll
+      for (int n = 0; n < WM; ++n) h[n] = hist[n][32 + qp];
+      __builtin_amdgcn_sched_barrier(0);  // (all reads issued before the first use)
+#pragma unroll
+      for (int n = 0; n < WM; ++n)
+        dst[n * WM + p] = (acc_p && n >= qp && n < na) ? (zlane ? h[n].y : h[n].x) * f : 0.0;
     }
   }
 }
