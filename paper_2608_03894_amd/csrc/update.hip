@@ -734,10 +734,98 @@ __device__ __forceinline__ void tile_edges(TileEdges<WM / 4>& e, int lane, int N
   }
 }
 
+// The two parts of the edges: the column snapshot at the quarter's rows
+// (U^T's operands) and the row snapshot at its columns (W's).
+template <int WM>
+__device__ __forceinline__ void tile_edges_g(double (&gb)[2][WM / 4], int lane, int N, int row0,
+                                             const double* __restrict__ csc) {
+  constexpr int PS = WM / 4;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) load_run<PS>(gb[b], csc + (size_t)min(row0 + 16 * b + lr, N - 1) * WM + PS * lk);
+}
+
+template <int WM>
+__device__ __forceinline__ void tile_edges_h(double (&hb)[2][WM / 4], int lane, int N, int col0,
+                                             const double* __restrict__ rsc) {
+  constexpr int PS = WM / 4;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) load_run<PS>(hb[b], rsc + (size_t)min(col0 + 16 * b + lr, N - 1) * WM + PS * lk);
+}
+
 // tile_apply: a 64 x 64 tile's quarter (wave (wave >> 1, wave & 1), rows
 // row0.., columns col0..) in registers takes the window's rank-a update
 // G += U W, U^T and W formed from Z, Z' (ops) and the tile's edges on the
-// MFMA.
+// MFMA: in one piece (tile_apply), or in two parts for several tiles of a
+// tile row, tile_ut (U^T of the quarter's rows, shared) and tile_wuw (W of
+// its columns and the product).  All compute the same values.
+template <int WM>
+__device__ __forceinline__ void tile_ut(v4d (&ut)[WM / 16][2], const WinOps<WM>& ops,
+                                        const double (&gb)[2][WM / 4], int wn, int a) {
+  constexpr int PS = WM / 4, NB = WM / 16;
+  const int nbl = (a + 15) >> 4;
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) ut[nb][b] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < PS; ++s)
+    if (s < wn) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        if (nb < nbl) {
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            ut[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.za[nb][s], gb[b][s], ut[nb][b], 0, 0, 0);
+        }
+    }
+}
+
+template <int WM>
+__device__ __forceinline__ void tile_wuw(v4d (&acc)[2][2], const WinOps<WM>& ops, double (&hb)[2][WM / 4],
+                                         const v4d (&ut)[WM / 16][2], int lane, int N, int w0, int wn, int a,
+                                         int col0) {
+  constexpr int PS = WM / 4, NB = WM / 16;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int nbl = (a + 15) >> 4;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int ch = min(col0 + 16 * b + lr, N - 1);
+#pragma unroll
+    for (int s = 0; s < PS; ++s) hb[b][s] = ((ch == w0 + PS * lk + s) ? 1.0 : 0.0) - hb[b][s];
+  }
+  v4d wt[NB][2];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) wt[nb][b] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < PS; ++s)
+    if (s < wn) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        if (nb < nbl) {
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            wt[nb][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ops.zpa[nb][s], hb[b][s], wt[nb][b], 0, 0, 0);
+        }
+    }
+  // G += U W, k-steps 16 nb + 4 j in increasing order (the order of k_flush_f64)
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (16 * nb + 4 * j < a) {
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+            acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ut[nb][bi][j], wt[nb][bj][j], acc[bi][bj], 0, 0, 0);
+      }
+}
+
+// (One tile: U^T and W formed together, eight independent MFMA chains.)
 template <int WM>
 __device__ __forceinline__ void tile_apply(v4d (&acc)[2][2], const WinOps<WM>& ops, TileEdges<WM / 4>& e,
                                            int lane, int N, int w0, int wn, int a, int col0) {
@@ -1089,13 +1177,15 @@ k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict
     slice_exit(ctl, nctl);
     return;
   }
-  // ---- TPW tiles (t = blockIdx.x - 1 + i nwg), held in registers for the whole slice
+  // ---- TPW consecutive tiles (t = (blockIdx.x - 1) TPW + i), held in
+  // registers for the whole slice; where they share a tile row (always when
+  // TPW divides the tiles per row) they share the window's U^T
   v4d acc[TPW][2][2];
   int row0[TPW], col0[TPW];
   bool live[TPW];
 #pragma unroll
   for (int i = 0; i < TPW; ++i) {
-    const int t = blockIdx.x - 1 + i * nwg;
+    const int t = (blockIdx.x - 1) * TPW + i;
     live[i] = t < T;
     const int tc = live[i] ? t : 0;
     row0[i] = (tc / gxt) * 64 + (wave >> 1) * 32;
@@ -1123,20 +1213,29 @@ k_slice_persist(double* __restrict__ G, int N, int gxt, const double* __restrict
       const double* csc = csb + (k & 1) * nwv;
       const double* rsc = rsb + (k & 1) * nwv;
       if (a > 0) {
-        // Z once for the window; the next tile's edges in flight while the
-        // current tile is on the MFMA (up to two tiles: with three, the
-        // second set of edges would not fit in the registers)
-        constexpr bool PF = TPW <= 2;
         WinOps<WM> ops;
         ops.load_z(Zb + (k & 1) * zz, Zpb + (k & 1) * zz, lane & 15, lane >> 4);
-        TileEdges<WM / 4> e[PF ? 2 : 1];
-        if (PF) tile_edges<WM>(e[0], lane, N, row0[0], col0[0], csc, rsc);
+        if constexpr (TPW == 1) {
+          TileEdges<WM / 4> e;
+          tile_edges<WM>(e, lane, N, row0[0], col0[0], csc, rsc);
+          if (live[0]) tile_apply<WM>(acc[0], ops, e, lane, N, w0, wn, a, col0[0]);
+        } else {
+          // Z once for the window; U^T once per tile row (the tiles of a
+          // workgroup share one unless they straddle two rows); each tile's
+          // column operands, the next tile's in flight while the current
+          // one is on the MFMA
+          v4d ut[WM / 16][2];
+          double gb[2][WM / 4], hb[2][2][WM / 4];
+          tile_edges_g<WM>(gb, lane, N, row0[0], csc);
+          tile_edges_h<WM>(hb[0], lane, N, col0[0], rsc);
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-          TileEdges<WM / 4>& ei = e[PF ? (i & 1) : 0];
-          if (PF && i + 1 < TPW) tile_edges<WM>(e[(i + 1) & 1], lane, N, row0[i + 1], col0[i + 1], csc, rsc);
-          if (!PF) tile_edges<WM>(ei, lane, N, row0[i], col0[i], csc, rsc);
-          if (live[i]) tile_apply<WM>(acc[i], ops, ei, lane, N, w0, wn, a, col0[i]);
+          for (int i = 0; i < TPW; ++i) {
+            if (i + 1 < TPW) tile_edges_h<WM>(hb[(i + 1) & 1], lane, N, col0[i + 1], rsc);
+            const bool new_row = i == 0 || (live[i] && row0[i] != row0[i - 1]);
+            if (i > 0 && new_row) tile_edges_g<WM>(gb, lane, N, row0[i], csc);
+            if (new_row) tile_ut<WM>(ut, ops, gb, wn, a);
+            if (live[i]) tile_wuw<WM>(acc[i], ops, hb[i & 1], ut, lane, N, w0, wn, a, col0[i]);
+          }
         }
       }
 #pragma unroll
