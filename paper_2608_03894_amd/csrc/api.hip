@@ -586,7 +586,7 @@ static int stabilize_timed(kdqmc_ctx* c, double* wrap_err_dev, size_t zn) {
   return rc;
 }
 
-// Reads every chain's health record (synchronizes).  latest: judge the
+// Reads every chain's health record (synchronizes).  latest: check the
 // latest stabilization only; otherwise everything since the last clear.
 static int read_health(kdqmc_ctx* c, bool latest, double* worst_out) {
   std::vector<double> h((size_t)c->nch * HL_COUNT);
