@@ -663,12 +663,12 @@ k_apply_wy_all(double* __restrict__ C, int ldc, int n, int ncols, const double* 
 __global__ void __launch_bounds__(1024)
 k_merge_t(const double* __restrict__ V, int ldv, int n, const double* __restrict__ Tq, PanelTable pt,
           int npan, double* __restrict__ Tm, size_t zs) {
-  __shared__ double T1[16][17], T2[16][17], S[16][17], X[16][17], Sp[4][16][17];
+  __shared__ double T1[16][17], T2[16][17], S[16][17], X[16][17], Sp[16][16][17];
   V = zw(V, zs);
   Tq = zw(Tq, zs);
   Tm = zw(Tm, zs);
   const int qp = blockIdx.x, p1 = 2 * qp, tid = threadIdx.x;
-  const int a = (tid >> 4) & 15, b = tid & 15, slice = tid >> 8;
+  const int a = (tid >> 4) & 15, b = tid & 15, slice = tid >> 8;  // (a, b) of the 16 x 16 products
   double* out = Tm + (size_t)qp * kNBmax * kNBmax;
   const double* t1 = Tq + (size_t)p1 * kNBmax * kNBmax;
   if (p1 + 1 >= npan) {
@@ -681,18 +681,33 @@ k_merge_t(const double* __restrict__ V, int ldv, int n, const double* __restrict
     T1[a][b] = (a < b1 && b < b1) ? t1[a * kNBmax + b] : 0.0;
     T2[a][b] = (a < b2 && b < b2) ? t2[a * kNBmax + b] : 0.0;
   }
-  // (V1^T V2)[a][b] over the rows from j2 on (V2 is zero above), every
-  // fourth row per slice
-  double sacc = 0.0;
-  if (a < b1 && b < b2) {
-#pragma unroll 16
-    for (int r = j2 + slice; r < n; r += 4)
-      sacc = fma(V[(size_t)r * ldv + j1 + a], V[(size_t)r * ldv + j2 + b], sacc);
+  // (V1^T V2)[a][b] over the rows from j2 on (V2 is zero above) on the FP64
+  // MFMA: wave w takes the 4-row k-steps j2 + 4 w + 64 i, a lane reading one
+  // entry of each panel's row (rows contiguous across the lanes); the 16
+  // waves' partial products are then summed
+  {
+    const int wave = tid >> 6, lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int r0 = j2 + 4 * wave; r0 < n; r0 += 64) {
+      const int r = r0 + lk;
+      const double* row = V + (size_t)min(r, n - 1) * ldv;
+      const double x1 = row[j1 + lr], x2 = row[j2 + lr];
+      const double va = (r < n && lr < b1) ? x1 : 0.0;
+      const double vb = (r < n && lr < b2) ? x2 : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va, vb, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Sp[wave][lk + 4 * e][lr] = acc[e];
   }
-  Sp[slice][a][b] = sacc;
   __syncthreads();
   if (tid >= 256) return;  // the rest is one 16 x 16 product chain
-  S[a][b] = (Sp[0][a][b] + Sp[1][a][b]) + (Sp[2][a][b] + Sp[3][a][b]);
+  {
+    double s8[8];
+#pragma unroll
+    for (int w = 0; w < 8; ++w) s8[w] = Sp[w][a][b] + Sp[w + 8][a][b];
+    S[a][b] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+  }
   __syncthreads();
   double x = 0.0;
   for (int k = 0; k < 16; ++k) x = fma(S[a][k], T2[k][b], x);
