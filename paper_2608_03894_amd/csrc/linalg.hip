@@ -481,50 +481,66 @@ template <int SW, int VB = 2>
 __device__ __forceinline__ void apply_wy_stripe(WyLds<SW, VB>& sh, double* __restrict__ C, int ldc, int n,
                                                 int j, int nbp, int ncols, int s0,
                                                 const double* __restrict__ V, int ldv,
-                                                const double* __restrict__ T, int trans,
-                                                double (*dst)[SW + 1] = nullptr, int dst_row0 = 0) {
+                                                const double* __restrict__ T, int trans) {
   constexpr int NW = 8;
   constexpr int BJ = SW / 16;
+  constexpr int U = SW >= 64 ? 2 : 4;  // k-steps of W = V^T C whose loads are issued together
   auto& Wp = sh.Wp;
   auto& W2 = sh.W2;
   auto& Tl = sh.Tl;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int m = n - j;
+  // Every global load below reads a clamped, in-range address unconditionally
+  // and the out-of-range values are zeroed afterwards: a guarded load would
+  // be a branch that waits for its data before the next load is issued.
+  bool vin[VB], cin[BJ];
+  int vcol[VB], ccol[BJ];
+#pragma unroll
+  for (int bi = 0; bi < VB; ++bi) {
+    vin[bi] = bi * 16 + lr < nbp;
+    vcol[bi] = j + (vin[bi] ? bi * 16 + lr : 0);
+  }
+#pragma unroll
+  for (int bj = 0; bj < BJ; ++bj) {
+    cin[bj] = s0 + bj * 16 + lr < ncols;
+    ccol[bj] = cin[bj] ? s0 + bj * 16 + lr : 0;
+  }
   // T's two elements per thread are loaded now and stored to LDS after the
   // V^T C loop, so that the loop does not wait for them
   double tv[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) tv[h] = T[tid + 512 * h];
-  // W = V^T C (32 x SW), rows split over waves in chunks of 4
+  // W = V^T C (32 x SW), rows split over waves in chunks of 4, U chunks per
+  // round of loads
   v4d acc[VB][BJ];
 #pragma unroll
   for (int bi = 0; bi < VB; ++bi)
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-  for (int kb = wave * 4; kb < m; kb += 4 * NW) {
-    const int r = j + kb + lk;
-    double av[VB], bv[BJ];
+  for (int kb0 = wave * 4; kb0 < m; kb0 += 4 * NW * U) {
+    double av[U][VB], bv[U][BJ];
 #pragma unroll
-    for (int bi = 0; bi < VB; ++bi) {
-      const int vc = bi * 16 + lr;
-      av[bi] = (r < n && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
+    for (int u = 0; u < U; ++u) {
+      const size_t rc = (size_t)min(j + kb0 + 4 * NW * u + lk, n - 1);
+#pragma unroll
+      for (int bi = 0; bi < VB; ++bi) av[u][bi] = V[rc * ldv + vcol[bi]];
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj) bv[u][bj] = C[rc * ldc + ccol[bj]];
     }
 #pragma unroll
-    for (int bj = 0; bj < BJ; ++bj) {
-      const int cc = s0 + bj * 16 + lr;
-      bv[bj] = (r < n && cc < ncols) ? C[(size_t)r * ldc + cc] : 0.0;
+    for (int u = 0; u < U; ++u) {
+      const bool rin = j + kb0 + 4 * NW * u + lk < n;
+#pragma unroll
+      for (int bi = 0; bi < VB; ++bi) av[u][bi] = (rin && vin[bi]) ? av[u][bi] : 0.0;
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj) bv[u][bj] = (rin && cin[bj]) ? bv[u][bj] : 0.0;
+#pragma unroll
+      for (int bi = 0; bi < VB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < BJ; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][bi], bv[u][bj], acc[bi][bj], 0, 0, 0);
     }
-    if (dst != nullptr && r >= dst_row0 && r < n) {  // keep the LDS rows' old values
-#pragma unroll
-      for (int bj = 0; bj < BJ; ++bj) dst[r - dst_row0][bj * 16 + lr] = bv[bj];
-    }
-#pragma unroll
-    for (int bi = 0; bi < VB; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < BJ; ++bj)
-        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
   }
 #pragma unroll
   for (int bi = 0; bi < VB; ++bi)
@@ -554,29 +570,41 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW, VB>& sh, double* __res
     W2[r][cc] = sacc;
   }
   __syncthreads();
-  // C -= V W2, 16-row blocks split over waves
-#pragma unroll 2
+  // C -= V W2, 16-row blocks split over waves; the block's rows of V (and,
+  // for one-tile stripes, the C elements it updates) are all loaded before
+  // the first product.  Wider stripes read C at the update: holding their
+  // 16 elements as well runs the whole-QR kernel out of registers.
   for (int rb = wave * 16; rb < m; rb += 16 * NW) {
+    const int r = j + rb + lr;
+    const size_t rc = (size_t)min(r, n - 1);
+    double av[4 * VB], cv[BJ][4];
+#pragma unroll
+    for (int q = 0; q < 4 * VB; ++q) {
+      const int vc = 4 * q + lk;
+      av[q] = V[rc * ldv + j + (vc < nbp ? vc : 0)];
+    }
+    if constexpr (BJ == 1) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cv[0][e] = C[(size_t)min(j + rb + lk + 4 * e, n - 1) * ldc + ccol[0]];
+    }
     v4d d[BJ];
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj) d[bj] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kk = 0; kk < 16 * VB; kk += 4) {
-      const int r = j + rb + lr, vc = kk + lk;
-      const double av = (r < n && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
+    for (int q = 0; q < 4 * VB; ++q) {
+      const double a = (r < n && 4 * q + lk < nbp) ? av[q] : 0.0;
 #pragma unroll
       for (int bj = 0; bj < BJ; ++bj)
-        d[bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W2[kk + lk][bj * 16 + lr], d[bj], 0, 0, 0);
+        d[bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, W2[4 * q + lk][bj * 16 + lr], d[bj], 0, 0, 0);
     }
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int r = j + rb + lk + 4 * e, cc = s0 + bj * 16 + lr;
-        if (dst != nullptr && r >= dst_row0) {  // in the caller's LDS rows (0 past ncols)
-          if (r < n) dst[r - dst_row0][bj * 16 + lr] -= d[bj][e];
-        } else if (r < n && cc < ncols) {
-          C[(size_t)r * ldc + cc] -= d[bj][e];
+        const int r2 = j + rb + lk + 4 * e;
+        if (r2 < n && cin[bj]) {
+          double* c = C + (size_t)r2 * ldc + ccol[bj];
+          *c = (BJ == 1 ? cv[bj][e] : *c) - d[bj][e];
         }
       }
   }
