@@ -910,24 +910,44 @@ k_wy_partial(const double* __restrict__ C, int ldc, int n, int j, int nbp, int n
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int kb = r0 + wave * 4; kb < r1; kb += 4 * NW) {
-    const int r = kb + lk;
-    double av[2], bv[BJ];
+  // clamped in-range loads, U k-steps' worth issued together, zeroed
+  // afterwards where out of range (a guarded load waits for its data)
+  constexpr int U = 4;
+  bool vin[2], cin[BJ];
+  int vcol[2], ccol[BJ];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
-      const int vc = bi * 16 + lr;
-      av[bi] = (r < r1 && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
+  for (int bi = 0; bi < 2; ++bi) {
+    vin[bi] = bi * 16 + lr < nbp;
+    vcol[bi] = j + (vin[bi] ? bi * 16 + lr : 0);
+  }
+#pragma unroll
+  for (int bj = 0; bj < BJ; ++bj) {
+    cin[bj] = s0 + bj * 16 + lr < ncols;
+    ccol[bj] = cin[bj] ? s0 + bj * 16 + lr : 0;
+  }
+  for (int kb0 = r0 + wave * 4; kb0 < r1; kb0 += 4 * NW * U) {
+    double av[U][2], bv[U][BJ];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t rcl = (size_t)min(kb0 + 4 * NW * u + lk, r1 - 1);
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) av[u][bi] = V[rcl * ldv + vcol[bi]];
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj) bv[u][bj] = C[rcl * ldc + ccol[bj]];
     }
 #pragma unroll
-    for (int bj = 0; bj < BJ; ++bj) {
-      const int cc = s0 + bj * 16 + lr;
-      bv[bj] = (r < r1 && cc < ncols) ? C[(size_t)r * ldc + cc] : 0.0;
+    for (int u = 0; u < U; ++u) {
+      const bool rin = kb0 + 4 * NW * u + lk < r1;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) av[u][bi] = (rin && vin[bi]) ? av[u][bi] : 0.0;
+#pragma unroll
+      for (int bj = 0; bj < BJ; ++bj) bv[u][bj] = (rin && cin[bj]) ? bv[u][bj] : 0.0;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < BJ; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][bi], bv[u][bj], acc[bi][bj], 0, 0, 0);
     }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < BJ; ++bj)
-        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi], bv[bj], acc[bi][bj], 0, 0, 0);
   }
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -957,11 +977,18 @@ k_wy_reduce(int nbp, int ncols, const double* __restrict__ T, int trans, double*
     const int r = idx >> 5, cc = idx & 31;
     Tl[r][cc] = (r < nbp && cc < nbp) ? T[r * kNBmax + cc] : 0.0;
   }
+  // all kWyChunks partials read at once (clamped chunk and column, the
+  // extra ones zeroed), then summed in chunk order
   for (int idx = tid; idx < 32 * SW; idx += 256) {
     const int r = idx / SW, cc = idx % SW;
+    const bool in = s0 + cc < ncols;
+    const int col = in ? s0 + cc : 0;
+    double pv[kWyChunks];
+#pragma unroll
+    for (int q = 0; q < kWyChunks; ++q) pv[q] = Wpart[((size_t)min(q, nq - 1) * 32 + r) * ncols + col];
     double sacc = 0.0;
-    if (s0 + cc < ncols)
-      for (int q = 0; q < nq; ++q) sacc += Wpart[((size_t)q * 32 + r) * ncols + s0 + cc];
+#pragma unroll
+    for (int q = 0; q < kWyChunks; ++q) sacc += (in && q < nq) ? pv[q] : 0.0;
     Ws[r][cc] = sacc;
   }
   __syncthreads();
@@ -985,29 +1012,45 @@ k_wy_update(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int s0 = blockIdx.x * SW;
+  // W2's stripe, the tile's rows of V and the C elements it updates are all
+  // read (clamped, in range) before the first product; out-of-range values
+  // are zeroed or not stored
+  const int rb = j + blockIdx.y * 64 + wave * 16;
+  const size_t rv = (size_t)min(rb + lr, n - 1);
+  double av[8], cv[BJ][4];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int vc = 4 * q + lk;
+    av[q] = V[rv * ldv + j + (vc < nbp ? vc : 0)];
+  }
+#pragma unroll
+  for (int bj = 0; bj < BJ; ++bj) {
+    const int cc = s0 + bj * 16 + lr, col = cc < ncols ? cc : 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) cv[bj][e] = C[(size_t)min(rb + lk + 4 * e, n - 1) * ldc + col];
+  }
   for (int idx = tid; idx < 32 * SW; idx += 256) {
     const int r = idx / SW, cc = idx % SW;
-    W2[r][cc] = (s0 + cc < ncols) ? W2g[(size_t)r * ncols + s0 + cc] : 0.0;
+    const double w = W2g[(size_t)r * ncols + (s0 + cc < ncols ? s0 + cc : 0)];
+    W2[r][cc] = (s0 + cc < ncols) ? w : 0.0;
   }
   __syncthreads();
-  const int rb = j + blockIdx.y * 64 + wave * 16;
   v4d d[BJ];
 #pragma unroll
   for (int bj = 0; bj < BJ; ++bj) d[bj] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int kk = 0; kk < 32; kk += 4) {
-    const int r = rb + lr, vc = kk + lk;
-    const double av = (r < n && vc < nbp) ? V[(size_t)r * ldv + j + vc] : 0.0;
+  for (int q = 0; q < 8; ++q) {
+    const double a = (rb + lr < n && 4 * q + lk < nbp) ? av[q] : 0.0;
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj)
-      d[bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, W2[kk + lk][bj * 16 + lr], d[bj], 0, 0, 0);
+      d[bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, W2[4 * q + lk][bj * 16 + lr], d[bj], 0, 0, 0);
   }
 #pragma unroll
   for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int r = rb + lk + 4 * e, cc = s0 + bj * 16 + lr;
-      if (r < n && cc < ncols) C[(size_t)r * ldc + cc] -= d[bj][e];
+      if (r < n && cc < ncols) C[(size_t)r * ldc + cc] = cv[bj][e] - d[bj][e];
     }
 }
 
