@@ -913,6 +913,7 @@ k_wy_partial(const double* __restrict__ C, int ldc, int n, int j, int nbp, int n
   // clamped in-range loads, U k-steps' worth issued together, zeroed
   // afterwards where out of range (a guarded load waits for its data)
   constexpr int U = 4;
+  const bool two = nbp > 16;  // reflector columns 16..31 present (same for every lane)
   bool vin[2], cin[BJ];
   int vcol[2], ccol[BJ];
 #pragma unroll
@@ -930,8 +931,8 @@ k_wy_partial(const double* __restrict__ C, int ldc, int n, int j, int nbp, int n
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const size_t rcl = (size_t)min(kb0 + 4 * NW * u + lk, r1 - 1);
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi) av[u][bi] = V[rcl * ldv + vcol[bi]];
+      av[u][0] = V[rcl * ldv + vcol[0]];
+      av[u][1] = two ? V[rcl * ldv + vcol[1]] : 0.0;
 #pragma unroll
       for (int bj = 0; bj < BJ; ++bj) bv[u][bj] = C[rcl * ldc + ccol[bj]];
     }
@@ -943,10 +944,13 @@ k_wy_partial(const double* __restrict__ C, int ldc, int n, int j, int nbp, int n
 #pragma unroll
       for (int bj = 0; bj < BJ; ++bj) bv[u][bj] = (rin && cin[bj]) ? bv[u][bj] : 0.0;
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
+      for (int bj = 0; bj < BJ; ++bj)
+        acc[0][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][0], bv[u][bj], acc[0][bj], 0, 0, 0);
+      if (two) {
 #pragma unroll
         for (int bj = 0; bj < BJ; ++bj)
-          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][bi], bv[u][bj], acc[bi][bj], 0, 0, 0);
+          acc[1][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][1], bv[u][bj], acc[1][bj], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
@@ -1012,16 +1016,23 @@ k_wy_update(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const int s0 = blockIdx.x * SW;
-  // W2's stripe, the tile's rows of V and the C elements it updates are all
-  // read (clamped, in range) before the first product; out-of-range values
-  // are zeroed or not stored
+  for (int idx = tid; idx < 32 * SW; idx += 256) {
+    const int r = idx / SW, cc = idx % SW;
+    W2[r][cc] = (s0 + cc < ncols) ? W2g[(size_t)r * ncols + s0 + cc] : 0.0;
+  }
+  __syncthreads();
+  // the tile's rows of V (the k-steps that hold reflector columns) and the C
+  // elements it updates are read (clamped, in range) before the first
+  // product; out-of-range values are zeroed or not stored.  Issued after the
+  // barrier, whose fence would wait for them.
   const int rb = j + blockIdx.y * 64 + wave * 16;
   const size_t rv = (size_t)min(rb + lr, n - 1);
+  const int nkq = (nbp + 3) / 4;  // 4-column k-steps holding reflector columns (same for every lane)
   double av[8], cv[BJ][4];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int vc = 4 * q + lk;
-    av[q] = V[rv * ldv + j + (vc < nbp ? vc : 0)];
+    av[q] = q < nkq ? V[rv * ldv + j + (vc < nbp ? vc : 0)] : 0.0;
   }
 #pragma unroll
   for (int bj = 0; bj < BJ; ++bj) {
@@ -1029,17 +1040,12 @@ k_wy_update(double* __restrict__ C, int ldc, int n, int j, int nbp, int ncols,
 #pragma unroll
     for (int e = 0; e < 4; ++e) cv[bj][e] = C[(size_t)min(rb + lk + 4 * e, n - 1) * ldc + col];
   }
-  for (int idx = tid; idx < 32 * SW; idx += 256) {
-    const int r = idx / SW, cc = idx % SW;
-    const double w = W2g[(size_t)r * ncols + (s0 + cc < ncols ? s0 + cc : 0)];
-    W2[r][cc] = (s0 + cc < ncols) ? w : 0.0;
-  }
-  __syncthreads();
   v4d d[BJ];
 #pragma unroll
   for (int bj = 0; bj < BJ; ++bj) d[bj] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
+    if (q >= nkq) break;
     const double a = (rb + lr < n && 4 * q + lk < nbp) ? av[q] : 0.0;
 #pragma unroll
     for (int bj = 0; bj < BJ; ++bj)
