@@ -464,27 +464,31 @@ k_qr_panel(double* __restrict__ A, int lda, int n, int j, int nbp, double* __res
 // C[j:n, s0:s0+SW] -= V op(T) (V^T C[j:n, s0:s0+SW]) for the panel at column
 // j (width nbp <= 32): op(T) = T^T applies H^T = H_{nbp-1} ... H_0 (the
 // factorization / Q^T direction), op(T) = T applies H = H_0 ... H_{nbp-1}.
-// One workgroup (8 waves) per SW-column stripe (SW = 16 or 32; narrow stripes
-// give more workgroups for the few-hundred-column matrices here).
+// One workgroup (8 waves, or 16 for forming Q) per SW-column stripe (SW = 16
+// or 32; narrow stripes give more workgroups for the few-hundred-column
+// matrices here).
 // W = V^T C: the waves split the rows and their partial 32 x SW products are
 // summed in LDS; then C -= V W2 with the waves splitting the rows.
-template <int SW, int VB = 2>
+template <int SW, int VB = 2, int NW = 8>
 struct WyLds {
-  double Wp[8][16 * VB][SW + 1];
+  double Wp[NW][16 * VB][SW + 1];
   double W2[16 * VB][SW + 1];
   double Tl[32][33];
 };
 
-// One panel applied to the stripe s0 of C (the body of k_apply_wy; 512 threads);
+// One panel applied to the stripe s0 of C (the body of k_apply_wy; NT threads);
 // VB = 1 for reflectors of at most 16 columns (half the products of VB = 2).
-template <int SW, int VB = 2>
-__device__ __forceinline__ void apply_wy_stripe(WyLds<SW, VB>& sh, double* __restrict__ C, int ldc, int n,
-                                                int j, int nbp, int ncols, int s0,
+template <int SW, int VB = 2, int NT = 512>
+__device__ __forceinline__ void apply_wy_stripe(WyLds<SW, VB, NT / 64>& sh, double* __restrict__ C, int ldc,
+                                                int n, int j, int nbp, int ncols, int s0,
                                                 const double* __restrict__ V, int ldv,
                                                 const double* __restrict__ T, int trans) {
-  constexpr int NW = 8;
+  constexpr int NW = NT / 64;
   constexpr int BJ = SW / 16;
-  constexpr int U = SW >= 64 ? 2 : 4;  // k-steps of W = V^T C whose loads are issued together
+  constexpr int TH = kNBmax * kNBmax / NT;  // elements of T per thread
+  // k-steps of W = V^T C whose loads are issued together (fewer where the
+  // registers per thread are fewer: wide stripes, 16-wave workgroups)
+  constexpr int U = (SW >= 64 || NT > 512) ? 2 : 4;
   auto& Wp = sh.Wp;
   auto& W2 = sh.W2;
   auto& Tl = sh.Tl;
@@ -508,9 +512,9 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW, VB>& sh, double* __res
   }
   // T's two elements per thread are loaded now and stored to LDS after the
   // V^T C loop, so that the loop does not wait for them
-  double tv[2];
+  double tv[TH];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) tv[h] = T[tid + 512 * h];
+  for (int h = 0; h < TH; ++h) tv[h] = T[tid + NT * h];
   // W = V^T C (32 x SW), rows split over waves in chunks of 4, U chunks per
   // round of loads
   v4d acc[VB][BJ];
@@ -549,12 +553,12 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW, VB>& sh, double* __res
 #pragma unroll
       for (int e = 0; e < 4; ++e) Wp[wave][bi * 16 + lk + 4 * e][bj * 16 + lr] = acc[bi][bj][e];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int idx = tid + 512 * h, r = idx >> 5, cc = idx & 31;
+  for (int h = 0; h < TH; ++h) {
+    const int idx = tid + NT * h, r = idx >> 5, cc = idx & 31;
     Tl[r][cc] = (r < nbp && cc < nbp) ? tv[h] : 0.0;
   }
   __syncthreads();
-  for (int idx = tid; idx < 16 * VB * SW; idx += 512) {
+  for (int idx = tid; idx < 16 * VB * SW; idx += NT) {
     const int r = idx / SW, cc = idx % SW;
     double sacc = 0.0;
 #pragma unroll
@@ -563,7 +567,7 @@ __device__ __forceinline__ void apply_wy_stripe(WyLds<SW, VB>& sh, double* __res
   }
   __syncthreads();
   // W2 = op(T) W
-  for (int idx = tid; idx < 16 * VB * SW; idx += 512) {
+  for (int idx = tid; idx < 16 * VB * SW; idx += NT) {
     const int r = idx / SW, cc = idx % SW;
     double sacc = 0.0;
     for (int t = 0; t < 16 * VB; ++t) sacc += (trans ? Tl[t][r] : Tl[r][t]) * Wp[0][t][cc];
@@ -663,11 +667,11 @@ k_qr_chain(double* __restrict__ A, int lda, int n, int ncol, double* __restrict_
   }
 }
 
-template <int SW>
-__global__ void __launch_bounds__(512)
+template <int SW, int NT>
+__global__ void __launch_bounds__(NT)
 k_apply_wy_all(double* __restrict__ C, int ldc, int n, int ncols, const double* __restrict__ V, int ldv,
                const double* __restrict__ Tq, PanelTable pt, int npan, int backward, size_t zs) {
-  __shared__ WyLds<SW> sh;
+  __shared__ WyLds<SW, 2, NT / 64> sh;
   C = zw(C, zs);
   V = zw(V, zs);
   Tq = zw(Tq, zs);
@@ -676,8 +680,8 @@ k_apply_wy_all(double* __restrict__ C, int ldc, int n, int ncols, const double* 
     const int p = backward ? npan - 1 - i : i;
     const int j = pt.start[p];
     if (backward && j > s0) continue;  // columns left of the panel are untouched
-    apply_wy_stripe<SW>(sh, C, ldc, n, j, pt.width[p], ncols, s0, V, ldv, Tq + (size_t)p * kNBmax * kNBmax,
-                        backward ? 0 : 1);
+    apply_wy_stripe<SW, 2, NT>(sh, C, ldc, n, j, pt.width[p], ncols, s0, V, ldv,
+                               Tq + (size_t)p * kNBmax * kNBmax, backward ? 0 : 1);
     __syncthreads();  // this panel's update is read by the next one
   }
 }
@@ -1143,10 +1147,12 @@ int launch_apply_all(kdqmc_ctx* c, double* C, int ld, int n, int ncols, bool bac
     pt.start[q] = c->qr_panel_start[2 * q];
     pt.width[q] = c->qr_panel_width[2 * q] + (2 * q + 1 < c->qr_npan ? c->qr_panel_width[2 * q + 1] : 0);
   }
-  constexpr int SW = 16;
+  // 16 waves per stripe: at these sizes there are fewer stripes than CUs,
+  // and each reflector's row loop is on the critical path of its stripe
+  constexpr int SW = 16, NT = 1024;
   const int e0 = prof_mark(c);
-  hipLaunchKernelGGL(k_apply_wy_all<SW>, dim3((ncols + SW - 1) / SW, 1, c->nch), dim3(512), 0, c->stream, C, ld,
-                     n, ncols, c->Vq, ld, c->Tm, pt, nm, backward ? 1 : 0, c->zs);
+  hipLaunchKernelGGL((k_apply_wy_all<SW, NT>), dim3((ncols + SW - 1) / SW, 1, c->nch), dim3(NT), 0, c->stream,
+                     C, ld, n, ncols, c->Vq, ld, c->Tm, pt, nm, backward ? 1 : 0, c->zs);
   prof_pair(c, PH_GEMM, e0, prof_mark(c));
   return KDQMC_OK;
 }
